@@ -1,0 +1,467 @@
+"""Pins of the CPU oracle against what the paper and the mathematics fix.
+
+No test here compares the oracle with a retyped copy of itself.  Each one
+checks it against a printed value of the paper (fixtures in tests/golden/),
+a published test vector, a library routine (scipy distance matrices), a
+closed form, an exhaustive enumeration, or an invariant that a plausible
+mistake (a dropped term, a wrong sign or offset, a reversed tie-break, an
+in-place update) would break.
+"""
+import itertools
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy.spatial.distance import cdist
+
+from paper_2209_00117_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _rows(name):
+    with open(os.path.join(GOLDEN, name)) as f:
+        return [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+
+
+def _rand_xy(rng, W, H, S, distinct=True):
+    if distinct:
+        p = rng.choice(W * H, size=S, replace=False)
+    else:
+        p = rng.integers(0, W * H, size=S)
+    return np.stack([p % W, p // W], axis=1).astype(np.int32)
+
+
+def _scipy_nearest(xy, W, H, metric):
+    """Definition of Eq. (1) through scipy: argmin of the distance matrix;
+    numpy's argmin returns the first minimum, i.e. the lowest seed index."""
+    yy, xx = np.mgrid[0:H, 0:W]
+    pix = np.stack([xx.ravel(), yy.ravel()], axis=1).astype(np.float64)
+    D = cdist(pix, xy.astype(np.float64), "sqeuclidean" if metric == 0 else "cityblock")
+    return np.argmin(D, axis=1).reshape(H, W).astype(np.int32), D.min(axis=1).reshape(H, W)
+
+
+# --------------------------------------------------------------------------
+# RNG
+# --------------------------------------------------------------------------
+def test_splitmix64_reference_vector(orc):
+    for n, hexval in _rows("splitmix64_seed0.txt"):
+        assert orc.stream_out(0, int(n)) == int(hexval, 16)
+        assert int(inputs.splitmix64(0, int(n), 1)[0]) == int(hexval, 16)
+
+
+def test_bounded_range_and_ends(orc):
+    for m in (1, 2, 3, 5, 9, 65473, 2 ** 31):
+        assert orc.bounded(0, m) == 0
+        assert orc.bounded(2 ** 64 - 1, m) == m - 1
+        r = inputs.splitmix64(11, 0, 1000)
+        vals = [orc.bounded(int(v), m) for v in r[:50]]
+        assert all(0 <= v < m for v in vals)
+        assert vals == [int(v) for v in inputs.bounded(r[:50], m)]
+
+
+@pytest.mark.parametrize("lo,hi", [(-1, 1), (-2, 2), (-4, 4), (-1, 3), (0, 0)])
+def test_move_uniform_clamped(orc, lo, hi):
+    """Sec. V-A: uniform random moves of up to d_max units; the grid clamps."""
+    W = H = 4096
+    S = 20000
+    xy = np.full((S, 2), 2048, np.int32)
+    moved = orc.move_seeds(xy, W, H, 1, 3, lo, hi)
+    d = moved - xy
+    assert d.min() >= lo and d.max() <= hi
+    span = hi - lo + 1
+    if span > 1:
+        for axis in (0, 1):
+            counts = np.bincount(d[:, axis] - lo, minlength=span)
+            expect = S / span
+            chi2 = float(((counts - expect) ** 2 / expect).sum())
+            assert chi2 < 3 * span + 30, (axis, counts)      # loose: df = span-1
+        # the two axes are drawn independently
+        joint = np.bincount((d[:, 0] - lo) * span + (d[:, 1] - lo), minlength=span * span)
+        expect = S / span ** 2
+        chi2 = float(((joint - expect) ** 2 / expect).sum())
+        assert chi2 < 3 * span * span + 30
+    # clamping at the borders
+    corner = np.zeros((S, 2), np.int32)
+    m2 = orc.move_seeds(corner, W, H, 1, 3, lo, hi)
+    assert m2.min() >= 0 and m2.max() <= max(hi, 0)
+
+
+def test_move_depends_only_on_step(orc):
+    """Moves of step t are a pure function of (seed, t, index): replaying
+    step 3 alone gives the same displacement as after steps 1 and 2."""
+    xy = np.full((64, 2), 100, np.int32)
+    a = orc.move_seeds(xy, 1000, 1000, 9, 3, -2, 2) - xy
+    b = orc.move_seeds(orc.move_seeds(xy, 1000, 1000, 9, 1, -2, 2), 1000, 1000, 9, 2, -2, 2)
+    c = orc.move_seeds(b, 1000, 1000, 9, 3, -2, 2) - b
+    assert np.array_equal(a, c)
+    assert not np.array_equal(a, orc.move_seeds(xy, 1000, 1000, 9, 4, -2, 2) - xy)
+
+
+# --------------------------------------------------------------------------
+# Schedules: Eq. (2) and Eq. (5)
+# --------------------------------------------------------------------------
+def test_eq2_worked_example(orc):
+    for row in _rows("eq2_worked_example.txt"):
+        W, H, ks = int(row[0]), int(row[1]), [int(v) for v in row[2:]]
+        assert [k for k, _ in orc.schedule(W, H, 1, False)] == ks
+        assert all(nb == orc.MOORE for _, nb in orc.schedule(W, H, 1, False))
+
+
+@pytest.mark.parametrize("N,k1", [(1, 0), (2, 1), (3, 2), (4, 2), (5, 4), (8, 4), (9, 8),
+                                  (512, 256), (1000, 512), (4096, 2048), (8192, 4096)])
+def test_eq2_k1(orc, N, k1):
+    assert orc.k1(N, N) == k1
+    assert orc.k1(N, 1) == k1 and orc.k1(1, N) == k1
+    if N > 1:
+        # log2(k1) + 1 passes, which is ceil(log2 N)
+        assert len(orc.schedule(N, N, 1, False)) == math.ceil(math.log2(N))
+
+
+def test_eq5_configs(orc):
+    """delta_1 of the three single-simulation workloads, worked by hand:
+    512^2/256 seeds: 2 L_avg = 2*32 = 64 -> 64 (7 passes);
+    4096^2/65536:    2 L_avg = 2*16 = 32 -> 32 (6 passes);
+    8192^2/2^20:     2 L_avg = 2*8  = 16 -> 16 (5 passes)."""
+    assert orc.delta1(512, 512, 256, 1) == 64
+    assert orc.delta1(4096, 4096, 65536, 2) == 32
+    assert orc.delta1(8192, 8192, 1 << 20, 4) == 16
+    assert len(orc.schedule(512, 512, 256, True, 1)) == 7
+    assert len(orc.schedule(4096, 4096, 65536, True, 2)) == 6
+    assert len(orc.schedule(8192, 8192, 1 << 20, True, 4)) == 5
+    # d_max dominates when moves exceed the region size (Sec. V-A)
+    assert orc.delta1(8192, 8192, 1 << 20, 100) == 128
+    # sparse seeds: as many passes as JFA, never more (Sec. V-A)
+    assert orc.delta1(8192, 8192, 1, 1) == orc.k1(8192, 8192)
+
+
+def test_eq5_matches_real_form(orc):
+    """Integer form == 2^ceil(log2 max(2 sqrt(n*n/s), d_max)) computed in
+    floating point, wherever the real value is not within rounding of a
+    power of two."""
+    checked = 0
+    for W in (16, 100, 512, 1000, 4096):
+        for S in (1, 3, 7, 64, 100, 1000, 4096, 65536):
+            if S > W * W:
+                continue
+            for dmax in (0, 1, 2, 3, 5, 17, 100):
+                x = max(2 * math.sqrt(W * W / S), dmax)
+                lg = math.log2(x)
+                if abs(lg - round(lg)) < 1e-9:
+                    continue
+                P = 2 ** math.ceil(lg)
+                assert orc.delta1(W, W, S, dmax) == min(P, orc.k1(W, W)), (W, S, dmax)
+                checked += 1
+    assert checked > 100
+
+
+def test_djfa_schedule_readings(orc):
+    """Sec. V-B: the first one or two passes use Von Neumann, the rest Moore;
+    the optional extra passes (JFA+1, JFA+2) come last."""
+    s = orc.schedule(512, 512, 256, True, 1, vn_passes=2, extra_passes=0)
+    assert s == [(64, 1), (32, 1), (16, 0), (8, 0), (4, 0), (2, 0), (1, 0)]
+    s = orc.schedule(512, 512, 256, True, 1, vn_passes=1, extra_passes=2)
+    assert s[0] == (64, 1) and s[1] == (32, 0) and s[-2:] == [(2, 0), (1, 0)]
+    # delta_1 = 2: only one pass may be Von Neumann; delta_1 = 1: none
+    assert orc.schedule(4, 4, 16, True, 1, vn_passes=2) == [(2, 1), (1, 0)]
+    assert orc.schedule(2, 2, 4, True, 1, vn_passes=2) == [(1, 0)]
+    assert orc.schedule(512, 512, 256, False, extra_passes=1)[-2:] == [(1, 0), (1, 0)]
+
+
+# --------------------------------------------------------------------------
+# Eq. (1): brute force
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("metric", [0, 1])
+def test_brute_force_matches_scipy(orc, metric):
+    rng = np.random.default_rng(3)
+    for (W, H, S, distinct) in [(1, 1, 1, True), (4, 3, 2, True), (17, 9, 5, True),
+                                (32, 32, 40, False), (7, 30, 7, False)]:
+        xy = _rand_xy(rng, W, H, S, distinct)
+        m = orc.brute_force(xy, W, H, metric)
+        ref, _ = _scipy_nearest(xy, W, H, metric)
+        assert np.array_equal(m, ref), (W, H, S)
+
+
+def test_brute_force_exhaustive_tiny(orc):
+    """Every placement of 2 or 3 seeds (coincident ones included) on a
+    3 x 2 grid: Eq. (1) with the lowest-index tie-break."""
+    W, H = 3, 2
+    cells = [(x, y) for y in range(H) for x in range(W)]
+    for S in (2, 3):
+        for combo in itertools.product(cells, repeat=S):
+            xy = np.array(combo, np.int32)
+            m = orc.brute_force(xy, W, H)
+            for y in range(H):
+                for x in range(W):
+                    ds = [(x - sx) ** 2 + (y - sy) ** 2 for sx, sy in combo]
+                    assert m[y, x] == ds.index(min(ds))
+
+
+def test_brute_force_bisector_tie(orc):
+    """Two seeds on one row: pixels on the perpendicular bisector are
+    equidistant (Sec. II) and go to the lower index."""
+    xy = np.array([[6, 0], [2, 0]], np.int32)
+    m = orc.brute_force(xy, 9, 3)
+    assert (m[:, 4] == 0).all()             # x = 4 is equidistant: lower index 0
+    assert (m[:, :4] == 1).all() and (m[:, 5:] == 0).all()
+
+
+def test_nearest_bucketed_equals_scan(orc):
+    rng = np.random.default_rng(5)
+    for (W, H, S) in [(64, 64, 1), (64, 64, 3), (300, 200, 500), (1024, 1024, 20000)]:
+        xy = _rand_xy(rng, W, H, S, distinct=False)
+        px, py = inputs.sample_pixels(W, H, 3000, seed=W + S)
+        i1, d1 = orc.nearest(xy, W, H, px, py, bucketed=True)
+        i2, d2 = orc.nearest(xy, W, H, px, py, bucketed=False)
+        assert np.array_equal(d1, d2) and np.array_equal(i1, i2)
+
+
+def test_nearest_matches_brute_force_full(orc):
+    rng = np.random.default_rng(6)
+    W, H, S = 50, 40, 30
+    xy = _rand_xy(rng, W, H, S, distinct=False)
+    yy, xx = np.mgrid[0:H, 0:W]
+    ids, _ = orc.nearest(xy, W, H, xx.ravel(), yy.ravel())
+    assert np.array_equal(ids.reshape(H, W), orc.brute_force(xy, W, H))
+
+
+# --------------------------------------------------------------------------
+# Table I, one pass, JFA
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("k", [1, 2, 3])
+def test_single_pass_reaches_table1(orc, k):
+    """From one splatted seed, one pass labels exactly the seed pixel and the
+    eight positions of Table I (Moore) or the four axis ones (Von Neumann)."""
+    offs = [(int(dx), int(dy)) for _, dx, dy in _rows("table1_moore_offsets.txt")]
+    W = H = 2 * k + 5
+    c = k + 2
+    xy = np.array([[c, c]], np.int32)
+    m0 = orc.splat(np.full((H, W), orc.EMPTY, np.int32), xy)
+    for nbhd, keep in ((orc.MOORE, offs), (orc.VN, [o for o in offs if 0 in o])):
+        m1 = orc.flood_pass(m0, xy, k, nbhd)
+        got = {(x - c, y - c) for y, x in zip(*np.nonzero(m1 == 0))}
+        assert got == {(0, 0)} | {(dx * k, dy * k) for dx, dy in keep}
+
+
+@pytest.mark.parametrize("W,H", [(1, 1), (1, 9), (13, 1), (8, 8), (9, 7), (33, 64), (100, 37)])
+def test_jfa_single_seed_exact(orc, W, H):
+    """With one seed, JFA reaches every pixel: per axis the offset to the
+    seed is a sum of distinct powers of two <= k_1 whose partial sums stay
+    inside the grid.  The map is all zeros, equal to the brute force."""
+    for (x, y) in {(0, 0), (W - 1, H - 1), (W // 2, H // 3), (W - 1, 0)}:
+        xy = np.array([[x, y]], np.int32)
+        for metric in (0, 1):
+            m = orc.jfa(xy, W, H, metric=metric)
+            assert (m == 0).all(), (W, H, x, y, metric)
+
+
+def test_von_neumann_only_jfa_is_incomplete(orc):
+    """Sec. V-B (Fig. 5): Von Neumann alone does not build a correct diagram
+    even for JFA.  With one seed, a pixel whose offset needs both axes at the
+    same step stays unreached."""
+    W = H = 16
+    xy = np.array([[8, 8]], np.int32)
+    m0 = orc.splat(np.full((H, W), orc.EMPTY, np.int32), xy)
+    vn = orc.run_passes(m0, xy, [(k, orc.VN) for k, _ in orc.schedule(W, H, 1, False)])
+    assert (vn == orc.EMPTY).any()
+    mo = orc.run_passes(m0, xy, orc.schedule(W, H, 1, False))
+    assert (mo == 0).all()
+
+
+def _tie_heavy_xy():
+    # a lattice with spacing 4 makes many pixels equidistant to 2 or 4 seeds;
+    # indices are assigned in a scrambled order so "lowest index" is not "first in scan"
+    pts = [(x, y) for y in range(1, 30, 4) for x in range(2, 30, 4)]
+    order = np.random.default_rng(1).permutation(len(pts))
+    return np.array([pts[i] for i in order], np.int32)
+
+
+@pytest.mark.parametrize("metric", [0, 1])
+def test_pass_fixed_point_on_exact_map(orc, metric):
+    """No candidate beats the exact (distance, lowest index) label, so every
+    pass, at any k and either neighbourhood, leaves the brute-force map
+    unchanged.  A wrong distance, sign or tie-break changes some pixel."""
+    rng = np.random.default_rng(7)
+    cases = [(_tie_heavy_xy(), 32, 32), (_rand_xy(rng, 40, 25, 12, False), 40, 25)]
+    for xy, W, H in cases:
+        bf = orc.brute_force(xy, W, H, metric)
+        for k in (1, 2, 3, 4, 8, 16, 32):
+            for nbhd in (orc.MOORE, orc.VN):
+                assert np.array_equal(orc.flood_pass(bf, xy, k, nbhd, metric), bf), (k, nbhd)
+
+
+def test_pass_fixed_point_xy_mode(orc):
+    """Same invariant in XY mode, against the exact map whose tie-break is
+    the lowest packed position (y << 16 | x), built from a distance matrix."""
+    xy = _tie_heavy_xy()
+    W = H = 32
+    yy, xx = np.mgrid[0:H, 0:W]
+    pix = np.stack([xx.ravel(), yy.ravel()], axis=1).astype(np.float64)
+    D = cdist(pix, xy.astype(np.float64), "sqeuclidean").astype(np.int64)
+    packed = (xy[:, 1].astype(np.int64) << 16) | xy[:, 0]
+    key = D * (1 << 32) + packed[None, :]
+    exact = packed[np.argmin(key, axis=1)].reshape(H, W).astype(np.int32)
+    for k in (1, 2, 4, 8, 16):
+        for nbhd in (orc.MOORE, orc.VN):
+            out = orc.flood_pass(exact, xy, k, nbhd, label_mode=orc.LABEL_XY)
+            assert np.array_equal(out, exact)
+
+
+def test_pass_monotone_and_gather(orc):
+    """Within a step the distance from each pixel to its label never grows
+    (the pixel's own label is a candidate).  The pass is a gather from an
+    unchanged input: splitting rows over threads gives the same bytes."""
+    W, H, S = 200, 150, 60
+    xy = _rand_xy(np.random.default_rng(8), W, H, S)
+    m = orc.splat(np.full((H, W), orc.EMPTY, np.int32), xy)
+    yy, xx = np.mgrid[0:H, 0:W]
+
+    def dist(mm):
+        d = (xx - xy[mm, 0]) ** 2 + (yy - xy[mm, 1]) ** 2
+        return np.where(mm == orc.EMPTY, np.iinfo(np.int64).max, d)
+
+    prev = dist(m)
+    for k, nb in orc.schedule(W, H, S, False):
+        m1 = orc.flood_pass(m, xy, k, nb, nthreads=1)
+        assert np.array_equal(m1, orc.flood_pass(m, xy, k, nb, nthreads=7))
+        cur = dist(m1)
+        assert (cur <= prev).all()
+        m, prev = m1, cur
+
+
+def test_jfa_coverage_and_seed_pixels(orc):
+    rng = np.random.default_rng(9)
+    for (W, H, S, distinct) in [(64, 64, 10, True), (61, 97, 200, False), (128, 32, 128 * 32, True)]:
+        xy = _rand_xy(rng, W, H, S, distinct)
+        m = orc.jfa(xy, W, H)
+        assert (m != orc.EMPTY).all()
+        first = {}
+        for i, (x, y) in enumerate(xy.tolist()):
+            first.setdefault((x, y), i)
+        for (x, y), i in first.items():
+            assert m[y, x] == i
+
+
+def test_jfa_close_to_exact(orc):
+    """JFA is approximate (Sec. III) but errs on few pixels; its extra
+    rounds (JFA+1, JFA+2) only repair."""
+    W = H = 512
+    xy = inputs.place_seeds(W, H, 256, 1)
+    bf = orc.brute_force(xy, W, H)
+    yy, xx = np.mgrid[0:H, 0:W]
+    _, nd = orc.nearest(xy, W, H, xx.ravel(), yy.ravel())
+    assert orc.count_exact(bf, xy, xx.ravel(), yy.ravel(), nd) == W * H     # self-check
+    prev = None
+    for extra in (0, 1, 2):
+        m = orc.jfa(xy, W, H, extra_passes=extra)
+        exact = orc.count_exact(m, xy, xx.ravel(), yy.ravel(), nd)
+        assert exact >= 0.999 * W * H
+        if prev is not None:
+            assert exact >= prev
+        prev = exact
+
+
+# --------------------------------------------------------------------------
+# dJFA
+# --------------------------------------------------------------------------
+def test_djfa_reduces_to_jfa(orc):
+    """With delta_1 := k_1, no Von Neumann passes and an empty start, the
+    dJFA pass loop is JFA: same bytes."""
+    W, H, S = 300, 200, 150
+    xy = inputs.place_seeds(W, H, S, 4)
+    m0 = orc.splat(np.full((H, W), orc.EMPTY, np.int32), xy)
+    sched = [(k, orc.MOORE) for k, _ in orc.schedule(W, H, S, False)]
+    assert np.array_equal(orc.run_passes(m0, xy, sched), orc.jfa(xy, W, H))
+
+
+@pytest.mark.parametrize("label_mode", [0, 1])
+def test_djfa_small_workload(orc, label_mode):
+    """512^2, 256 seeds, 5 steps of moves in [-1, 1]: every step covers the
+    grid, keeps each seed's own pixel, and stays close to JFA and to the
+    exact diagram ("nearly 100%" for dJFAe, Sec. VI-B)."""
+    spec = inputs.small().sims[0]
+    xy = spec.positions()
+    d = orc.Sim(spec.width, spec.height, xy, spec.sim_seed, spec.disp_lo, spec.disp_hi,
+                label_mode=label_mode)
+    j = orc.Sim(spec.width, spec.height, xy, spec.sim_seed, spec.disp_lo, spec.disp_hi,
+                label_mode=label_mode)
+    yy, xx = np.mgrid[0:spec.height, 0:spec.width]
+    for _ in range(spec.steps):
+        d.move(), j.move()
+        assert np.array_equal(d.xy, j.xy)
+        md, mj = d.djfa_step(), j.jfa_step()
+        assert (md != orc.EMPTY).all()
+        first = {}
+        for i, (x, y) in enumerate(d.xy.tolist()):
+            first.setdefault((x, y), i)
+        for (x, y), i in first.items():
+            assert md[y, x] == (i if label_mode == 0 else (y << 16 | x))
+        _, nd = orc.nearest(d.xy, spec.width, spec.height, xx.ravel(), yy.ravel())
+        assert orc.count_exact(md, d.xy, xx.ravel(), yy.ravel(), nd, label_mode) >= 0.99 * xx.size
+        if label_mode == 0:
+            assert orc.count_equal(md, mj) >= 0.99 * xx.size
+
+
+def test_seed_pixel_invariant_with_collisions(orc):
+    """Drift [-1, 3] piles seeds on the far borders; a shared pixel takes the
+    lowest index of the seeds on it, after JFA and after dJFA."""
+    W = H = 64
+    xy = inputs.place_seeds(W, H, 500, 21)
+    s = orc.Sim(W, H, xy, 21, -1, 3)
+    for _ in range(30):
+        s.move()
+        m = s.djfa_step()
+        first = {}
+        for i, (x, y) in enumerate(s.xy.tolist()):
+            first.setdefault((x, y), i)
+        assert len(first) < s.S        # collisions happened
+        for (x, y), i in first.items():
+            assert m[y, x] == i
+        mj = orc.jfa(s.xy, W, H)
+        for (x, y), i in first.items():
+            assert mj[y, x] == i
+
+
+def test_relabel_xy_translation(orc):
+    """XY labels name positions.  Translating every seed by (+3, +1) with no
+    clamping relabels every pixel to its label plus (3, 1)."""
+    W = H = 64
+    xy = inputs.place_seeds(40, 40, 30, 2)
+    m = orc.jfa(xy, W, H, label_mode=orc.LABEL_XY)
+    new = xy + np.array([3, 1], np.int32)
+    r = orc.relabel_xy(m, xy, new)
+    assert np.array_equal(r, m + (1 << 16) + 3)
+    assert np.array_equal(orc.relabel_xy(m, xy, xy), m)
+
+
+def test_xy_and_id_modes_agree_up_to_ties(orc):
+    """Both label encodings find seeds at the same distance on every pixel
+    where the two tie-breaks agree; on a tie-free input they coincide."""
+    W = H = 128
+    xy = inputs.place_seeds(W, H, 40, 8)
+    mi = orc.jfa(xy, W, H)
+    mx = orc.jfa(xy, W, H, label_mode=orc.LABEL_XY)
+    packed = (xy[:, 1] << 16) | xy[:, 0]
+    yy, xx = np.mgrid[0:H, 0:W]
+    di = (xx - xy[mi, 0]) ** 2 + (yy - xy[mi, 1]) ** 2
+    dx = (xx - (mx & 0xFFFF)) ** 2 + (yy - (mx >> 16)) ** 2
+    same = packed[mi] == mx
+    assert same.mean() > 0.99
+    assert (di[~same] == dx[~same]).mean() > 0.5
+
+
+def test_manhattan_similarity_band(orc):
+    """Sec. VI-B: dJFAm is less precise than dJFAe against the Euclidean
+    diagram.  Only the ordering is checked (the paper's figures are lost)."""
+    spec = inputs.small().sims[0]
+    xy = spec.positions()
+    e = orc.Sim(spec.width, spec.height, xy, 1, -1, 1)
+    m = orc.Sim(spec.width, spec.height, xy, 1, -1, 1, metric=orc.MANHATTAN)
+    yy, xx = np.mgrid[0:spec.height, 0:spec.width]
+    e.move(), m.move()
+    me, mm = e.djfa_step(), m.djfa_step()
+    _, nd = orc.nearest(e.xy, spec.width, spec.height, xx.ravel(), yy.ravel())
+    ce = orc.count_exact(me, e.xy, xx.ravel(), yy.ravel(), nd)
+    cm = orc.count_exact(mm, m.xy, xx.ravel(), yy.ravel(), nd)
+    assert cm < ce
