@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Benchmark of the JFA / dJFA hot path on one MI355X.
+
+One benchmark step is one simulation time step of the whole path: every
+seed moves (on the device), a JFA simulation recomputes its diagram from
+scratch, and a dJFA simulation with the same seed trajectory updates its
+diagram from the previous step (Alg. 1).  Inputs are resident in HBM before
+the timed region; nothing leaves the device inside it.
+
+Prints one JSON line.  `value` is pixel-updates/s over the timed region:
+width*height*(JFA passes + dJFA passes) per step, divided by the measured
+time of the whole step (moves, fills and splats included).
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload single]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "pixel-updates/s and ms per time step (dJFA vs JFA), % HBM peak; p50/p99 step latency"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
+BYTES_PER_PIXEL_UPDATE = 8     # one 4-byte label read + one 4-byte label write per pass
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2209_00117_amd", "csrc", "vd_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "flood_traffic.json")
+
+
+def kernel_sha() -> str:
+    with open(KERNEL_SOURCE, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per flood launch from the committed rocprofv3 counter runs,
+    or None when they were taken on a different kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    entry = rec.get(workload)
+    if not entry or entry.get("kernel_sha") != kernel_sha():
+        return None
+    return entry.get("bytes_per_launch")
+
+
+def pct(a, q):
+    return float(np.percentile(np.asarray(a), q)) if len(a) else None
+
+
+def cpu_baseline(spec, xy, budget_s: float):
+    """The CPU oracle, as it is, on a bounded sample of the same workload:
+    whole time steps (move, JFA, dJFA) of the same simulation until about
+    budget_s seconds of work have run."""
+    import oracle as O
+    threads = O.default_threads()
+    od = O.Sim(spec.width, spec.height, xy, spec.sim_seed, spec.disp_lo, spec.disp_hi,
+               nthreads=threads)
+    oj = O.Sim(spec.width, spec.height, xy, spec.sim_seed, spec.disp_lo, spec.disp_hi,
+               nthreads=threads)
+    pj = len(O.schedule(spec.width, spec.height, spec.num_seeds, False))
+    pd = len(O.schedule(spec.width, spec.height, spec.num_seeds, True, od.dmax))
+    steps, elapsed = 0, 0.0
+    while elapsed < budget_s and steps < spec.steps:
+        t0 = time.perf_counter()
+        od.move(), oj.move()
+        oj.jfa_step()
+        od.djfa_step()
+        elapsed += time.perf_counter() - t0
+        steps += 1
+    upd = steps * spec.width * spec.height * (pj + pd)
+    return {"value": upd / elapsed, "unit": "pixel-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{steps} whole time steps (move + JFA + dJFA) of the same "
+                      f"{spec.width}x{spec.height} S={spec.num_seeds} simulation, "
+                      f"{elapsed:.1f} s, rows split over {threads} threads"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="single", choices=["small", "single", "large"])
+    ap.add_argument("--label", default="id", choices=["id", "xy"])
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-pass-timing", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (this path has no multi-GPU mode); "
+              f"got --gpus {args.gpus}", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2209_00117_amd import inputs, vdflood as V
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    V.lib()
+    wl = inputs.WORKLOADS[args.workload]()
+    spec = wl.sims[0]
+    W, H = spec.width, spec.height
+    label = V.LABEL_ID32 if args.label == "id" else V.LABEL_XY16
+    xy = spec.positions()
+    kw = dict(disp_lo=spec.disp_lo, disp_hi=spec.disp_hi, sim_seed=spec.sim_seed, label=label)
+    stream = torch.cuda.current_stream()
+    sj = V.Sim(W, H, xy, stream=stream, **kw)
+    sd = V.Sim(W, H, xy, stream=stream, **kw)
+    info = sd.info()
+    pj, pd = info.passes_jfa, info.passes_djfa
+
+    def one_step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        sj.move_seeds()
+        sd.move_seeds()
+        if ev is not None:
+            ev[1].record(stream)
+        sj.jfa_step()
+        if ev is not None:
+            ev[2].record(stream)
+        sd.djfa_step()
+        if ev is not None:
+            ev[3].record(stream)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+
+    if not args.no_pass_timing:
+        V.set_timing(sj.handle, True)
+        V.set_timing(sd.handle, True)
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    start.record(stream)
+    for i in range(args.steps):
+        one_step(events[i])
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = start.elapsed_time(stop)
+
+    jfa_ms = [e[1].elapsed_time(e[2]) for e in events]
+    djfa_ms = [e[2].elapsed_time(e[3]) for e in events]
+    move_ms = [e[0].elapsed_time(e[1]) for e in events]
+    tj = tdd = None
+    if not args.no_pass_timing:
+        tj, tdd = V.get_timing(sj.handle), V.get_timing(sd.handle)
+        V.set_timing(sj.handle, False)
+        V.set_timing(sd.handle, False)
+
+    # dJFA vs JFA similarity at the last step (Sec. VI-A), device maps read back
+    mj, md = sj.read_map(), sd.read_map()
+    sim_jfa = float((mj == md).mean())
+
+    px_updates = args.steps * W * H * (pj + pd)
+    value = px_updates / (total_ms / 1e3)
+    roofline = None
+    if tj is not None and tj.flood_launches + tdd.flood_launches > 0:
+        launches = tj.flood_launches + tdd.flood_launches
+        avg_ms = (tj.flood_ms + tdd.flood_ms) / launches
+        achieved = BYTES_PER_PIXEL_UPDATE * W * H / (avg_ms / 1e3) / 1e9
+        traffic = measured_traffic(args.workload + ("" if label == 0 else "-xy"))
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": traffic, "kernel": "flood pass",
+                    "avg_launch_us": round(avg_ms * 1e3, 3), "launches": launches,
+                    "algorithmic_bytes_per_launch": BYTES_PER_PIXEL_UPDATE * W * H}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pixel-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (uniform random seeds and moves, splitmix64)",
+        "config": {"workload": wl.name, "width": W, "height": H, "seeds": spec.num_seeds,
+                   "disp": [spec.disp_lo, spec.disp_hi], "label": args.label,
+                   "passes_jfa": pj, "passes_djfa": pd, "k1": info.k1, "delta1": info.delta1},
+        "jfa": {"ms_per_step": float(np.mean(jfa_ms)), "p50_ms": pct(jfa_ms, 50),
+                "p99_ms": pct(jfa_ms, 99),
+                "pixel_updates_per_s": W * H * pj / (np.mean(jfa_ms) / 1e3)},
+        "djfa": {"ms_per_step": float(np.mean(djfa_ms)), "p50_ms": pct(djfa_ms, 50),
+                 "p99_ms": pct(djfa_ms, 99),
+                 "pixel_updates_per_s": W * H * pd / (np.mean(djfa_ms) / 1e3)},
+        "move_ms_per_step": float(np.mean(move_ms)),
+        "speedup_djfa_vs_jfa": float(np.mean(jfa_ms) / np.mean(djfa_ms)),
+        "similarity_djfa_vs_jfa": sim_jfa,
+        "wall_s": wall,
+        "roofline": roofline,
+        "cpu_baseline": None,
+    }
+    sj.close(), sd.close()
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(spec, xy, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

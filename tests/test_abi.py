@@ -1,0 +1,85 @@
+"""The C-ABI library loads and exports what include/vdflood.h declares;
+argument validation that needs no device (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2209_00117_amd import vdflood as V
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "vdflood.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return set(re.findall(r"\b(vd_[a-z_]+)\s*\(", src))
+
+
+def test_library_exports_every_declared_symbol():
+    L = V.lib()
+    declared = _declared()
+    assert {"vd_init_sim", "vd_move_seeds", "vd_jfa_step", "vd_djfa_step",
+            "vd_read_map"} <= declared
+    for name in declared:
+        assert hasattr(L, name), name
+    assert declared == set(V.SIGNATURES), declared ^ set(V.SIGNATURES)
+
+
+def test_binding_struct_layout_matches_header():
+    # vd_config: 10 int32 then one uint64 -> 48 bytes with alignment
+    assert ctypes.sizeof(V.Config) == 48
+    assert ctypes.sizeof(V.SimInfo) == 48
+    assert ctypes.sizeof(V.Timing) == 40
+
+
+def test_footprint():
+    c = V.config(512, 512, 256)
+    npix = 512 * 512 * 4
+    assert V.footprint_bytes(c) == 2 * npix + 1024 + 256
+    cx = V.config(512, 512, 256, label=V.LABEL_XY16)
+    assert V.footprint_bytes(cx) == 2 * npix + 2 * 1024 + 256
+    big = V.config(8192, 8192, 1 << 20)
+    assert V.footprint_bytes(big) == 2 * 8192 * 8192 * 4 + 4 * (1 << 20) + 256
+
+
+@pytest.mark.parametrize("kw", [
+    dict(width=0, height=8, num_seeds=1), dict(width=8, height=16385, num_seeds=1),
+    dict(width=8, height=8, num_seeds=0), dict(width=8, height=8, num_seeds=65),
+    dict(width=8, height=8, num_seeds=2, disp_lo=2, disp_hi=1),
+    dict(width=8, height=8, num_seeds=2, label=7), dict(width=8, height=8, num_seeds=2, metric=3),
+    dict(width=8, height=8, num_seeds=2, extra_passes=3),
+    dict(width=8, height=8, num_seeds=2, vn_passes=-1),
+])
+def test_invalid_config_rejected_before_device_work(kw):
+    w, h, s = kw.pop("width"), kw.pop("height"), kw.pop("num_seeds")
+    c = V.config(w, h, s, **kw)
+    assert V.footprint_bytes(c) == 0
+    out = ctypes.c_void_p()
+    xy = (ctypes.c_int32 * 4)(0, 0, 1, 1)
+    st = V.lib().vd_init_sim(ctypes.byref(c), ctypes.cast(xy, ctypes.c_void_p),
+                             ctypes.c_void_p(0x1000), 1 << 30, None, ctypes.byref(out))
+    assert st == -1 and not out.value
+    assert V.last_error()
+
+
+def test_null_and_small_workspace():
+    c = V.config(8, 8, 2)
+    xy = (ctypes.c_int32 * 4)(0, 0, 1, 1)
+    out = ctypes.c_void_p()
+    L = V.lib()
+    assert L.vd_init_sim(ctypes.byref(c), None, ctypes.c_void_p(0x1000), 1 << 20, None,
+                         ctypes.byref(out)) == -1
+    assert L.vd_init_sim(ctypes.byref(c), ctypes.cast(xy, ctypes.c_void_p), None, 1 << 20, None,
+                         ctypes.byref(out)) == -1
+    assert L.vd_init_sim(ctypes.byref(c), ctypes.cast(xy, ctypes.c_void_p),
+                         ctypes.c_void_p(0x1000), 100, None, ctypes.byref(out)) == -2
+    assert "workspace" in V.last_error()
+    bad = (ctypes.c_int32 * 4)(0, 0, 8, 1)       # x = 8 is off an 8-wide grid
+    assert L.vd_init_sim(ctypes.byref(c), ctypes.cast(bad, ctypes.c_void_p),
+                         ctypes.c_void_p(0x1000), 1 << 20, None, ctypes.byref(out)) == -1
+    assert "outside" in V.last_error()
+    for fn in ("vd_move_seeds", "vd_jfa_step", "vd_djfa_step"):
+        assert getattr(L, fn)(None) == -1
+    L.vd_destroy(None)

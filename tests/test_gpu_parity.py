@@ -1,0 +1,140 @@
+"""GPU parity: the HIP path against the CPU oracle, bit for bit.
+
+Every map is integer labels, so the bar is exact equality at every time
+step, for both the JFA and the dJFA simulation of each case.  The cases span
+several tiles with ragged tails, degenerate grids (1 pixel, 1 row, 1
+column), one seed, a saturated grid (S = W*H), heavy seed collisions, both
+label encodings, both metrics and every pass option; the full-size
+workloads run a few steps each in the launch configuration the benchmark
+uses.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2209_00117_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def V():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2209_00117_amd import vdflood
+    vdflood.lib()                    # fails loudly if the library is missing
+    return vdflood
+
+
+def _seed_pixels_ok(m, xy, label_mode):
+    first = {}
+    for i, (x, y) in enumerate(xy.tolist()):
+        first.setdefault((x, y), i)
+    for (x, y), i in first.items():
+        want = i if label_mode == 0 else (y << 16 | x)
+        if m[y, x] != want:
+            return False
+    return True
+
+
+def run_twin(V, W, H, xy, steps, lo, hi, sim_seed=1, label=0, metric=0, vn=2, extra=0,
+             dmax=0, tag=""):
+    """Runs a JFA and a dJFA simulation side by side on the GPU and in the
+    oracle; asserts equal positions and maps at every step."""
+    print(f"[parity] {tag} W={W} H={H} S={len(xy)} steps={steps} disp=[{lo},{hi}] "
+          f"label={label} metric={metric} vn={vn} extra={extra}", flush=True)
+    kw = dict(disp_lo=lo, disp_hi=hi, label=label, metric=metric, vn_passes=vn,
+              extra_passes=extra, dmax_override=dmax, sim_seed=sim_seed)
+    gj = V.Sim(W, H, xy, **kw)
+    gd = V.Sim(W, H, xy, **kw)
+    okw = dict(label_mode=label, metric=metric, vn_passes=vn, extra_passes=extra,
+               dmax=dmax if dmax > 0 else None)
+    oj = O.Sim(W, H, xy, sim_seed, lo, hi, **okw)
+    od = O.Sim(W, H, xy, sim_seed, lo, hi, **okw)
+    m0 = gj.read_map()
+    assert np.array_equal(m0, oj.map), f"{tag}: VD_0 differs"
+    assert np.array_equal(gd.read_map(), oj.map)
+    info = gd.info()
+    assert info.passes_jfa == len(O.schedule(W, H, len(xy), False, extra_passes=extra))
+    assert info.passes_djfa == len(O.schedule(W, H, len(xy), True, od.dmax, vn, extra))
+    for t in range(1, steps + 1):
+        gj.move_seeds(), gd.move_seeds(), oj.move(), od.move()
+        gj.jfa_step(), gd.djfa_step()
+        oj.jfa_step(), od.djfa_step()
+        assert np.array_equal(gj.read_seeds(), oj.xy), f"{tag}: positions differ at t={t}"
+        mj, md = gj.read_map(), gd.read_map()
+        nj = int((mj != oj.map).sum())
+        nd = int((md != od.map).sum())
+        assert nj == 0, f"{tag}: JFA map differs at t={t} on {nj} pixels"
+        assert nd == 0, f"{tag}: dJFA map differs at t={t} on {nd} pixels"
+        assert _seed_pixels_ok(md, od.xy, label) and _seed_pixels_ok(mj, oj.xy, label)
+    gj.close(), gd.close()
+    return oj, od
+
+
+def test_small_workload_id(V):
+    spec = inputs.small().sims[0]
+    oj, od = run_twin(V, spec.width, spec.height, spec.positions(), spec.steps, spec.disp_lo,
+                      spec.disp_hi, tag="small")
+    sim = O.count_equal(oj.map, od.map) / oj.map.size
+    print(f"[parity] small: dJFA vs JFA similarity at last step {100 * sim:.3f}%")
+
+
+def test_small_workload_xy(V):
+    spec = inputs.small().sims[0]
+    run_twin(V, spec.width, spec.height, spec.positions(), spec.steps, spec.disp_lo,
+             spec.disp_hi, label=1, tag="small-xy")
+
+
+@pytest.mark.parametrize("W,H,S,steps,lo,hi", [
+    (1000, 1000, 50, 3, -2, 2),       # 50 seeds on 1000 x 1000, as in Fig. 6
+    (1, 1, 1, 2, -1, 1),
+    (1, 37, 5, 3, -1, 1),
+    (53, 1, 3, 3, -2, 2),
+    (333, 77, 1000, 3, -1, 1),
+    (64, 64, 4096, 2, -1, 1),         # every pixel a seed
+    (257, 129, 300, 6, -1, 3),        # drift piles seeds onto the far borders
+    (130, 200, 1, 3, -5, 5),          # one seed: dJFA equals the exact diagram
+])
+@pytest.mark.parametrize("label", [0, 1])
+def test_ragged_and_degenerate(V, W, H, S, steps, lo, hi, label):
+    xy = inputs.place_seeds(W, H, S, W * 7 + H)
+    run_twin(V, W, H, xy, steps, lo, hi, sim_seed=W + H, label=label, tag="ragged")
+
+
+@pytest.mark.parametrize("metric,vn,extra", [
+    (1, 2, 0), (0, 0, 0), (0, 1, 1), (0, 2, 2), (1, 1, 2), (0, 5, 0),
+])
+def test_pass_options(V, metric, vn, extra):
+    xy = inputs.place_seeds(700, 450, 900, 3)
+    for label in (0, 1):
+        run_twin(V, 700, 450, xy, 3, -2, 2, sim_seed=5, label=label, metric=metric, vn=vn,
+                 extra=extra, tag="options")
+
+
+def test_dmax_override(V):
+    xy = inputs.place_seeds(512, 512, 4000, 9)
+    run_twin(V, 512, 512, xy, 3, -1, 1, dmax=40, tag="dmax")
+
+
+def _full_size(V, spec, steps, label=0):
+    """A full-size workload for a few steps; positions and maps compared in
+    full against the threaded oracle."""
+    return run_twin(V, spec.width, spec.height, spec.positions(), steps, spec.disp_lo,
+                    spec.disp_hi, sim_seed=spec.sim_seed, label=label, tag=spec.width)
+
+
+def test_single_full_size(V):
+    oj, od = _full_size(V, inputs.single().sims[0], 2)
+    print(f"[parity] 4096^2: dJFA vs JFA similarity {100 * O.count_equal(oj.map, od.map) / oj.map.size:.4f}%")
+
+
+def test_large_full_size(V):
+    _full_size(V, inputs.large().sims[0], 1)
+
+
+def test_large_full_size_xy(V):
+    _full_size(V, inputs.large().sims[0], 1, label=1)
