@@ -52,9 +52,11 @@ enum { VD_LABEL_ID32 = 0, VD_LABEL_XY16 = 1 };
 enum { VD_EUCLID = 0, VD_MANHATTAN = 1 };
 
 #define VD_EMPTY (-1)
-/* Largest grid side.  Squared distances stay below 2^29, and positions pack
- * into two 16-bit halves. */
-#define VD_MAX_SIDE 16384
+/* Largest grid side (2^14 - 16).  Positions pack into two 16-bit halves
+ * with an offset of 16384, and every squared distance, to a seed or to the
+ * library's far sentinel position (-16384, -16384), stays below
+ * 2^31 - 2^20. */
+#define VD_MAX_SIDE 16368
 #define VD_MAX_EXTRA_PASSES 2
 
 /* Parameters of one simulation (Sec. II: grid X, seed set S; Sec. V-A: the
@@ -99,8 +101,9 @@ typedef struct vd_timing {
 void vd_config_default(vd_config *cfg);
 
 /* Device bytes vd_init_sim needs for cfg: two ping-pong label maps
- * (4 B per pixel each), the seed table (4 B per seed, twice in XY mode) and
- * 256 B of alignment slack.  Returns 0 if cfg is invalid. */
+ * (4 B per pixel each), the seed table (4 B per seed plus one sentinel
+ * entry; in XY mode also the positions the diagram refers to) and 256 B of
+ * alignment slack.  Returns 0 if cfg is invalid. */
 size_t vd_footprint_bytes(const vd_config *cfg);
 
 /* Creates a simulation (Sec. IV: the diagram VD and the seed set S are the
@@ -151,7 +154,9 @@ int vd_read_seeds(vd_sim *sim, int32_t *host_xy, size_t count);
 
 /* Device address of the current diagram (width*height uint32 labels).  It
  * stays valid until the next step call; the data are ready once the
- * simulation's stream has reached this point. */
+ * simulation's stream has reached this point.  ID labels are as read by
+ * vd_read_map.  XY labels are stored as ((y + 16384) << 16) | (x + 16384)
+ * with 0 for EMPTY; vd_read_map converts them. */
 int vd_map_device(vd_sim *sim, const void **dev_map);
 
 /* Sizes, schedule and time step of a simulation. */

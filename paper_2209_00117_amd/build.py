@@ -30,6 +30,9 @@ def compile_flags() -> list:
         f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
         # packed FP32 instructions are kept out of every kernel
         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+        # keys are minimised as doubles (see vd_kernels.hip): no IEEE-mode
+        # canonicalisation, so one v_min_f64 per candidate
+        "-mno-amdgpu-ieee", "-fno-honor-nans",
         "-I", os.path.join(ROOT, "include"),
     ]
 

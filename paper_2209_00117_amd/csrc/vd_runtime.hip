@@ -111,8 +111,8 @@ size_t footprint(const vd_config *c)
 {
     size_t npix = (size_t)c->width * (size_t)c->height;
     size_t seeds = (size_t)c->num_seeds * 4;
-    size_t b = 2 * align_up(npix * 4) + align_up(seeds);
-    if (c->label == VD_LABEL_XY16) b += align_up(seeds);
+    size_t b = 2 * align_up(npix * 4) + align_up(seeds + 4);   // + the sentinel entry
+    if (c->label == VD_LABEL_XY16) b += align_up(seeds + 4);
     return b + kAlign;
 }
 
@@ -129,8 +129,8 @@ struct vd_sim {
     int device = 0;
     uint32_t *map[2] = {nullptr, nullptr};
     int cur = 0;                 // map[cur] holds the current diagram
-    uint32_t *pos = nullptr;     // current positions
-    uint32_t *pos_map = nullptr; // XY mode: positions the diagram's labels refer to
+    uint32_t *pos = nullptr;     // seed table: sentinel, then current positions
+    uint32_t *pos_map = nullptr; // XY mode: the table the diagram's labels refer to
     int64_t t = 0;
     int32_t dmax = 0;
     int32_t k1 = 0, delta1 = 0;
@@ -190,9 +190,9 @@ int run_passes(vd_sim *s, const std::vector<Pass> &passes)
         size_t slot = 0;
         int r = record(s, 0, true, &slot);
         if (r) return r;
-        VD_HIP(vd::launch_flood(s->map[s->cur], s->map[s->cur ^ 1], s->pos, s->cfg.width,
-                                s->cfg.height, p.k, p.vn, s->cfg.label, s->cfg.metric,
-                                s->stream));
+        VD_HIP(vd::launch_flood(s->map[s->cur], s->map[s->cur ^ 1], s->pos, s->cfg.num_seeds,
+                                s->cfg.width, s->cfg.height, p.k, p.vn, s->cfg.label,
+                                s->cfg.metric, s->stream));
         r = record(s, 0, false, &slot);
         if (r) return r;
         s->cur ^= 1;
@@ -212,11 +212,11 @@ int do_jfa(vd_sim *s)
     if (c.label == VD_LABEL_XY16)
         VD_HIP(vd::launch_splat_xy(s->map[s->cur], s->pos, c.num_seeds, c.width, s->stream));
     else
-        VD_HIP(vd::launch_splat_min(s->map[s->cur], s->pos, c.num_seeds, c.width, s->stream));
+        VD_HIP(vd::launch_splat_id(s->map[s->cur], s->pos, c.num_seeds, c.width, s->stream));
     int r = run_passes(s, s->jfa_passes);
     if (r) return r;
     if (c.label == VD_LABEL_XY16)
-        VD_HIP(hipMemcpyAsync(s->pos_map, s->pos, (size_t)c.num_seeds * 4,
+        VD_HIP(hipMemcpyAsync(s->pos_map, s->pos, ((size_t)c.num_seeds + 1) * 4,
                               hipMemcpyDeviceToDevice, s->stream));
     return VD_OK;
 }
@@ -233,13 +233,12 @@ int do_djfa(vd_sim *s)
         VD_HIP(vd::launch_relabel(cur, idx, s->pos, c.num_seeds, c.width, c.height, s->stream));
         VD_HIP(vd::launch_splat_xy(cur, s->pos, c.num_seeds, c.width, s->stream));
     } else {
-        VD_HIP(vd::launch_splat_reset(cur, s->pos, c.num_seeds, c.width, s->stream));
-        VD_HIP(vd::launch_splat_min(cur, s->pos, c.num_seeds, c.width, s->stream));
+        VD_HIP(vd::launch_splat_id(cur, s->pos, c.num_seeds, c.width, s->stream));
     }
     int r = run_passes(s, s->djfa_passes);
     if (r) return r;
     if (c.label == VD_LABEL_XY16)
-        VD_HIP(hipMemcpyAsync(s->pos_map, s->pos, (size_t)c.num_seeds * 4,
+        VD_HIP(hipMemcpyAsync(s->pos_map, s->pos, ((size_t)c.num_seeds + 1) * 4,
                               hipMemcpyDeviceToDevice, s->stream));
     return VD_OK;
 }
@@ -297,7 +296,7 @@ int vd_init_sim(const vd_config *cfg, const int32_t *host_xy, void *dev_workspac
     const int32_t S = cfg->num_seeds;
     std::vector<uint32_t> packed;
     try {
-        packed.resize((size_t)S);
+        packed.resize((size_t)S + 1);
     } catch (...) {
         return fail(VD_ENOMEM, "host allocation of %d seeds failed", S);
     }
@@ -306,8 +305,9 @@ int vd_init_sim(const vd_config *cfg, const int32_t *host_xy, void *dev_workspac
         if (x < 0 || x >= cfg->width || y < 0 || y >= cfg->height)
             return fail(VD_EINVAL, "seed %d at (%d, %d) is outside the %d x %d grid", i, x, y,
                         cfg->width, cfg->height);
-        packed[(size_t)i] = ((uint32_t)y << 16) | (uint32_t)x;
+        packed[(size_t)i + 1] = vd::pack_pos(x, y);
     }
+    packed[0] = 0;   // sentinel: the position (-kOff, -kOff), beyond every seed
     vd_sim *s = new (std::nothrow) vd_sim;
     if (!s) return fail(VD_ENOMEM, "host allocation of the handle failed");
     s->cfg = *cfg;
@@ -323,7 +323,7 @@ int vd_init_sim(const vd_config *cfg, const int32_t *host_xy, void *dev_workspac
     s->map[1] = (uint32_t *)base;
     base += align_up(npix * 4);
     s->pos = (uint32_t *)base;
-    base += align_up((size_t)S * 4);
+    base += align_up((size_t)S * 4 + 4);
     if (cfg->label == VD_LABEL_XY16) s->pos_map = (uint32_t *)base;
     s->dmax = cfg->dmax_override > 0 ? cfg->dmax_override
                                      : (abs(cfg->disp_lo) > abs(cfg->disp_hi) ? abs(cfg->disp_lo)
@@ -333,8 +333,8 @@ int vd_init_sim(const vd_config *cfg, const int32_t *host_xy, void *dev_workspac
     s->jfa_passes = schedule(s->k1, 0, cfg->extra_passes);
     s->djfa_passes = schedule(s->delta1, cfg->vn_passes, cfg->extra_passes);
     s->move_seed = mix64(cfg->sim_seed ^ 0x6D6F7665ull);
-    hipError_t e = hipMemcpyAsync(s->pos, packed.data(), (size_t)S * 4, hipMemcpyHostToDevice,
-                                  s->stream);
+    hipError_t e = hipMemcpyAsync(s->pos, packed.data(), ((size_t)S + 1) * 4,
+                                  hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);   // packed is a local buffer
     if (e != hipSuccess) {
         delete s;
@@ -372,7 +372,11 @@ int vd_read_map(vd_sim *s, int32_t *host_dst, size_t count)
     if (!s || !host_dst) return fail(VD_EINVAL, "NULL argument");
     size_t npix = (size_t)s->cfg.width * s->cfg.height;
     if (count != npix) return fail(VD_EINVAL, "count %zu != width*height %zu", count, npix);
-    VD_HIP(hipMemcpyAsync(host_dst, s->map[s->cur], npix * 4, hipMemcpyDeviceToHost, s->stream));
+    // convert into the idle ping-pong buffer, then copy that
+    VD_HIP(vd::launch_export(s->map[s->cur], s->map[s->cur ^ 1], (int64_t)npix, s->cfg.label,
+                             s->stream));
+    VD_HIP(hipMemcpyAsync(host_dst, s->map[s->cur ^ 1], npix * 4, hipMemcpyDeviceToHost,
+                          s->stream));
     VD_HIP(hipStreamSynchronize(s->stream));
     return VD_OK;
 }
@@ -388,11 +392,11 @@ int vd_read_seeds(vd_sim *s, int32_t *host_xy, size_t count)
     } catch (...) {
         return fail(VD_ENOMEM, "host allocation failed");
     }
-    VD_HIP(hipMemcpyAsync(packed.data(), s->pos, S * 4, hipMemcpyDeviceToHost, s->stream));
+    VD_HIP(hipMemcpyAsync(packed.data(), s->pos + 1, S * 4, hipMemcpyDeviceToHost, s->stream));
     VD_HIP(hipStreamSynchronize(s->stream));
     for (size_t i = 0; i < S; ++i) {
-        host_xy[2 * i] = (int32_t)(packed[i] & 0xFFFFu);
-        host_xy[2 * i + 1] = (int32_t)(packed[i] >> 16);
+        host_xy[2 * i] = (int32_t)(packed[i] & 0xFFFFu) - (int32_t)vd::kOff;
+        host_xy[2 * i + 1] = (int32_t)(packed[i] >> 16) - (int32_t)vd::kOff;
     }
     return VD_OK;
 }

@@ -18,7 +18,7 @@ import numpy as np
 LABEL_ID32, LABEL_XY16 = 0, 1
 EUCLID, MANHATTAN = 0, 1
 EMPTY = -1
-MAX_SIDE = 16384
+MAX_SIDE = 16368
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvdflood.so")

@@ -37,15 +37,18 @@ def test_binding_struct_layout_matches_header():
 def test_footprint():
     c = V.config(512, 512, 256)
     npix = 512 * 512 * 4
-    assert V.footprint_bytes(c) == 2 * npix + 1024 + 256
+    # two maps, the seed table with its sentinel entry (256-B aligned), slack
+    assert V.footprint_bytes(c) == 2 * npix + 1280 + 256
     cx = V.config(512, 512, 256, label=V.LABEL_XY16)
-    assert V.footprint_bytes(cx) == 2 * npix + 2 * 1024 + 256
+    assert V.footprint_bytes(cx) == 2 * npix + 1280 + 1280 + 256
     big = V.config(8192, 8192, 1 << 20)
-    assert V.footprint_bytes(big) == 2 * 8192 * 8192 * 4 + 4 * (1 << 20) + 256
+    assert V.footprint_bytes(big) == 2 * 8192 * 8192 * 4 + 4 * (1 << 20) + 256 + 256
+    assert V.footprint_bytes(V.config(16368, 16368, 1)) > 0
+    assert V.footprint_bytes(V.config(16369, 8, 1)) == 0
 
 
 @pytest.mark.parametrize("kw", [
-    dict(width=0, height=8, num_seeds=1), dict(width=8, height=16385, num_seeds=1),
+    dict(width=0, height=8, num_seeds=1), dict(width=8, height=16369, num_seeds=1),
     dict(width=8, height=8, num_seeds=0), dict(width=8, height=8, num_seeds=65),
     dict(width=8, height=8, num_seeds=2, disp_lo=2, disp_hi=1),
     dict(width=8, height=8, num_seeds=2, label=7), dict(width=8, height=8, num_seeds=2, metric=3),
