@@ -170,6 +170,14 @@ int vd_set_timing(vd_sim *sim, int enable);
  * enabled or last read; then clears them. */
 int vd_get_timing(vd_sim *sim, vd_timing *out);
 
+/* Selects the flood-pass kernel variant for every pass of this simulation:
+ * 0, 1 or 2 request each row's labels 1, 2 or 3 rows ahead of the row being
+ * written; 3 shares each row across a workgroup through LDS for steps up to
+ * 128 (and is 1 above); -1 restores the default (3 for ID labels, 1 for
+ * XY labels).  Variants differ in speed only: every variant writes the same
+ * labels. */
+int vd_set_flood_variant(vd_sim *sim, int variant);
+
 /* Releases the handle (never the caller's workspace).  Waits for the
  * simulation's pending work.  NULL is ignored. */
 void vd_destroy(vd_sim *sim);

@@ -60,8 +60,13 @@ hipError_t launch_export(const uint32_t *map, uint32_t *out, int64_t n, int32_t 
 
 // One flood pass at step k: dst[p] = best of src[p] and src[p + o] over the
 // Moore (vn == 0) or Von Neumann (vn != 0) offsets o at distance k.
+// `variant` (0 .. kFloodVariants - 1) selects the kernel; every variant
+// gives the same map.  0, 1, 2: the chain walk requesting loads 1, 2 or 3
+// rows ahead; 3: rows shared through LDS for k <= 128 (2 rows ahead),
+// otherwise variant 1.
+constexpr int kFloodVariants = 4;
 hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *table, int32_t S,
                         int32_t W, int32_t H, int32_t k, int32_t vn, int32_t label,
-                        int32_t metric, hipStream_t s);
+                        int32_t metric, int32_t variant, hipStream_t s);
 
 }  // namespace vd

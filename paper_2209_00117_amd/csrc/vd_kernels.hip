@@ -25,6 +25,8 @@
 // gives (dx, dy) and one v_dot2 gives dx*dx + dy*dy exactly in int32.
 #include "vd_kernels.h"
 
+#include <utility>
+
 typedef int32_t vd_i32x4 __attribute__((ext_vector_type(4)));
 
 // Indexed (structured) buffer load: address = base + index * stride.
@@ -39,6 +41,8 @@ namespace {
 constexpr int kBlock = 256;
 constexpr int kTW = 256;           // flood pass: columns per workgroup (one per thread)
 constexpr int kMaxSegRows = 32;    // flood pass: rows of one chain segment, at most
+constexpr int kMaxLdsK = 128;      // flood pass, shared-row variant: largest step
+constexpr int kLdsRow = kTW + 2 * kMaxLdsK;   // entries of one shared row
 constexpr int32_t kRsrcWord3 = 0x00020000;   // buffer descriptor word 3 on gfx9 parts
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
@@ -191,25 +195,44 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const uint32_t *base,
     return __builtin_amdgcn_make_buffer_rsrc((void *)p, 0, in ? W * 4 : 0, kRsrcWord3);
 }
 
-template <int LABEL>
-__device__ __forceinline__ Ent make_ent(uint32_t l, i32x4 tab)
-{
-    Ent e;
-    e.l = l;
-    e.s = LABEL == kLabelId ? vd_struct_buffer_load(tab, (int32_t)l, 0, 0, 0) : l;
-    return e;
-}
-
-template <int LABEL>
-__device__ __forceinline__ Row load_row(const uint32_t *src, int32_t y, int32_t W, int32_t H,
-                                        i32x4 tab, int32_t ow, int32_t oc, int32_t oe)
+// Labels of one row (columns x - k, x, x + k); off-grid reads return 0.
+__device__ __forceinline__ void load_labels(Row &row, const uint32_t *src, int32_t y, int32_t W,
+                                            int32_t H, int32_t ow, int32_t oc, int32_t oe)
 {
     __amdgpu_buffer_rsrc_t r = row_rsrc(src, y, W, H);
-    Row row;
-    row.w = make_ent<LABEL>(__builtin_amdgcn_raw_buffer_load_b32(r, ow, 0, 0), tab);
-    row.c = make_ent<LABEL>(__builtin_amdgcn_raw_buffer_load_b32(r, oc, 0, 0), tab);
-    row.e = make_ent<LABEL>(__builtin_amdgcn_raw_buffer_load_b32(r, oe, 0, 0), tab);
-    return row;
+    row.w.l = __builtin_amdgcn_raw_buffer_load_b32(r, ow, 0, 0);
+    row.c.l = __builtin_amdgcn_raw_buffer_load_b32(r, oc, 0, 0);
+    row.e.l = __builtin_amdgcn_raw_buffer_load_b32(r, oe, 0, 0);
+}
+
+// Seed positions of a row's labels: ID labels index the seed table (entry 0,
+// the unclaimed label, is the sentinel); XY labels are positions already.
+template <int LABEL>
+__device__ __forceinline__ void lookup_positions(Row &row, i32x4 tab)
+{
+    if (LABEL == kLabelId) {
+        row.w.s = vd_struct_buffer_load(tab, (int32_t)row.w.l, 0, 0, 0);
+        row.c.s = vd_struct_buffer_load(tab, (int32_t)row.c.l, 0, 0, 0);
+        row.e.s = vd_struct_buffer_load(tab, (int32_t)row.e.l, 0, 0, 0);
+    } else {
+        row.w.s = row.w.l;
+        row.c.s = row.c.l;
+        row.e.s = row.e.l;
+    }
+}
+
+// f(integral_constant<int, 0>, ..., integral_constant<int, N - 1>): a loop
+// body instantiated N times with compile-time indices.
+template <class F, int... I>
+__device__ __forceinline__ bool expand_impl(F &f, std::integer_sequence<int, I...>)
+{
+    return f(std::integral_constant<int, I>{}...);
+}
+
+template <int N, class F>
+__device__ __forceinline__ bool expand(F &f)
+{
+    return expand_impl(f, std::make_integer_sequence<int, N>{});
 }
 
 template <int METRIC>
@@ -252,7 +275,7 @@ __device__ __forceinline__ void emit(uint32_t *dst, const Row &a, const Row &b, 
                                           oc, 0, 0);
 }
 
-template <int LABEL, int METRIC, int VN>
+template <int LABEL, int METRIC, int VN, int P>
 __global__ void __launch_bounds__(kTW) k_flood(const uint32_t *__restrict__ src,
                                                uint32_t *__restrict__ dst,
                                                const uint32_t *__restrict__ table, uint32_t S,
@@ -281,27 +304,144 @@ __global__ void __launch_bounds__(kTW) k_flood(const uint32_t *__restrict__ src,
                        (int32_t)(S + 1), kRsrcWord3};
     int32_t y = r + j * k;
 
-    // Four row registers rotate through the roles (above, current, below,
-    // prefetched); the loop is unrolled four times so no row is copied.
-    Row r0 = load_row<LABEL>(src, y - k, W, H, tab, ow, oc, oe);
-    Row r1 = load_row<LABEL>(src, y, W, H, tab, ow, oc, oe);
-    Row r2 = load_row<LABEL>(src, y + k, W, H, tab, ow, oc, oe);
-    Row r3;
-#define VD_FLOOD_STEP(A, B, C, N)                                                       \
-    {                                                                                   \
-        if (j >= jend) break;                                                           \
-        N = load_row<LABEL>(src, y + 2 * k, W, H, tab, ow, oc, oe);                       \
-        emit<METRIC, VN>(dst, A, B, C, y, k, W, H, px, oc);                              \
-        ++j;                                                                            \
-        y += k;                                                                         \
+    // NR row registers rotate through the roles: at unrolled step u, slot
+    // (u + m + 1) % NR holds row y + m*k for m = -1 .. P.  Labels are
+    // requested P + 1 rows ahead of the output row and their positions P
+    // rows ahead, so neither load is waited for in the step that issues it.
+    // The loop is unrolled NR times, so no row is ever copied.
+    constexpr int NR = P + 3;
+    Row R[NR];
+#pragma unroll
+    for (int m = -1; m <= P; ++m) load_labels(R[m + 1], src, y + m * k, W, H, ow, oc, oe);
+#pragma unroll
+    for (int m = -1; m < P; ++m) lookup_positions<LABEL>(R[m + 1], tab);
+    // One output row with the slots of unrolled step U; false once the
+    // segment is done.
+    auto step = [&](auto U) -> bool {
+        constexpr int u = decltype(U)::value;
+        if (j >= jend) return false;
+        load_labels(R[(u + NR - 1) % NR], src, y + (P + 1) * k, W, H, ow, oc, oe);
+        lookup_positions<LABEL>(R[(u + NR - 2) % NR], tab);
+        emit<METRIC, VN>(dst, R[u % NR], R[(u + 1) % NR], R[(u + 2) % NR], y, k, W, H, px, oc);
+        ++j;
+        y += k;
+        return true;
+    };
+    auto round = [&](auto... U) -> bool { return (step(U) && ...); };
+    while (expand<NR>(round)) {
     }
-    for (;;) {
-        VD_FLOOD_STEP(r0, r1, r2, r3)
-        VD_FLOOD_STEP(r1, r2, r3, r0)
-        VD_FLOOD_STEP(r2, r3, r0, r1)
-        VD_FLOOD_STEP(r3, r0, r1, r2)
+}
+
+// Shared-row variant (steps k <= kMaxLdsK).  The same chain walk, but the
+// 256 + 2k entries of each row that a workgroup needs (its columns plus k on
+// either side) are fetched once, one or two per thread, and exchanged
+// through LDS, where each thread reads its three (x - k, x, x + k).  A
+// thread therefore issues one or two label loads and, for ID labels, one or
+// two seed-table lookups per row instead of three of each.  Two LDS row
+// buffers alternate; the barrier of each exchange also orders the reuse of
+// the buffer written two exchanges earlier.
+struct Raw {
+    uint32_t l1, l2;   // labels of this thread's entries t and kTW + t
+    uint32_t s1, s2;   // their positions
+};
+
+struct Slot {
+    Raw raw;
+    Row win;
+};
+
+template <int LABEL, int METRIC, int VN, int P>
+__global__ void __launch_bounds__(kTW) k_flood_lds(const uint32_t *__restrict__ src,
+                                                   uint32_t *__restrict__ dst,
+                                                   const uint32_t *__restrict__ table,
+                                                   uint32_t S, int32_t W, int32_t H, int32_t k,
+                                                   uint32_t ncol, uint32_t nseg, int32_t L,
+                                                   uint32_t nblocks)
+{
+    __shared__ uint2 lds[2][kLdsRow];
+    const uint32_t b = blockIdx.x;
+    const uint32_t q = nblocks >> 3, rem = nblocks & 7u, xcd = b & 7u;
+    const uint32_t logical = xcd * q + min(xcd, rem) + (b >> 3);
+    const uint32_t col = __builtin_amdgcn_readfirstlane(logical % ncol);
+    const uint32_t rs = logical / ncol;
+    const int32_t seg = __builtin_amdgcn_readfirstlane((int32_t)(rs % nseg));
+    const int32_t r = __builtin_amdgcn_readfirstlane((int32_t)(rs / nseg));
+    const int32_t nj = (H - 1 - r) / k + 1;
+    int32_t j = seg * L;
+    if (j >= nj) return;
+    const int32_t jend = min(j + L, nj);
+    const int32_t t = (int32_t)threadIdx.x;
+    const int32_t x0 = (int32_t)col * kTW;
+    const int32_t x = x0 + t;
+    const uint32_t px = (uint32_t)(x + (int32_t)kOff);
+    const int32_t oc = 4 * x;
+    // entry t is column x0 - k + t; entry kTW + t (only for t < 2k) is
+    // column x0 + kTW - k + t; an unused second entry reads out of range
+    const int32_t o1 = 4 * (x0 - k + t);
+    const bool has2 = t < 2 * k;
+    const int32_t o2 = has2 ? 4 * (x0 + kTW - k + t) : INT32_MIN;
+    const bool wave2 = __builtin_amdgcn_readfirstlane(t & ~63) < 2 * k;   // any lane of the wave
+    const uint64_t ta = (uint64_t)table;
+    const i32x4 tab = {(int32_t)(uint32_t)ta, (int32_t)(((uint32_t)(ta >> 32) & 0xFFFFu) | (4u << 16)),
+                       (int32_t)(S + 1), kRsrcWord3};
+    int32_t y = r + j * k;
+    int32_t exchanges = 0;
+
+    auto load = [&](Slot &sl, int32_t yy) {
+        __amdgpu_buffer_rsrc_t rr = row_rsrc(src, yy, W, H);
+        sl.raw.l1 = __builtin_amdgcn_raw_buffer_load_b32(rr, o1, 0, 0);
+        sl.raw.l2 = wave2 ? __builtin_amdgcn_raw_buffer_load_b32(rr, o2, 0, 0) : 0u;
+    };
+    auto lookup = [&](Slot &sl) {
+        if (LABEL == kLabelId) {
+            sl.raw.s1 = vd_struct_buffer_load(tab, (int32_t)sl.raw.l1, 0, 0, 0);
+            sl.raw.s2 = wave2 ? vd_struct_buffer_load(tab, (int32_t)sl.raw.l2, 0, 0, 0) : 0u;
+        } else {
+            sl.raw.s1 = sl.raw.l1;
+            sl.raw.s2 = sl.raw.l2;
+        }
+    };
+    auto exchange = [&](Slot &sl) {
+        uint2 *row = lds[exchanges & 1];
+        ++exchanges;
+        row[t] = make_uint2(sl.raw.l1, sl.raw.s1);
+        if (has2) row[kTW + t] = make_uint2(sl.raw.l2, sl.raw.s2);
+        __syncthreads();
+        const uint2 w = row[t], c = row[t + k], e = row[t + 2 * k];
+        sl.win.w.l = w.x;
+        sl.win.w.s = w.y;
+        sl.win.c.l = c.x;
+        sl.win.c.s = c.y;
+        sl.win.e.l = e.x;
+        sl.win.e.s = e.y;
+    };
+
+    // Ring of NR slots as in k_flood: slot (u + m + 1) % NR holds row
+    // y + m*k; labels are requested P + 1 rows ahead, positions P rows
+    // ahead, and the row entering the window (m = 1) is exchanged.
+    constexpr int NR = P + 3;
+    Slot R[NR];
+#pragma unroll
+    for (int m = -1; m <= P; ++m) load(R[m + 1], y + m * k);
+#pragma unroll
+    for (int m = -1; m < P; ++m) lookup(R[m + 1]);
+    exchange(R[0]);
+    exchange(R[1]);
+    auto step = [&](auto U) -> bool {
+        constexpr int u = decltype(U)::value;
+        if (j >= jend) return false;
+        load(R[(u + NR - 1) % NR], y + (P + 1) * k);
+        lookup(R[(u + NR - 2) % NR]);
+        exchange(R[(u + 2) % NR]);
+        emit<METRIC, VN>(dst, R[u % NR].win, R[(u + 1) % NR].win, R[(u + 2) % NR].win, y, k, W,
+                         H, px, oc);
+        ++j;
+        y += k;
+        return true;
+    };
+    auto round = [&](auto... U) -> bool { return (step(U) && ...); };
+    while (expand<NR>(round)) {
     }
-#undef VD_FLOOD_STEP
 }
 
 inline dim3 grid1d(int64_t n, int64_t cap = 1 << 20)
@@ -368,7 +508,7 @@ hipError_t launch_export(const uint32_t *map, uint32_t *out, int64_t n, int32_t 
 
 hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *table, int32_t S,
                         int32_t W, int32_t H, int32_t k, int32_t vn, int32_t label,
-                        int32_t metric, hipStream_t s)
+                        int32_t metric, int32_t variant, hipStream_t s)
 {
     // Segment length: long enough to amortise the two overlap rows, short
     // enough to give the 256 CUs about 2048 workgroups.
@@ -383,22 +523,35 @@ hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *tabl
     if (k < 1 || nblocks == 0 || nblocks > 0x7FFFFFFFull) return hipErrorInvalidValue;
     dim3 grid((unsigned)nblocks), block(kTW);
     uint32_t nb = (uint32_t)nblocks, uS = (uint32_t)S;
-#define VD_LAUNCH(LB, MT, V)                                                                 \
-    hipLaunchKernelGGL((k_flood<LB, MT, V>), grid, block, 0, s, src, dst, table, uS, W, H, k, \
-                       ncol, nseg, L, nb)
+#define VD_LAUNCH(LB, MT, V, P)                                                              \
+    hipLaunchKernelGGL((k_flood<LB, MT, V, P>), grid, block, 0, s, src, dst, table, uS, W, H,  \
+                       k, ncol, nseg, L, nb)
+#define VD_LAUNCH_LDS(LB, MT, V, P)                                                           \
+    hipLaunchKernelGGL((k_flood_lds<LB, MT, V, P>), grid, block, 0, s, src, dst, table, uS, W,  \
+                       H, k, ncol, nseg, L, nb)
+#define VD_LAUNCH_P(LB, MT, V)                                                                \
+    do {                                                                                      \
+        if (variant == 0) VD_LAUNCH(LB, MT, V, 1);                                            \
+        else if (variant == 1 || (variant == 3 && k > kMaxLdsK)) VD_LAUNCH(LB, MT, V, 2);     \
+        else if (variant == 2) VD_LAUNCH(LB, MT, V, 3);                                       \
+        else VD_LAUNCH_LDS(LB, MT, V, 2);                                                     \
+    } while (0)
+    if (variant < 0 || variant >= kFloodVariants) return hipErrorInvalidValue;
     if (label == kLabelId) {
         if (metric == kEuclid) {
-            if (vn) VD_LAUNCH(kLabelId, kEuclid, 1); else VD_LAUNCH(kLabelId, kEuclid, 0);
+            if (vn) VD_LAUNCH_P(kLabelId, kEuclid, 1); else VD_LAUNCH_P(kLabelId, kEuclid, 0);
         } else {
-            if (vn) VD_LAUNCH(kLabelId, kManhattan, 1); else VD_LAUNCH(kLabelId, kManhattan, 0);
+            if (vn) VD_LAUNCH_P(kLabelId, kManhattan, 1); else VD_LAUNCH_P(kLabelId, kManhattan, 0);
         }
     } else {
         if (metric == kEuclid) {
-            if (vn) VD_LAUNCH(kLabelXy, kEuclid, 1); else VD_LAUNCH(kLabelXy, kEuclid, 0);
+            if (vn) VD_LAUNCH_P(kLabelXy, kEuclid, 1); else VD_LAUNCH_P(kLabelXy, kEuclid, 0);
         } else {
-            if (vn) VD_LAUNCH(kLabelXy, kManhattan, 1); else VD_LAUNCH(kLabelXy, kManhattan, 0);
+            if (vn) VD_LAUNCH_P(kLabelXy, kManhattan, 1); else VD_LAUNCH_P(kLabelXy, kManhattan, 0);
         }
     }
+#undef VD_LAUNCH_P
+#undef VD_LAUNCH_LDS
 #undef VD_LAUNCH
     return hipGetLastError();
 }

@@ -58,12 +58,18 @@ int32_t first_delta(int32_t W, int32_t H, int32_t S, int32_t dmax)
 struct Pass {
     int32_t k;
     int32_t vn;
+    int32_t variant;   // flood kernel variant (same result, different speed)
 };
+
+// Measured on MI355X: ID labels run fastest with rows shared through LDS
+// (fewer seed-table lookups), XY labels with the plain chain walk that
+// requests rows two ahead.
+int32_t default_variant(int32_t label) { return label == VD_LABEL_ID32 ? 3 : 1; }
 
 // Pass list of one step: k = first, first/2, ..., 1; the first vn of them
 // Von Neumann (clamped so the last main pass is Moore); extra passes k = 1
 // (one extra) or k = 2, 1 (two extras), Moore.
-std::vector<Pass> schedule(int32_t first, int32_t vn_passes, int32_t extra)
+std::vector<Pass> schedule(int32_t first, int32_t vn_passes, int32_t extra, int32_t variant)
 {
     std::vector<Pass> out;
     int32_t n = 0;
@@ -71,8 +77,9 @@ std::vector<Pass> schedule(int32_t first, int32_t vn_passes, int32_t extra)
     int32_t vn = vn_passes < n - 1 ? vn_passes : n - 1;
     if (vn < 0) vn = 0;
     int32_t i = 0;
-    for (int32_t k = first; k >= 1; k >>= 1, ++i) out.push_back({k, i < vn ? 1 : 0});
-    for (int32_t e = extra; e >= 1; --e) out.push_back({e, 0});
+    for (int32_t k = first; k >= 1; k >>= 1, ++i)
+        out.push_back({k, i < vn ? 1 : 0, variant});
+    for (int32_t e = extra; e >= 1; --e) out.push_back({e, 0, variant});
     return out;
 }
 
@@ -192,7 +199,7 @@ int run_passes(vd_sim *s, const std::vector<Pass> &passes)
         if (r) return r;
         VD_HIP(vd::launch_flood(s->map[s->cur], s->map[s->cur ^ 1], s->pos, s->cfg.num_seeds,
                                 s->cfg.width, s->cfg.height, p.k, p.vn, s->cfg.label,
-                                s->cfg.metric, s->stream));
+                                s->cfg.metric, p.variant, s->stream));
         r = record(s, 0, false, &slot);
         if (r) return r;
         s->cur ^= 1;
@@ -330,8 +337,9 @@ int vd_init_sim(const vd_config *cfg, const int32_t *host_xy, void *dev_workspac
                                                                               : abs(cfg->disp_hi));
     s->k1 = first_k(cfg->width, cfg->height);
     s->delta1 = first_delta(cfg->width, cfg->height, S, s->dmax);
-    s->jfa_passes = schedule(s->k1, 0, cfg->extra_passes);
-    s->djfa_passes = schedule(s->delta1, cfg->vn_passes, cfg->extra_passes);
+    s->jfa_passes = schedule(s->k1, 0, cfg->extra_passes, default_variant(cfg->label));
+    s->djfa_passes = schedule(s->delta1, cfg->vn_passes, cfg->extra_passes,
+                              default_variant(cfg->label));
     s->move_seed = mix64(cfg->sim_seed ^ 0x6D6F7665ull);
     hipError_t e = hipMemcpyAsync(s->pos, packed.data(), ((size_t)S + 1) * 4,
                                   hipMemcpyHostToDevice, s->stream);
@@ -455,6 +463,18 @@ void vd_destroy(vd_sim *s)
         if (p.b) (void)hipEventDestroy(p.b);
     }
     delete s;
+}
+
+int vd_set_flood_variant(vd_sim *s, int variant)
+{
+    if (!s) return fail(VD_EINVAL, "sim is NULL");
+    if (variant < -1 || variant >= vd::kFloodVariants)
+        return fail(VD_EINVAL, "variant must be -1 or in [0, %d), got %d", vd::kFloodVariants,
+                    variant);
+    int32_t v = variant < 0 ? default_variant(s->cfg.label) : variant;
+    for (Pass &p : s->jfa_passes) p.variant = v;
+    for (Pass &p : s->djfa_passes) p.variant = v;
+    return VD_OK;
 }
 
 const char *vd_last_error(void) { return g_err; }

@@ -73,6 +73,7 @@ SIGNATURES = {
     "vd_get_info": (ctypes.c_int, [_P, ctypes.POINTER(SimInfo)]),
     "vd_set_timing": (ctypes.c_int, [_P, ctypes.c_int]),
     "vd_get_timing": (ctypes.c_int, [_P, ctypes.POINTER(Timing)]),
+    "vd_set_flood_variant": (ctypes.c_int, [_P, ctypes.c_int]),
     "vd_destroy": (None, [_P]),
     "vd_last_error": (ctypes.c_char_p, []),
 }
@@ -180,6 +181,10 @@ def get_timing(h) -> Timing:
     t = Timing()
     _check(lib().vd_get_timing(h, ctypes.byref(t)))
     return t
+
+
+def set_flood_variant(h, variant: int):
+    _check(lib().vd_set_flood_variant(h, variant))
 
 
 def destroy(h):

@@ -41,15 +41,18 @@ def _seed_pixels_ok(m, xy, label_mode):
 
 
 def run_twin(V, W, H, xy, steps, lo, hi, sim_seed=1, label=0, metric=0, vn=2, extra=0,
-             dmax=0, tag=""):
+             dmax=0, tag="", variant=None):
     """Runs a JFA and a dJFA simulation side by side on the GPU and in the
     oracle; asserts equal positions and maps at every step."""
     print(f"[parity] {tag} W={W} H={H} S={len(xy)} steps={steps} disp=[{lo},{hi}] "
-          f"label={label} metric={metric} vn={vn} extra={extra}", flush=True)
+          f"label={label} metric={metric} vn={vn} extra={extra} variant={variant}", flush=True)
     kw = dict(disp_lo=lo, disp_hi=hi, label=label, metric=metric, vn_passes=vn,
               extra_passes=extra, dmax_override=dmax, sim_seed=sim_seed)
     gj = V.Sim(W, H, xy, **kw)
     gd = V.Sim(W, H, xy, **kw)
+    if variant is not None:
+        V.set_flood_variant(gj.handle, variant)
+        V.set_flood_variant(gd.handle, variant)
     okw = dict(label_mode=label, metric=metric, vn_passes=vn, extra_passes=extra,
                dmax=dmax if dmax > 0 else None)
     oj = O.Sim(W, H, xy, sim_seed, lo, hi, **okw)
@@ -113,6 +116,18 @@ def test_pass_options(V, metric, vn, extra):
     for label in (0, 1):
         run_twin(V, 700, 450, xy, 3, -2, 2, sim_seed=5, label=label, metric=metric, vn=vn,
                  extra=extra, tag="options")
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+@pytest.mark.parametrize("W,H,S", [(100, 90, 40), (700, 450, 900), (1100, 300, 5000),
+                                   (257, 1200, 600)])
+def test_flood_variants(V, variant, W, H, S):
+    """Every kernel variant writes the same maps (k from 1 to 1024, widths
+    below, at and across the 256-column tile, heights with ragged chains)."""
+    xy = inputs.place_seeds(W, H, S, W + 3 * H)
+    for label in (0, 1):
+        run_twin(V, W, H, xy, 2, -2, 2, sim_seed=7, label=label, variant=variant,
+                 tag="variant")
 
 
 def test_dmax_override(V):
