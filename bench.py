@@ -86,6 +86,27 @@ def cpu_baseline(spec, xy, budget_s: float):
                       f"{elapsed:.1f} s, rows split over {threads} threads"}
 
 
+def calibrate(torch, nbytes=512 << 20, reps=20):
+    """Plain copy of nbytes between two device buffers: reads nbytes and
+    writes nbytes per launch."""
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1)
+    for _ in range(3):
+        b.copy_(a)
+    s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    s1.record()
+    torch.cuda.synchronize()
+    ms = s0.elapsed_time(s1) / reps
+    print(json.dumps({"calibration": "device copy", "bytes_read": nbytes, "bytes_written": nbytes,
+                      "ms_per_copy": ms, "GBps_read_plus_write": 2 * nbytes / (ms / 1e3) / 1e9}),
+          flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +117,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-pass-timing", action="store_true")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="time a plain device-to-device copy of known size instead (HBM "
+                         "reference for the roofline and for scaling rocprof byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -107,6 +131,9 @@ def main():
     from paper_2209_00117_amd import inputs, vdflood as V
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate:
+        calibrate(torch)
+        return
     V.lib()
     wl = inputs.WORKLOADS[args.workload]()
     spec = wl.sims[0]
