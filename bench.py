@@ -107,12 +107,176 @@ def calibrate(torch, nbytes=512 << 20, reps=20):
           flush=True)
 
 
+def bench_batched(torch, inputs, V, args):
+    """64 simulations of uneven sizes.  Timed three ways on the same GPU,
+    each over args.steps time steps (move + step): fused batched dJFA and
+    fused batched JFA (one persistent launch per pass level, replayed as a
+    hipGraph), and the same 64 simulations run one at a time with plain JFA
+    (per-simulation launches).  Every batched member's map equals its
+    one-at-a-time run bit for bit (tests/test_gpu_batch.py)."""
+    wl = inputs.batched()
+    stream = torch.cuda.current_stream()
+    specs = wl.sims
+    made = [(s, s.positions()) for s in specs]
+
+    def make():
+        return [V.Sim(s.width, s.height, xy, stream=stream, disp_lo=s.disp_lo,
+                      disp_hi=s.disp_hi, sim_seed=s.sim_seed) for s, xy in made]
+
+    px = sum(s.width * s.height for s in specs)
+    out = {}
+    for name, mode in (("batched_djfa", V.STEP_DJFA), ("batched_jfa", V.STEP_JFA)):
+        sims = make()
+        b = V.Batch(sims, stream=stream)
+        b.set_graph(not args.no_graph)
+        lj, ld, grid = b.info()
+        upd = sum(s.width * s.height * (sm.info().passes_djfa if mode == V.STEP_DJFA
+                                        else sm.info().passes_jfa)
+                  for s, sm in zip(specs, sims))
+        for _ in range(args.warmup):
+            b.step(mode, True)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+        torch.cuda.synchronize()
+        ev[0].record(stream)
+        for i in range(args.steps):
+            b.step(mode, True)
+            ev[i + 1].record(stream)
+        torch.cuda.synchronize()
+        lat = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
+        total = ev[0].elapsed_time(ev[-1])
+        out[name] = {"ms_per_step": total / args.steps, "p50_ms": pct(lat, 50),
+                     "p99_ms": pct(lat, 99), "pixel_updates_per_s": upd * args.steps / (total / 1e3),
+                     "levels": ld if mode == V.STEP_DJFA else lj, "grid": grid,
+                     "graph": not args.no_graph}
+        b.close()
+        for x in sims:
+            x.close()
+    # baseline: the same simulations one at a time, plain JFA
+    sims = make()
+    upd = sum(s.width * s.height * sm.info().passes_jfa for s, sm in zip(specs, sims))
+    for _ in range(args.warmup):
+        for x in sims:
+            x.move_seeds()
+            x.jfa_step()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    torch.cuda.synchronize()
+    ev[0].record(stream)
+    for i in range(args.steps):
+        for x in sims:
+            x.move_seeds()
+            x.jfa_step()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    lat = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
+    total = ev[0].elapsed_time(ev[-1])
+    out["sequential_jfa"] = {"ms_per_step": total / args.steps, "p50_ms": pct(lat, 50),
+                             "p99_ms": pct(lat, 99),
+                             "pixel_updates_per_s": upd * args.steps / (total / 1e3)}
+    for x in sims:
+        x.close()
+    seq = out["sequential_jfa"]["ms_per_step"]
+    line = {"metric": METRIC, "value": out["batched_djfa"]["pixel_updates_per_s"],
+            "unit": "pixel-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+            "ms_per_step": out["batched_djfa"]["ms_per_step"], "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+            "data": "synthetic (uniform random seeds and moves, splitmix64)",
+            "config": {"workload": wl.name, "sims": len(specs), "pixels": px},
+            **out,
+            "speedup_vs_sequential_jfa": {"batched_djfa": seq / out["batched_djfa"]["ms_per_step"],
+                                          "batched_jfa": seq / out["batched_jfa"]["ms_per_step"]}}
+    print(json.dumps(line), flush=True)
+
+
+def bench_serving(torch, inputs, V, args):
+    """256 resident simulations of mixed sizes; Poisson arrivals of time-step
+    requests (move + dJFA) at args.rate per second, uniformly over the
+    simulations, for 1 s of warm-up and args.seconds measured.  Latency runs
+    from submission to the request's completion on the GPU.  The same
+    arrival stream is then served one request at a time with plain JFA
+    (move + JFA per request, each waited for before the next starts)."""
+    wl = inputs.serving()
+    specs = wl.sims
+    stream = torch.cuda.current_stream()
+    made = [(s, s.positions()) for s in specs]
+    fp = sum((V.footprint_bytes(V.config(s.width, s.height, s.num_seeds)) + 255) // 256 * 256
+             for s in specs)
+    pool = V.Server.footprint_bytes(len(specs)) + fp + (1 << 20)
+    sv = V.Server(len(specs), pool, stream=stream)
+    ids = [sv.add_sim(s.width, s.height, xy, disp_lo=s.disp_lo, disp_hi=s.disp_hi,
+                      sim_seed=s.sim_seed) for s, xy in made]
+    sv.drain()
+    warm = 1.0
+    times, targets = inputs.poisson_arrivals(args.rate, warm + args.seconds, len(specs))
+
+    def serve(submit, t_start):
+        for at, tgt in zip(times, targets):
+            while time.perf_counter() - t_start < at:
+                pass
+            submit(int(tgt), at)
+
+    t_start = time.perf_counter()
+    reset_done = [False]
+
+    def submit_server(tgt, at):
+        if not reset_done[0] and at >= warm:
+            sv.stats(reset=True)
+            reset_done[0] = True
+        sv.submit(ids[tgt], V.STEP_DJFA)
+
+    serve(submit_server, t_start)
+    sv.drain()
+    st = sv.stats()
+    px = sum(s.width * s.height for s in specs)
+    served = {"requests": st["completed"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+              "mean_ms": st["mean_ms"], "max_ms": st["max_ms"],
+              "pixel_updates_per_s": st["pixel_updates"] / st["elapsed_s"],
+              "requests_per_s": st["completed"] / st["elapsed_s"], "ticks": st["ticks"],
+              "elapsed_s": st["elapsed_s"]}
+    sv.close()
+
+    # one request at a time, plain JFA, same arrivals
+    sims = [V.Sim(s.width, s.height, xy, stream=stream, disp_lo=s.disp_lo, disp_hi=s.disp_hi,
+                  sim_seed=s.sim_seed) for s, xy in made]
+    lat, upd = [], [0]
+    t_start = time.perf_counter()
+
+    def submit_plain(tgt, at):
+        x = sims[tgt]
+        x.move_seeds()
+        x.jfa_step()
+        torch.cuda.synchronize()
+        if at >= warm:
+            lat.append((time.perf_counter() - t_start - at) * 1e3)
+            upd[0] += x.cfg.width * x.cfg.height * x.info().passes_jfa
+
+    serve(submit_plain, t_start)
+    plain_elapsed = time.perf_counter() - t_start - warm
+    plain = {"requests": len(lat), "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+             "mean_ms": float(np.mean(lat)) if lat else None,
+             "pixel_updates_per_s": upd[0] / plain_elapsed}
+    for x in sims:
+        x.close()
+    line = {"metric": METRIC, "value": served["pixel_updates_per_s"], "unit": "pixel-updates/s",
+            "n_gpus": 1, "steps": served["requests"], "warmup": 0,
+            "ms_per_step": served["mean_ms"], "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "int32",
+            "data": "synthetic (uniform random seeds and moves, Poisson arrivals, splitmix64)",
+            "config": {"workload": wl.name, "sims": len(specs), "pixels": px,
+                       "rate_per_s": args.rate, "seconds": args.seconds, "pool_bytes": pool},
+            "served_djfa": served, "one_at_a_time_jfa": plain}
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="single", choices=["small", "single", "large"])
+    ap.add_argument("--workload", default="single",
+                    choices=["small", "single", "large", "batched", "serving"])
+    ap.add_argument("--rate", type=float, default=2000.0, help="serving: requests per second")
+    ap.add_argument("--seconds", type=float, default=10.0, help="serving: measured seconds")
+    ap.add_argument("--no-graph", action="store_true", help="batched: launch kernels directly")
     ap.add_argument("--label", default="id", choices=["id", "xy"])
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -135,6 +299,12 @@ def main():
         calibrate(torch)
         return
     V.lib()
+    if args.workload == "batched":
+        bench_batched(torch, inputs, V, args)
+        return
+    if args.workload == "serving":
+        bench_serving(torch, inputs, V, args)
+        return
     wl = inputs.WORKLOADS[args.workload]()
     spec = wl.sims[0]
     W, H = spec.width, spec.height

@@ -45,7 +45,8 @@ typedef enum vd_status {
     VD_EINVAL = -1,   /* an argument is out of range or NULL */
     VD_ENOMEM = -2,   /* workspace too small, or a host allocation failed */
     VD_EDEVICE = -3,  /* a HIP call failed (the message names it) */
-    VD_ESTATE = -4    /* the call does not fit the object's state */
+    VD_ESTATE = -4,   /* the call does not fit the object's state */
+    VD_EBUSY = -5     /* a wait timed out; the work is still in progress */
 } vd_status;
 
 enum { VD_LABEL_ID32 = 0, VD_LABEL_XY16 = 1 };
@@ -178,12 +179,166 @@ int vd_get_timing(vd_sim *sim, vd_timing *out);
  * labels. */
 int vd_set_flood_variant(vd_sim *sim, int variant);
 
+/* Chooses, by timing, the kernel variant and the segment length of every
+ * flood pass of this simulation's JFA and dJFA steps: each candidate runs
+ * reps times (after one warm-up launch) reading the current diagram and
+ * writing the idle buffer, so the simulation's state does not change.
+ * The choices also enter a process-wide table keyed by (GPU architecture,
+ * width, height, seed count, label, metric, k, neighbourhood) that later
+ * vd_init_sim calls consult.  Results never depend on the choices.
+ * Waits for the stream. */
+int vd_autotune(vd_sim *sim, int32_t reps);
+
+/* Variant and segment length (0: automatic) of each pass, JFA passes first
+ * then dJFA passes; cap must be at least passes_jfa + passes_djfa.  Either
+ * output array may be NULL. */
+int vd_get_tuning(const vd_sim *sim, int32_t *variants, int32_t *seg_rows, int32_t cap);
+
+/* The process-wide tuning table as text, one "key|variant|seg_rows" line
+ * per entry.  *needed receives the size including the terminating NUL; buf
+ * may be NULL to query it. */
+int vd_tuning_export(char *buf, size_t cap, size_t *needed);
+
+/* Adds the entries of a text produced by vd_tuning_export (overwriting
+ * equal keys); simulations created afterwards use them. */
+int vd_tuning_import(const char *text);
+
 /* Releases the handle (never the caller's workspace).  Waits for the
- * simulation's pending work.  NULL is ignored. */
+ * simulation's pending work.  NULL is ignored, and so is a simulation that
+ * still belongs to a batch (destroy the batch first). */
 void vd_destroy(vd_sim *sim);
+
+/* ---------------------------------------------------------------------- */
+/* Batches: many simulations advanced together with fused launches.        */
+/* ---------------------------------------------------------------------- */
+
+typedef struct vd_batch vd_batch;   /* opaque; owned by the library */
+
+enum { VD_STEP_JFA = 0, VD_STEP_DJFA = 1 };
+
+/* Device bytes of a batch of n simulations (its tables and counters); 0 if
+ * n is outside [1, 32768]. */
+size_t vd_batch_footprint_bytes(int32_t n);
+
+/* Groups n existing simulations so that vd_batch_step advances them all.
+ * Members must use ID labels, one metric and the batch's hip_stream (the
+ * stream they were created on); their own workspaces stay in use.  While a
+ * simulation belongs to the batch, vd_move_seeds / vd_jfa_step /
+ * vd_djfa_step on it return VD_ESTATE and vd_destroy ignores it; reads and
+ * vd_get_info keep working.  dev_workspace (any alignment, at least
+ * vd_batch_footprint_bytes(n) bytes) is owned by the caller and must stay
+ * untouched until vd_batch_destroy.  The pointer array is copied. */
+int vd_batch_create(vd_sim *const *sims, int32_t n, void *dev_workspace, size_t ws_bytes,
+                    void *hip_stream, vd_batch **out);
+
+/* One time step of every member: if move != 0 the seeds move first
+ * (exactly as vd_move_seeds), then a JFA (mode VD_STEP_JFA) or a dJFA
+ * (VD_STEP_DJFA) step, each member's result identical to running that
+ * member alone.  Pass level i of every member runs in one persistent
+ * launch that balances the members' tiles over the GPU.  Asynchronous. */
+int vd_batch_step(vd_batch *b, int32_t mode, int32_t move);
+
+/* enable != 0: each kind of step (mode, move) is captured into a hipGraph
+ * the first time it runs and replayed afterwards (one graph launch per
+ * step).  enable == 0 drops the graphs and launches kernels directly. */
+int vd_batch_set_graph(vd_batch *b, int enable);
+
+/* Persistent flood grid: wg_per_cu workgroups per compute unit (0: as
+ * many as fit, the default).  Speed only; results do not change. */
+int vd_batch_set_shape(vd_batch *b, int32_t wg_per_cu);
+
+/* Chooses by timing, separately for JFA and dJFA steps, the persistent
+ * grid (1, 2, 4 or 8 workgroups per compute unit, or as many as fit): each
+ * candidate runs every pass level reps times reading the current diagrams
+ * and writing the idle buffers, so no simulation changes.  Drops captured
+ * graphs.  Waits for the stream. */
+int vd_batch_autotune(vd_batch *b, int32_t reps);
+
+/* Per-level flood and per-step timing with HIP events, as for a single
+ * simulation (not recorded inside captured graphs: with graphs on, only
+ * whole steps are timed). */
+int vd_batch_set_timing(vd_batch *b, int enable);
+int vd_batch_get_timing(vd_batch *b, vd_timing *out);
+
+/* Pass levels of a JFA and a dJFA step, and the persistent grid size. */
+int vd_batch_info(const vd_batch *b, int32_t *levels_jfa, int32_t *levels_djfa, int32_t *grid);
+
+/* Waits for the batch's work and releases it; members become free
+ * simulations again, with their state as the last step left it. */
+void vd_batch_destroy(vd_batch *b);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *vd_last_error(void);
+
+/* ---------------------------------------------------------------------- */
+/* Serving: time-step requests of many resident simulations, continuously  */
+/* batched at flood-pass granularity by a scheduler thread.                */
+/* ---------------------------------------------------------------------- */
+
+typedef struct vd_server vd_server;   /* opaque; owned by the library */
+
+typedef struct vd_server_stats {
+    int64_t submitted;        /* requests submitted since the last reset */
+    int64_t completed;        /* requests finished since the last reset */
+    int64_t pixel_updates;    /* flood pixel-updates of finished ticks */
+    int64_t ticks;            /* fused launches issued */
+    double elapsed_s;         /* wall time since the last reset */
+    double mean_ms, p50_ms, p99_ms, max_ms;   /* request latency: submit -> done */
+    int32_t resident;         /* simulations with device state */
+    int32_t waiting_admission;/* simulations waiting for memory */
+} vd_server_stats_t;
+
+/* Device bytes the server's own tables take from the pool for up to
+ * max_sims simulations; simulations need vd_footprint_bytes each on top. */
+size_t vd_server_footprint_bytes(int32_t max_sims);
+
+/* Starts a server (and its scheduler thread) for up to max_sims ID-label
+ * simulations of one metric.  dev_pool (pool_bytes, any alignment) is
+ * caller-owned device memory holding the server tables and every
+ * simulation's workspace; it must outlive vd_server_destroy.  All device
+ * work runs on hip_stream. */
+int vd_server_create(int32_t max_sims, int32_t metric, void *dev_pool, size_t pool_bytes,
+                     void *hip_stream, vd_server **out);
+
+/* Registers a simulation (cfg as for vd_init_sim; label must be ID and the
+ * metric the server's) and returns its id.  It becomes resident (workspace
+ * placed in the pool, VD_0 computed) as soon as its footprint fits;
+ * simulations wait for memory in registration order.  host_xy is copied. */
+int vd_server_add_sim(vd_server *sv, const vd_config *cfg, const int32_t *host_xy,
+                      int32_t *sim_id);
+
+/* Queues one time step of a simulation: a move, then a JFA (VD_STEP_JFA) or
+ * dJFA (VD_STEP_DJFA) step.  Requests of one simulation run in submission
+ * order; its result equals the same sequence of vd_move_seeds + step calls
+ * on a lone simulation.  Returns at once with a ticket. */
+int vd_server_submit(vd_server *sv, int32_t sim_id, int32_t mode, int64_t *ticket);
+
+/* Waits (timeout_ms < 0: without limit) until a ticket's step has
+ * finished on the GPU; *latency_ms receives submit-to-finish time.  A
+ * ticket can be waited for once.  VD_EBUSY on timeout. */
+int vd_server_wait(vd_server *sv, int64_t ticket, double timeout_ms, double *latency_ms);
+
+/* Waits until every submitted request has finished (VD_EBUSY on timeout). */
+int vd_server_drain(vd_server *sv, double timeout_ms);
+
+/* Unregisters a simulation: waits for its running request, drops queued
+ * ones, frees its memory (admitting waiting simulations). */
+int vd_server_remove_sim(vd_server *sv, int32_t sim_id);
+
+/* The current diagram of an idle resident simulation (VD_ESTATE while it
+ * has requests in progress or is not resident); as vd_read_map. */
+int vd_server_read_map(vd_server *sv, int32_t sim_id, int32_t *host_dst, size_t count);
+
+/* Whether a simulation is resident, its time step and its pending requests. */
+int vd_server_sim_state(vd_server *sv, int32_t sim_id, int32_t *resident, int64_t *t,
+                        int32_t *pending);
+
+/* Counters and latency quantiles since the last reset (reset != 0 starts a
+ * new measuring window). */
+int vd_server_stats(vd_server *sv, vd_server_stats_t *out, int reset);
+
+/* Stops the scheduler, waits for the GPU and releases every simulation. */
+void vd_server_destroy(vd_server *sv);
 
 #ifdef __cplusplus
 }

@@ -1,0 +1,748 @@
+// Batched time steps over many simulations of different sizes.
+//
+// One batch step advances every member simulation by one time step (move,
+// then a JFA or a dJFA step, Sec. III / Sec. V) with a fixed number of
+// launches, whatever the number of simulations:
+//   begin (clear work counters), move, fill (JFA only), splat x 2, then one
+//   persistent flood launch per pass level, then end (advance t, flip the
+//   current-map index where the pass count is odd).
+// Level i runs pass i of every simulation that has one; the tiles of all of
+// them form one work list.  A fixed grid of workgroups (as many as fit on
+// the GPU at once) takes tiles from it until it is empty: each XCD first
+// drains its own eighth of the list (tiles of a simulation are contiguous,
+// so neighbouring tiles meet in that XCD's L2), then helps the others.
+//
+// The current-map index and the time step of each simulation live in device
+// memory and are read by the kernels, so a step captured once in a hipGraph
+// replays correctly for every later step (no node holds a step-dependent
+// argument).  The host mirrors both values in each vd_sim, which keeps
+// vd_read_map, vd_read_seeds and vd_get_info valid between batch steps.
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <vector>
+
+#include "vd_device.h"
+#include "vd_sim.h"
+
+namespace vd {
+
+namespace {
+
+struct BatchSim {        // device copy of one member simulation
+    uint32_t *map[2];
+    uint32_t *table;
+    int32_t W, H, S;
+    int32_t lo;          // move range [lo, lo + span)
+    uint32_t span;
+    int32_t pad;
+    uint64_t move_seed;
+};
+
+struct DevState {        // per-simulation state the kernels read and update
+    int32_t cur;         // map[cur] holds the current diagram
+    int32_t pad;
+    uint64_t t;          // time step
+};
+
+struct LevelSim {        // one simulation's pass at one level
+    int32_t k;           // 0: no pass at this level
+    int32_t vn;
+    FloodGrid g;
+    uint32_t first;      // index of its first item in the level's work list
+    uint32_t per;        // tiles per item
+};
+
+struct LevelInfo {
+    uint32_t total;      // tiles at this level
+    uint32_t chunk[9];   // XCD c drains tiles [chunk[c], chunk[c + 1]) first
+};
+
+constexpr int kMaxLevels = 24;   // > ceil(log2 16368) + 2 extra passes
+
+// A wave-uniform 32-bit value or pointer, stated as such to the compiler.
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t uni(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)v);
+}
+template <class T>
+__device__ __forceinline__ T *uni_ptr(T *p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)v);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)(v >> 32));
+    return (T *)(lo | (hi << 32));
+}
+
+__global__ void __launch_bounds__(kBlock) k_batch_begin(uint32_t *__restrict__ ctr, int32_t n)
+{
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) ctr[i] = 0u;
+}
+
+__global__ void __launch_bounds__(kBlock) k_batch_move(const BatchSim *__restrict__ sims,
+                                                       const DevState *__restrict__ st)
+{
+    const BatchSim sm = sims[blockIdx.y];
+    const uint64_t t = st[blockIdx.y].t + 1;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < sm.S;
+         i += gridDim.x * blockDim.x) {
+        uint64_t n = ((t - 1) * (uint64_t)sm.S + (uint64_t)i) * 2u;
+        uint32_t p = sm.table[i + 1];
+        int32_t x = (int32_t)(p & 0xFFFFu) - (int32_t)kOff + draw(sm.move_seed, n + 0, sm.lo, sm.span);
+        int32_t y = (int32_t)(p >> 16) - (int32_t)kOff + draw(sm.move_seed, n + 1, sm.lo, sm.span);
+        x = min(max(x, 0), sm.W - 1);
+        y = min(max(y, 0), sm.H - 1);
+        sm.table[i + 1] = ((uint32_t)(y + (int32_t)kOff) << 16) | (uint32_t)(x + (int32_t)kOff);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_batch_fill(const BatchSim *__restrict__ sims,
+                                                       const DevState *__restrict__ st)
+{
+    const BatchSim sm = sims[blockIdx.y];
+    uint32_t *map = sm.map[st[blockIdx.y].cur];
+    const int64_t n = (int64_t)sm.W * sm.H;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        map[i] = kEmpty;
+}
+
+// Seed pixels, lowest index where seeds coincide (as launch_splat_id).
+template <bool RESET>
+__global__ void __launch_bounds__(kBlock) k_batch_splat(const BatchSim *__restrict__ sims,
+                                                        const DevState *__restrict__ st)
+{
+    const BatchSim sm = sims[blockIdx.y];
+    uint32_t *map = sm.map[st[blockIdx.y].cur];
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < sm.S;
+         i += gridDim.x * blockDim.x) {
+        uint32_t *px = &map[pixel_of(sm.table[i + 1], sm.W)];
+        if (RESET)
+            *px = 0xFFFFFFFFu;
+        else
+            atomicMin(px, (uint32_t)(i + 1));
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_batch_end(DevState *__restrict__ st,
+                                                      const int32_t *__restrict__ npasses,
+                                                      int32_t n, int32_t moved)
+{
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        st[i].cur ^= npasses[i] & 1;
+        st[i].t += (uint64_t)moved;
+    }
+}
+
+// Persistent flood pass of one level over every member simulation (ID
+// labels).  Each iteration takes one work item: one or more adjacent tiles
+// (256 columns of one chain segment) of one simulation, run by the same tile
+// functions as the single-simulation kernels (LDS-shared rows for k <= 128,
+// else the chain walk with rows requested two ahead).
+template <int METRIC>
+__global__ void __launch_bounds__(kTW) k_batch_flood(const BatchSim *__restrict__ sims,
+                                                     const DevState *__restrict__ st,
+                                                     const LevelSim *__restrict__ ls,
+                                                     const LevelInfo *__restrict__ info,
+                                                     int32_t n, int32_t level,
+                                                     uint32_t *__restrict__ ctr)
+{
+    __shared__ uint2 lds[2][kLdsRow];
+    __shared__ uint32_t s_item;
+    const uint32_t home = blockIdx.x & 7u;
+    uint32_t probe = 0;       // chunks already found empty
+    for (;;) {
+        __syncthreads();      // the previous tile's LDS reads are finished
+        if (threadIdx.x == 0) {
+            uint32_t item = 0xFFFFFFFFu;
+            while (probe < 8u) {
+                const uint32_t c = (home + probe) & 7u;
+                const uint32_t lo = info->chunk[c], hi = info->chunk[c + 1];
+                const uint32_t i = lo < hi ? atomicAdd(&ctr[c], 1u) : 0xFFFFFFFFu;
+                if (i < hi - lo) {
+                    item = lo + i;
+                    break;
+                }
+                ++probe;
+            }
+            s_item = item;
+        }
+        __syncthreads();
+        const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
+        if (item == 0xFFFFFFFFu) return;
+        // the last simulation whose first tile is <= item owns it (a
+        // simulation without tiles shares its first with the next one).
+        // Every value read from the tables below is the same for the whole
+        // workgroup; readfirstlane states it, so addresses and descriptors
+        // stay in scalar registers.
+        int32_t a = 0, b = n;
+        while (b - a > 1) {
+            const int32_t m = (a + b) >> 1;
+            if (uni(ls[m].first) <= item) a = m; else b = m;
+        }
+        const LevelSim &lv = ls[a];
+        const BatchSim &sm = sims[a];
+        const int32_t k = uni(lv.k), vn = uni(lv.vn);
+        FloodGrid g;
+        g.ncol = uni(lv.g.ncol);
+        g.nseg = uni(lv.g.nseg);
+        g.L = uni(lv.g.L);
+        g.nblocks = uni(lv.g.nblocks);
+        const int32_t W = uni(sm.W), H = uni(sm.H), S = uni(sm.S);
+        const int32_t c = uni(st[a].cur) ^ (level & 1);
+        uint32_t *m0 = uni_ptr(sm.map[0]), *m1 = uni_ptr(sm.map[1]);
+        const uint32_t *src = c ? m1 : m0;
+        uint32_t *dst = c ? m0 : m1;
+        const i32x4 tab = table_rsrc(uni_ptr(sm.table), (uint32_t)S);
+        const uint32_t per = uni(lv.per);
+        const uint32_t t0 = (item - uni(lv.first)) * per;
+        const uint32_t t1 = min(t0 + per, g.nblocks);
+        for (uint32_t tile = t0; tile < t1; ++tile) {
+            if (tile != t0) __syncthreads();   // LDS of the previous tile is free
+            if (k <= kMaxLdsStep) {
+                if (vn)
+                    flood_lds_tile<kLabelId, METRIC, 1, 2>(src, dst, tab, W, H, k, g, tile, lds);
+                else
+                    flood_lds_tile<kLabelId, METRIC, 0, 2>(src, dst, tab, W, H, k, g, tile, lds);
+            } else {
+                if (vn)
+                    flood_chain_tile<kLabelId, METRIC, 1, 2>(src, dst, tab, W, H, k, g, tile);
+                else
+                    flood_chain_tile<kLabelId, METRIC, 0, 2>(src, dst, tab, W, H, k, g, tile);
+            }
+        }
+    }
+}
+
+size_t align_up(size_t v) { return (v + 255) / 256 * 256; }
+
+struct Layout {
+    size_t sims, state, info[2], ls[2], npasses[2], ctr, total;
+};
+
+Layout layout(int32_t n)
+{
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off += align_up(bytes);
+        return at;
+    };
+    L.sims = take(sizeof(BatchSim) * (size_t)n);
+    L.state = take(sizeof(DevState) * (size_t)n);
+    for (int m = 0; m < 2; ++m) {
+        L.info[m] = take(sizeof(LevelInfo) * kMaxLevels);
+        L.ls[m] = take(sizeof(LevelSim) * (size_t)kMaxLevels * (size_t)n);
+        L.npasses[m] = take(sizeof(int32_t) * (size_t)n);
+    }
+    L.ctr = take(sizeof(uint32_t) * 8 * kMaxLevels);
+    L.total = off + 256;   // alignment slack of the caller's pointer
+    return L;
+}
+
+}  // namespace
+
+}  // namespace vd
+
+using vd::fail;
+
+struct vd_batch {
+    std::vector<vd_sim *> sims;
+    hipStream_t stream = nullptr;
+    uint8_t *base = nullptr;      // aligned start of the device workspace
+    vd::Layout lay{};
+    int32_t metric = 0;
+    int32_t levels[2] = {0, 0};   // pass levels of a JFA / dJFA step
+    std::vector<int64_t> level_pixels[2];    // pixel-updates per level (timing)
+    int32_t grid[2] = {0, 0};     // persistent flood workgroups per mode
+    int32_t fit = 1;              // flood workgroups that fit on one CU
+    int32_t cus = 1;
+    bool use_graph = false;
+    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [mode][moved]
+    hipStream_t capture = nullptr;   // private stream to capture on (the caller's may be
+                                     // the null stream, which cannot be captured)
+    bool timing = false;
+    std::vector<vd::EventPair> pool;
+    size_t used = 0;
+    vd_timing acc{};
+    bool broken = false;
+};
+
+namespace {
+
+#define VD_HIP(call)                                                                     \
+    do {                                                                                 \
+        hipError_t e_ = (call);                                                          \
+        if (e_ != hipSuccess)                                                            \
+            return fail(VD_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));      \
+    } while (0)
+
+template <class T>
+T *at(vd_batch *b, size_t off)
+{
+    return (T *)(b->base + off);
+}
+
+int batch_record(vd_batch *b, int kind, bool begin, size_t *slot)
+{
+    if (!b->timing) return VD_OK;
+    if (begin) {
+        if (b->used == b->pool.size()) {
+            vd::EventPair p;
+            VD_HIP(hipEventCreate(&p.a));
+            VD_HIP(hipEventCreate(&p.b));
+            b->pool.push_back(p);
+        }
+        *slot = b->used++;
+        b->pool[*slot].kind = kind;
+        VD_HIP(hipEventRecord(b->pool[*slot].a, b->stream));
+    } else {
+        VD_HIP(hipEventRecord(b->pool[*slot].b, b->stream));
+    }
+    return VD_OK;
+}
+
+int batch_harvest(vd_batch *b)
+{
+    if (b->used == 0) return VD_OK;
+    VD_HIP(hipStreamSynchronize(b->stream));
+    for (size_t i = 0; i < b->used; ++i) {
+        float ms = 0.f;
+        VD_HIP(hipEventElapsedTime(&ms, b->pool[i].a, b->pool[i].b));
+        int kind = b->pool[i].kind;
+        if (kind >= 2) {   // flood level: kind = 2 + mode * kMaxLevels + level
+            int mode = (kind - 2) / vd::kMaxLevels, level = (kind - 2) % vd::kMaxLevels;
+            b->acc.flood_launches += 1;
+            b->acc.flood_ms += ms;
+            b->acc.flood_pixels += b->level_pixels[mode][level];
+        } else {
+            b->acc.step_count += 1;
+            b->acc.step_ms += ms;
+        }
+    }
+    b->used = 0;
+    return VD_OK;
+}
+
+// Flood launch of level `lvl` of `mode` using the level parity of
+// `parity_level`: equal to lvl in a step; 0 while tuning, so the launch
+// reads the current diagrams and writes the idle buffers.
+hipError_t launch_level(vd_batch *b, int mode, int32_t lvl, int32_t parity_level, int32_t grid,
+                        hipStream_t stream)
+{
+    const int32_t n = (int32_t)b->sims.size();
+    const vd::BatchSim *sims = at<vd::BatchSim>(b, b->lay.sims);
+    const vd::DevState *st = at<vd::DevState>(b, b->lay.state);
+    const vd::LevelSim *ls = at<vd::LevelSim>(b, b->lay.ls[mode]) + (size_t)lvl * n;
+    const vd::LevelInfo *info = at<vd::LevelInfo>(b, b->lay.info[mode]) + lvl;
+    uint32_t *ctr = at<uint32_t>(b, b->lay.ctr) + 8 * lvl;
+    if (b->metric == VD_EUCLID)
+        hipLaunchKernelGGL(vd::k_batch_flood<vd::kEuclid>, dim3((unsigned)grid), dim3(vd::kTW),
+                           0, stream, sims, st, ls, info, n, parity_level, ctr);
+    else
+        hipLaunchKernelGGL(vd::k_batch_flood<vd::kManhattan>, dim3((unsigned)grid),
+                           dim3(vd::kTW), 0, stream, sims, st, ls, info, n, parity_level, ctr);
+    return hipGetLastError();
+}
+
+// Enqueues one batch step on `stream` (b->stream, or the capture stream
+// while a graph is recorded; then timing is off).
+int enqueue_step(vd_batch *b, int mode, int moved, hipStream_t stream)
+{
+    const int32_t n = (int32_t)b->sims.size();
+    int32_t maxS = 1;
+    for (vd_sim *s : b->sims) maxS = std::max(maxS, s->cfg.num_seeds);
+    const vd::BatchSim *sims = at<vd::BatchSim>(b, b->lay.sims);
+    vd::DevState *st = at<vd::DevState>(b, b->lay.state);
+    uint32_t *ctr = at<uint32_t>(b, b->lay.ctr);
+    const dim3 blk(vd::kBlock);
+    const dim3 gseeds((unsigned)std::min<int64_t>((maxS + vd::kBlock - 1) / vd::kBlock, 1024),
+                      (unsigned)n);
+    hipLaunchKernelGGL(vd::k_batch_begin, dim3(1), blk, 0, stream, ctr,
+                       8 * vd::kMaxLevels);
+    VD_HIP(hipGetLastError());
+    if (moved) {
+        hipLaunchKernelGGL(vd::k_batch_move, gseeds, blk, 0, stream, sims,
+                           (const vd::DevState *)st);
+        VD_HIP(hipGetLastError());
+    }
+    if (mode == VD_STEP_JFA) {
+        hipLaunchKernelGGL(vd::k_batch_fill, dim3(256, (unsigned)n), blk, 0, stream, sims,
+                           (const vd::DevState *)st);
+        VD_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL(vd::k_batch_splat<true>, gseeds, blk, 0, stream, sims,
+                       (const vd::DevState *)st);
+    VD_HIP(hipGetLastError());
+    hipLaunchKernelGGL(vd::k_batch_splat<false>, gseeds, blk, 0, stream, sims,
+                       (const vd::DevState *)st);
+    VD_HIP(hipGetLastError());
+    for (int32_t lvl = 0; lvl < b->levels[mode]; ++lvl) {
+        size_t slot = 0;
+        int r = batch_record(b, 2 + mode * vd::kMaxLevels + lvl, true, &slot);
+        if (r) return r;
+        VD_HIP(launch_level(b, mode, lvl, lvl, b->grid[mode], stream));
+        r = batch_record(b, 0, false, &slot);
+        if (r) return r;
+    }
+    hipLaunchKernelGGL(vd::k_batch_end, dim3(1), blk, 0, stream, st,
+                       (const int32_t *)at<int32_t>(b, b->lay.npasses[mode]), n, moved);
+    VD_HIP(hipGetLastError());
+    return VD_OK;
+}
+
+int query_fit(vd_batch *b)
+{
+    int dev = 0, cus = 0, fit = 0;
+    VD_HIP(hipGetDevice(&dev));
+    VD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    if (b->metric == VD_EUCLID)
+        VD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &fit, vd::k_batch_flood<vd::kEuclid>, vd::kTW, 0));
+    else
+        VD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &fit, vd::k_batch_flood<vd::kManhattan>, vd::kTW, 0));
+    b->cus = std::max(cus, 1);
+    b->fit = std::max(fit, 1);
+    return VD_OK;
+}
+
+int32_t grid_for(const vd_batch *b, int32_t wg_per_cu)
+{
+    return b->cus * (wg_per_cu > 0 ? std::min(wg_per_cu, b->fit) : b->fit);
+}
+
+void drop_graphs(vd_batch *b)
+{
+    for (auto &row : b->graph)
+        for (hipGraphExec_t &g : row)
+            if (g) {
+                (void)hipGraphExecDestroy(g);
+                g = nullptr;
+            }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t vd_batch_footprint_bytes(int32_t n)
+{
+    if (n < 1 || n > (1 << 15)) return 0;
+    return vd::layout(n).total;
+}
+
+int vd_batch_create(vd_sim *const *sims, int32_t n, void *dev_workspace, size_t ws_bytes,
+                    void *hip_stream, vd_batch **out)
+{
+    if (!out) return fail(VD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!sims || n < 1 || n > (1 << 15))
+        return fail(VD_EINVAL, "need 1 <= n <= 32768 simulations, got %d", n);
+    if (!dev_workspace) return fail(VD_EINVAL, "dev_workspace is NULL");
+    vd::Layout lay = vd::layout(n);
+    if (ws_bytes < lay.total)
+        return fail(VD_ENOMEM, "workspace holds %zu bytes, the batch needs %zu", ws_bytes,
+                    lay.total);
+    hipStream_t stream = (hipStream_t)hip_stream;
+    for (int32_t i = 0; i < n; ++i) {
+        const vd_sim *s = sims[i];
+        if (!s) return fail(VD_EINVAL, "simulation %d is NULL", i);
+        if (s->batch) return fail(VD_ESTATE, "simulation %d already belongs to a batch", i);
+        if (s->broken) return fail(VD_ESTATE, "simulation %d is unusable", i);
+        if (s->cfg.label != VD_LABEL_ID32)
+            return fail(VD_EINVAL, "batches take ID-label simulations (simulation %d)", i);
+        if (s->cfg.metric != sims[0]->cfg.metric)
+            return fail(VD_EINVAL, "all simulations of a batch share one metric");
+        if (s->stream != stream)
+            return fail(VD_EINVAL, "simulation %d runs on another stream than the batch", i);
+        for (int32_t j = 0; j < i; ++j)
+            if (sims[j] == s) return fail(VD_EINVAL, "simulation %d appears twice", i);
+    }
+    vd_batch *b = new (std::nothrow) vd_batch;
+    if (!b) return fail(VD_ENOMEM, "host allocation of the batch failed");
+    b->sims.assign(sims, sims + n);
+    b->stream = stream;
+    b->lay = lay;
+    b->metric = sims[0]->cfg.metric;
+    b->base = (uint8_t *)(((uintptr_t)dev_workspace + 255) / 256 * 256);
+
+    // host images of the device tables
+    std::vector<vd::BatchSim> hs((size_t)n);
+    std::vector<vd::DevState> hst((size_t)n);
+    std::vector<vd::LevelInfo> hinfo[2];
+    std::vector<vd::LevelSim> hls[2];
+    std::vector<int32_t> hnp[2];
+    for (int32_t i = 0; i < n; ++i) {
+        const vd_sim *s = sims[i];
+        vd::BatchSim &d = hs[(size_t)i];
+        memset(&d, 0, sizeof d);
+        d.map[0] = s->map[0];
+        d.map[1] = s->map[1];
+        d.table = s->pos;
+        d.W = s->cfg.width;
+        d.H = s->cfg.height;
+        d.S = s->cfg.num_seeds;
+        d.lo = s->cfg.disp_lo;
+        d.span = (uint32_t)(s->cfg.disp_hi - s->cfg.disp_lo + 1);
+        d.move_seed = s->move_seed;
+        hst[(size_t)i] = vd::DevState{s->cur, 0, (uint64_t)s->t};
+    }
+    for (int m = 0; m < 2; ++m) {
+        int32_t levels = 0;
+        for (vd_sim *s : b->sims)
+            levels = std::max<int32_t>(levels, (int32_t)(m ? s->djfa_passes : s->jfa_passes).size());
+        if (levels > vd::kMaxLevels) {
+            delete b;
+            return fail(VD_EINVAL, "too many passes per step (%d)", levels);
+        }
+        b->levels[m] = levels;
+        hinfo[m].assign(vd::kMaxLevels, vd::LevelInfo{});
+        hls[m].assign((size_t)vd::kMaxLevels * n, vd::LevelSim{});
+        hnp[m].resize((size_t)n);
+        b->level_pixels[m].assign(vd::kMaxLevels, 0);
+        for (int32_t lvl = 0; lvl < levels; ++lvl) {
+            uint32_t first = 0;
+            for (int32_t i = 0; i < n; ++i) {
+                const vd_sim *s = sims[i];
+                const std::vector<vd::Pass> &ps = m ? s->djfa_passes : s->jfa_passes;
+                vd::LevelSim &e = hls[m][(size_t)lvl * n + i];
+                e.first = first;
+                if (lvl < (int32_t)ps.size()) {
+                    e.k = ps[(size_t)lvl].k;
+                    e.vn = ps[(size_t)lvl].vn;
+                    const vd::ItemGrid ig = vd::item_grid(s->cfg.width, s->cfg.height, e.k);
+                    e.g = ig.g;
+                    e.per = ig.per;
+                    if (ig.items == 0 || (uint64_t)first + ig.items > 0xFFFFFFF0ull) {
+                        delete b;
+                        return fail(VD_EINVAL, "level %d of the batch is too large", lvl);
+                    }
+                    first += ig.items;
+                    b->level_pixels[m][(size_t)lvl] +=
+                        (int64_t)s->cfg.width * s->cfg.height;
+                }
+            }
+            vd::LevelInfo &li = hinfo[m][(size_t)lvl];
+            li.total = first;
+            for (int c = 0; c <= 8; ++c) li.chunk[c] = (uint32_t)((uint64_t)first * c / 8);
+        }
+        for (int32_t i = 0; i < n; ++i)
+            hnp[m][(size_t)i] = (int32_t)(m ? sims[i]->djfa_passes : sims[i]->jfa_passes).size();
+    }
+    hipError_t e = hipMemcpyAsync(b->base + lay.sims, hs.data(), sizeof(vd::BatchSim) * n,
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->base + lay.state, hst.data(), sizeof(vd::DevState) * n,
+                           hipMemcpyHostToDevice, stream);
+    for (int m = 0; m < 2 && e == hipSuccess; ++m) {
+        e = hipMemcpyAsync(b->base + lay.info[m], hinfo[m].data(),
+                           sizeof(vd::LevelInfo) * vd::kMaxLevels, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->base + lay.ls[m], hls[m].data(),
+                               sizeof(vd::LevelSim) * hls[m].size(), hipMemcpyHostToDevice,
+                               stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->base + lay.npasses[m], hnp[m].data(), sizeof(int32_t) * n,
+                               hipMemcpyHostToDevice, stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);   // the host images are locals
+    if (e != hipSuccess) {
+        delete b;
+        return fail(VD_EDEVICE, "uploading the batch tables failed: %s", hipGetErrorString(e));
+    }
+    int r = query_fit(b);
+    if (r) {
+        delete b;
+        return r;
+    }
+    b->grid[0] = b->grid[1] = grid_for(b, 0);
+    for (vd_sim *s : b->sims) s->batch = b;
+    *out = b;
+    return VD_OK;
+}
+
+int vd_batch_step(vd_batch *b, int32_t mode, int32_t move)
+{
+    if (!b) return fail(VD_EINVAL, "batch is NULL");
+    if (b->broken) return fail(VD_ESTATE, "batch unusable after an earlier device error");
+    if (mode != VD_STEP_JFA && mode != VD_STEP_DJFA)
+        return fail(VD_EINVAL, "mode must be VD_STEP_JFA or VD_STEP_DJFA, got %d", mode);
+    const int moved = move ? 1 : 0;
+    size_t slot = 0;
+    int r = batch_record(b, 1, true, &slot);
+    if (r) return r;
+    if (b->use_graph) {
+        hipGraphExec_t &g = b->graph[mode][moved];
+        if (!g) {
+            hipGraph_t graph = nullptr;
+            const bool was_timing = b->timing;
+            b->timing = false;   // no event nodes inside the graph
+            hipError_t e = hipSuccess;
+            if (!b->capture) e = hipStreamCreateWithFlags(&b->capture, hipStreamNonBlocking);
+            if (e == hipSuccess)
+                e = hipStreamBeginCapture(b->capture, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) {
+                b->timing = was_timing;
+                return fail(VD_EDEVICE, "hipStreamBeginCapture failed: %s", hipGetErrorString(e));
+            }
+            r = enqueue_step(b, mode, moved, b->capture);
+            e = hipStreamEndCapture(b->capture, &graph);
+            b->timing = was_timing;
+            if (r == VD_OK && e != hipSuccess)
+                r = fail(VD_EDEVICE, "hipStreamEndCapture failed: %s", hipGetErrorString(e));
+            if (r == VD_OK) {
+                e = hipGraphInstantiate(&g, graph, nullptr, nullptr, 0);
+                if (e != hipSuccess)
+                    r = fail(VD_EDEVICE, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+            }
+            if (graph) (void)hipGraphDestroy(graph);
+            if (r) {
+                g = nullptr;
+                b->broken = true;
+                return r;
+            }
+        }
+        hipError_t e = hipGraphLaunch(g, b->stream);
+        if (e != hipSuccess) {
+            b->broken = true;
+            return fail(VD_EDEVICE, "hipGraphLaunch failed: %s", hipGetErrorString(e));
+        }
+    } else {
+        r = enqueue_step(b, mode, moved, b->stream);
+        if (r) {
+            b->broken = true;
+            return r;
+        }
+    }
+    r = batch_record(b, 1, false, &slot);
+    if (r) return r;
+    for (vd_sim *s : b->sims) {   // host mirror of the device-side state
+        const size_t np = (mode == VD_STEP_DJFA ? s->djfa_passes : s->jfa_passes).size();
+        s->cur ^= (int)(np & 1);
+        s->t += moved;
+    }
+    if (b->timing && b->used >= 4096) return batch_harvest(b);
+    return VD_OK;
+}
+
+int vd_batch_set_graph(vd_batch *b, int enable)
+{
+    if (!b) return fail(VD_EINVAL, "batch is NULL");
+    b->use_graph = enable != 0;
+    if (!b->use_graph) drop_graphs(b);
+    return VD_OK;
+}
+
+int vd_batch_set_shape(vd_batch *b, int32_t wg_per_cu)
+{
+    if (!b) return fail(VD_EINVAL, "batch is NULL");
+    if (wg_per_cu < 0 || wg_per_cu > 64)
+        return fail(VD_EINVAL, "wg_per_cu must be in [0, 64], got %d", wg_per_cu);
+    b->grid[0] = b->grid[1] = grid_for(b, wg_per_cu);
+    drop_graphs(b);   // the grid is baked into captured launches
+    return VD_OK;
+}
+
+int vd_batch_autotune(vd_batch *b, int32_t reps)
+{
+    if (!b) return fail(VD_EINVAL, "batch is NULL");
+    if (b->broken) return fail(VD_ESTATE, "batch unusable after an earlier device error");
+    if (reps < 1 || reps > 1000) return fail(VD_EINVAL, "reps must be in [1, 1000], got %d", reps);
+    std::vector<int32_t> cand;
+    for (int32_t w : {1, 2, 4, 8, 0}) {
+        int32_t g = grid_for(b, w);
+        if (std::find(cand.begin(), cand.end(), g) == cand.end()) cand.push_back(g);
+    }
+    uint32_t *ctr = at<uint32_t>(b, b->lay.ctr);
+    for (int mode = 0; mode < 2; ++mode) {
+        if (b->levels[mode] == 0) continue;
+        std::vector<hipEvent_t> ev(2 * cand.size(), nullptr);
+        int r = VD_OK;
+        for (hipEvent_t &e : ev)
+            if (hipEventCreate(&e) != hipSuccess) r = fail(VD_EDEVICE, "hipEventCreate failed");
+        for (size_t c = 0; r == VD_OK && c <= cand.size(); ++c) {
+            // c == 0 is a warm-up of the first candidate, untimed
+            const size_t ci = c == 0 ? 0 : c - 1;
+            hipError_t e = c ? hipEventRecord(ev[2 * ci], b->stream) : hipSuccess;
+            for (int32_t k = 0; k < reps && e == hipSuccess; ++k)
+                for (int32_t lvl = 0; lvl < b->levels[mode] && e == hipSuccess; ++lvl) {
+                    hipLaunchKernelGGL(vd::k_batch_begin, dim3(1), dim3(vd::kBlock), 0,
+                                       b->stream, ctr, 8 * vd::kMaxLevels);
+                    e = hipGetLastError();
+                    if (e == hipSuccess) e = launch_level(b, mode, lvl, 0, cand[ci], b->stream);
+                }
+            if (e == hipSuccess && c) e = hipEventRecord(ev[2 * ci + 1], b->stream);
+            if (e != hipSuccess)
+                r = fail(VD_EDEVICE, "batch autotune launch failed: %s", hipGetErrorString(e));
+        }
+        if (r == VD_OK && hipStreamSynchronize(b->stream) != hipSuccess)
+            r = fail(VD_EDEVICE, "hipStreamSynchronize failed");
+        if (r == VD_OK) {
+            float best = 1e30f;
+            for (size_t c = 0; c < cand.size(); ++c) {
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, ev[2 * c], ev[2 * c + 1]) == hipSuccess &&
+                    ms < best) {
+                    best = ms;
+                    b->grid[mode] = cand[c];
+                }
+            }
+        }
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+        if (r) return r;
+    }
+    drop_graphs(b);
+    return VD_OK;
+}
+
+int vd_batch_set_timing(vd_batch *b, int enable)
+{
+    if (!b) return fail(VD_EINVAL, "batch is NULL");
+    if (b->used) {
+        VD_HIP(hipStreamSynchronize(b->stream));
+        b->used = 0;
+    }
+    b->timing = enable != 0;
+    memset(&b->acc, 0, sizeof b->acc);
+    return VD_OK;
+}
+
+int vd_batch_get_timing(vd_batch *b, vd_timing *out)
+{
+    if (!b || !out) return fail(VD_EINVAL, "NULL argument");
+    int r = batch_harvest(b);
+    if (r) return r;
+    *out = b->acc;
+    memset(&b->acc, 0, sizeof b->acc);
+    return VD_OK;
+}
+
+int vd_batch_info(const vd_batch *b, int32_t *levels_jfa, int32_t *levels_djfa, int32_t *grid)
+{
+    if (!b) return fail(VD_EINVAL, "batch is NULL");
+    if (levels_jfa) *levels_jfa = b->levels[VD_STEP_JFA];
+    if (levels_djfa) *levels_djfa = b->levels[VD_STEP_DJFA];
+    if (grid) *grid = b->grid[VD_STEP_DJFA];
+    return VD_OK;
+}
+
+void vd_batch_destroy(vd_batch *b)
+{
+    if (!b) return;
+    (void)hipStreamSynchronize(b->stream);
+    drop_graphs(b);
+    for (vd::EventPair &p : b->pool) {
+        if (p.a) (void)hipEventDestroy(p.a);
+        if (p.b) (void)hipEventDestroy(p.b);
+    }
+    for (vd_sim *s : b->sims) s->batch = nullptr;
+    if (b->capture) (void)hipStreamDestroy(b->capture);
+    delete b;
+}
+
+}  // extern "C"

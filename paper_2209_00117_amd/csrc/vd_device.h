@@ -1,0 +1,407 @@
+// Device building blocks of the vdflood kernels (included by the kernel
+// translation units; everything has internal linkage).
+//
+// Flood pass (Sec. III, Table I; Sec. V-B, Alg. 1).  The paper's kernel has
+// each pixel push its seed into its neighbours in place, which races when
+// two pixels push into one.  Here each pixel gathers from the symmetric
+// neighbourhood instead and the pass reads one buffer and writes the other,
+// so the result is a function of the input map alone.
+//
+// Candidate order.  A candidate is the pair (d, label) with d the distance
+// from the pixel to the label's seed; the smaller d wins and a tie goes to
+// the smaller label.  Both are packed into one 64-bit key, d in the high
+// word, and the key is minimised as an IEEE double: for a non-negative high
+// word below 0x7FF00000 (no NaN or infinity patterns) doubles order exactly
+// like their bit patterns read as unsigned integers, denormals included,
+// so one v_min_f64 replaces a 64-bit compare and two selects.  Squared
+// distances stay below 2^31 - 2^20 because grid sides are at most 16368 and
+// the sentinel position is (-16384, -16384).  An unclaimed pixel carries
+// label 0 in both modes, whose position is the sentinel: it is farther from
+// every pixel than any seed, so an unclaimed candidate never beats a
+// claimed one, and if every candidate is unclaimed the result is label 0,
+// unclaimed.  The kernels are built without IEEE mode and with denormals
+// kept (the code object's default), so v_min_f64 is exact on these keys.
+//
+// Distances are computed on packed 16-bit coordinates: one v_pk_sub_i16
+// gives (dx, dy) and one v_dot2 gives dx*dx + dy*dy exactly in int32.
+#pragma once
+
+#include <utility>
+
+#include "vd_kernels.h"
+
+typedef int32_t vd_i32x4 __attribute__((ext_vector_type(4)));
+
+// Indexed (structured) buffer load: address = base + index * stride.
+__device__ uint32_t vd_struct_buffer_load(vd_i32x4 rsrc, int32_t vindex, int32_t voffset,
+                                          int32_t soffset, int32_t aux)
+    __asm("llvm.amdgcn.struct.buffer.load.i32");
+
+namespace vd {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kTW = 256;           // flood pass: columns per workgroup (one per thread)
+constexpr int kMaxSegRows = 32;    // flood pass: rows of one chain segment, at most
+constexpr int kLdsRow = kTW + 2 * kMaxLdsStep;   // entries of one shared row
+constexpr int32_t kRsrcWord3 = 0x00020000;   // buffer descriptor word 3 on gfx9 parts
+
+typedef short short2_t __attribute__((ext_vector_type(2)));
+typedef vd_i32x4 i32x4;
+
+
+__device__ __forceinline__ int64_t pixel_of(uint32_t p, int32_t W)
+{
+    return (int64_t)((int32_t)(p >> 16) - (int32_t)kOff) * W +
+           ((int32_t)(p & 0xFFFFu) - (int32_t)kOff);
+}
+
+// splitmix64 (Steele, Lea and Flood, OOPSLA 2014): output n of the stream
+// seeded with s is mix64(s + (n + 1) * gamma); Stafford's variant-13 mixer.
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ int32_t draw(uint64_t seed, uint64_t n, int32_t lo, uint32_t span)
+{
+    uint64_t r = mix64(seed + (n + 1) * 0x9E3779B97F4A7C15ull);
+    return lo + (int32_t)(((r >> 32) * (uint64_t)span) >> 32);
+}
+
+// ---------------------------------------------------------------------------
+// Flood pass.
+//
+// Residue-chain schedule.  At step k, output row y reads input rows y - k,
+// y and y + k, which all lie on the chain of rows congruent to y mod k.  A
+// workgroup owns 256 adjacent columns of a segment of one chain and walks it
+// downwards with a window of three input rows held in registers, so each
+// input row is fetched once per segment (plus two rows of overlap between
+// segments) whatever k is.  The next row is requested one iteration ahead.
+// Horizontal neighbours (x - k, x + k) are separate loads of the same row;
+// for k < 256 they fall in lines the workgroup fetches anyway, for larger k
+// in lines the workgroups of the neighbouring column tiles fetch.
+//
+// Buffer addressing.  Each row is read through its own buffer descriptor
+// (base = row start, size = one row; size 0 for a row off the grid), with
+// per-lane byte offsets 4(x - k), 4x, 4(x + k) fixed for the whole walk.
+// The hardware returns 0 -- the unclaimed label -- for any offset outside
+// the row, so off-grid neighbours need no compare, and stores from lanes
+// past the right edge are dropped the same way.  ID labels fetch their
+// position with an indexed buffer load from the seed table (stride 4).
+//
+// XCD-aware block order.  Workgroups are dispatched round-robin over the 8
+// XCDs (block b goes to XCD b % 8).  Block b is given logical tile
+// xcd * (blocks / 8) + b / 8, so each XCD walks one contiguous run of
+// logical tiles (chain-major, column-minor): horizontal neighbours and the
+// overlap rows of consecutive segments are then fetched by the same XCD,
+// close in time, and hit its L2.
+// ---------------------------------------------------------------------------
+struct Ent {
+    uint32_t l;   // label
+    uint32_t s;   // its seed's packed position
+};
+
+struct Row {
+    Ent w, c, e;  // columns x - k, x, x + k
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const uint32_t *base, int32_t y,
+                                                           int32_t W, int32_t H)
+{
+    const bool in = y >= 0 && y < H;
+    const uint32_t *p = base + (in ? (int64_t)y * W : 0);
+    return __builtin_amdgcn_make_buffer_rsrc((void *)p, 0, in ? W * 4 : 0, kRsrcWord3);
+}
+
+// Labels of one row (columns x - k, x, x + k); off-grid reads return 0.
+__device__ __forceinline__ void load_labels(Row &row, const uint32_t *src, int32_t y, int32_t W,
+                                            int32_t H, int32_t ow, int32_t oc, int32_t oe)
+{
+    __amdgpu_buffer_rsrc_t r = row_rsrc(src, y, W, H);
+    row.w.l = __builtin_amdgcn_raw_buffer_load_b32(r, ow, 0, 0);
+    row.c.l = __builtin_amdgcn_raw_buffer_load_b32(r, oc, 0, 0);
+    row.e.l = __builtin_amdgcn_raw_buffer_load_b32(r, oe, 0, 0);
+}
+
+// Position of an ID label: an indexed load from the seed table (entry 0,
+// the unclaimed label, is the sentinel) -- unless the same column k rows
+// up carried the same label, whose position is reused.  In a converged map
+// most labels repeat down a column, so most lanes skip the lookup.
+__device__ __forceinline__ uint32_t seed_pos(uint32_t l, uint32_t prev_l, uint32_t prev_s,
+                                             i32x4 tab)
+{
+    uint32_t p = prev_s;
+    if (l != prev_l) p = vd_struct_buffer_load(tab, (int32_t)l, 0, 0, 0);
+    return p;
+}
+
+// Seed positions of a row's labels; `up` is the row k above on the chain
+// (or a row of unclaimed labels).  XY labels are positions already.
+template <int LABEL>
+__device__ __forceinline__ void lookup_positions(Row &row, const Row &up, i32x4 tab)
+{
+    if (LABEL == kLabelId) {
+        row.w.s = seed_pos(row.w.l, up.w.l, up.w.s, tab);
+        row.c.s = seed_pos(row.c.l, up.c.l, up.c.s, tab);
+        row.e.s = seed_pos(row.e.l, up.e.l, up.e.s, tab);
+    } else {
+        row.w.s = row.w.l;
+        row.c.s = row.c.l;
+        row.e.s = row.e.l;
+    }
+}
+
+// f(integral_constant<int, 0>, ..., integral_constant<int, N - 1>): a loop
+// body instantiated N times with compile-time indices.
+template <class F, int... I>
+__device__ __forceinline__ bool expand_impl(F &f, std::integer_sequence<int, I...>)
+{
+    return f(std::integral_constant<int, I>{}...);
+}
+
+template <int N, class F>
+__device__ __forceinline__ bool expand(F &f)
+{
+    return expand_impl(f, std::make_integer_sequence<int, N>{});
+}
+
+template <int METRIC>
+__device__ __forceinline__ double cand_key(uint32_t p, const Ent &e)
+{
+    short2_t dv = __builtin_bit_cast(short2_t, p) - __builtin_bit_cast(short2_t, e.s);
+    int32_t d;
+    if (METRIC == kEuclid)
+        d = __builtin_amdgcn_sdot2(dv, dv, 0, false);
+    else
+        d = abs((int32_t)dv.x) + abs((int32_t)dv.y);
+    return __hiloint2double(d, (int32_t)e.l);
+}
+
+// Output row y from the window a (row y - k), b (row y), c (row y + k).
+template <int METRIC, int VN>
+__device__ __forceinline__ void emit(uint32_t *dst, const Row &a, const Row &b, const Row &c,
+                                     int32_t y, int32_t k, int32_t W, int32_t H, uint32_t px,
+                                     int32_t oc)
+{
+    uint32_t p = ((uint32_t)(y + (int32_t)kOff) << 16) | px;
+    double best = cand_key<METRIC>(p, b.c);
+    best = __builtin_fmin(best, cand_key<METRIC>(p, b.w));
+    best = __builtin_fmin(best, cand_key<METRIC>(p, b.e));
+    if (y >= k) {
+        best = __builtin_fmin(best, cand_key<METRIC>(p, a.c));
+        if (!VN) {
+            best = __builtin_fmin(best, cand_key<METRIC>(p, a.w));
+            best = __builtin_fmin(best, cand_key<METRIC>(p, a.e));
+        }
+    }
+    if (y + k < H) {
+        best = __builtin_fmin(best, cand_key<METRIC>(p, c.c));
+        if (!VN) {
+            best = __builtin_fmin(best, cand_key<METRIC>(p, c.w));
+            best = __builtin_fmin(best, cand_key<METRIC>(p, c.e));
+        }
+    }
+    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)__double2loint(best), row_rsrc(dst, y, W, H),
+                                          oc, 0, 0);
+}
+
+struct Tile {
+    int32_t x0;        // first column
+    int32_t y0;        // first output row
+    int32_t j0, jend;  // chain indices of the segment's rows
+};
+
+__device__ __forceinline__ Tile decode_tile(uint32_t logical, const FloodGrid &g, int32_t k,
+                                            int32_t H)
+{
+    // The integer divisions run on the vector unit; readfirstlane tells
+    // the compiler the results are wave-uniform, so every row address and
+    // buffer descriptor derived from them stays scalar.
+    const uint32_t col = __builtin_amdgcn_readfirstlane(logical % g.ncol);
+    const uint32_t rs = logical / g.ncol;
+    const int32_t seg = __builtin_amdgcn_readfirstlane((int32_t)(rs % g.nseg));
+    const int32_t r = __builtin_amdgcn_readfirstlane((int32_t)(rs / g.nseg));   // rows r, r + k, ...
+    const int32_t nj = (H - 1 - r) / k + 1;                                      // rows on the chain
+    Tile t;
+    t.x0 = (int32_t)col * kTW;
+    t.j0 = seg * g.L;
+    t.jend = min(t.j0 + g.L, nj);
+    t.y0 = r + t.j0 * k;
+    return t;
+}
+
+// Block b of a launch -> logical tile: each XCD (block b runs on XCD b % 8)
+// gets one contiguous run of tiles.
+__device__ __forceinline__ uint32_t xcd_logical(uint32_t b, uint32_t nblocks)
+{
+    const uint32_t q = nblocks >> 3, rem = nblocks & 7u, xcd = b & 7u;
+    return xcd * q + min(xcd, rem) + (b >> 3);
+}
+
+// Indexed descriptor of a seed table with S + 1 entries of 4 bytes.
+__device__ __forceinline__ i32x4 table_rsrc(const uint32_t *table, uint32_t S)
+{
+    const uint64_t ta = (uint64_t)table;
+    return i32x4{(int32_t)(uint32_t)ta, (int32_t)(((uint32_t)(ta >> 32) & 0xFFFFu) | (4u << 16)),
+                 (int32_t)(S + 1), kRsrcWord3};
+}
+
+// One tile of a pass: 256 columns of one segment of one chain, walked with
+// a three-row register window (see the note above).
+template <int LABEL, int METRIC, int VN, int P>
+__device__ __forceinline__ void flood_chain_tile(const uint32_t *src, uint32_t *dst, i32x4 tab,
+                                                 int32_t W, int32_t H, int32_t k,
+                                                 const FloodGrid &g, uint32_t logical)
+{
+    const Tile tl = decode_tile(logical, g, k, H);
+    int32_t j = tl.j0;
+    if (j >= tl.jend) return;
+    const int32_t jend = tl.jend;
+    const int32_t x = tl.x0 + (int32_t)threadIdx.x;
+    const uint32_t px = (uint32_t)(x + (int32_t)kOff);
+    const int32_t ow = 4 * (x - k), oc = 4 * x, oe = 4 * (x + k);
+    int32_t y = tl.y0;
+
+    // NR row registers rotate through the roles: at unrolled step u, slot
+    // (u + m + 1) % NR holds row y + m*k for m = -1 .. P.  Labels are
+    // requested P + 1 rows ahead of the output row and their positions P
+    // rows ahead, so neither load is waited for in the step that issues it.
+    // The loop is unrolled NR times, so no row is ever copied.
+    constexpr int NR = P + 3;
+    Row R[NR];
+#pragma unroll
+    for (int m = -1; m <= P; ++m) load_labels(R[m + 1], src, y + m * k, W, H, ow, oc, oe);
+    const Row none = {{kEmpty, 0u}, {kEmpty, 0u}, {kEmpty, 0u}};   // label 0 -> sentinel 0
+    lookup_positions<LABEL>(R[0], none, tab);
+#pragma unroll
+    for (int m = 0; m < P; ++m) lookup_positions<LABEL>(R[m + 1], R[m], tab);
+    // One output row with the slots of unrolled step U; false once the
+    // segment is done.
+    auto step = [&](auto U) -> bool {
+        constexpr int u = decltype(U)::value;
+        if (j >= jend) return false;
+        load_labels(R[(u + NR - 1) % NR], src, y + (P + 1) * k, W, H, ow, oc, oe);
+        lookup_positions<LABEL>(R[(u + NR - 2) % NR], R[(u + NR - 3) % NR], tab);
+        emit<METRIC, VN>(dst, R[u % NR], R[(u + 1) % NR], R[(u + 2) % NR], y, k, W, H, px, oc);
+        ++j;
+        y += k;
+        return true;
+    };
+    auto round = [&](auto... U) -> bool { return (step(U) && ...); };
+    while (expand<NR>(round)) {
+    }
+}
+
+// Shared-row variant (steps k <= kMaxLdsStep).  The same chain walk, but the
+// 256 + 2k entries of each row that a workgroup needs (its columns plus k on
+// either side) are fetched once, one or two per thread, and exchanged
+// through LDS, where each thread reads its three (x - k, x, x + k).  A
+// thread therefore issues one or two label loads and, for ID labels, one or
+// two seed-table lookups per row instead of three of each.  Two LDS row
+// buffers alternate; the barrier of each exchange also orders the reuse of
+// the buffer written two exchanges earlier.
+struct Raw {
+    uint32_t l1, l2;   // labels of this thread's entries t and kTW + t
+    uint32_t s1, s2;   // their positions
+};
+
+struct Slot {
+    Raw raw;
+    Row win;
+};
+
+// One tile of a pass with shared rows; `lds` holds two rows of kLdsRow
+// entries.  Callers must not let a previous use of `lds` overlap the first
+// exchange (a barrier between tiles suffices).
+template <int LABEL, int METRIC, int VN, int P>
+__device__ __forceinline__ void flood_lds_tile(const uint32_t *src, uint32_t *dst, i32x4 tab,
+                                               int32_t W, int32_t H, int32_t k,
+                                               const FloodGrid &g, uint32_t logical,
+                                               uint2 (*lds)[kLdsRow])
+{
+    const Tile tl = decode_tile(logical, g, k, H);
+    int32_t j = tl.j0;
+    if (j >= tl.jend) return;
+    const int32_t jend = tl.jend;
+    const int32_t t = (int32_t)threadIdx.x;
+    const int32_t x0 = tl.x0;
+    const int32_t x = x0 + t;
+    const uint32_t px = (uint32_t)(x + (int32_t)kOff);
+    const int32_t oc = 4 * x;
+    // entry t is column x0 - k + t; entry kTW + t (only for t < 2k) is
+    // column x0 + kTW - k + t; an unused second entry reads out of range
+    const int32_t o1 = 4 * (x0 - k + t);
+    const bool has2 = t < 2 * k;
+    const int32_t o2 = has2 ? 4 * (x0 + kTW - k + t) : INT32_MIN;
+    const bool wave2 = __builtin_amdgcn_readfirstlane(t & ~63) < 2 * k;   // any lane of the wave
+    int32_t y = tl.y0;
+    int32_t exchanges = 0;
+
+    auto load = [&](Slot &sl, int32_t yy) {
+        __amdgpu_buffer_rsrc_t rr = row_rsrc(src, yy, W, H);
+        sl.raw.l1 = __builtin_amdgcn_raw_buffer_load_b32(rr, o1, 0, 0);
+        sl.raw.l2 = wave2 ? __builtin_amdgcn_raw_buffer_load_b32(rr, o2, 0, 0) : 0u;
+    };
+    // `up` holds the row k above on the chain; its positions are reused
+    // where the label repeats.
+    auto lookup = [&](Slot &sl, const Raw &up) {
+        if (LABEL == kLabelId) {
+            sl.raw.s1 = seed_pos(sl.raw.l1, up.l1, up.s1, tab);
+            sl.raw.s2 = wave2 ? seed_pos(sl.raw.l2, up.l2, up.s2, tab) : 0u;
+        } else {
+            sl.raw.s1 = sl.raw.l1;
+            sl.raw.s2 = sl.raw.l2;
+        }
+    };
+    auto exchange = [&](Slot &sl) {
+        uint2 *row = lds[exchanges & 1];
+        ++exchanges;
+        row[t] = make_uint2(sl.raw.l1, sl.raw.s1);
+        if (has2) row[kTW + t] = make_uint2(sl.raw.l2, sl.raw.s2);
+        __syncthreads();
+        const uint2 w = row[t], c = row[t + k], e = row[t + 2 * k];
+        sl.win.w.l = w.x;
+        sl.win.w.s = w.y;
+        sl.win.c.l = c.x;
+        sl.win.c.s = c.y;
+        sl.win.e.l = e.x;
+        sl.win.e.s = e.y;
+    };
+
+    // Ring of NR slots as in k_flood: slot (u + m + 1) % NR holds row
+    // y + m*k; labels are requested P + 1 rows ahead, positions P rows
+    // ahead, and the row entering the window (m = 1) is exchanged.
+    constexpr int NR = P + 3;
+    Slot R[NR];
+#pragma unroll
+    for (int m = -1; m <= P; ++m) load(R[m + 1], y + m * k);
+    const Raw none = {kEmpty, kEmpty, 0u, 0u};   // label 0 -> sentinel position 0
+    lookup(R[0], none);
+#pragma unroll
+    for (int m = 0; m < P; ++m) lookup(R[m + 1], R[m].raw);
+    exchange(R[0]);
+    exchange(R[1]);
+    auto step = [&](auto U) -> bool {
+        constexpr int u = decltype(U)::value;
+        if (j >= jend) return false;
+        load(R[(u + NR - 1) % NR], y + (P + 1) * k);
+        lookup(R[(u + NR - 2) % NR], R[(u + NR - 3) % NR].raw);
+        exchange(R[(u + 2) % NR]);
+        emit<METRIC, VN>(dst, R[u % NR].win, R[(u + 1) % NR].win, R[(u + 2) % NR].win, y, k, W,
+                         H, px, oc);
+        ++j;
+        y += k;
+        return true;
+    };
+    auto round = [&](auto... U) -> bool { return (step(U) && ...); };
+    while (expand<NR>(round)) {
+    }
+}
+
+}  // namespace
+
+}  // namespace vd

@@ -45,18 +45,47 @@ hipError_t launch_splat_xy(uint32_t *map, const uint32_t *table, int32_t S, int3
 hipError_t launch_move(uint32_t *table, int32_t S, int32_t W, int32_t H, uint64_t move_seed,
                        int64_t t, int32_t lo, int32_t hi, hipStream_t s);
 
-// XY labels after a move.  idx[old position of seed i] = lowest such i + 1
-// (old_table holds the positions the map refers to, sentinel first); then
-// every label, an old position, becomes the new position of that seed.
-// idx is a width*height scratch map; only entries at old positions are read.
-hipError_t launch_index_old(uint32_t *idx, const uint32_t *old_table, int32_t S, int32_t W,
-                            hipStream_t s);
-hipError_t launch_relabel(uint32_t *map, const uint32_t *idx, const uint32_t *table,
-                          int32_t S, int32_t W, int32_t H, hipStream_t s);
+// XY labels after a move.  idx[old position] = new position of the lowest
+// seed that sat there (old_table: the positions the map refers to, table:
+// the current ones, both sentinel first); then every label, an old position,
+// becomes idx of it.  idx is a width*height scratch map; only entries at old
+// positions are written or read.
+hipError_t launch_index_old(uint32_t *idx, const uint32_t *old_table, const uint32_t *table,
+                            int32_t S, int32_t W, hipStream_t s);
+hipError_t launch_relabel(uint32_t *map, const uint32_t *idx, int32_t W, int32_t H,
+                          hipStream_t s);
 
 // Internal labels to the external encoding of include/vdflood.h.
 hipError_t launch_export(const uint32_t *map, uint32_t *out, int64_t n, int32_t label,
                          hipStream_t s);
+
+// Tile decomposition of one flood pass: ncol column tiles of 256 x
+// min(k, H) chains (rows congruent mod k) x nseg segments of at most L rows,
+// numbered chain-major, column-minor; nblocks tiles in all.
+struct FloodGrid {
+    uint32_t ncol, nseg;
+    int32_t L;
+    uint32_t nblocks;
+};
+
+// Grid of a pass at step k >= 1 on a W x H map with segments of seg_rows
+// rows (<= 0: chosen from the map size); nblocks == 0 if too large.
+constexpr int kMaxTunedSegRows = 128;
+FloodGrid flood_grid(int32_t W, int32_t H, int32_t k, int32_t seg_rows);
+
+// Work items of a persistent (batched or served) pass: tiles of 32-row
+// segments (the batch gives parallelism, so segments need not be short),
+// grouped so that one item covers about 8192 output pixels even where
+// chains are short (large k).  Item i covers tiles [i*per, (i+1)*per).
+struct ItemGrid {
+    FloodGrid g;
+    uint32_t per;      // tiles per item
+    uint32_t items;
+};
+ItemGrid item_grid(int32_t W, int32_t H, int32_t k);
+
+// Largest step the shared-row (LDS) kernel handles.
+constexpr int kMaxLdsStep = 128;
 
 // One flood pass at step k: dst[p] = best of src[p] and src[p + o] over the
 // Moore (vn == 0) or Von Neumann (vn != 0) offsets o at distance k.
@@ -67,6 +96,6 @@ hipError_t launch_export(const uint32_t *map, uint32_t *out, int64_t n, int32_t 
 constexpr int kFloodVariants = 4;
 hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *table, int32_t S,
                         int32_t W, int32_t H, int32_t k, int32_t vn, int32_t label,
-                        int32_t metric, int32_t variant, hipStream_t s);
+                        int32_t metric, int32_t variant, int32_t seg_rows, hipStream_t s);
 
 }  // namespace vd

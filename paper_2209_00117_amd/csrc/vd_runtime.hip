@@ -4,13 +4,16 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
+#include <map>
+#include <mutex>
 #include <new>
+#include <string>
 #include <vector>
 
-#include "vd_kernels.h"
-#include "../../include/vdflood.h"
+#include "vd_sim.h"
 
-namespace {
+namespace vd {
 
 thread_local char g_err[512] = "";
 
@@ -22,6 +25,14 @@ int fail(int status, const char *fmt, ...)
     va_end(ap);
     return status;
 }
+
+}  // namespace vd
+
+using vd::fail;
+using vd::Pass;
+using vd::EventPair;
+
+namespace {
 
 #define VD_HIP(call)                                                                     \
     do {                                                                                 \
@@ -55,12 +66,6 @@ int32_t first_delta(int32_t W, int32_t H, int32_t S, int32_t dmax)
     return P < k1 ? (int32_t)P : k1;
 }
 
-struct Pass {
-    int32_t k;
-    int32_t vn;
-    int32_t variant;   // flood kernel variant (same result, different speed)
-};
-
 // Measured on MI355X: ID labels run fastest with rows shared through LDS
 // (fewer seed-table lookups), XY labels with the plain chain walk that
 // requests rows two ahead.
@@ -78,8 +83,8 @@ std::vector<Pass> schedule(int32_t first, int32_t vn_passes, int32_t extra, int3
     if (vn < 0) vn = 0;
     int32_t i = 0;
     for (int32_t k = first; k >= 1; k >>= 1, ++i)
-        out.push_back({k, i < vn ? 1 : 0, variant});
-    for (int32_t e = extra; e >= 1; --e) out.push_back({e, 0, variant});
+        out.push_back({k, i < vn ? 1 : 0, variant, 0});
+    for (int32_t e = extra; e >= 1; --e) out.push_back({e, 0, variant, 0});
     return out;
 }
 
@@ -123,32 +128,7 @@ size_t footprint(const vd_config *c)
     return b + kAlign;
 }
 
-struct EventPair {
-    hipEvent_t a = nullptr, b = nullptr;
-    int kind = 0;   // 0: flood pass, 1: whole step
-};
-
 }  // namespace
-
-struct vd_sim {
-    vd_config cfg{};
-    hipStream_t stream = nullptr;
-    int device = 0;
-    uint32_t *map[2] = {nullptr, nullptr};
-    int cur = 0;                 // map[cur] holds the current diagram
-    uint32_t *pos = nullptr;     // seed table: sentinel, then current positions
-    uint32_t *pos_map = nullptr; // XY mode: the table the diagram's labels refer to
-    int64_t t = 0;
-    int32_t dmax = 0;
-    int32_t k1 = 0, delta1 = 0;
-    uint64_t move_seed = 0;
-    std::vector<Pass> jfa_passes, djfa_passes;
-    bool timing = false;
-    std::vector<EventPair> pool;   // recorded pairs
-    size_t used = 0;
-    vd_timing acc{};
-    bool broken = false;
-};
 
 namespace {
 
@@ -199,7 +179,7 @@ int run_passes(vd_sim *s, const std::vector<Pass> &passes)
         if (r) return r;
         VD_HIP(vd::launch_flood(s->map[s->cur], s->map[s->cur ^ 1], s->pos, s->cfg.num_seeds,
                                 s->cfg.width, s->cfg.height, p.k, p.vn, s->cfg.label,
-                                s->cfg.metric, p.variant, s->stream));
+                                s->cfg.metric, p.variant, p.seg_rows, s->stream));
         r = record(s, 0, false, &slot);
         if (r) return r;
         s->cur ^= 1;
@@ -236,8 +216,8 @@ int do_djfa(vd_sim *s)
         // The idle ping-pong buffer serves as the old-position index; the
         // first flood pass overwrites it.
         uint32_t *idx = s->map[s->cur ^ 1];
-        VD_HIP(vd::launch_index_old(idx, s->pos_map, c.num_seeds, c.width, s->stream));
-        VD_HIP(vd::launch_relabel(cur, idx, s->pos, c.num_seeds, c.width, c.height, s->stream));
+        VD_HIP(vd::launch_index_old(idx, s->pos_map, s->pos, c.num_seeds, c.width, s->stream));
+        VD_HIP(vd::launch_relabel(cur, idx, c.width, c.height, s->stream));
         VD_HIP(vd::launch_splat_xy(cur, s->pos, c.num_seeds, c.width, s->stream));
     } else {
         VD_HIP(vd::launch_splat_id(cur, s->pos, c.num_seeds, c.width, s->stream));
@@ -254,6 +234,7 @@ int step(vd_sim *s, bool dynamic)
 {
     if (!s) return fail(VD_EINVAL, "sim is NULL");
     if (s->broken) return fail(VD_ESTATE, "simulation unusable after an earlier device error");
+    if (s->batch) return fail(VD_ESTATE, "simulation is driven by a batch (vd_batch_step)");
     size_t slot = 0;
     int r = record(s, 1, true, &slot);
     if (r) return r;
@@ -263,9 +244,186 @@ int step(vd_sim *s, bool dynamic)
     return r;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuning.  A pass's kernel variant and segment length change its speed,
+// never its output, so they can be chosen by timing.  Choices live in a
+// process-wide table keyed by (GPU architecture, grid, seed count, label,
+// metric, k, neighbourhood); simulations created later with the same key
+// start from them.  The table can be exported and imported as text.
+// ---------------------------------------------------------------------------
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int32_t, int32_t>> g_tune;   // key -> (variant, seg_rows)
+
+std::string arch_name()
+{
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+        return "unknown";
+    std::string a = prop.gcnArchName;
+    size_t colon = a.find(':');
+    return colon == std::string::npos ? a : a.substr(0, colon);
+}
+
+std::string tune_key(const std::string &arch, const vd_config &c, const Pass &p)
+{
+    char buf[192];
+    snprintf(buf, sizeof buf, "%s %dx%d S%d %s %s k%d %s", arch.c_str(), c.width, c.height,
+             c.num_seeds, c.label == VD_LABEL_XY16 ? "xy" : "id",
+             c.metric == VD_MANHATTAN ? "manhattan" : "euclid", p.k, p.vn ? "vn" : "moore");
+    return buf;
+}
+
+void apply_tuning(vd_sim *s)
+{
+    const std::string arch = arch_name();
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    for (std::vector<Pass> *ps : {&s->jfa_passes, &s->djfa_passes})
+        for (Pass &p : *ps) {
+            auto it = g_tune.find(tune_key(arch, s->cfg, p));
+            if (it != g_tune.end()) {
+                p.variant = it->second.first;
+                p.seg_rows = it->second.second;
+            }
+        }
+}
+
 }  // namespace
 
 extern "C" {
+
+int vd_autotune(vd_sim *s, int32_t reps)
+{
+    if (!s) return fail(VD_EINVAL, "sim is NULL");
+    if (s->broken) return fail(VD_ESTATE, "simulation unusable after an earlier device error");
+    if (reps < 1 || reps > 1000) return fail(VD_EINVAL, "reps must be in [1, 1000], got %d", reps);
+    const vd_config &c = s->cfg;
+    static const int32_t kSegRows[] = {0, 8, 16, 64};
+    struct Cand {
+        int32_t variant, seg_rows;
+    };
+    std::vector<Cand> cands;
+    for (int32_t v = 0; v < vd::kFloodVariants; ++v)
+        for (int32_t L : kSegRows) cands.push_back({v, L});
+    const std::string arch = arch_name();
+    // distinct passes of both schedules
+    std::vector<Pass *> todo;
+    std::vector<std::string> keys;
+    for (std::vector<Pass> *ps : {&s->jfa_passes, &s->djfa_passes})
+        for (Pass &p : *ps) {
+            std::string key = tune_key(arch, c, p);
+            if (std::find(keys.begin(), keys.end(), key) == keys.end()) {
+                keys.push_back(key);
+                todo.push_back(&p);
+            }
+        }
+    std::vector<hipEvent_t> ev(2 * cands.size() * todo.size(), nullptr);
+    int r = VD_OK;
+    for (hipEvent_t &e : ev)
+        if (hipEventCreate(&e) != hipSuccess) {
+            r = fail(VD_EDEVICE, "hipEventCreate failed");
+            break;
+        }
+    // Every candidate reads the current diagram and writes the idle buffer,
+    // so the simulation's state is unchanged.
+    for (size_t i = 0; r == VD_OK && i < todo.size(); ++i)
+        for (size_t j = 0; r == VD_OK && j < cands.size(); ++j) {
+            const Pass &p = *todo[i];
+            auto launch = [&]() {
+                return vd::launch_flood(s->map[s->cur], s->map[s->cur ^ 1], s->pos, c.num_seeds,
+                                        c.width, c.height, p.k, p.vn, c.label, c.metric,
+                                        cands[j].variant, cands[j].seg_rows, s->stream);
+            };
+            hipError_t e = launch();   // warm-up
+            size_t at = 2 * (i * cands.size() + j);
+            if (e == hipSuccess) e = hipEventRecord(ev[at], s->stream);
+            for (int32_t k = 0; k < reps && e == hipSuccess; ++k) e = launch();
+            if (e == hipSuccess) e = hipEventRecord(ev[at + 1], s->stream);
+            if (e != hipSuccess) r = fail(VD_EDEVICE, "autotune launch failed: %s",
+                                          hipGetErrorString(e));
+        }
+    if (r == VD_OK && hipStreamSynchronize(s->stream) != hipSuccess)
+        r = fail(VD_EDEVICE, "hipStreamSynchronize failed");
+    if (r == VD_OK) {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        for (size_t i = 0; i < todo.size(); ++i) {
+            float best = 1e30f;
+            Cand pick = {todo[i]->variant, todo[i]->seg_rows};
+            for (size_t j = 0; j < cands.size(); ++j) {
+                float ms = 0.f;
+                size_t at = 2 * (i * cands.size() + j);
+                if (hipEventElapsedTime(&ms, ev[at], ev[at + 1]) == hipSuccess && ms < best) {
+                    best = ms;
+                    pick = cands[j];
+                }
+            }
+            g_tune[keys[i]] = {pick.variant, pick.seg_rows};
+        }
+    }
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (r == VD_OK) apply_tuning(s);
+    return r;
+}
+
+int vd_tuning_export(char *buf, size_t cap, size_t *needed)
+{
+    std::string text;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        for (const auto &kv : g_tune) {
+            char line[256];
+            snprintf(line, sizeof line, "%s|%d|%d\n", kv.first.c_str(), kv.second.first,
+                     kv.second.second);
+            text += line;
+        }
+    }
+    if (needed) *needed = text.size() + 1;
+    if (!buf) return VD_OK;
+    if (cap < text.size() + 1)
+        return fail(VD_ENOMEM, "buffer of %zu bytes, the table needs %zu", cap, text.size() + 1);
+    memcpy(buf, text.c_str(), text.size() + 1);
+    return VD_OK;
+}
+
+int vd_tuning_import(const char *text)
+{
+    if (!text) return fail(VD_EINVAL, "text is NULL");
+    std::map<std::string, std::pair<int32_t, int32_t>> add;
+    const char *p = text;
+    while (*p) {
+        const char *end = strchr(p, '\n');
+        std::string line = end ? std::string(p, end) : std::string(p);
+        p = end ? end + 1 : p + line.size();
+        if (line.empty()) continue;
+        size_t a = line.find('|'), b = line.rfind('|');
+        if (a == std::string::npos || a == b)
+            return fail(VD_EINVAL, "malformed tuning line: %s", line.c_str());
+        int32_t variant = atoi(line.substr(a + 1, b - a - 1).c_str());
+        int32_t seg = atoi(line.substr(b + 1).c_str());
+        if (variant < 0 || variant >= vd::kFloodVariants || seg < 0 || seg > vd::kMaxTunedSegRows)
+            return fail(VD_EINVAL, "tuning values out of range: %s", line.c_str());
+        add[line.substr(0, a)] = {variant, seg};
+    }
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    for (const auto &kv : add) g_tune[kv.first] = kv.second;
+    return VD_OK;
+}
+
+int vd_get_tuning(const vd_sim *s, int32_t *variants, int32_t *seg_rows, int32_t cap)
+{
+    if (!s) return fail(VD_EINVAL, "sim is NULL");
+    int32_t n = (int32_t)(s->jfa_passes.size() + s->djfa_passes.size());
+    if (cap < n) return fail(VD_EINVAL, "need room for %d passes, got %d", n, cap);
+    int32_t i = 0;
+    for (const std::vector<Pass> *ps : {&s->jfa_passes, &s->djfa_passes})
+        for (const Pass &p : *ps) {
+            if (variants) variants[i] = p.variant;
+            if (seg_rows) seg_rows[i] = p.seg_rows;
+            ++i;
+        }
+    return VD_OK;
+}
 
 void vd_config_default(vd_config *cfg)
 {
@@ -341,6 +499,7 @@ int vd_init_sim(const vd_config *cfg, const int32_t *host_xy, void *dev_workspac
     s->djfa_passes = schedule(s->delta1, cfg->vn_passes, cfg->extra_passes,
                               default_variant(cfg->label));
     s->move_seed = mix64(cfg->sim_seed ^ 0x6D6F7665ull);
+    apply_tuning(s);
     hipError_t e = hipMemcpyAsync(s->pos, packed.data(), ((size_t)S + 1) * 4,
                                   hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);   // packed is a local buffer
@@ -361,6 +520,7 @@ int vd_move_seeds(vd_sim *s)
 {
     if (!s) return fail(VD_EINVAL, "sim is NULL");
     if (s->broken) return fail(VD_ESTATE, "simulation unusable after an earlier device error");
+    if (s->batch) return fail(VD_ESTATE, "simulation is driven by a batch (vd_batch_step)");
     s->t += 1;
     hipError_t e = vd::launch_move(s->pos, s->cfg.num_seeds, s->cfg.width, s->cfg.height,
                                    s->move_seed, s->t, s->cfg.disp_lo, s->cfg.disp_hi, s->stream);
@@ -456,7 +616,7 @@ int vd_get_timing(vd_sim *s, vd_timing *out)
 
 void vd_destroy(vd_sim *s)
 {
-    if (!s) return;
+    if (!s || s->batch) return;   // a batch member is released after vd_batch_destroy
     (void)hipStreamSynchronize(s->stream);
     for (EventPair &p : s->pool) {
         if (p.a) (void)hipEventDestroy(p.a);
@@ -477,6 +637,6 @@ int vd_set_flood_variant(vd_sim *s, int variant)
     return VD_OK;
 }
 
-const char *vd_last_error(void) { return g_err; }
+const char *vd_last_error(void) { return vd::g_err; }
 
 }  // extern "C"

@@ -1,0 +1,787 @@
+// Serving loop: time-step requests of many resident simulations, continuously
+// batched at flood-pass granularity.
+//
+// A request asks for one time step of one simulation (move, then a JFA or a
+// dJFA step); requests of one simulation run in submission order.  A
+// scheduler thread forms "ticks".  In a tick, every simulation that starts a
+// request joins (its move and seed splat run in two or three small batched
+// launches), and one persistent flood launch then runs the next pass of
+// every active simulation, each at its own pass index and step size, with
+// the same tile functions as the single-simulation kernels.  A simulation
+// that has run its last pass leaves; its request completes when the tick's
+// event fires.  New requests thus join at the next pass boundary instead of
+// waiting for running steps to finish, and ticks are enqueued back to back
+// (up to kRing in flight), so the work of many requests overlaps on the GPU.
+//
+// Memory: the caller hands the server one device pool.  The server keeps
+// its tick tables in it and places each simulation's workspace (two maps
+// and the seed table) with a first-fit allocator; a simulation is admitted
+// (made resident, with VD_0 computed) only when its footprint fits, and
+// waits in arrival order otherwise.  Removing a simulation frees its memory
+// and admits waiting ones.  A resident simulation keeps its positions and
+// current diagram on the device between requests: the state dJFA reuses.
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "vd_device.h"
+#include "vd_sim.h"
+
+namespace vd {
+
+namespace {
+
+constexpr int kRing = 16;   // tick tables in flight
+
+struct TickSim {            // one active simulation's pass in a tick
+    const uint32_t *src;
+    uint32_t *dst;
+    const uint32_t *table;
+    int32_t W, H, S, k, vn;
+    FloodGrid g;
+    uint32_t first;         // its first item in the tick's work list
+    uint32_t per;           // tiles per item
+    int32_t pad;
+};
+
+struct TickPrep {           // one simulation starting a request in a tick
+    uint32_t *map;          // its current diagram
+    uint32_t *table;
+    int32_t W, H, S, lo;
+    uint32_t span;
+    int32_t fill;           // JFA: clear the map first
+    uint64_t move_seed;
+    uint64_t t;             // the time step being entered (>= 1)
+};
+
+struct TickHeader {
+    uint32_t total;         // tiles in the flood launch
+    uint32_t chunk[9];      // XCD c drains tiles [chunk[c], chunk[c + 1]) first
+    uint32_t ctr[8];        // claim counters (zero when uploaded)
+    int32_t nactive, nprep;
+};
+
+__device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ uint32_t uni(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)v);
+}
+template <class T>
+__device__ __forceinline__ T *uni_ptr(T *p)
+{
+    const uint64_t v = (uint64_t)p;
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)v);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int32_t)(uint32_t)(v >> 32));
+    return (T *)(lo | (hi << 32));
+}
+
+__global__ void __launch_bounds__(kBlock) k_tick_fill(const TickPrep *__restrict__ prep)
+{
+    const TickPrep p = prep[blockIdx.y];
+    if (!p.fill) return;
+    const int64_t n = (int64_t)p.W * p.H;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p.map[i] = kEmpty;
+}
+
+// Moves seed i (as k_move) and marks its new pixel for the splat.
+__global__ void __launch_bounds__(kBlock) k_tick_move_reset(const TickPrep *__restrict__ prep)
+{
+    const TickPrep p = prep[blockIdx.y];
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < p.S;
+         i += gridDim.x * blockDim.x) {
+        uint64_t n = ((p.t - 1) * (uint64_t)p.S + (uint64_t)i) * 2u;
+        uint32_t q = p.table[i + 1];
+        int32_t x = (int32_t)(q & 0xFFFFu) - (int32_t)kOff + draw(p.move_seed, n + 0, p.lo, p.span);
+        int32_t y = (int32_t)(q >> 16) - (int32_t)kOff + draw(p.move_seed, n + 1, p.lo, p.span);
+        x = min(max(x, 0), p.W - 1);
+        y = min(max(y, 0), p.H - 1);
+        q = ((uint32_t)(y + (int32_t)kOff) << 16) | (uint32_t)(x + (int32_t)kOff);
+        p.table[i + 1] = q;
+        p.map[pixel_of(q, p.W)] = 0xFFFFFFFFu;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_tick_splat_min(const TickPrep *__restrict__ prep)
+{
+    const TickPrep p = prep[blockIdx.y];
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < p.S;
+         i += gridDim.x * blockDim.x)
+        atomicMin(&p.map[pixel_of(p.table[i + 1], p.W)], (uint32_t)(i + 1));
+}
+
+template <int METRIC>
+__global__ void __launch_bounds__(kTW) k_tick_flood(TickHeader *__restrict__ hd,
+                                                    const TickSim *__restrict__ sims)
+{
+    __shared__ uint2 lds[2][kLdsRow];
+    __shared__ uint32_t s_item;
+    const uint32_t home = blockIdx.x & 7u;
+    const int32_t n = uni(hd->nactive);
+    uint32_t probe = 0;
+    for (;;) {
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t item = 0xFFFFFFFFu;
+            while (probe < 8u) {
+                const uint32_t c = (home + probe) & 7u;
+                const uint32_t lo = hd->chunk[c], hi = hd->chunk[c + 1];
+                const uint32_t i = lo < hi ? atomicAdd(&hd->ctr[c], 1u) : 0xFFFFFFFFu;
+                if (i < hi - lo) {
+                    item = lo + i;
+                    break;
+                }
+                ++probe;
+            }
+            s_item = item;
+        }
+        __syncthreads();
+        const uint32_t item = uni(s_item);
+        if (item == 0xFFFFFFFFu) return;
+        int32_t a = 0, b = n;
+        while (b - a > 1) {
+            const int32_t m = (a + b) >> 1;
+            if (uni(sims[m].first) <= item) a = m; else b = m;
+        }
+        const TickSim &ts = sims[a];
+        const int32_t k = uni(ts.k), vn = uni(ts.vn);
+        FloodGrid g;
+        g.ncol = uni(ts.g.ncol);
+        g.nseg = uni(ts.g.nseg);
+        g.L = uni(ts.g.L);
+        g.nblocks = uni(ts.g.nblocks);
+        const int32_t W = uni(ts.W), H = uni(ts.H), S = uni(ts.S);
+        const uint32_t *src = uni_ptr(ts.src);
+        uint32_t *dst = uni_ptr(ts.dst);
+        const i32x4 tab = table_rsrc(uni_ptr(ts.table), (uint32_t)S);
+        const uint32_t per = uni(ts.per);
+        const uint32_t t0 = (item - uni(ts.first)) * per;
+        const uint32_t t1 = min(t0 + per, g.nblocks);
+        for (uint32_t tile = t0; tile < t1; ++tile) {
+            if (tile != t0) __syncthreads();   // LDS of the previous tile is free
+            if (k <= kMaxLdsStep) {
+                if (vn)
+                    flood_lds_tile<kLabelId, METRIC, 1, 2>(src, dst, tab, W, H, k, g, tile, lds);
+                else
+                    flood_lds_tile<kLabelId, METRIC, 0, 2>(src, dst, tab, W, H, k, g, tile, lds);
+            } else {
+                if (vn)
+                    flood_chain_tile<kLabelId, METRIC, 1, 2>(src, dst, tab, W, H, k, g, tile);
+                else
+                    flood_chain_tile<kLabelId, METRIC, 0, 2>(src, dst, tab, W, H, k, g, tile);
+            }
+        }
+    }
+}
+
+size_t align_up(size_t v) { return (v + 255) / 256 * 256; }
+
+using Clock = std::chrono::steady_clock;
+
+double ms_between(Clock::time_point a, Clock::time_point b)
+{
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+}  // namespace
+
+}  // namespace vd
+
+using vd::fail;
+
+namespace {
+
+struct Request {
+    int64_t ticket;
+    int32_t mode;
+    vd::Clock::time_point submitted;
+};
+
+struct Served {
+    int32_t id = -1;
+    vd_config cfg{};
+    std::vector<int32_t> xy;      // initial positions, kept until admission
+    size_t bytes = 0, off = 0;
+    vd_sim *sim = nullptr;        // resident once admitted
+    bool removing = false;
+    std::deque<Request> fifo;     // waiting requests
+    bool active = false;          // a request is on the GPU
+    Request req{};
+    int32_t pass = 0, npasses = 0;
+    int32_t inflight = 0;         // enqueued ticks touching it, not yet finished
+};
+
+struct Tick {
+    hipEvent_t done = nullptr;
+    int slot = 0;
+    std::vector<std::pair<int32_t, Request>> completes;   // (sim id, request)
+    std::vector<int32_t> members;                         // simulations it touches
+    int64_t pixel_updates = 0;
+};
+
+struct Pool {                     // first-fit allocator over [0, size)
+    size_t size = 0;
+    std::map<size_t, size_t> free;   // offset -> length
+    bool alloc(size_t bytes, size_t *off)
+    {
+        for (auto it = free.begin(); it != free.end(); ++it)
+            if (it->second >= bytes) {
+                *off = it->first;
+                size_t rest = it->second - bytes, at = it->first + bytes;
+                free.erase(it);
+                if (rest) free[at] = rest;
+                return true;
+            }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        auto it = free.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free.erase(nx);
+        }
+        if (it != free.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free.erase(it);
+            }
+        }
+    }
+};
+
+}  // namespace
+
+struct vd_server {
+    int32_t max_sims = 0, metric = 0;
+    hipStream_t stream = nullptr;
+    uint8_t *base = nullptr;      // aligned device pool
+    size_t ring_bytes = 0;        // tick tables at the start of the pool
+    size_t slot_bytes = 0;
+    Pool pool;
+    uint8_t *host_ring = nullptr; // pinned staging, kRing slots
+    int grid = 0;
+    std::mutex mu;
+    std::condition_variable cv;   // new work or state change
+    std::condition_variable done_cv;
+    std::map<int32_t, Served> sims;
+    std::deque<int32_t> admit_queue;   // waiting for memory, in arrival order
+    std::vector<int32_t> order;   // resident ids in admission order (tick order)
+    int32_t next_id = 0;
+    int64_t next_ticket = 1;
+    std::map<int64_t, double> finished;    // ticket -> latency (ms), until collected
+    std::vector<double> latencies;         // since the last stats reset
+    int64_t submitted = 0, completed = 0, pixel_updates = 0, ticks = 0;
+    vd::Clock::time_point stats_t0 = vd::Clock::now();
+    std::deque<Tick> inflight;
+    bool stop = false;
+    int error = VD_OK;
+    char error_msg[256] = "";
+    std::thread worker;
+};
+
+namespace {
+
+size_t slot_size(int32_t max_sims)
+{
+    return vd::align_up(sizeof(vd::TickHeader)) +
+           vd::align_up(sizeof(vd::TickSim) * (size_t)max_sims) +
+           vd::align_up(sizeof(vd::TickPrep) * (size_t)max_sims);
+}
+
+// Called with mu held.  Admits waiting simulations in arrival order while
+// their footprints fit; VD_0 is computed by a full JFA on the stream.
+void admit(vd_server *sv)
+{
+    while (!sv->admit_queue.empty()) {
+        Served &s = sv->sims[sv->admit_queue.front()];
+        if (s.removing) {
+            sv->sims.erase(s.id);
+            sv->admit_queue.pop_front();
+            continue;
+        }
+        size_t off = 0;
+        if (!sv->pool.alloc(s.bytes, &off)) return;
+        vd_sim *sim = nullptr;
+        int r = vd_init_sim(&s.cfg, s.xy.data(), sv->base + off, s.bytes, sv->stream, &sim);
+        if (r != VD_OK) {
+            sv->pool.release(off, s.bytes);
+            sv->error = r;
+            snprintf(sv->error_msg, sizeof sv->error_msg, "admitting simulation %d: %s", s.id,
+                     vd_last_error());
+            return;
+        }
+        s.off = off;
+        s.sim = sim;
+        s.xy.clear();
+        s.xy.shrink_to_fit();
+        sv->order.push_back(s.id);
+        sv->admit_queue.pop_front();
+    }
+}
+
+// Completes every finished tick at the front of the queue (mu held).  Only
+// the scheduler thread calls it, so only it destroys tick events.
+void reap(vd_server *sv, bool wait_one)
+{
+    while (!sv->inflight.empty()) {
+        Tick &t = sv->inflight.front();
+        hipError_t q = wait_one ? hipEventSynchronize(t.done) : hipEventQuery(t.done);
+        wait_one = false;
+        if (q == hipErrorNotReady) return;
+        if (q != hipSuccess) {
+            sv->error = VD_EDEVICE;
+            snprintf(sv->error_msg, sizeof sv->error_msg, "tick failed: %s", hipGetErrorString(q));
+            return;
+        }
+        const vd::Clock::time_point now = vd::Clock::now();
+        for (auto &c : t.completes) {
+            double ms = vd::ms_between(c.second.submitted, now);
+            sv->finished[c.second.ticket] = ms;
+            sv->latencies.push_back(ms);
+            sv->completed += 1;
+        }
+        sv->pixel_updates += t.pixel_updates;
+        for (int32_t id : t.members) sv->sims[id].inflight -= 1;
+        (void)hipEventDestroy(t.done);
+        sv->inflight.pop_front();
+        sv->done_cv.notify_all();
+    }
+}
+
+// Builds and enqueues one tick (mu held).  Returns false if there is no work.
+bool tick(vd_server *sv)
+{
+    // start the next request of every idle resident simulation
+    std::vector<int32_t> joiners;
+    for (int32_t id : sv->order) {
+        Served &s = sv->sims[id];
+        if (!s.active && !s.fifo.empty() && !s.removing) {
+            s.req = s.fifo.front();
+            s.fifo.pop_front();
+            s.active = true;
+            s.pass = 0;
+            s.npasses = (int32_t)(s.req.mode == VD_STEP_DJFA ? s.sim->djfa_passes
+                                                             : s.sim->jfa_passes).size();
+            joiners.push_back(id);
+        }
+    }
+    std::vector<int32_t> active;
+    for (int32_t id : sv->order)
+        if (sv->sims[id].active) active.push_back(id);
+    if (active.empty()) return false;
+    if ((int)sv->inflight.size() >= vd::kRing) reap(sv, true);
+    if (sv->error) return false;
+    const int slot = (int)(sv->ticks % vd::kRing);
+    uint8_t *h = sv->host_ring + (size_t)slot * sv->slot_bytes;
+    uint8_t *d = sv->base + (size_t)slot * sv->slot_bytes;
+    vd::TickHeader *hh = (vd::TickHeader *)h;
+    vd::TickSim *hs = (vd::TickSim *)(h + vd::align_up(sizeof(vd::TickHeader)));
+    vd::TickPrep *hp = (vd::TickPrep *)(h + vd::align_up(sizeof(vd::TickHeader)) +
+                                       vd::align_up(sizeof(vd::TickSim) * sv->max_sims));
+    memset(hh, 0, sizeof *hh);
+    Tick t;
+    t.slot = slot;
+    for (int32_t id : active) {
+        t.members.push_back(id);
+        sv->sims[id].inflight += 1;
+    }
+    int32_t maxS = 1;
+    for (size_t j = 0; j < joiners.size(); ++j) {
+        Served &s = sv->sims[joiners[j]];
+        vd_sim *m = s.sim;
+        m->t += 1;
+        vd::TickPrep &p = hp[j];
+        memset(&p, 0, sizeof p);
+        p.map = m->map[m->cur];
+        p.table = m->pos;
+        p.W = m->cfg.width;
+        p.H = m->cfg.height;
+        p.S = m->cfg.num_seeds;
+        p.lo = m->cfg.disp_lo;
+        p.span = (uint32_t)(m->cfg.disp_hi - m->cfg.disp_lo + 1);
+        p.fill = s.req.mode == VD_STEP_JFA;
+        p.move_seed = m->move_seed;
+        p.t = (uint64_t)m->t;
+        maxS = std::max(maxS, p.S);
+    }
+    uint32_t first = 0;
+    int32_t na = 0;
+    for (int32_t id : active) {
+        Served &s = sv->sims[id];
+        vd_sim *m = s.sim;
+        if (s.pass < s.npasses) {
+            const vd::Pass &ps = (s.req.mode == VD_STEP_DJFA ? m->djfa_passes
+                                                              : m->jfa_passes)[(size_t)s.pass];
+            vd::TickSim &e = hs[na++];
+            memset(&e, 0, sizeof e);
+            e.src = m->map[m->cur];
+            e.dst = m->map[m->cur ^ 1];
+            e.table = m->pos;
+            e.W = m->cfg.width;
+            e.H = m->cfg.height;
+            e.S = m->cfg.num_seeds;
+            e.k = ps.k;
+            e.vn = ps.vn;
+            const vd::ItemGrid ig = vd::item_grid(e.W, e.H, e.k);
+            e.g = ig.g;
+            e.per = ig.per;
+            e.first = first;
+            first += ig.items;
+            t.pixel_updates += (int64_t)e.W * e.H;
+            m->cur ^= 1;
+            s.pass += 1;
+        }
+        if (s.pass >= s.npasses) {   // leaves after this tick
+            s.active = false;
+            t.completes.emplace_back(id, s.req);
+        }
+    }
+    hh->total = first;
+    for (int c = 0; c <= 8; ++c) hh->chunk[c] = (uint32_t)((uint64_t)first * c / 8);
+    hh->nactive = na;
+    hh->nprep = (int32_t)joiners.size();
+    const size_t used = vd::align_up(sizeof(vd::TickHeader)) +
+                        vd::align_up(sizeof(vd::TickSim) * sv->max_sims) +
+                        sizeof(vd::TickPrep) * joiners.size();
+    hipError_t e = hipMemcpyAsync(d, h, used, hipMemcpyHostToDevice, sv->stream);
+    const vd::TickPrep *dp = (const vd::TickPrep *)(d + vd::align_up(sizeof(vd::TickHeader)) +
+                                                   vd::align_up(sizeof(vd::TickSim) *
+                                                                sv->max_sims));
+    const dim3 blk(vd::kBlock);
+    if (e == hipSuccess && !joiners.empty()) {
+        const unsigned nj = (unsigned)joiners.size();
+        const unsigned gs = (unsigned)std::min<int64_t>((maxS + vd::kBlock - 1) / vd::kBlock, 1024);
+        hipLaunchKernelGGL(vd::k_tick_fill, dim3(256, nj), blk, 0, sv->stream, dp);
+        hipLaunchKernelGGL(vd::k_tick_move_reset, dim3(gs, nj), blk, 0, sv->stream, dp);
+        hipLaunchKernelGGL(vd::k_tick_splat_min, dim3(gs, nj), blk, 0, sv->stream, dp);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && na > 0) {
+        vd::TickHeader *dh = (vd::TickHeader *)d;
+        const vd::TickSim *ds = (const vd::TickSim *)(d + vd::align_up(sizeof(vd::TickHeader)));
+        if (sv->metric == VD_EUCLID)
+            hipLaunchKernelGGL(vd::k_tick_flood<vd::kEuclid>, dim3((unsigned)sv->grid),
+                               dim3(vd::kTW), 0, sv->stream, dh, ds);
+        else
+            hipLaunchKernelGGL(vd::k_tick_flood<vd::kManhattan>, dim3((unsigned)sv->grid),
+                               dim3(vd::kTW), 0, sv->stream, dh, ds);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&t.done, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(t.done, sv->stream);
+    if (e != hipSuccess) {
+        sv->error = VD_EDEVICE;
+        snprintf(sv->error_msg, sizeof sv->error_msg, "enqueueing a tick failed: %s",
+                 hipGetErrorString(e));
+        return false;
+    }
+    sv->ticks += 1;
+    sv->inflight.push_back(std::move(t));
+    return true;
+}
+
+void worker_main(vd_server *sv)
+{
+    std::unique_lock<std::mutex> lock(sv->mu);
+    while (!sv->stop) {
+        if (sv->error) {
+            sv->done_cv.notify_all();
+            sv->cv.wait(lock, [&] { return sv->stop; });
+            break;
+        }
+        admit(sv);
+        reap(sv, false);
+        if (tick(sv)) continue;
+        if (!sv->inflight.empty()) {
+            // nothing new to start: let the GPU finish the oldest tick (the
+            // event stays valid: only this thread destroys tick events)
+            lock.unlock();
+            hipEvent_t ev = sv->inflight.front().done;
+            (void)hipEventSynchronize(ev);
+            lock.lock();
+            continue;
+        }
+        sv->cv.wait_for(lock, std::chrono::milliseconds(5));
+    }
+}
+
+int server_error(vd_server *sv)
+{
+    return fail(sv->error, "%s", sv->error_msg);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t vd_server_footprint_bytes(int32_t max_sims)
+{
+    if (max_sims < 1 || max_sims > (1 << 15)) return 0;
+    return (size_t)vd::kRing * slot_size(max_sims) + 256;
+}
+
+int vd_server_create(int32_t max_sims, int32_t metric, void *dev_pool, size_t pool_bytes,
+                     void *hip_stream, vd_server **out)
+{
+    if (!out) return fail(VD_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (max_sims < 1 || max_sims > (1 << 15))
+        return fail(VD_EINVAL, "max_sims must be in [1, 32768], got %d", max_sims);
+    if (metric != VD_EUCLID && metric != VD_MANHATTAN)
+        return fail(VD_EINVAL, "unknown metric %d", metric);
+    if (!dev_pool) return fail(VD_EINVAL, "dev_pool is NULL");
+    size_t ring = (size_t)vd::kRing * slot_size(max_sims);
+    if (pool_bytes < ring + 256)
+        return fail(VD_ENOMEM, "pool holds %zu bytes, the server tables need %zu", pool_bytes,
+                    ring + 256);
+    vd_server *sv = new (std::nothrow) vd_server;
+    if (!sv) return fail(VD_ENOMEM, "host allocation of the server failed");
+    sv->max_sims = max_sims;
+    sv->metric = metric;
+    sv->stream = (hipStream_t)hip_stream;
+    sv->base = (uint8_t *)(((uintptr_t)dev_pool + 255) / 256 * 256);
+    sv->slot_bytes = slot_size(max_sims);
+    sv->ring_bytes = ring;
+    size_t usable = pool_bytes - 256 - ring;
+    sv->pool.size = usable;
+    sv->pool.free[ring] = usable;   // offsets are relative to base
+    int dev = 0, cus = 0, fit = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = metric == VD_EUCLID
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, vd::k_tick_flood<vd::kEuclid>,
+                                                               vd::kTW, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                      &fit, vd::k_tick_flood<vd::kManhattan>, vd::kTW, 0);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&sv->host_ring, ring, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        delete sv;
+        return fail(VD_EDEVICE, "server set-up failed: %s", hipGetErrorString(e));
+    }
+    sv->grid = std::max(cus, 1) * std::max(fit, 1);
+    try {
+        sv->worker = std::thread(worker_main, sv);
+    } catch (...) {
+        (void)hipHostFree(sv->host_ring);
+        delete sv;
+        return fail(VD_ENOMEM, "could not start the scheduler thread");
+    }
+    *out = sv;
+    return VD_OK;
+}
+
+int vd_server_add_sim(vd_server *sv, const vd_config *cfg, const int32_t *host_xy,
+                      int32_t *sim_id)
+{
+    if (!sv || !cfg || !host_xy || !sim_id) return fail(VD_EINVAL, "NULL argument");
+    if (cfg->label != VD_LABEL_ID32)
+        return fail(VD_EINVAL, "the server takes ID-label simulations");
+    if (cfg->metric != sv->metric)
+        return fail(VD_EINVAL, "simulation metric %d differs from the server's %d", cfg->metric,
+                    sv->metric);
+    size_t bytes = vd_footprint_bytes(cfg);
+    if (bytes == 0) return VD_EINVAL;   // message set by the validation
+    for (int64_t i = 0; i < 2 * (int64_t)cfg->num_seeds; i += 2)
+        if (host_xy[i] < 0 || host_xy[i] >= cfg->width || host_xy[i + 1] < 0 ||
+            host_xy[i + 1] >= cfg->height)
+            return fail(VD_EINVAL, "seed %lld is outside the grid", (long long)(i / 2));
+    std::lock_guard<std::mutex> lock(sv->mu);
+    if (sv->error) return server_error(sv);
+    if ((int32_t)sv->sims.size() >= sv->max_sims)
+        return fail(VD_ENOMEM, "the server holds its maximum of %d simulations", sv->max_sims);
+    if (bytes > sv->pool.size)
+        return fail(VD_ENOMEM, "simulation needs %zu bytes, the whole pool has %zu", bytes,
+                    sv->pool.size);
+    Served s;
+    s.id = sv->next_id++;
+    s.cfg = *cfg;
+    s.bytes = vd::align_up(bytes);
+    try {
+        s.xy.assign(host_xy, host_xy + 2 * (size_t)cfg->num_seeds);
+    } catch (...) {
+        return fail(VD_ENOMEM, "host allocation failed");
+    }
+    sv->sims[s.id] = std::move(s);
+    sv->admit_queue.push_back(sv->next_id - 1);
+    *sim_id = sv->next_id - 1;
+    sv->cv.notify_all();
+    return VD_OK;
+}
+
+int vd_server_submit(vd_server *sv, int32_t sim_id, int32_t mode, int64_t *ticket)
+{
+    if (!sv || !ticket) return fail(VD_EINVAL, "NULL argument");
+    if (mode != VD_STEP_JFA && mode != VD_STEP_DJFA)
+        return fail(VD_EINVAL, "mode must be VD_STEP_JFA or VD_STEP_DJFA, got %d", mode);
+    std::lock_guard<std::mutex> lock(sv->mu);
+    if (sv->error) return server_error(sv);
+    auto it = sv->sims.find(sim_id);
+    if (it == sv->sims.end() || it->second.removing)
+        return fail(VD_EINVAL, "no simulation %d", sim_id);
+    Request r{sv->next_ticket++, mode, vd::Clock::now()};
+    it->second.fifo.push_back(r);
+    sv->submitted += 1;
+    *ticket = r.ticket;
+    sv->cv.notify_all();
+    return VD_OK;
+}
+
+int vd_server_wait(vd_server *sv, int64_t ticket, double timeout_ms, double *latency_ms)
+{
+    if (!sv) return fail(VD_EINVAL, "server is NULL");
+    std::unique_lock<std::mutex> lock(sv->mu);
+    if (ticket < 1 || ticket >= sv->next_ticket) return fail(VD_EINVAL, "unknown ticket %lld",
+                                                             (long long)ticket);
+    auto ready = [&] { return sv->error || sv->finished.count(ticket); };
+    bool ok = timeout_ms < 0 ? (sv->done_cv.wait(lock, ready), true)
+                             : sv->done_cv.wait_for(
+                                   lock, std::chrono::duration<double, std::milli>(timeout_ms),
+                                   ready);
+    if (sv->error) return server_error(sv);
+    if (!ok) return fail(VD_EBUSY, "ticket %lld not finished", (long long)ticket);
+    if (latency_ms) *latency_ms = sv->finished[ticket];
+    sv->finished.erase(ticket);
+    return VD_OK;
+}
+
+int vd_server_drain(vd_server *sv, double timeout_ms)
+{
+    if (!sv) return fail(VD_EINVAL, "server is NULL");
+    std::unique_lock<std::mutex> lock(sv->mu);
+    auto idle = [&] {
+        if (sv->error) return true;
+        if (!sv->inflight.empty()) return false;
+        for (auto &kv : sv->sims)
+            if (kv.second.active || !kv.second.fifo.empty()) return false;
+        return true;
+    };
+    sv->cv.notify_all();
+    bool ok = timeout_ms < 0 ? (sv->done_cv.wait(lock, idle), true)
+                             : sv->done_cv.wait_for(
+                                   lock, std::chrono::duration<double, std::milli>(timeout_ms),
+                                   idle);
+    if (sv->error) return server_error(sv);
+    return ok ? VD_OK : fail(VD_EBUSY, "requests still pending");
+}
+
+int vd_server_remove_sim(vd_server *sv, int32_t sim_id)
+{
+    if (!sv) return fail(VD_EINVAL, "server is NULL");
+    std::unique_lock<std::mutex> lock(sv->mu);
+    auto it = sv->sims.find(sim_id);
+    if (it == sv->sims.end() || it->second.removing)
+        return fail(VD_EINVAL, "no simulation %d", sim_id);
+    Served &s = it->second;
+    s.removing = true;
+    s.fifo.clear();
+    if (!s.sim) {   // still waiting for admission: the worker drops it
+        sv->cv.notify_all();
+        return VD_OK;
+    }
+    sv->cv.notify_all();
+    sv->done_cv.wait(lock, [&] { return sv->error || (!s.active && s.inflight == 0); });
+    if (sv->error) return server_error(sv);
+    vd_sim *sim = s.sim;
+    sv->order.erase(std::find(sv->order.begin(), sv->order.end(), sim_id));
+    sv->pool.release(s.off, s.bytes);
+    sv->sims.erase(it);
+    vd_destroy(sim);
+    sv->cv.notify_all();   // memory freed: waiting simulations may be admitted
+    return VD_OK;
+}
+
+int vd_server_read_map(vd_server *sv, int32_t sim_id, int32_t *host_dst, size_t count)
+{
+    if (!sv) return fail(VD_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lock(sv->mu);
+    auto it = sv->sims.find(sim_id);
+    if (it == sv->sims.end()) return fail(VD_EINVAL, "no simulation %d", sim_id);
+    Served &s = it->second;
+    if (!s.sim) return fail(VD_ESTATE, "simulation %d is not resident yet", sim_id);
+    if (s.active || !s.fifo.empty())
+        return fail(VD_ESTATE, "simulation %d has requests in progress", sim_id);
+    return vd_read_map(s.sim, host_dst, count);
+}
+
+int vd_server_sim_state(vd_server *sv, int32_t sim_id, int32_t *resident, int64_t *t,
+                        int32_t *pending)
+{
+    if (!sv) return fail(VD_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lock(sv->mu);
+    auto it = sv->sims.find(sim_id);
+    if (it == sv->sims.end()) return fail(VD_EINVAL, "no simulation %d", sim_id);
+    const Served &s = it->second;
+    if (resident) *resident = s.sim != nullptr;
+    if (t) *t = s.sim ? s.sim->t : 0;
+    if (pending) *pending = (int32_t)s.fifo.size() + (s.active ? 1 : 0);
+    return VD_OK;
+}
+
+int vd_server_stats(vd_server *sv, vd_server_stats_t *out, int reset)
+{
+    if (!sv || !out) return fail(VD_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lock(sv->mu);
+    memset(out, 0, sizeof *out);
+    out->submitted = sv->submitted;
+    out->completed = sv->completed;
+    out->pixel_updates = sv->pixel_updates;
+    out->ticks = sv->ticks;
+    out->elapsed_s = vd::ms_between(sv->stats_t0, vd::Clock::now()) / 1e3;
+    int32_t res = 0;
+    for (auto &kv : sv->sims) res += kv.second.sim != nullptr;
+    out->resident = res;
+    out->waiting_admission = (int32_t)sv->admit_queue.size();
+    std::vector<double> l = sv->latencies;
+    if (!l.empty()) {
+        std::sort(l.begin(), l.end());
+        auto q = [&](double p) {
+            size_t i = (size_t)std::min<double>((double)l.size() - 1, p * (l.size() - 1) + 0.5);
+            return l[i];
+        };
+        double sum = 0;
+        for (double v : l) sum += v;
+        out->mean_ms = sum / l.size();
+        out->p50_ms = q(0.50);
+        out->p99_ms = q(0.99);
+        out->max_ms = l.back();
+    }
+    if (reset) {
+        sv->latencies.clear();
+        sv->submitted = sv->completed = sv->pixel_updates = sv->ticks = 0;
+        sv->stats_t0 = vd::Clock::now();
+    }
+    return sv->error ? server_error(sv) : VD_OK;
+}
+
+void vd_server_destroy(vd_server *sv)
+{
+    if (!sv) return;
+    {
+        std::lock_guard<std::mutex> lock(sv->mu);
+        sv->stop = true;
+        sv->cv.notify_all();
+    }
+    if (sv->worker.joinable()) sv->worker.join();
+    (void)hipStreamSynchronize(sv->stream);
+    for (Tick &t : sv->inflight)
+        if (t.done) (void)hipEventDestroy(t.done);
+    for (auto &kv : sv->sims)
+        if (kv.second.sim) vd_destroy(kv.second.sim);
+    if (sv->host_ring) (void)hipHostFree(sv->host_ring);
+    delete sv;
+}
+
+}  // extern "C"

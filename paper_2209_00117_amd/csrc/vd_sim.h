@@ -1,0 +1,52 @@
+// Internal state of a simulation, shared by the runtime translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "vd_kernels.h"
+#include "../../include/vdflood.h"
+
+namespace vd {
+
+struct Pass {
+    int32_t k;
+    int32_t vn;
+    int32_t variant;    // flood kernel variant (same result, different speed)
+    int32_t seg_rows;   // rows per chain segment, 0: chosen from the map size
+};
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    int kind = 0;   // 0: flood pass, 1: whole step
+};
+
+// Sets this thread's vd_last_error() message; returns status.
+int fail(int status, const char *fmt, ...);
+
+}  // namespace vd
+
+struct vd_batch;
+
+struct vd_sim {
+    vd_config cfg{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    uint32_t *map[2] = {nullptr, nullptr};
+    int cur = 0;                 // map[cur] holds the current diagram
+    uint32_t *pos = nullptr;     // seed table: sentinel, then current positions
+    uint32_t *pos_map = nullptr; // XY mode: the table the diagram's labels refer to
+    int64_t t = 0;
+    int32_t dmax = 0;
+    int32_t k1 = 0, delta1 = 0;
+    uint64_t move_seed = 0;
+    std::vector<vd::Pass> jfa_passes, djfa_passes;
+    bool timing = false;
+    std::vector<vd::EventPair> pool;   // recorded pairs
+    size_t used = 0;
+    vd_timing acc{};
+    bool broken = false;
+    vd_batch *batch = nullptr;   // set while a batch drives this simulation
+};

@@ -76,7 +76,57 @@ SIGNATURES = {
     "vd_set_flood_variant": (ctypes.c_int, [_P, ctypes.c_int]),
     "vd_destroy": (None, [_P]),
     "vd_last_error": (ctypes.c_char_p, []),
+    "vd_batch_footprint_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
+    "vd_batch_create": (ctypes.c_int, [ctypes.POINTER(_P), ctypes.c_int32, _P, ctypes.c_size_t,
+                                       _P, ctypes.POINTER(_P)]),
+    "vd_batch_step": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
+    "vd_batch_set_graph": (ctypes.c_int, [_P, ctypes.c_int]),
+    "vd_batch_set_shape": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "vd_batch_set_timing": (ctypes.c_int, [_P, ctypes.c_int]),
+    "vd_batch_get_timing": (ctypes.c_int, [_P, ctypes.POINTER(Timing)]),
+    "vd_batch_info": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32),
+                                     ctypes.POINTER(ctypes.c_int32)]),
+    "vd_batch_destroy": (None, [_P]),
+    "vd_batch_autotune": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "vd_autotune": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "vd_get_tuning": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
+    "vd_tuning_export": (ctypes.c_int, [_P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
+    "vd_tuning_import": (ctypes.c_int, [ctypes.c_char_p]),
 }
+
+STEP_JFA, STEP_DJFA = 0, 1
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+        ("pixel_updates", ctypes.c_int64), ("ticks", ctypes.c_int64),
+        ("elapsed_s", ctypes.c_double), ("mean_ms", ctypes.c_double),
+        ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+        ("resident", ctypes.c_int32), ("waiting_admission", ctypes.c_int32),
+    ]
+
+
+SIGNATURES.update({
+    "vd_server_footprint_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
+    "vd_server_create": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_size_t, _P,
+                                        ctypes.POINTER(_P)]),
+    "vd_server_add_sim": (ctypes.c_int, [_P, ctypes.POINTER(Config), _P,
+                                         ctypes.POINTER(ctypes.c_int32)]),
+    "vd_server_submit": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int64)]),
+    "vd_server_wait": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_double,
+                                      ctypes.POINTER(ctypes.c_double)]),
+    "vd_server_drain": (ctypes.c_int, [_P, ctypes.c_double]),
+    "vd_server_remove_sim": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "vd_server_read_map": (ctypes.c_int, [_P, ctypes.c_int32, _P, ctypes.c_size_t]),
+    "vd_server_sim_state": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int64),
+                                           ctypes.POINTER(ctypes.c_int32)]),
+    "vd_server_stats": (ctypes.c_int, [_P, ctypes.POINTER(ServerStats), ctypes.c_int]),
+    "vd_server_destroy": (None, [_P]),
+})
 
 _lib = None
 
@@ -187,6 +237,55 @@ def set_flood_variant(h, variant: int):
     _check(lib().vd_set_flood_variant(h, variant))
 
 
+def autotune(h, reps: int = 3):
+    _check(lib().vd_autotune(h, reps))
+
+
+def get_tuning(h):
+    """[(variant, seg_rows)] per pass, JFA passes first, then dJFA."""
+    info = get_info(h)
+    n = info.passes_jfa + info.passes_djfa
+    v = np.zeros(max(n, 1), np.int32)
+    r = np.zeros(max(n, 1), np.int32)
+    _check(lib().vd_get_tuning(h, v.ctypes.data_as(_P), r.ctypes.data_as(_P), n))
+    return list(zip(v[:n].tolist(), r[:n].tolist()))
+
+
+def tuning_export() -> dict:
+    """The process-wide tuning table as {key: [variant, seg_rows]}."""
+    need = ctypes.c_size_t()
+    _check(lib().vd_tuning_export(None, 0, ctypes.byref(need)))
+    buf = ctypes.create_string_buffer(need.value)
+    _check(lib().vd_tuning_export(buf, need.value, ctypes.byref(need)))
+    out = {}
+    for line in buf.value.decode().splitlines():
+        key, v, r = line.rsplit("|", 2)
+        out[key] = [int(v), int(r)]
+    return out
+
+
+def tuning_import(table: dict):
+    text = "".join(f"{k}|{v[0]}|{v[1]}\n" for k, v in table.items())
+    _check(lib().vd_tuning_import(text.encode()))
+
+
+def save_tuning(path: str):
+    """Writes the tuning table as JSON."""
+    import json
+    with open(path, "w") as f:
+        json.dump(tuning_export(), f, indent=1, sort_keys=True)
+
+
+def load_tuning(path: str):
+    import json
+    with open(path) as f:
+        tuning_import(json.load(f))
+
+
+def batch_autotune(b, reps: int = 3):
+    _check(lib().vd_batch_autotune(b, reps))
+
+
 def destroy(h):
     if h:
         lib().vd_destroy(h)
@@ -230,6 +329,164 @@ class Sim:
     def close(self):
         if self.handle:
             destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --- batches ----------------------------------------------------------------
+def batch_footprint_bytes(n: int) -> int:
+    return int(lib().vd_batch_footprint_bytes(n))
+
+
+def batch_create(handles, workspace, stream=None) -> ctypes.c_void_p:
+    arr = (ctypes.c_void_p * len(handles))(*[h.value if isinstance(h, ctypes.c_void_p) else h
+                                             for h in handles])
+    out = ctypes.c_void_p()
+    _check(lib().vd_batch_create(arr, len(handles), ctypes.c_void_p(workspace.data_ptr()),
+                                 workspace.numel(), _stream_ptr(stream), ctypes.byref(out)))
+    return out
+
+
+def batch_step(b, mode: int, move: bool):
+    _check(lib().vd_batch_step(b, mode, int(bool(move))))
+
+
+def batch_set_graph(b, enable: bool):
+    _check(lib().vd_batch_set_graph(b, int(bool(enable))))
+
+
+def batch_set_shape(b, wg_per_cu: int):
+    _check(lib().vd_batch_set_shape(b, wg_per_cu))
+
+
+def batch_set_timing(b, enable: bool):
+    _check(lib().vd_batch_set_timing(b, int(bool(enable))))
+
+
+def batch_get_timing(b) -> Timing:
+    t = Timing()
+    _check(lib().vd_batch_get_timing(b, ctypes.byref(t)))
+    return t
+
+
+def batch_info(b):
+    lj, ld, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().vd_batch_info(b, ctypes.byref(lj), ctypes.byref(ld), ctypes.byref(g)))
+    return lj.value, ld.value, g.value
+
+
+def batch_destroy(b):
+    if b:
+        lib().vd_batch_destroy(b)
+
+
+class Batch:
+    """Simulations advanced together (vd_batch_*); keeps them and the
+    batch workspace alive."""
+
+    def __init__(self, sims, device="cuda", stream=None):
+        import torch
+        self.sims = list(sims)
+        n = len(self.sims)
+        self.workspace = torch.empty(batch_footprint_bytes(n), dtype=torch.uint8, device=device)
+        self.handle = batch_create([s.handle for s in self.sims], self.workspace, stream)
+
+    def step(self, mode: int, move: bool = True):
+        batch_step(self.handle, mode, move)
+
+    def set_graph(self, enable: bool):
+        batch_set_graph(self.handle, enable)
+
+    def set_shape(self, wg_per_cu: int):
+        batch_set_shape(self.handle, wg_per_cu)
+
+    def autotune(self, reps: int = 3):
+        batch_autotune(self.handle, reps)
+
+    def info(self):
+        return batch_info(self.handle)
+
+    def close(self):
+        if self.handle:
+            batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# --- serving ----------------------------------------------------------------
+class Server:
+    """A serving loop over resident simulations (vd_server_*): time-step
+    requests are queued per simulation and continuously batched on the GPU
+    by the library's scheduler thread."""
+
+    def __init__(self, max_sims: int, pool_bytes: int, metric=EUCLID, device="cuda",
+                 stream=None):
+        import torch
+        self.pool = torch.empty(pool_bytes, dtype=torch.uint8, device=device)
+        h = ctypes.c_void_p()
+        _check(lib().vd_server_create(max_sims, metric, ctypes.c_void_p(self.pool.data_ptr()),
+                                      pool_bytes, _stream_ptr(stream), ctypes.byref(h)))
+        self.handle = h
+        self.shapes = {}
+
+    @staticmethod
+    def footprint_bytes(max_sims: int) -> int:
+        return int(lib().vd_server_footprint_bytes(max_sims))
+
+    def add_sim(self, width, height, xy, **kw) -> int:
+        cfg = config(width, height, int(np.asarray(xy).shape[0]), **kw)
+        xy = np.ascontiguousarray(xy, dtype=np.int32)
+        sid = ctypes.c_int32()
+        _check(lib().vd_server_add_sim(self.handle, ctypes.byref(cfg), xy.ctypes.data_as(_P),
+                                       ctypes.byref(sid)))
+        self.shapes[sid.value] = (height, width)
+        return sid.value
+
+    def submit(self, sim_id: int, mode: int) -> int:
+        t = ctypes.c_int64()
+        _check(lib().vd_server_submit(self.handle, sim_id, mode, ctypes.byref(t)))
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: float = -1.0) -> float:
+        lat = ctypes.c_double()
+        _check(lib().vd_server_wait(self.handle, ticket, timeout_ms, ctypes.byref(lat)))
+        return lat.value
+
+    def drain(self, timeout_ms: float = -1.0):
+        _check(lib().vd_server_drain(self.handle, timeout_ms))
+
+    def remove_sim(self, sim_id: int):
+        _check(lib().vd_server_remove_sim(self.handle, sim_id))
+
+    def read_map(self, sim_id: int) -> np.ndarray:
+        out = np.empty(self.shapes[sim_id], np.int32)
+        _check(lib().vd_server_read_map(self.handle, sim_id, out.ctypes.data_as(_P), out.size))
+        return out
+
+    def sim_state(self, sim_id: int):
+        r, t, p = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32()
+        _check(lib().vd_server_sim_state(self.handle, sim_id, ctypes.byref(r), ctypes.byref(t),
+                                         ctypes.byref(p)))
+        return {"resident": bool(r.value), "t": t.value, "pending": p.value}
+
+    def stats(self, reset: bool = False) -> dict:
+        st = ServerStats()
+        _check(lib().vd_server_stats(self.handle, ctypes.byref(st), int(bool(reset))))
+        return {f: getattr(st, f) for f, _ in ServerStats._fields_}
+
+    def close(self):
+        if self.handle:
+            lib().vd_server_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

@@ -86,3 +86,14 @@ def test_null_and_small_workspace():
     for fn in ("vd_move_seeds", "vd_jfa_step", "vd_djfa_step"):
         assert getattr(L, fn)(None) == -1
     L.vd_destroy(None)
+
+
+def test_tuning_table_round_trip():
+    """The tuning table's text form (no device work involved)."""
+    V.tuning_import({"gfx950 64x64 S10 id euclid k32 moore": [3, 16],
+                     "gfx950 64x64 S10 xy euclid k1 vn": [1, 0]})
+    t = V.tuning_export()
+    assert t["gfx950 64x64 S10 id euclid k32 moore"] == [3, 16]
+    assert t["gfx950 64x64 S10 xy euclid k1 vn"] == [1, 0]
+    for bad in ("no separators\n", "k|9|0\n", "k|1|999\n"):
+        assert V.lib().vd_tuning_import(bad.encode()) == -1

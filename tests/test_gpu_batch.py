@@ -1,0 +1,114 @@
+"""Batched steps (vd_batch_*): every member of a batch ends each step with
+exactly the map and positions it has when it is stepped alone, in both
+modes, with and without moves, with launches or replayed graphs; and the
+alone runs equal the CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2209_00117_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def V():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2209_00117_amd import vdflood
+    vdflood.lib()
+    return vdflood
+
+
+# uneven members: sizes below, at and across the 256-column tile, tall,
+# wide, one pixel, one seed, dense and sparse (so pass counts differ)
+SHAPES = [(300, 200, 120, -2, 2), (64, 64, 4096, -1, 1), (1, 1, 1, -1, 1), (1000, 37, 50, -1, 3),
+          (37, 900, 400, -2, 2), (512, 512, 256, -1, 1), (1024, 700, 30000, -3, 3),
+          (257, 257, 1, -5, 5), (2048, 256, 2000, -1, 3)]
+
+
+def _make(V, specs, metric=0):
+    out = []
+    for j, (W, H, S, lo, hi) in enumerate(specs):
+        xy = inputs.place_seeds(W, H, S, 50 + j)
+        out.append((xy, dict(disp_lo=lo, disp_hi=hi, sim_seed=900 + j, metric=metric)))
+    return out
+
+
+def _run(V, specs, plan, metric=0, graph=False, tune=False):
+    made = _make(V, specs, metric)
+    members = [V.Sim(s[0], s[1], xy, **kw) for s, (xy, kw) in zip(specs, made)]
+    alone = [V.Sim(s[0], s[1], xy, **kw) for s, (xy, kw) in zip(specs, made)]
+    b = V.Batch(members)
+    if tune:
+        b.autotune(2)
+    b.set_graph(graph)
+    for t, (mode, move) in enumerate(plan):
+        print(f"[batch] n={len(specs)} step={t} mode={mode} move={move} graph={graph}", flush=True)
+        b.step(mode, move)
+        for a in alone:
+            if move:
+                a.move_seeds()
+            a.djfa_step() if mode == V.STEP_DJFA else a.jfa_step()
+        for j, (m, a) in enumerate(zip(members, alone)):
+            assert np.array_equal(m.read_seeds(), a.read_seeds()), (j, t)
+            diff = int((m.read_map() != a.read_map()).sum())
+            assert diff == 0, f"member {j} {specs[j]} differs from alone on {diff} px at step {t}"
+            assert m.info().t == a.info().t
+    b.close()
+    return members, alone, made
+
+
+def test_batch_equals_alone(V):
+    plan = [(1, True), (1, True), (0, True), (1, False), (0, False), (1, True)]
+    _run(V, SHAPES, plan)
+
+
+def test_batch_graph_replays(V):
+    """Graphs are captured on first use and replayed; eager reads between
+    replays; every replay matches the alone runs."""
+    plan = [(1, True)] * 4 + [(0, True)] * 2 + [(1, True)] * 2
+    _run(V, SHAPES[:6], plan, graph=True)
+
+
+def test_batch_autotuned(V):
+    """The tuned persistent grid changes speed only."""
+    _run(V, SHAPES, [(1, True), (0, True), (1, True)], graph=True, tune=True)
+
+
+def test_batch_manhattan(V):
+    _run(V, SHAPES[:5], [(1, True), (0, True), (1, True)], metric=1)
+
+
+def test_batch_members_equal_oracle(V):
+    specs = SHAPES[:5]
+    members, _, made = _run(V, specs, [(1, True), (1, True), (0, True)])
+    for (W, H, S, lo, hi), m, (xy, kw) in zip(specs, members, made):
+        o = O.Sim(W, H, xy, kw["sim_seed"], lo, hi)
+        for mode in (1, 1, 0):
+            o.move()
+            o.djfa_step() if mode == 1 else o.jfa_step()
+        assert np.array_equal(m.read_map(), o.map)
+
+
+def test_batch_rejects_misuse(V):
+    xy = inputs.place_seeds(100, 100, 10, 3)
+    a = V.Sim(100, 100, xy)
+    b = V.Batch([a])
+    with pytest.raises(V.VdError):
+        a.djfa_step()                      # driven by the batch
+    with pytest.raises(V.VdError):
+        V.Batch([a])                       # already in a batch
+    b.close()
+    a.djfa_step()                          # free again
+    x = V.Sim(100, 100, xy, label=V.LABEL_XY16)
+    with pytest.raises(V.VdError):
+        V.Batch([x])                       # XY labels are not batched
+
+
+def test_batched_workload_subset(V):
+    """The batched recipe's members at their real sizes (first 12 of 64)."""
+    wl = inputs.batched()
+    specs = [(s.width, s.height, s.num_seeds, s.disp_lo, s.disp_hi) for s in wl.sims[:12]]
+    _run(V, specs, [(1, True), (0, True), (1, True)], graph=True)

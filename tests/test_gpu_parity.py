@@ -153,3 +153,30 @@ def test_large_full_size(V):
 
 def test_large_full_size_xy(V):
     _full_size(V, inputs.large().sims[0], 1, label=1)
+
+
+def test_autotune_keeps_results(V):
+    """Tuned kernel variants and segment lengths change speed only: a tuned
+    simulation, a new one that adopts the table, and an untuned one stay
+    bit-identical to each other and to the oracle."""
+    W, H, S = 700, 500, 2000
+    xy = inputs.place_seeds(W, H, S, 4)
+    kw = dict(disp_lo=-2, disp_hi=2, sim_seed=3)
+    a = V.Sim(W, H, xy, **kw)
+    b = V.Sim(W, H, xy, **kw)
+    m_before = a.read_map()
+    V.autotune(a.handle, 2)
+    assert np.array_equal(a.read_map(), m_before)          # tuning leaves the state alone
+    tuned = V.get_tuning(a.handle)
+    assert all(0 <= v < 4 and r in (0, 8, 16, 64) for v, r in tuned)
+    c = V.Sim(W, H, xy, **kw)                               # adopts the process-wide table
+    assert V.get_tuning(c.handle) == tuned
+    o = O.Sim(W, H, xy, 3, -2, 2)
+    for mode in (1, 1, 0, 1):
+        for s in (a, b, c):
+            s.move_seeds()
+            s.djfa_step() if mode else s.jfa_step()
+        o.move()
+        o.djfa_step() if mode else o.jfa_step()
+        for s in (a, b, c):
+            assert np.array_equal(s.read_map(), o.map)

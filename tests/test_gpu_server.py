@@ -1,0 +1,117 @@
+"""Serving (vd_server_*): requests of many simulations are batched on the
+GPU while others run; each simulation's result equals a lone simulation
+given the same request sequence, bit for bit, and admission by memory
+footprint holds simulations back until memory frees."""
+import random
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2209_00117_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def V():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2209_00117_amd import vdflood
+    vdflood.lib()
+    return vdflood
+
+
+SHAPES = [(300, 200, 120, -2, 2), (64, 64, 4096, -1, 1), (1, 1, 1, -1, 1), (1000, 37, 50, -1, 3),
+          (37, 900, 400, -2, 2), (512, 512, 256, -1, 1), (1024, 700, 30000, -3, 3),
+          (257, 257, 1, -5, 5)]
+
+
+def _sims(specs, base_seed=70):
+    out = []
+    for j, (W, H, S, lo, hi) in enumerate(specs):
+        out.append((W, H, inputs.place_seeds(W, H, S, base_seed + j),
+                    dict(disp_lo=lo, disp_hi=hi, sim_seed=base_seed + 100 + j)))
+    return out
+
+
+def _alone(V, W, H, xy, kw, modes):
+    a = V.Sim(W, H, xy, **kw)
+    for m in modes:
+        a.move_seeds()
+        a.djfa_step() if m == V.STEP_DJFA else a.jfa_step()
+    return a.read_map()
+
+
+def test_server_mix_equals_alone(V):
+    made = _sims(SHAPES)
+    sv = V.Server(len(made), 1 << 30)
+    ids = [sv.add_sim(W, H, xy, **kw) for W, H, xy, kw in made]
+    rng = random.Random(5)
+    plan = {i: [] for i in ids}
+    tickets = []
+    for _ in range(60):                      # interleaved bursts: work overlaps on the GPU
+        i = rng.choice(ids)
+        m = V.STEP_DJFA if rng.random() < 0.75 else V.STEP_JFA
+        plan[i].append(m)
+        tickets.append(sv.submit(i, m))
+    print(f"[server] {len(tickets)} requests over {len(ids)} sims", flush=True)
+    lat = [sv.wait(t, 60000) for t in tickets]
+    assert all(x > 0 for x in lat)
+    st = sv.stats()
+    assert st["completed"] == st["submitted"] == 60 and st["resident"] == len(ids)
+    assert st["ticks"] < 60 * 13             # requests shared launches
+    for (W, H, xy, kw), i in zip(made, ids):
+        got = sv.read_map(i)
+        assert sv.sim_state(i)["t"] == len(plan[i])
+        assert np.array_equal(got, _alone(V, W, H, xy, kw, plan[i])), (i, plan[i])
+    # and the lone runs equal the oracle (two sims)
+    for (W, H, xy, kw), i in list(zip(made, ids))[:2]:
+        o = O.Sim(W, H, xy, kw["sim_seed"], kw["disp_lo"], kw["disp_hi"])
+        for m in plan[i]:
+            o.move()
+            o.djfa_step() if m == V.STEP_DJFA else o.jfa_step()
+        assert np.array_equal(sv.read_map(i), o.map)
+    sv.close()
+
+
+def test_server_admission_by_footprint(V):
+    """A pool that holds two of four simulations: the others wait, their
+    requests wait with them, and removing a simulation admits the next."""
+    specs = [(512, 512, 500, -2, 2)] * 4
+    made = _sims(specs, base_seed=300)
+    one = V.footprint_bytes(V.config(512, 512, 500))
+    pool = V.Server.footprint_bytes(4) + 2 * ((one + 255) // 256 * 256) + 4096
+    sv = V.Server(4, pool)
+    ids = [sv.add_sim(W, H, xy, **kw) for W, H, xy, kw in made]
+    t0 = [sv.submit(i, V.STEP_DJFA) for i in ids]
+    sv.wait(t0[0], 60000), sv.wait(t0[1], 60000)
+    st = sv.stats()
+    assert st["resident"] == 2 and st["waiting_admission"] == 2
+    assert not sv.sim_state(ids[2])["resident"] and sv.sim_state(ids[2])["pending"] == 1
+    sv.remove_sim(ids[0])
+    sv.wait(t0[2], 60000)                    # admitted into the freed memory, then served
+    assert sv.sim_state(ids[2])["resident"]
+    sv.remove_sim(ids[1])
+    sv.wait(t0[3], 60000)
+    for (W, H, xy, kw), i in list(zip(made, ids))[2:]:
+        assert np.array_equal(sv.read_map(i), _alone(V, W, H, xy, kw, [V.STEP_DJFA]))
+    sv.close()
+
+
+def test_server_rejects_misuse(V):
+    sv = V.Server(2, 1 << 26)
+    xy = inputs.place_seeds(100, 100, 10, 1)
+    with pytest.raises(V.VdError):
+        sv.add_sim(100, 100, xy, label=V.LABEL_XY16)
+    i = sv.add_sim(100, 100, xy)
+    with pytest.raises(V.VdError):
+        sv.submit(i, 7)
+    with pytest.raises(V.VdError):
+        sv.submit(99, V.STEP_DJFA)
+    t = sv.submit(i, V.STEP_DJFA)
+    sv.wait(t, 60000)
+    with pytest.raises(V.VdError):
+        sv.wait(t, 10)                       # a ticket is collected once
+    sv.close()
