@@ -31,13 +31,18 @@ if ROOT not in sys.path:
 METRIC = "pixel-updates/s and ms per time step (dJFA vs JFA), % HBM peak; p50/p99 step latency"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
 BYTES_PER_PIXEL_UPDATE = 8     # one 4-byte label read + one 4-byte label write per pass
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2209_00117_amd", "csrc", "vd_kernels.hip")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2209_00117_amd", "csrc", f)
+                  for f in ("vd_device.h", "vd_kernels.hip", "vd_kernels.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "flood_traffic.json")
 
 
 def kernel_sha() -> str:
-    with open(KERNEL_SOURCE, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    """Hash of the flood kernels' sources (the traffic record names it)."""
+    h = hashlib.sha256()
+    for path in KERNEL_SOURCES:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(workload: str):

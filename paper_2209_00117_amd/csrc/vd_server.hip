@@ -10,8 +10,9 @@
 // the same tile functions as the single-simulation kernels.  A simulation
 // that has run its last pass leaves; its request completes when the tick's
 // event fires.  New requests thus join at the next pass boundary instead of
-// waiting for running steps to finish, and ticks are enqueued back to back
-// (up to kRing in flight), so the work of many requests overlaps on the GPU.
+// waiting for running steps to finish, and the next tick is enqueued while
+// the current one runs (two in flight), so the work of many requests
+// overlaps on the GPU without long queues in front of newcomers.
 //
 // Memory: the caller hands the server one device pool.  The server keeps
 // its tick tables in it and places each simulation's workspace (two maps
@@ -39,7 +40,9 @@ namespace vd {
 
 namespace {
 
-constexpr int kRing = 16;   // tick tables in flight
+constexpr int kRing = 4;       // tick table slots
+constexpr int kMaxInflight = 2;   // ticks enqueued ahead of the GPU: enough to keep it busy,
+                                  // few enough that a new request joins within a tick
 
 struct TickSim {            // one active simulation's pass in a tick
     const uint32_t *src;
@@ -63,10 +66,17 @@ struct TickPrep {           // one simulation starting a request in a tick
 };
 
 struct TickHeader {
-    uint32_t total;         // tiles in the flood launch
-    uint32_t chunk[9];      // XCD c drains tiles [chunk[c], chunk[c + 1]) first
-    uint32_t ctr[8];        // claim counters (zero when uploaded)
+    uint32_t total;         // items in the flood launch
+    uint32_t chunk[9];      // XCD c drains items [chunk[c], chunk[c + 1]) first
     int32_t nactive, nprep;
+};
+
+// Claim counters of a tick (zero when uploaded).  They live in their own
+// 256-byte block: atomics on a line that every workgroup also reads the
+// chunk bounds from slowed the flood launch down almost threefold.
+struct TickCounters {
+    uint32_t ctr[8];
+    uint32_t pad[56];
 };
 
 __device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -120,8 +130,9 @@ __global__ void __launch_bounds__(kBlock) k_tick_splat_min(const TickPrep *__res
 }
 
 template <int METRIC>
-__global__ void __launch_bounds__(kTW) k_tick_flood(TickHeader *__restrict__ hd,
-                                                    const TickSim *__restrict__ sims)
+__global__ void __launch_bounds__(kTW) k_tick_flood(const TickHeader *__restrict__ hd,
+                                                    const TickSim *__restrict__ sims,
+                                                    uint32_t *__restrict__ ctr)
 {
     __shared__ uint2 lds[2][kLdsRow];
     __shared__ uint32_t s_item;
@@ -135,7 +146,7 @@ __global__ void __launch_bounds__(kTW) k_tick_flood(TickHeader *__restrict__ hd,
             while (probe < 8u) {
                 const uint32_t c = (home + probe) & 7u;
                 const uint32_t lo = hd->chunk[c], hi = hd->chunk[c + 1];
-                const uint32_t i = lo < hi ? atomicAdd(&hd->ctr[c], 1u) : 0xFFFFFFFFu;
+                const uint32_t i = lo < hi ? atomicAdd(&ctr[c], 1u) : 0xFFFFFFFFu;
                 if (i < hi - lo) {
                     item = lo + i;
                     break;
@@ -293,11 +304,16 @@ struct vd_server {
 
 namespace {
 
+// A tick slot: header | counters | active-simulation table | joiner table.
+size_t off_counters() { return vd::align_up(sizeof(vd::TickHeader)); }
+size_t off_sims() { return off_counters() + vd::align_up(sizeof(vd::TickCounters)); }
+size_t off_prep(int32_t max_sims)
+{
+    return off_sims() + vd::align_up(sizeof(vd::TickSim) * (size_t)max_sims);
+}
 size_t slot_size(int32_t max_sims)
 {
-    return vd::align_up(sizeof(vd::TickHeader)) +
-           vd::align_up(sizeof(vd::TickSim) * (size_t)max_sims) +
-           vd::align_up(sizeof(vd::TickPrep) * (size_t)max_sims);
+    return off_prep(max_sims) + vd::align_up(sizeof(vd::TickPrep) * (size_t)max_sims);
 }
 
 // Called with mu held.  Admits waiting simulations in arrival order while
@@ -381,16 +397,18 @@ bool tick(vd_server *sv)
     for (int32_t id : sv->order)
         if (sv->sims[id].active) active.push_back(id);
     if (active.empty()) return false;
-    if ((int)sv->inflight.size() >= vd::kRing) reap(sv, true);
+    while ((int)sv->inflight.size() >= vd::kMaxInflight && !sv->error) reap(sv, true);
     if (sv->error) return false;
     const int slot = (int)(sv->ticks % vd::kRing);
     uint8_t *h = sv->host_ring + (size_t)slot * sv->slot_bytes;
     uint8_t *d = sv->base + (size_t)slot * sv->slot_bytes;
+    // slot layout this tick: header | counters | TickSim x active | TickPrep x joiners
     vd::TickHeader *hh = (vd::TickHeader *)h;
-    vd::TickSim *hs = (vd::TickSim *)(h + vd::align_up(sizeof(vd::TickHeader)));
-    vd::TickPrep *hp = (vd::TickPrep *)(h + vd::align_up(sizeof(vd::TickHeader)) +
-                                       vd::align_up(sizeof(vd::TickSim) * sv->max_sims));
+    vd::TickSim *hs = (vd::TickSim *)(h + off_sims());
+    const size_t prep_at = off_sims() + vd::align_up(sizeof(vd::TickSim) * active.size());
+    vd::TickPrep *hp = (vd::TickPrep *)(h + prep_at);
     memset(hh, 0, sizeof *hh);
+    memset(h + off_counters(), 0, sizeof(vd::TickCounters));
     Tick t;
     t.slot = slot;
     for (int32_t id : active) {
@@ -452,31 +470,30 @@ bool tick(vd_server *sv)
     for (int c = 0; c <= 8; ++c) hh->chunk[c] = (uint32_t)((uint64_t)first * c / 8);
     hh->nactive = na;
     hh->nprep = (int32_t)joiners.size();
-    const size_t used = vd::align_up(sizeof(vd::TickHeader)) +
-                        vd::align_up(sizeof(vd::TickSim) * sv->max_sims) +
-                        sizeof(vd::TickPrep) * joiners.size();
+    const size_t used = prep_at + sizeof(vd::TickPrep) * joiners.size();
     hipError_t e = hipMemcpyAsync(d, h, used, hipMemcpyHostToDevice, sv->stream);
-    const vd::TickPrep *dp = (const vd::TickPrep *)(d + vd::align_up(sizeof(vd::TickHeader)) +
-                                                   vd::align_up(sizeof(vd::TickSim) *
-                                                                sv->max_sims));
+    const vd::TickPrep *dp = (const vd::TickPrep *)(d + prep_at);
+    bool any_fill = false;
+    for (size_t j = 0; j < joiners.size(); ++j) any_fill |= hp[j].fill != 0;
     const dim3 blk(vd::kBlock);
     if (e == hipSuccess && !joiners.empty()) {
         const unsigned nj = (unsigned)joiners.size();
         const unsigned gs = (unsigned)std::min<int64_t>((maxS + vd::kBlock - 1) / vd::kBlock, 1024);
-        hipLaunchKernelGGL(vd::k_tick_fill, dim3(256, nj), blk, 0, sv->stream, dp);
+        if (any_fill) hipLaunchKernelGGL(vd::k_tick_fill, dim3(256, nj), blk, 0, sv->stream, dp);
         hipLaunchKernelGGL(vd::k_tick_move_reset, dim3(gs, nj), blk, 0, sv->stream, dp);
         hipLaunchKernelGGL(vd::k_tick_splat_min, dim3(gs, nj), blk, 0, sv->stream, dp);
         e = hipGetLastError();
     }
     if (e == hipSuccess && na > 0) {
-        vd::TickHeader *dh = (vd::TickHeader *)d;
-        const vd::TickSim *ds = (const vd::TickSim *)(d + vd::align_up(sizeof(vd::TickHeader)));
+        const vd::TickHeader *dh = (const vd::TickHeader *)d;
+        const vd::TickSim *ds = (const vd::TickSim *)(d + off_sims());
+        uint32_t *dc = (uint32_t *)(d + off_counters());
         if (sv->metric == VD_EUCLID)
             hipLaunchKernelGGL(vd::k_tick_flood<vd::kEuclid>, dim3((unsigned)sv->grid),
-                               dim3(vd::kTW), 0, sv->stream, dh, ds);
+                               dim3(vd::kTW), 0, sv->stream, dh, ds, dc);
         else
             hipLaunchKernelGGL(vd::k_tick_flood<vd::kManhattan>, dim3((unsigned)sv->grid),
-                               dim3(vd::kTW), 0, sv->stream, dh, ds);
+                               dim3(vd::kTW), 0, sv->stream, dh, ds, dc);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&t.done, hipEventDisableTiming);

@@ -1,0 +1,67 @@
+"""Similarity of the GPU diagrams (Sec. VI-A), reported per workload.
+
+sim_bf: share of (sampled) pixels whose label's seed is at the exact nearest
+distance, from the oracle's exact nearest-seed search (all pixels of the
+small workload; 2^20 sampled pixels of the single and large workloads).
+sim_jfa: share of pixels whose dJFA label equals the JFA label (the paper's
+metric).  The paper reports dJFAe "nearly 100%" against JFA (Sec. VI-B);
+the assertions hold the GPU to 99%.  The numbers are printed and written
+to gpurun_out/similarity.json when that folder exists.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2209_00117_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def V():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2209_00117_amd import vdflood
+    vdflood.lib()
+    return vdflood
+
+
+RESULTS = {}
+
+
+@pytest.mark.parametrize("name,steps", [("small", 5), ("single", 4), ("large", 2)])
+def test_similarity_per_workload(V, name, steps):
+    wl = inputs.WORKLOADS[name]()
+    spec = wl.sims[0]
+    W, H = spec.width, spec.height
+    xy = spec.positions()
+    kw = dict(disp_lo=spec.disp_lo, disp_hi=spec.disp_hi, sim_seed=spec.sim_seed)
+    sj, sd = V.Sim(W, H, xy, **kw), V.Sim(W, H, xy, **kw)
+    if wl.sample_pixels:
+        px, py = inputs.sample_pixels(W, H, wl.sample_pixels, seed=7)
+    else:
+        yy, xx = np.mgrid[0:H, 0:W]
+        px, py = xx.ravel().astype(np.int32), yy.ravel().astype(np.int32)
+    rows = []
+    for t in range(1, steps + 1):
+        sj.move_seeds(), sd.move_seeds()
+        sj.jfa_step(), sd.djfa_step()
+        pos = sd.read_seeds()
+        _, nd = O.nearest(pos, W, H, px, py)
+        md, mj = sd.read_map(), sj.read_map()
+        bf_d = O.count_exact(md, pos, px, py, nd) / len(px)
+        bf_j = O.count_exact(mj, pos, px, py, nd) / len(px)
+        sim_jfa = O.count_equal(md, mj) / md.size
+        rows.append({"t": t, "djfa_vs_exact": bf_d, "jfa_vs_exact": bf_j, "djfa_vs_jfa": sim_jfa})
+        print(f"[similarity] {name} t={t} dJFA vs exact {100 * bf_d:.4f}%  JFA vs exact "
+              f"{100 * bf_j:.4f}%  dJFA vs JFA {100 * sim_jfa:.4f}%", flush=True)
+        assert bf_d >= 0.99 and sim_jfa >= 0.99
+    RESULTS[name] = {"workload": wl.name, "sampled_pixels": int(len(px)), "steps": rows}
+    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    if os.path.isdir(out):
+        with open(os.path.join(out, "similarity.json"), "w") as f:
+            json.dump(RESULTS, f, indent=1)
