@@ -286,6 +286,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-pass-timing", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="skip the autotuner (run every pass with the default kernel variant)")
     ap.add_argument("--calibrate", action="store_true",
                     help="time a plain device-to-device copy of known size instead (HBM "
                          "reference for the roofline and for scaling rocprof byte counters)")
@@ -318,9 +320,22 @@ def main():
     kw = dict(disp_lo=spec.disp_lo, disp_hi=spec.disp_hi, sim_seed=spec.sim_seed, label=label)
     stream = torch.cuda.current_stream()
     sj = V.Sim(W, H, xy, stream=stream, **kw)
+    tuning = None
+    if not args.no_tune:
+        # Untimed: every pass of both step kinds is timed per kernel variant
+        # and segment length on its real input; the twin created next adopts
+        # the process-wide table.  The simulation's state is left unchanged.
+        V.autotune(sj.handle, 3)
     sd = V.Sim(W, H, xy, stream=stream, **kw)
     info = sd.info()
     pj, pd = info.passes_jfa, info.passes_djfa
+    if not args.no_tune:
+        ks = [info.k1 >> i for i in range(pj)]
+        kd = [info.delta1 >> i for i in range(pd)]
+        choice, us = V.get_tuning(sd.handle), V.get_tuning_us(sd.handle)
+        rows = [[k, v, r, round(t, 2)] for k, (v, r), t in zip(ks + kd, choice, us)]
+        tuning = {"columns": ["k", "variant", "seg_rows", "best_us"], "jfa": rows[:pj],
+                  "djfa": rows[pj:]}
 
     def one_step(ev=None):
         if ev is not None:
@@ -410,6 +425,7 @@ def main():
         "wall_s": wall,
         "roofline": roofline,
         "cpu_baseline": None,
+        "tuning": tuning,
     }
     sj.close(), sd.close()
     if not args.no_cpu:

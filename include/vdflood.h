@@ -174,20 +174,32 @@ int vd_get_timing(vd_sim *sim, vd_timing *out);
 /* Selects the flood-pass kernel variant for every pass of this simulation:
  * 0, 1 or 2 request each row's labels 1, 2 or 3 rows ahead of the row being
  * written; 3 shares each row across a workgroup through LDS for steps up to
- * 128 (and is 1 above); -1 restores the default (3 for ID labels, 1 for
- * XY labels).  Variants differ in speed only: every variant writes the same
- * labels. */
+ * 128 (and is 1 above); 4 gives each lane four adjacent columns (16-byte
+ * loads and stores) where the width is a multiple of 4, and is 3 (ID) or 1
+ * (XY) for other widths; -1 restores the default
+ * (3 for ID labels, 1 for XY labels).  Variants differ in speed only: every
+ * variant writes the same labels. */
 int vd_set_flood_variant(vd_sim *sim, int variant);
 
 /* Chooses, by timing, the kernel variant and the segment length of every
- * flood pass of this simulation's JFA and dJFA steps: each candidate runs
- * reps times (after one warm-up launch) reading the current diagram and
- * writing the idle buffer, so the simulation's state does not change.
- * The choices also enter a process-wide table keyed by (GPU architecture,
- * width, height, seed count, label, metric, k, neighbourhood) that later
- * vd_init_sim calls consult.  Results never depend on the choices.
- * Waits for the stream. */
+ * flood pass of this simulation's JFA and dJFA steps.  One JFA step (from
+ * scratch on the current seeds) and one dJFA step (from the current
+ * diagram) are replayed; before each pass every candidate runs reps times
+ * (after one warm-up launch) on that pass's actual input.  The diagram is
+ * saved first and put back after (device scratch of width*height*4 bytes,
+ * plus the seed table in XY mode, is allocated and freed), so the
+ * simulation's state does not change.  The choices also enter a
+ * process-wide table keyed by (GPU architecture, width, height, seed count,
+ * label, metric, k, neighbourhood, step kind) that later vd_init_sim calls
+ * consult.  Results never depend on the choices.  Waits for the stream.
+ * VD_ENOMEM if the scratch cannot be allocated. */
 int vd_autotune(vd_sim *sim, int32_t reps);
+
+/* Best measured duration (microseconds per launch) of each pass's chosen
+ * candidate in this process's autotuning, JFA passes first then dJFA
+ * passes; 0 for a pass never tuned.  cap must be at least passes_jfa +
+ * passes_djfa. */
+int vd_get_tuning_us(const vd_sim *sim, float *us, int32_t cap);
 
 /* Variant and segment length (0: automatic) of each pass, JFA passes first
  * then dJFA passes; cap must be at least passes_jfa + passes_djfa.  Either

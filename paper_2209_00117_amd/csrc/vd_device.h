@@ -117,11 +117,36 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t row_rsrc(const uint32_t *base,
     return __builtin_amdgcn_make_buffer_rsrc((void *)p, 0, in ? W * 4 : 0, kRsrcWord3);
 }
 
-// Labels of one row (columns x - k, x, x + k); off-grid reads return 0.
-__device__ __forceinline__ void load_labels(Row &row, const uint32_t *src, int32_t y, int32_t W,
-                                            int32_t H, int32_t ow, int32_t oc, int32_t oe)
+// A row of a chain walk addressed incrementally: `addr` is the byte address
+// of the row's first pixel and moves on by k rows per step, so a step costs
+// two scalar adds instead of a 64-bit multiply.  Rows the walk reaches are
+// never above the grid; a row below it gets an empty descriptor.
+struct Cursor {
+    uint64_t addr;
+    int32_t y;
+};
+
+__device__ __forceinline__ Cursor cursor_at(const uint32_t *base, int32_t y, int32_t W)
 {
-    __amdgpu_buffer_rsrc_t r = row_rsrc(src, y, W, H);
+    return Cursor{(uint64_t)base + 4ull * (uint64_t)((int64_t)y * W), y};
+}
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t cursor_rsrc(const Cursor &c, int32_t W,
+                                                              int32_t H)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void *)c.addr, 0, c.y < H ? W * 4 : 0, kRsrcWord3);
+}
+
+__device__ __forceinline__ void advance(Cursor &c, uint32_t step_bytes, int32_t k)
+{
+    c.addr += step_bytes;
+    c.y += k;
+}
+
+// Labels of one row (columns x - k, x, x + k); off-grid reads return 0.
+__device__ __forceinline__ void load_labels(Row &row, __amdgpu_buffer_rsrc_t r, int32_t ow,
+                                            int32_t oc, int32_t oe)
+{
     row.w.l = __builtin_amdgcn_raw_buffer_load_b32(r, ow, 0, 0);
     row.c.l = __builtin_amdgcn_raw_buffer_load_b32(r, oc, 0, 0);
     row.e.l = __builtin_amdgcn_raw_buffer_load_b32(r, oe, 0, 0);
@@ -130,13 +155,15 @@ __device__ __forceinline__ void load_labels(Row &row, const uint32_t *src, int32
 // Position of an ID label: an indexed load from the seed table (entry 0,
 // the unclaimed label, is the sentinel) -- unless the same column k rows
 // up carried the same label, whose position is reused.  In a converged map
-// most labels repeat down a column, so most lanes skip the lookup.
+// most labels repeat down a column.  A lane that reuses sends the load an
+// index past the table, which the hardware answers with 0 without touching
+// memory; this keeps the lookup free of exec-mask branches.
 __device__ __forceinline__ uint32_t seed_pos(uint32_t l, uint32_t prev_l, uint32_t prev_s,
                                              i32x4 tab)
 {
-    uint32_t p = prev_s;
-    if (l != prev_l) p = vd_struct_buffer_load(tab, (int32_t)l, 0, 0, 0);
-    return p;
+    const bool fresh = l != prev_l;
+    const uint32_t v = vd_struct_buffer_load(tab, fresh ? (int32_t)l : -1, 0, 0, 0);
+    return fresh ? v : prev_s;
 }
 
 // Seed positions of a row's labels; `up` is the row k above on the chain
@@ -174,39 +201,36 @@ __device__ __forceinline__ double cand_key(uint32_t p, const Ent &e)
 {
     short2_t dv = __builtin_bit_cast(short2_t, p) - __builtin_bit_cast(short2_t, e.s);
     int32_t d;
+    // The clamped form cannot saturate (d < 2^31, see above); it makes the
+    // compiler emit the three-operand v_dot2 with an inline zero rather
+    // than the accumulating form plus a move of zero into the accumulator.
     if (METRIC == kEuclid)
-        d = __builtin_amdgcn_sdot2(dv, dv, 0, false);
+        d = __builtin_amdgcn_sdot2(dv, dv, 0, true);
     else
         d = abs((int32_t)dv.x) + abs((int32_t)dv.y);
     return __hiloint2double(d, (int32_t)e.l);
 }
 
-// Output row y from the window a (row y - k), b (row y), c (row y + k).
+// Output pixel p (packed position) from the window a (row y - k), b (row
+// y), c (row y + k), stored through `out` at byte offset oc.  A row off the
+// grid reads as unclaimed labels, whose sentinel keys lose to every claimed
+// candidate and tie with each other, so the edge rows need no special case.
 template <int METRIC, int VN>
-__device__ __forceinline__ void emit(uint32_t *dst, const Row &a, const Row &b, const Row &c,
-                                     int32_t y, int32_t k, int32_t W, int32_t H, uint32_t px,
-                                     int32_t oc)
+__device__ __forceinline__ void emit(__amdgpu_buffer_rsrc_t out, const Row &a, const Row &b,
+                                     const Row &c, uint32_t p, int32_t oc)
 {
-    uint32_t p = ((uint32_t)(y + (int32_t)kOff) << 16) | px;
     double best = cand_key<METRIC>(p, b.c);
     best = __builtin_fmin(best, cand_key<METRIC>(p, b.w));
     best = __builtin_fmin(best, cand_key<METRIC>(p, b.e));
-    if (y >= k) {
-        best = __builtin_fmin(best, cand_key<METRIC>(p, a.c));
-        if (!VN) {
-            best = __builtin_fmin(best, cand_key<METRIC>(p, a.w));
-            best = __builtin_fmin(best, cand_key<METRIC>(p, a.e));
-        }
+    best = __builtin_fmin(best, cand_key<METRIC>(p, a.c));
+    best = __builtin_fmin(best, cand_key<METRIC>(p, c.c));
+    if (!VN) {
+        best = __builtin_fmin(best, cand_key<METRIC>(p, a.w));
+        best = __builtin_fmin(best, cand_key<METRIC>(p, a.e));
+        best = __builtin_fmin(best, cand_key<METRIC>(p, c.w));
+        best = __builtin_fmin(best, cand_key<METRIC>(p, c.e));
     }
-    if (y + k < H) {
-        best = __builtin_fmin(best, cand_key<METRIC>(p, c.c));
-        if (!VN) {
-            best = __builtin_fmin(best, cand_key<METRIC>(p, c.w));
-            best = __builtin_fmin(best, cand_key<METRIC>(p, c.e));
-        }
-    }
-    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)__double2loint(best), row_rsrc(dst, y, W, H),
-                                          oc, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)__double2loint(best), out, oc, 0, 0);
 }
 
 struct Tile {
@@ -264,7 +288,10 @@ __device__ __forceinline__ void flood_chain_tile(const uint32_t *src, uint32_t *
     const int32_t x = tl.x0 + (int32_t)threadIdx.x;
     const uint32_t px = (uint32_t)(x + (int32_t)kOff);
     const int32_t ow = 4 * (x - k), oc = 4 * x, oe = 4 * (x + k);
-    int32_t y = tl.y0;
+    const uint32_t step_bytes = 4u * (uint32_t)k * (uint32_t)W;   // < 2^31 for sides <= 16368
+    // packed position of the output pixel; the row field moves on by k per step
+    uint32_t p = ((uint32_t)(tl.y0 + (int32_t)kOff) << 16) | px;
+    const uint32_t p_step = (uint32_t)k << 16;
 
     // NR row registers rotate through the roles: at unrolled step u, slot
     // (u + m + 1) % NR holds row y + m*k for m = -1 .. P.  Labels are
@@ -274,21 +301,27 @@ __device__ __forceinline__ void flood_chain_tile(const uint32_t *src, uint32_t *
     constexpr int NR = P + 3;
     Row R[NR];
 #pragma unroll
-    for (int m = -1; m <= P; ++m) load_labels(R[m + 1], src, y + m * k, W, H, ow, oc, oe);
+    for (int m = -1; m <= P; ++m)
+        load_labels(R[m + 1], row_rsrc(src, tl.y0 + m * k, W, H), ow, oc, oe);
     const Row none = {{kEmpty, 0u}, {kEmpty, 0u}, {kEmpty, 0u}};   // label 0 -> sentinel 0
     lookup_positions<LABEL>(R[0], none, tab);
 #pragma unroll
     for (int m = 0; m < P; ++m) lookup_positions<LABEL>(R[m + 1], R[m], tab);
+    Cursor in = cursor_at(src, tl.y0 + (P + 1) * k, W);   // next row to load
+    Cursor out = cursor_at(dst, tl.y0, W);                // next row to store (always on the grid)
     // One output row with the slots of unrolled step U; false once the
     // segment is done.
     auto step = [&](auto U) -> bool {
         constexpr int u = decltype(U)::value;
         if (j >= jend) return false;
-        load_labels(R[(u + NR - 1) % NR], src, y + (P + 1) * k, W, H, ow, oc, oe);
+        load_labels(R[(u + NR - 1) % NR], cursor_rsrc(in, W, H), ow, oc, oe);
         lookup_positions<LABEL>(R[(u + NR - 2) % NR], R[(u + NR - 3) % NR], tab);
-        emit<METRIC, VN>(dst, R[u % NR], R[(u + 1) % NR], R[(u + 2) % NR], y, k, W, H, px, oc);
+        emit<METRIC, VN>(cursor_rsrc(out, W, H), R[u % NR], R[(u + 1) % NR], R[(u + 2) % NR], p,
+                         oc);
+        advance(in, step_bytes, k);
+        advance(out, step_bytes, k);
+        p += p_step;
         ++j;
-        y += k;
         return true;
     };
     auto round = [&](auto... U) -> bool { return (step(U) && ...); };
@@ -332,17 +365,18 @@ __device__ __forceinline__ void flood_lds_tile(const uint32_t *src, uint32_t *ds
     const int32_t x = x0 + t;
     const uint32_t px = (uint32_t)(x + (int32_t)kOff);
     const int32_t oc = 4 * x;
-    // entry t is column x0 - k + t; entry kTW + t (only for t < 2k) is
+    // entry t is column x0 - k + t; entry kTW + t (only read for t < 2k) is
     // column x0 + kTW - k + t; an unused second entry reads out of range
     const int32_t o1 = 4 * (x0 - k + t);
-    const bool has2 = t < 2 * k;
-    const int32_t o2 = has2 ? 4 * (x0 + kTW - k + t) : INT32_MIN;
+    const int32_t o2 = t < 2 * k ? 4 * (x0 + kTW - k + t) : INT32_MIN;
     const bool wave2 = __builtin_amdgcn_readfirstlane(t & ~63) < 2 * k;   // any lane of the wave
-    int32_t y = tl.y0;
-    int32_t exchanges = 0;
+    const uint32_t step_bytes = 4u * (uint32_t)k * (uint32_t)W;
+    uint32_t p = ((uint32_t)(tl.y0 + (int32_t)kOff) << 16) | px;
+    const uint32_t p_step = (uint32_t)k << 16;
+    // byte offset of the LDS row written next; the two rows alternate
+    uint32_t lds_sel = 0;
 
-    auto load = [&](Slot &sl, int32_t yy) {
-        __amdgpu_buffer_rsrc_t rr = row_rsrc(src, yy, W, H);
+    auto load = [&](Slot &sl, __amdgpu_buffer_rsrc_t rr) {
         sl.raw.l1 = __builtin_amdgcn_raw_buffer_load_b32(rr, o1, 0, 0);
         sl.raw.l2 = wave2 ? __builtin_amdgcn_raw_buffer_load_b32(rr, o2, 0, 0) : 0u;
     };
@@ -351,17 +385,25 @@ __device__ __forceinline__ void flood_lds_tile(const uint32_t *src, uint32_t *ds
     auto lookup = [&](Slot &sl, const Raw &up) {
         if (LABEL == kLabelId) {
             sl.raw.s1 = seed_pos(sl.raw.l1, up.l1, up.s1, tab);
-            sl.raw.s2 = wave2 ? seed_pos(sl.raw.l2, up.l2, up.s2, tab) : 0u;
+            // Only the load sits under the wave-uniform branch: a select
+            // inside it would wait for the load on the spot.  Waves without
+            // second entries carry label 0 there, so they always reuse.
+            const bool fresh2 = sl.raw.l2 != up.l2;
+            uint32_t v2 = 0;
+            if (wave2) v2 = vd_struct_buffer_load(tab, fresh2 ? (int32_t)sl.raw.l2 : -1, 0, 0, 0);
+            sl.raw.s2 = fresh2 ? v2 : up.s2;
         } else {
             sl.raw.s1 = sl.raw.l1;
             sl.raw.s2 = sl.raw.l2;
         }
     };
+    // Every thread writes both of its entries (entries past 256 + 2k are
+    // never read), so the writes need no exec mask.
     auto exchange = [&](Slot &sl) {
-        uint2 *row = lds[exchanges & 1];
-        ++exchanges;
+        uint2 *row = (uint2 *)((char *)lds + lds_sel);
+        lds_sel ^= (uint32_t)sizeof(lds[0]);
         row[t] = make_uint2(sl.raw.l1, sl.raw.s1);
-        if (has2) row[kTW + t] = make_uint2(sl.raw.l2, sl.raw.s2);
+        row[kTW + t] = make_uint2(sl.raw.l2, sl.raw.s2);
         __syncthreads();
         const uint2 w = row[t], c = row[t + k], e = row[t + 2 * k];
         sl.win.w.l = w.x;
@@ -378,23 +420,27 @@ __device__ __forceinline__ void flood_lds_tile(const uint32_t *src, uint32_t *ds
     constexpr int NR = P + 3;
     Slot R[NR];
 #pragma unroll
-    for (int m = -1; m <= P; ++m) load(R[m + 1], y + m * k);
+    for (int m = -1; m <= P; ++m) load(R[m + 1], row_rsrc(src, tl.y0 + m * k, W, H));
     const Raw none = {kEmpty, kEmpty, 0u, 0u};   // label 0 -> sentinel position 0
     lookup(R[0], none);
 #pragma unroll
     for (int m = 0; m < P; ++m) lookup(R[m + 1], R[m].raw);
     exchange(R[0]);
     exchange(R[1]);
+    Cursor in = cursor_at(src, tl.y0 + (P + 1) * k, W);
+    Cursor out = cursor_at(dst, tl.y0, W);
     auto step = [&](auto U) -> bool {
         constexpr int u = decltype(U)::value;
         if (j >= jend) return false;
-        load(R[(u + NR - 1) % NR], y + (P + 1) * k);
+        load(R[(u + NR - 1) % NR], cursor_rsrc(in, W, H));
         lookup(R[(u + NR - 2) % NR], R[(u + NR - 3) % NR].raw);
         exchange(R[(u + 2) % NR]);
-        emit<METRIC, VN>(dst, R[u % NR].win, R[(u + 1) % NR].win, R[(u + 2) % NR].win, y, k, W,
-                         H, px, oc);
+        emit<METRIC, VN>(cursor_rsrc(out, W, H), R[u % NR].win, R[(u + 1) % NR].win,
+                         R[(u + 2) % NR].win, p, oc);
+        advance(in, step_bytes, k);
+        advance(out, step_bytes, k);
+        p += p_step;
         ++j;
-        y += k;
         return true;
     };
     auto round = [&](auto... U) -> bool { return (step(U) && ...); };

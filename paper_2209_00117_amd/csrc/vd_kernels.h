@@ -87,13 +87,21 @@ ItemGrid item_grid(int32_t W, int32_t H, int32_t k);
 // Largest step the shared-row (LDS) kernel handles.
 constexpr int kMaxLdsStep = 128;
 
+// Grid of the four-columns-per-lane kernels (1024 columns per workgroup),
+// and whether they handle a pass: width a multiple of 4 and k = 1, 2 or a
+// multiple of 4.
+FloodGrid flood_grid_quad(int32_t W, int32_t H, int32_t k, int32_t seg_rows);
+bool quad_ok(int32_t W, int32_t k);
+
 // One flood pass at step k: dst[p] = best of src[p] and src[p + o] over the
 // Moore (vn == 0) or Von Neumann (vn != 0) offsets o at distance k.
 // `variant` (0 .. kFloodVariants - 1) selects the kernel; every variant
 // gives the same map.  0, 1, 2: the chain walk requesting loads 1, 2 or 3
 // rows ahead; 3: rows shared through LDS for k <= 128 (2 rows ahead),
-// otherwise variant 1.
-constexpr int kFloodVariants = 4;
+// otherwise variant 1; 4: four columns per lane where quad_ok holds (ID
+// labels: rows shared through LDS for k <= 128, direct loads above),
+// otherwise variant 3 (ID) or 1 (XY).
+constexpr int kFloodVariants = 5;
 hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *table, int32_t S,
                         int32_t W, int32_t H, int32_t k, int32_t vn, int32_t label,
                         int32_t metric, int32_t variant, int32_t seg_rows, hipStream_t s);

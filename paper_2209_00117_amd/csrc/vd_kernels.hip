@@ -2,6 +2,7 @@
 // launchers.  The flood-pass device code (and the reasoning behind it) is in
 // vd_device.h.
 #include "vd_device.h"
+#include "vd_quad.h"
 
 namespace vd {
 
@@ -124,6 +125,37 @@ __global__ void __launch_bounds__(kTW) k_flood_lds(const uint32_t *__restrict__ 
                                          xcd_logical(blockIdx.x, g.nblocks), lds);
 }
 
+template <int METRIC, int VN, int KC>
+__global__ void __launch_bounds__(kBlock) k_flood_quad_xy(const uint32_t *__restrict__ src,
+                                                          uint32_t *__restrict__ dst, int32_t W,
+                                                          int32_t H, int32_t k, FloodGrid g)
+{
+    flood_quad_xy_tile<METRIC, VN, KC>(src, dst, W, H, k, g, xcd_logical(blockIdx.x, g.nblocks));
+}
+
+template <int METRIC, int VN, int KC>
+__global__ void __launch_bounds__(kBlock) k_flood_quad_id(const uint32_t *__restrict__ src,
+                                                          uint32_t *__restrict__ dst,
+                                                          const uint32_t *__restrict__ table,
+                                                          uint32_t S, int32_t W, int32_t H,
+                                                          int32_t k, FloodGrid g)
+{
+    __shared__ QuadRow lds[2];
+    flood_quad_id_tile<METRIC, VN, KC>(src, dst, table_rsrc(table, S), W, H, k, g,
+                                       xcd_logical(blockIdx.x, g.nblocks), lds);
+}
+
+template <int METRIC, int VN>
+__global__ void __launch_bounds__(kBlock) k_flood_quad_idd(const uint32_t *__restrict__ src,
+                                                           uint32_t *__restrict__ dst,
+                                                           const uint32_t *__restrict__ table,
+                                                           uint32_t S, int32_t W, int32_t H,
+                                                           int32_t k, FloodGrid g)
+{
+    flood_quad_id_direct_tile<METRIC, VN>(src, dst, table_rsrc(table, S), W, H, k, g,
+                                          xcd_logical(blockIdx.x, g.nblocks));
+}
+
 inline dim3 grid1d(int64_t n, int64_t cap = 1 << 20)
 {
     int64_t b = (n + kBlock - 1) / kBlock;
@@ -190,23 +222,42 @@ hipError_t launch_export(const uint32_t *map, uint32_t *out, int64_t n, int32_t 
     return hipGetLastError();
 }
 
-FloodGrid flood_grid(int32_t W, int32_t H, int32_t k, int32_t seg_rows)
+namespace {
+
+// Segment length (seg_rows <= 0): long enough to amortise the two overlap
+// rows, short enough to give the 256 CUs about `blocks` workgroups.
+FloodGrid grid_of(int32_t W, int32_t H, int32_t k, int32_t seg_rows, int32_t tw, int64_t blocks)
 {
-    // Segment length (seg_rows <= 0): long enough to amortise the two
-    // overlap rows, short enough to give the 256 CUs about 2048 workgroups.
     FloodGrid g{};
     int64_t npix = (int64_t)W * H;
-    int32_t L = (int32_t)(npix / ((int64_t)kTW * 2048));
+    int32_t L = (int32_t)(npix / ((int64_t)tw * blocks));
     L = L < 1 ? 1 : (L > kMaxSegRows ? kMaxSegRows : L);
     if (seg_rows > 0) L = seg_rows < kMaxTunedSegRows ? seg_rows : kMaxTunedSegRows;
     uint32_t nres = (uint32_t)(k < H ? k : H);
     int32_t chain = (H + k - 1) / k;                      // rows on the longest chain
-    g.ncol = (uint32_t)((W + kTW - 1) / kTW);
+    g.ncol = (uint32_t)((W + tw - 1) / tw);
     g.nseg = (uint32_t)((chain + L - 1) / L);
     g.L = L;
     uint64_t nb = (uint64_t)g.ncol * nres * g.nseg;
     g.nblocks = (k < 1 || nb > 0x7FFFFFFFull) ? 0u : (uint32_t)nb;
     return g;
+}
+
+}  // namespace
+
+FloodGrid flood_grid(int32_t W, int32_t H, int32_t k, int32_t seg_rows)
+{
+    return grid_of(W, H, k, seg_rows, kTW, 2048);
+}
+
+FloodGrid flood_grid_quad(int32_t W, int32_t H, int32_t k, int32_t seg_rows)
+{
+    return grid_of(W, H, k, seg_rows, kTWQ, 1024);
+}
+
+bool quad_ok(int32_t W, int32_t k)
+{
+    return W % kQuad == 0 && (k == 1 || k == 2 || k % kQuad == 0);
 }
 
 ItemGrid item_grid(int32_t W, int32_t H, int32_t k)
@@ -226,10 +277,46 @@ hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *tabl
                         int32_t W, int32_t H, int32_t k, int32_t vn, int32_t label,
                         int32_t metric, int32_t variant, int32_t seg_rows, hipStream_t s)
 {
+    if (variant < 0 || variant >= kFloodVariants) return hipErrorInvalidValue;
+    uint32_t uS = (uint32_t)S;
+    if (variant == 4) {
+        if (!quad_ok(W, k)) {
+            variant = label == kLabelId ? 3 : 1;   // same labels, single-column kernels
+        } else {
+            FloodGrid g = flood_grid_quad(W, H, k, seg_rows);
+            if (g.nblocks == 0) return hipErrorInvalidValue;
+            dim3 grid(g.nblocks), block(kBlock);
+#define VD_QUAD(MT, V, KC)                                                                     \
+    do {                                                                                       \
+        if (label == kLabelId && k > kMaxLdsStep)                                              \
+            hipLaunchKernelGGL((k_flood_quad_idd<MT, V>), grid, block, 0, s, src, dst, table,    \
+                               uS, W, H, k, g);                                                \
+        else if (label == kLabelId)                                                            \
+            hipLaunchKernelGGL((k_flood_quad_id<MT, V, KC>), grid, block, 0, s, src, dst, table, \
+                               uS, W, H, k, g);                                                \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_flood_quad_xy<MT, V, KC>), grid, block, 0, s, src, dst, W, H,  \
+                               k, g);                                                          \
+    } while (0)
+#define VD_QUAD_K(MT, V)                                                                       \
+    do {                                                                                       \
+        if (k == 1) VD_QUAD(MT, V, 1);                                                         \
+        else if (k == 2) VD_QUAD(MT, V, 2);                                                    \
+        else VD_QUAD(MT, V, 0);                                                                \
+    } while (0)
+            if (metric == kEuclid) {
+                if (vn) VD_QUAD_K(kEuclid, 1); else VD_QUAD_K(kEuclid, 0);
+            } else {
+                if (vn) VD_QUAD_K(kManhattan, 1); else VD_QUAD_K(kManhattan, 0);
+            }
+#undef VD_QUAD_K
+#undef VD_QUAD
+            return hipGetLastError();
+        }
+    }
     FloodGrid g = flood_grid(W, H, k, seg_rows);
     if (g.nblocks == 0) return hipErrorInvalidValue;
     dim3 grid(g.nblocks), block(kTW);
-    uint32_t uS = (uint32_t)S;
 #define VD_LAUNCH(LB, MT, V, P)                                                              \
     hipLaunchKernelGGL((k_flood<LB, MT, V, P>), grid, block, 0, s, src, dst, table, uS, W, H,  \
                        k, g)
@@ -243,7 +330,6 @@ hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *tabl
         else if (variant == 2) VD_LAUNCH(LB, MT, V, 3);                                       \
         else VD_LAUNCH_LDS(LB, MT, V, 2);                                                     \
     } while (0)
-    if (variant < 0 || variant >= kFloodVariants) return hipErrorInvalidValue;
     if (label == kLabelId) {
         if (metric == kEuclid) {
             if (vn) VD_LAUNCH_P(kLabelId, kEuclid, 1); else VD_LAUNCH_P(kLabelId, kEuclid, 0);

@@ -1,0 +1,369 @@
+// Flood pass with four columns per lane (grids whose width is a multiple of
+// four).  Same pass as the tiles in vd_device.h (Sec. III, Table I; Sec.
+// V-B, Alg. 1) and the same residue-chain walk, but each lane owns four
+// adjacent columns, so every row costs a lane one 16-byte load and one
+// 16-byte store, and the per-row scalar work (descriptors, loop control,
+// barrier) is shared by four pixels.  A workgroup covers 1024 columns.
+//
+// Groups.  A lane with columns x .. x+3 needs, from each input row, the
+// groups at x - h, x and x + h, where h = k for k >= 4 (whole groups, since
+// k is a power of two) and h = 4 for k = 1, 2 (the neighbouring groups,
+// from which the columns x - k .. x + 3 + k are picked at compile time).
+// With the width a multiple of four a group lies wholly inside or wholly
+// outside a row, so the buffer range check returns 0 -- the unclaimed
+// label -- for groups off the grid, exactly as for single columns.
+//
+// Rolling accumulators.  Input row y (chain index s) is a candidate row of
+// the outputs y - k (as the row below), y (same row) and y + k (as the row
+// above).  Each lane keeps the running best key of those three output rows
+// and folds every input row into all three as soon as it arrives, so an
+// input row is consumed once and no three-row window is held; the output
+// y - k is then complete and is stored.  The accumulators rotate through
+// three registers sets, which the unrolling by three makes static.
+#pragma once
+
+#include "vd_device.h"
+
+namespace vd {
+
+namespace {
+
+constexpr int kQuad = 4;                             // columns per lane
+constexpr int kTWQ = kBlock * kQuad;                 // columns per workgroup
+constexpr int kQuadLdsRow = kTWQ + 2 * kMaxLdsStep;  // entries of one shared row
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Labels and positions of one group of four columns.
+struct G4 {
+    u32x4 l, s;
+};
+
+// Columns a lane reads from one input row: groups at x - h, x, x + h.
+struct Three {
+    G4 a, b, c;
+};
+
+// Candidate j (0: west, 1: centre, 2: east) of pixel i of the lane, as
+// (label, position).  KC = 0: k >= 4; KC = 1, 2: k = KC, picked from the
+// twelve columns x - 4 .. x + 7.
+template <int KC>
+__device__ __forceinline__ Ent cand(const Three &t, int i, int j)
+{
+    int g, e;
+    if (KC == 0) {
+        g = j;
+        e = i;
+    } else {
+        const int col = 4 + i + (j - 1) * KC;   // 0 .. 11
+        g = col >> 2;
+        e = col & 3;
+    }
+    const G4 &q = g == 0 ? t.a : (g == 1 ? t.b : t.c);
+    return Ent{q.l[e], q.s[e]};
+}
+
+// Folds the three candidates (or the centre only) of input row t into the
+// best keys of the lane's four pixels of one output row.
+template <int METRIC, int KC, bool CENTRE_ONLY, bool INIT>
+__device__ __forceinline__ void fold(double (&best)[4], const u32x4 &p, const Three &t)
+{
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        double b = cand_key<METRIC>(p[i], cand<KC>(t, i, 1));
+        if (!INIT) b = __builtin_fmin(best[i], b);
+        if (!CENTRE_ONLY) {
+            b = __builtin_fmin(b, cand_key<METRIC>(p[i], cand<KC>(t, i, 0)));
+            b = __builtin_fmin(b, cand_key<METRIC>(p[i], cand<KC>(t, i, 2)));
+        }
+        best[i] = b;
+    }
+}
+
+__device__ __forceinline__ u32x4 labels_of(const double (&best)[4])
+{
+    return u32x4{(uint32_t)__double2loint(best[0]), (uint32_t)__double2loint(best[1]),
+                 (uint32_t)__double2loint(best[2]), (uint32_t)__double2loint(best[3])};
+}
+
+__device__ __forceinline__ u32x4 load4(__amdgpu_buffer_rsrc_t r, int32_t off)
+{
+    return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+
+__device__ __forceinline__ void store4(u32x4 v, __amdgpu_buffer_rsrc_t r, int32_t off)
+{
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, v), r, off, 0, 0);
+}
+
+// Seed positions of four ID labels, reusing those of the same columns k
+// rows up where the label repeats (see seed_pos).
+__device__ __forceinline__ u32x4 seed_pos4(u32x4 l, const G4 &up, i32x4 tab)
+{
+    return u32x4{seed_pos(l[0], up.l[0], up.s[0], tab), seed_pos(l[1], up.l[1], up.s[1], tab),
+                 seed_pos(l[2], up.l[2], up.s[2], tab), seed_pos(l[3], up.l[3], up.s[3], tab)};
+}
+
+struct TileQ {
+    int32_t x0;        // first column
+    int32_t y0;        // first output row
+    int32_t j0, jend;  // chain indices of the segment's output rows
+};
+
+__device__ __forceinline__ TileQ decode_tile_q(uint32_t logical, const FloodGrid &g, int32_t k,
+                                               int32_t H)
+{
+    const uint32_t col = __builtin_amdgcn_readfirstlane(logical % g.ncol);
+    const uint32_t rs = logical / g.ncol;
+    const int32_t seg = __builtin_amdgcn_readfirstlane((int32_t)(rs % g.nseg));
+    const int32_t r = __builtin_amdgcn_readfirstlane((int32_t)(rs / g.nseg));
+    const int32_t nj = (H - 1 - r) / k + 1;
+    TileQ t;
+    t.x0 = (int32_t)col * kTWQ;
+    t.j0 = seg * g.L;
+    t.jend = min(t.j0 + g.L, nj);
+    t.y0 = r + t.j0 * k;
+    return t;
+}
+
+template <int N>
+using IC = std::integral_constant<int, N>;
+
+// The walk shared by both label kinds.  Input row s of the segment is grid
+// row y0 + (s - 1) k, and output row j (grid row y0 + j k) takes input rows
+// j, j + 1 and j + 2.  Input rows rotate through three slots (row s in slot
+// s % 3).  `request(s, Slot, Phase)` starts fetching row s into its slot
+// (Phase 0 and 1: the first two rows, which may lie above the grid; Phase
+// 2: any later row); `fetch(Slot)` returns the row in a slot as a Three.
+// Rows are requested two rows ahead of their use.  Every slot and phase is
+// a compile-time constant, so the ring lives in registers.
+template <int METRIC, int VN, int KC, class Request, class Fetch>
+__device__ __forceinline__ void quad_walk(uint32_t *dst, int32_t W, int32_t H, int32_t k,
+                                          const TileQ &tl, int32_t oc, Request &request,
+                                          Fetch &fetch)
+{
+    const int32_t nout = tl.jend - tl.j0;
+    const int32_t x = tl.x0 + kQuad * (int32_t)threadIdx.x;
+    const uint32_t pk = (uint32_t)k << 16;
+    // packed positions of the lane's four pixels in output row 0
+    const uint32_t p0 = ((uint32_t)(tl.y0 + (int32_t)kOff) << 16) | (uint32_t)(x + (int32_t)kOff);
+    u32x4 prow[3];   // pixel positions of the output rows held in acc[]
+    double acc[3][4];
+    Cursor out = cursor_at(dst, tl.y0, W);
+    const uint32_t step_bytes = 4u * (uint32_t)k * (uint32_t)W;
+
+    request(0, IC<0>{}, IC<0>{});
+    request(1, IC<1>{}, IC<1>{});
+    request(2, IC<2>{}, IC<2>{});
+    // input rows 0 and 1 open output rows 0 and 1
+    {
+        prow[0] = u32x4{p0, p0 + 1, p0 + 2, p0 + 3};
+        const Three t = fetch(IC<0>{});
+        fold<METRIC, KC, VN != 0, true>(acc[0], prow[0], t);
+    }
+    request(3, IC<0>{}, IC<2>{});
+    {
+        prow[1] = prow[0] + pk;
+        const Three t = fetch(IC<1>{});
+        fold<METRIC, KC, false, false>(acc[0], prow[0], t);
+        fold<METRIC, KC, VN != 0, true>(acc[1], prow[1], t);
+    }
+    // Input row s (s >= 2) closes output row s - 2, continues s - 1 and
+    // opens s (rows opened past the segment are never stored).
+    int32_t s = 2;
+    auto step = [&](auto U) -> bool {
+        constexpr int u = decltype(U)::value;   // s % 3
+        constexpr int c0 = (u + 1) % 3, c1 = (u + 2) % 3, c2 = u;
+        if (s - 2 >= nout) return false;
+        request(s + 2, IC<(u + 2) % 3>{}, IC<2>{});
+        prow[c2] = prow[c1] + pk;
+        const Three t = fetch(IC<u>{});
+        fold<METRIC, KC, VN != 0, false>(acc[c0], prow[c0], t);
+        store4(labels_of(acc[c0]), cursor_rsrc(out, W, H), oc);
+        fold<METRIC, KC, false, false>(acc[c1], prow[c1], t);
+        fold<METRIC, KC, VN != 0, true>(acc[c2], prow[c2], t);
+        advance(out, step_bytes, k);
+        ++s;
+        return true;
+    };
+    // s % 3 runs 2, 0, 1, 2, 0, 1, ...
+    while (step(IC<2>{}) && step(IC<0>{}) && step(IC<1>{})) {
+    }
+}
+
+// XY labels: positions are the labels, so a lane loads its three groups of
+// each row directly (the neighbouring groups come from L2) and needs no
+// exchange.  Input rows are requested two rows ahead into a ring of three.
+template <int METRIC, int VN, int KC>
+__device__ __forceinline__ void flood_quad_xy_tile(const uint32_t *src, uint32_t *dst,
+                                                   int32_t W, int32_t H, int32_t k,
+                                                   const FloodGrid &g, uint32_t logical)
+{
+    const TileQ tl = decode_tile_q(logical, g, k, H);
+    if (tl.j0 >= tl.jend) return;
+    const int32_t h = KC == 0 ? k : 4;
+    const int32_t x = tl.x0 + kQuad * (int32_t)threadIdx.x;
+    const int32_t oc = 4 * x, oa = 4 * (x - h), ob = 4 * (x + h);
+    const uint32_t step_bytes = 4u * (uint32_t)k * (uint32_t)W;
+    u32x4 ring[3][3];
+    // input row s of the segment is grid row y0 + (s - 1) k; rows above the
+    // grid only occur among the first two
+    Cursor in = cursor_at(src, tl.y0 + k, W);   // input row 2
+    auto request = [&](int32_t s, auto Slot, auto Phase) {
+        __amdgpu_buffer_rsrc_t r;
+        if (decltype(Phase)::value < 2) {
+            r = row_rsrc(src, tl.y0 + (s - 1) * k, W, H);
+        } else {
+            r = cursor_rsrc(in, W, H);
+            advance(in, step_bytes, k);
+        }
+        u32x4 *q = ring[decltype(Slot)::value];
+        q[0] = load4(r, oa);
+        q[1] = load4(r, oc);
+        q[2] = load4(r, ob);
+    };
+    auto fetch = [&](auto Slot) -> Three {
+        const u32x4 *q = ring[decltype(Slot)::value];
+        return Three{{q[0], q[0]}, {q[1], q[1]}, {q[2], q[2]}};
+    };
+    quad_walk<METRIC, VN, KC>(dst, W, H, k, tl, oc, request, fetch);
+}
+
+// ID labels at large steps (k > kMaxLdsStep, a multiple of 4): the groups
+// at x - k and x + k belong to other workgroups' columns, so each lane loads
+// its three groups itself and looks up all twelve positions (each reused
+// where the label repeats k rows up).  Labels are requested two rows
+// ahead, positions one row ahead.
+template <int METRIC, int VN>
+__device__ __forceinline__ void flood_quad_id_direct_tile(const uint32_t *src, uint32_t *dst,
+                                                          i32x4 tab, int32_t W, int32_t H,
+                                                          int32_t k, const FloodGrid &g,
+                                                          uint32_t logical)
+{
+    const TileQ tl = decode_tile_q(logical, g, k, H);
+    if (tl.j0 >= tl.jend) return;
+    const int32_t x = tl.x0 + kQuad * (int32_t)threadIdx.x;
+    const int32_t oc = 4 * x, oa = 4 * (x - k), ob = 4 * (x + k);
+    const uint32_t step_bytes = 4u * (uint32_t)k * (uint32_t)W;
+    Three ring[3];
+    const Three none = {};   // labels 0 -> sentinel position 0
+    Cursor in = cursor_at(src, tl.y0 + k, W);   // input row 2
+    auto request = [&](int32_t s, auto Slot, auto Phase) {
+        constexpr int slot = decltype(Slot)::value, phase = decltype(Phase)::value;
+        __amdgpu_buffer_rsrc_t r;
+        if (phase < 2) {
+            r = row_rsrc(src, tl.y0 + (s - 1) * k, W, H);
+        } else {
+            r = cursor_rsrc(in, W, H);
+            advance(in, step_bytes, k);
+        }
+        Three &q = ring[slot];
+        q.a.l = load4(r, oa);
+        q.b.l = load4(r, oc);
+        q.c.l = load4(r, ob);
+        if (phase >= 1) {
+            Three &n = ring[(slot + 2) % 3];
+            const Three &up = phase >= 2 ? ring[(slot + 1) % 3] : none;
+            n.a.s = seed_pos4(n.a.l, up.a, tab);
+            n.b.s = seed_pos4(n.b.l, up.b, tab);
+            n.c.s = seed_pos4(n.c.l, up.c, tab);
+        }
+    };
+    auto fetch = [&](auto Slot) -> Three { return ring[decltype(Slot)::value]; };
+    quad_walk<METRIC, VN, 0>(dst, W, H, k, tl, oc, request, fetch);
+}
+
+// Shared rows of the ID tile, in groups of four entries: entry e is column
+// x0 - h + e.  Labels and positions are kept apart so that a lane moves 16
+// contiguous bytes of each array per group.
+struct QuadRow {
+    u32x4 l[kQuadLdsRow / kQuad];
+    u32x4 s[kQuadLdsRow / kQuad];
+};
+
+// ID labels (steps k <= kMaxLdsStep): the 1024 + 2h columns a workgroup
+// needs are fetched once -- group t by lane t, the 2h / 4 groups past the
+// end by the first lanes of wave 0 -- their positions looked up once, and
+// the three groups each lane needs are read back from LDS.  Labels are
+// requested two rows ahead and looked up one row ahead; two LDS rows
+// alternate, and the barrier of each exchange also orders the reuse of the
+// row written two exchanges earlier.  Callers must not let a previous use
+// of `lds` overlap the first exchange (a barrier between tiles suffices).
+template <int METRIC, int VN, int KC>
+__device__ __forceinline__ void flood_quad_id_tile(const uint32_t *src, uint32_t *dst, i32x4 tab,
+                                                   int32_t W, int32_t H, int32_t k,
+                                                   const FloodGrid &g, uint32_t logical,
+                                                   QuadRow *lds)
+{
+    const TileQ tl = decode_tile_q(logical, g, k, H);
+    if (tl.j0 >= tl.jend) return;
+    const int32_t h = KC == 0 ? k : 4;
+    const int32_t t = (int32_t)threadIdx.x;
+    const int32_t oc = 4 * (tl.x0 + kQuad * t);
+    const int32_t o1 = 4 * (tl.x0 - h + kQuad * t);
+    const int32_t o2 = t < h / 2 ? 4 * (tl.x0 - h + kTWQ + kQuad * t) : INT32_MIN;
+    const bool wave2 = __builtin_amdgcn_readfirstlane(t & ~63) < h / 2;   // any lane of the wave
+    const uint32_t step_bytes = 4u * (uint32_t)k * (uint32_t)W;
+    struct Slot_ {
+        G4 g1, g2;   // groups t and 256 + t
+    };
+    Slot_ ring[3];
+    const G4 none = {u32x4{0u, 0u, 0u, 0u}, u32x4{0u, 0u, 0u, 0u}};   // label 0 -> sentinel 0
+    Cursor in = cursor_at(src, tl.y0 + k, W);   // input row 2
+    uint32_t lds_sel = 0;
+
+    // Labels of input row s, and positions of input row s - 1.
+    auto request = [&](int32_t s, auto Slot, auto Phase) {
+        constexpr int slot = decltype(Slot)::value, phase = decltype(Phase)::value;
+        __amdgpu_buffer_rsrc_t r;
+        if (phase < 2) {
+            r = row_rsrc(src, tl.y0 + (s - 1) * k, W, H);
+        } else {
+            r = cursor_rsrc(in, W, H);
+            advance(in, step_bytes, k);
+        }
+        Slot_ &q = ring[slot];
+        q.g1.l = load4(r, o1);
+        q.g2.l = wave2 ? load4(r, o2) : u32x4{0u, 0u, 0u, 0u};
+        if (phase >= 1) {
+            Slot_ &n = ring[(slot + 2) % 3];
+            const G4 &up1 = phase >= 2 ? ring[(slot + 1) % 3].g1 : none;
+            n.g1.s = seed_pos4(n.g1.l, up1, tab);
+            // The few halo groups are looked up without reuse: their loads
+            // then write the positions directly under the wave-uniform
+            // branch, with no select that would wait for them there.
+            if (wave2) {
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    n.g2.s[e] = vd_struct_buffer_load(tab, (int32_t)n.g2.l[e], 0, 0, 0);
+            }
+        }
+    };
+    auto fetch = [&](auto Slot) -> Three {
+        const Slot_ &q = ring[decltype(Slot)::value];
+        QuadRow *row = (QuadRow *)((char *)lds + lds_sel);
+        lds_sel ^= (uint32_t)sizeof(QuadRow);
+        row->l[t] = q.g1.l;
+        row->s[t] = q.g1.s;
+        if (wave2) {
+            row->l[kBlock + t] = q.g2.l;
+            row->s[kBlock + t] = q.g2.s;
+        }
+        __syncthreads();
+        // groups of columns x - h, x and x + h
+        const int32_t ga = t, gb = t + h / kQuad, gc = t + 2 * (h / kQuad);
+        Three th;
+        th.a.l = row->l[ga];
+        th.a.s = row->s[ga];
+        th.b.l = row->l[gb];
+        th.b.s = row->s[gb];
+        th.c.l = row->l[gc];
+        th.c.s = row->s[gc];
+        return th;
+    };
+    quad_walk<METRIC, VN, KC>(dst, W, H, k, tl, oc, request, fetch);
+}
+
+}  // namespace
+
+}  // namespace vd

@@ -191,7 +191,8 @@ int run_passes(vd_sim *s, const std::vector<Pass> &passes)
     return VD_OK;
 }
 
-int do_jfa(vd_sim *s)
+// The map a JFA step floods: unclaimed everywhere but the seed pixels.
+int jfa_prologue(vd_sim *s)
 {
     const vd_config &c = s->cfg;
     int64_t npix = (int64_t)c.width * c.height;
@@ -200,15 +201,12 @@ int do_jfa(vd_sim *s)
         VD_HIP(vd::launch_splat_xy(s->map[s->cur], s->pos, c.num_seeds, c.width, s->stream));
     else
         VD_HIP(vd::launch_splat_id(s->map[s->cur], s->pos, c.num_seeds, c.width, s->stream));
-    int r = run_passes(s, s->jfa_passes);
-    if (r) return r;
-    if (c.label == VD_LABEL_XY16)
-        VD_HIP(hipMemcpyAsync(s->pos_map, s->pos, ((size_t)c.num_seeds + 1) * 4,
-                              hipMemcpyDeviceToDevice, s->stream));
     return VD_OK;
 }
 
-int do_djfa(vd_sim *s)
+// The map a dJFA step floods: the previous diagram (XY: relabelled to the
+// moved positions) with every seed pixel claimed by its seed.
+int djfa_prologue(vd_sim *s)
 {
     const vd_config &c = s->cfg;
     uint32_t *cur = s->map[s->cur];
@@ -222,12 +220,33 @@ int do_djfa(vd_sim *s)
     } else {
         VD_HIP(vd::launch_splat_id(cur, s->pos, c.num_seeds, c.width, s->stream));
     }
-    int r = run_passes(s, s->djfa_passes);
-    if (r) return r;
+    return VD_OK;
+}
+
+// XY mode: the diagram now refers to the current positions.
+int step_epilogue(vd_sim *s)
+{
+    const vd_config &c = s->cfg;
     if (c.label == VD_LABEL_XY16)
         VD_HIP(hipMemcpyAsync(s->pos_map, s->pos, ((size_t)c.num_seeds + 1) * 4,
                               hipMemcpyDeviceToDevice, s->stream));
     return VD_OK;
+}
+
+int do_jfa(vd_sim *s)
+{
+    int r = jfa_prologue(s);
+    if (r == VD_OK) r = run_passes(s, s->jfa_passes);
+    if (r == VD_OK) r = step_epilogue(s);
+    return r;
+}
+
+int do_djfa(vd_sim *s)
+{
+    int r = djfa_prologue(s);
+    if (r == VD_OK) r = run_passes(s, s->djfa_passes);
+    if (r == VD_OK) r = step_epilogue(s);
+    return r;
 }
 
 int step(vd_sim *s, bool dynamic)
@@ -253,6 +272,7 @@ int step(vd_sim *s, bool dynamic)
 // ---------------------------------------------------------------------------
 std::mutex g_tune_mu;
 std::map<std::string, std::pair<int32_t, int32_t>> g_tune;   // key -> (variant, seg_rows)
+std::map<std::string, float> g_tune_us;   // key -> best measured pass time (this process)
 
 std::string arch_name()
 {
@@ -265,12 +285,16 @@ std::string arch_name()
     return colon == std::string::npos ? a : a.substr(0, colon);
 }
 
-std::string tune_key(const std::string &arch, const vd_config &c, const Pass &p)
+// A pass of a JFA step and one of a dJFA step with the same k read very
+// different maps (partly flooded vs nearly converged), so the step kind is
+// part of the key.
+std::string tune_key(const std::string &arch, const vd_config &c, const Pass &p, bool dynamic)
 {
     char buf[192];
-    snprintf(buf, sizeof buf, "%s %dx%d S%d %s %s k%d %s", arch.c_str(), c.width, c.height,
+    snprintf(buf, sizeof buf, "%s %dx%d S%d %s %s k%d %s %s", arch.c_str(), c.width, c.height,
              c.num_seeds, c.label == VD_LABEL_XY16 ? "xy" : "id",
-             c.metric == VD_MANHATTAN ? "manhattan" : "euclid", p.k, p.vn ? "vn" : "moore");
+             c.metric == VD_MANHATTAN ? "manhattan" : "euclid", p.k, p.vn ? "vn" : "moore",
+             dynamic ? "djfa" : "jfa");
     return buf;
 }
 
@@ -278,9 +302,9 @@ void apply_tuning(vd_sim *s)
 {
     const std::string arch = arch_name();
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    for (std::vector<Pass> *ps : {&s->jfa_passes, &s->djfa_passes})
-        for (Pass &p : *ps) {
-            auto it = g_tune.find(tune_key(arch, s->cfg, p));
+    for (int dyn = 0; dyn < 2; ++dyn)
+        for (Pass &p : dyn ? s->djfa_passes : s->jfa_passes) {
+            auto it = g_tune.find(tune_key(arch, s->cfg, p, dyn != 0));
             if (it != g_tune.end()) {
                 p.variant = it->second.first;
                 p.seg_rows = it->second.second;
@@ -296,6 +320,7 @@ int vd_autotune(vd_sim *s, int32_t reps)
 {
     if (!s) return fail(VD_EINVAL, "sim is NULL");
     if (s->broken) return fail(VD_ESTATE, "simulation unusable after an earlier device error");
+    if (s->batch) return fail(VD_ESTATE, "simulation is driven by a batch (vd_batch_step)");
     if (reps < 1 || reps > 1000) return fail(VD_EINVAL, "reps must be in [1, 1000], got %d", reps);
     const vd_config &c = s->cfg;
     static const int32_t kSegRows[] = {0, 8, 16, 64};
@@ -306,49 +331,80 @@ int vd_autotune(vd_sim *s, int32_t reps)
     for (int32_t v = 0; v < vd::kFloodVariants; ++v)
         for (int32_t L : kSegRows) cands.push_back({v, L});
     const std::string arch = arch_name();
-    // distinct passes of both schedules
-    std::vector<Pass *> todo;
-    std::vector<std::string> keys;
-    for (std::vector<Pass> *ps : {&s->jfa_passes, &s->djfa_passes})
-        for (Pass &p : *ps) {
-            std::string key = tune_key(arch, c, p);
-            if (std::find(keys.begin(), keys.end(), key) == keys.end()) {
-                keys.push_back(key);
-                todo.push_back(&p);
-            }
-        }
-    std::vector<hipEvent_t> ev(2 * cands.size() * todo.size(), nullptr);
+    const size_t npix = (size_t)c.width * c.height;
+    const size_t tab_bytes = ((size_t)c.num_seeds + 1) * 4;
+    const int cur0 = s->cur;
+
+    // The replayed steps overwrite both maps (and, in XY mode, nothing
+    // else); the diagram and the XY position table are saved and put back.
+    uint32_t *save = nullptr, *save_pm = nullptr;
+    if (hipMalloc((void **)&save, npix * 4) != hipSuccess ||
+        (s->pos_map && hipMalloc((void **)&save_pm, tab_bytes) != hipSuccess)) {
+        if (save) (void)hipFree(save);
+        return fail(VD_ENOMEM, "autotune needs %zu bytes of device scratch", npix * 4 + tab_bytes);
+    }
+    std::vector<std::string> keys;     // distinct passes, in replay order
+    std::vector<hipEvent_t> ev;        // two per (pass, candidate)
     int r = VD_OK;
-    for (hipEvent_t &e : ev)
-        if (hipEventCreate(&e) != hipSuccess) {
-            r = fail(VD_EDEVICE, "hipEventCreate failed");
-            break;
+    auto hip = [&](hipError_t e, const char *what) {
+        if (e != hipSuccess && r == VD_OK)
+            r = fail(VD_EDEVICE, "autotune: %s failed: %s", what, hipGetErrorString(e));
+        return r == VD_OK;
+    };
+    hip(hipMemcpyAsync(save, s->map[s->cur], npix * 4, hipMemcpyDeviceToDevice, s->stream),
+        "save");
+    if (save_pm)
+        hip(hipMemcpyAsync(save_pm, s->pos_map, tab_bytes, hipMemcpyDeviceToDevice, s->stream),
+            "save");
+    // Replay one JFA step (from scratch) and one dJFA step (from the saved
+    // diagram).  Before each pass, every candidate runs on the pass's real
+    // input (reading it, writing the idle buffer); the pass itself then
+    // advances the replay.
+    for (int dyn = 0; dyn < 2 && r == VD_OK; ++dyn) {
+        if (dyn) {
+            hip(hipMemcpyAsync(s->map[s->cur], save, npix * 4, hipMemcpyDeviceToDevice,
+                               s->stream), "restore");
+            if (save_pm)
+                hip(hipMemcpyAsync(s->pos_map, save_pm, tab_bytes, hipMemcpyDeviceToDevice,
+                                   s->stream), "restore");
         }
-    // Every candidate reads the current diagram and writes the idle buffer,
-    // so the simulation's state is unchanged.
-    for (size_t i = 0; r == VD_OK && i < todo.size(); ++i)
-        for (size_t j = 0; r == VD_OK && j < cands.size(); ++j) {
-            const Pass &p = *todo[i];
-            auto launch = [&]() {
+        if (r == VD_OK) {
+            int pr = dyn ? djfa_prologue(s) : jfa_prologue(s);
+            if (pr) r = pr;
+        }
+        for (const Pass &p : dyn ? s->djfa_passes : s->jfa_passes) {
+            if (r != VD_OK) break;
+            std::string key = tune_key(arch, c, p, dyn != 0);
+            bool fresh = std::find(keys.begin(), keys.end(), key) == keys.end();
+            auto launch = [&](int32_t variant, int32_t seg_rows) {
                 return vd::launch_flood(s->map[s->cur], s->map[s->cur ^ 1], s->pos, c.num_seeds,
                                         c.width, c.height, p.k, p.vn, c.label, c.metric,
-                                        cands[j].variant, cands[j].seg_rows, s->stream);
+                                        variant, seg_rows, s->stream);
             };
-            hipError_t e = launch();   // warm-up
-            size_t at = 2 * (i * cands.size() + j);
-            if (e == hipSuccess) e = hipEventRecord(ev[at], s->stream);
-            for (int32_t k = 0; k < reps && e == hipSuccess; ++k) e = launch();
-            if (e == hipSuccess) e = hipEventRecord(ev[at + 1], s->stream);
-            if (e != hipSuccess) r = fail(VD_EDEVICE, "autotune launch failed: %s",
-                                          hipGetErrorString(e));
+            if (fresh) {
+                keys.push_back(key);
+                for (const Cand &cd : cands) {
+                    hipEvent_t e0 = nullptr, e1 = nullptr;
+                    if (!hip(hipEventCreate(&e0), "hipEventCreate")) break;
+                    ev.push_back(e0);
+                    if (!hip(hipEventCreate(&e1), "hipEventCreate")) break;
+                    ev.push_back(e1);
+                    if (!hip(launch(cd.variant, cd.seg_rows), "launch")) break;   // warm-up
+                    if (!hip(hipEventRecord(e0, s->stream), "hipEventRecord")) break;
+                    for (int32_t i = 0; i < reps && r == VD_OK; ++i)
+                        hip(launch(cd.variant, cd.seg_rows), "launch");
+                    if (!hip(hipEventRecord(e1, s->stream), "hipEventRecord")) break;
+                }
+            }
+            if (hip(launch(p.variant, p.seg_rows), "launch")) s->cur ^= 1;
         }
-    if (r == VD_OK && hipStreamSynchronize(s->stream) != hipSuccess)
-        r = fail(VD_EDEVICE, "hipStreamSynchronize failed");
-    if (r == VD_OK) {
+    }
+    hip(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    if (r == VD_OK && ev.size() == 2 * keys.size() * cands.size()) {
         std::lock_guard<std::mutex> lock(g_tune_mu);
-        for (size_t i = 0; i < todo.size(); ++i) {
+        for (size_t i = 0; i < keys.size(); ++i) {
             float best = 1e30f;
-            Cand pick = {todo[i]->variant, todo[i]->seg_rows};
+            Cand pick = cands[0];
             for (size_t j = 0; j < cands.size(); ++j) {
                 float ms = 0.f;
                 size_t at = 2 * (i * cands.size() + j);
@@ -358,12 +414,44 @@ int vd_autotune(vd_sim *s, int32_t reps)
                 }
             }
             g_tune[keys[i]] = {pick.variant, pick.seg_rows};
+            g_tune_us[keys[i]] = 1e3f * best / reps;
         }
     }
-    for (hipEvent_t e : ev)
-        if (e) (void)hipEventDestroy(e);
+    // put the diagram back where the simulation expects it
+    s->cur = cur0;
+    hipError_t e1 = hipMemcpyAsync(s->map[s->cur], save, npix * 4, hipMemcpyDeviceToDevice,
+                                   s->stream);
+    hipError_t e2 = save_pm ? hipMemcpyAsync(s->pos_map, save_pm, tab_bytes,
+                                             hipMemcpyDeviceToDevice, s->stream)
+                            : hipSuccess;
+    hipError_t e3 = hipStreamSynchronize(s->stream);
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    (void)hipFree(save);
+    if (save_pm) (void)hipFree(save_pm);
+    if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+        s->broken = true;
+        if (r == VD_OK) r = fail(VD_EDEVICE, "autotune: restoring the diagram failed");
+    }
+    if (r == VD_EDEVICE) s->broken = true;
     if (r == VD_OK) apply_tuning(s);
     return r;
+}
+
+int vd_get_tuning_us(const vd_sim *s, float *us, int32_t cap)
+{
+    if (!s) return fail(VD_EINVAL, "sim is NULL");
+    if (!us) return fail(VD_EINVAL, "us is NULL");
+    int32_t n = (int32_t)(s->jfa_passes.size() + s->djfa_passes.size());
+    if (cap < n) return fail(VD_EINVAL, "need room for %d passes, got %d", n, cap);
+    const std::string arch = arch_name();
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    int32_t i = 0;
+    for (int dyn = 0; dyn < 2; ++dyn)
+        for (const Pass &p : dyn ? s->djfa_passes : s->jfa_passes) {
+            auto it = g_tune_us.find(tune_key(arch, s->cfg, p, dyn != 0));
+            us[i++] = it == g_tune_us.end() ? 0.f : it->second;
+        }
+    return VD_OK;
 }
 
 int vd_tuning_export(char *buf, size_t cap, size_t *needed)

@@ -91,6 +91,7 @@ SIGNATURES = {
     "vd_batch_autotune": (ctypes.c_int, [_P, ctypes.c_int32]),
     "vd_autotune": (ctypes.c_int, [_P, ctypes.c_int32]),
     "vd_get_tuning": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
+    "vd_get_tuning_us": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
     "vd_tuning_export": (ctypes.c_int, [_P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
     "vd_tuning_import": (ctypes.c_int, [ctypes.c_char_p]),
 }
@@ -249,6 +250,16 @@ def get_tuning(h):
     r = np.zeros(max(n, 1), np.int32)
     _check(lib().vd_get_tuning(h, v.ctypes.data_as(_P), r.ctypes.data_as(_P), n))
     return list(zip(v[:n].tolist(), r[:n].tolist()))
+
+
+def get_tuning_us(h):
+    """Best measured microseconds per launch of each pass's tuned choice
+    (0 where never tuned), JFA passes first, then dJFA."""
+    info = get_info(h)
+    n = info.passes_jfa + info.passes_djfa
+    us = np.zeros(max(n, 1), np.float32)
+    _check(lib().vd_get_tuning_us(h, us.ctypes.data_as(_P), n))
+    return us[:n].tolist()
 
 
 def tuning_export() -> dict:

@@ -108,19 +108,23 @@ def test_ragged_and_degenerate(V, W, H, S, steps, lo, hi, label):
     run_twin(V, W, H, xy, steps, lo, hi, sim_seed=W + H, label=label, tag="ragged")
 
 
+@pytest.mark.parametrize("variant", [None, 4])
 @pytest.mark.parametrize("metric,vn,extra", [
     (1, 2, 0), (0, 0, 0), (0, 1, 1), (0, 2, 2), (1, 1, 2), (0, 5, 0),
 ])
-def test_pass_options(V, metric, vn, extra):
+def test_pass_options(V, metric, vn, extra, variant):
     xy = inputs.place_seeds(700, 450, 900, 3)
     for label in (0, 1):
         run_twin(V, 700, 450, xy, 3, -2, 2, sim_seed=5, label=label, metric=metric, vn=vn,
-                 extra=extra, tag="options")
+                 extra=extra, tag="options", variant=variant)
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+# Widths: below, at and across the 256- and 1024-column tiles, one not a
+# multiple of 4 (the four-column kernels then fall back); heights with
+# ragged chains.
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4])
 @pytest.mark.parametrize("W,H,S", [(100, 90, 40), (700, 450, 900), (1100, 300, 5000),
-                                   (257, 1200, 600)])
+                                   (257, 1200, 600), (2060, 340, 3000), (1024, 1030, 700)])
 def test_flood_variants(V, variant, W, H, S):
     """Every kernel variant writes the same maps (k from 1 to 1024, widths
     below, at and across the 256-column tile, heights with ragged chains)."""
@@ -155,23 +159,34 @@ def test_large_full_size_xy(V):
     _full_size(V, inputs.large().sims[0], 1, label=1)
 
 
-def test_autotune_keeps_results(V):
+@pytest.mark.parametrize("label", [0, 1])
+def test_autotune_keeps_results(V, label):
     """Tuned kernel variants and segment lengths change speed only: a tuned
     simulation, a new one that adopts the table, and an untuned one stay
-    bit-identical to each other and to the oracle."""
+    bit-identical to each other and to the oracle.  Tuning replays a JFA and
+    a dJFA step and then puts the diagram (and in XY mode the table it
+    refers to) back, so it is run mid-trajectory here."""
     W, H, S = 700, 500, 2000
     xy = inputs.place_seeds(W, H, S, 4)
-    kw = dict(disp_lo=-2, disp_hi=2, sim_seed=3)
+    kw = dict(disp_lo=-2, disp_hi=2, sim_seed=3, label=label)
     a = V.Sim(W, H, xy, **kw)
     b = V.Sim(W, H, xy, **kw)
+    o = O.Sim(W, H, xy, 3, -2, 2, label_mode=label)
+    for s in (a, b):
+        s.move_seeds()
+        s.djfa_step()
+    o.move()
+    o.djfa_step()
     m_before = a.read_map()
     V.autotune(a.handle, 2)
     assert np.array_equal(a.read_map(), m_before)          # tuning leaves the state alone
     tuned = V.get_tuning(a.handle)
-    assert all(0 <= v < 4 and r in (0, 8, 16, 64) for v, r in tuned)
+    assert all(0 <= v < 5 and r in (0, 8, 16, 64) for v, r in tuned)
+    assert all(us > 0 for us in V.get_tuning_us(a.handle))
     c = V.Sim(W, H, xy, **kw)                               # adopts the process-wide table
     assert V.get_tuning(c.handle) == tuned
-    o = O.Sim(W, H, xy, 3, -2, 2)
+    c.move_seeds()
+    c.djfa_step()
     for mode in (1, 1, 0, 1):
         for s in (a, b, c):
             s.move_seeds()
