@@ -32,7 +32,7 @@ METRIC = "pixel-updates/s and ms per time step (dJFA vs JFA), % HBM peak; p50/p9
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
 BYTES_PER_PIXEL_UPDATE = 8     # one 4-byte label read + one 4-byte label write per pass
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2209_00117_amd", "csrc", f)
-                  for f in ("vd_device.h", "vd_kernels.hip", "vd_kernels.h")]
+                  for f in ("vd_device.h", "vd_quad.h", "vd_kernels.hip", "vd_kernels.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "flood_traffic.json")
 
 

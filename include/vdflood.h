@@ -86,11 +86,13 @@ typedef struct vd_sim_info {
     int64_t t;               /* time step: 0 after init, +1 per vd_move_seeds */
 } vd_sim_info;
 
-/* Per-kernel timing gathered with HIP events on the simulation's stream
- * while enabled (vd_set_timing).  Durations are summed over launches. */
+/* Timing gathered with HIP events on the simulation's stream while enabled
+ * (vd_set_timing).  The flood passes of a step are timed as one run between
+ * two events (so flood_ms includes the short gaps between consecutive
+ * passes); durations are summed over runs and steps. */
 typedef struct vd_timing {
     int64_t flood_launches;  /* flood passes timed */
-    double flood_ms;         /* their summed duration */
+    double flood_ms;         /* their summed duration (gaps between passes included) */
     int64_t flood_pixels;    /* pixel-updates they performed (width*height each) */
     int64_t step_count;      /* whole JFA / dJFA steps timed */
     double step_ms;          /* their summed duration (fill/splat/relabel + passes) */
@@ -174,9 +176,10 @@ int vd_get_timing(vd_sim *sim, vd_timing *out);
 /* Selects the flood-pass kernel variant for every pass of this simulation:
  * 0, 1 or 2 request each row's labels 1, 2 or 3 rows ahead of the row being
  * written; 3 shares each row across a workgroup through LDS for steps up to
- * 128 (and is 1 above); 4 gives each lane four adjacent columns (16-byte
- * loads and stores) where the width is a multiple of 4, and is 3 (ID) or 1
- * (XY) for other widths; -1 restores the default
+ * 128 (and is 1 above); 4 and 5 give each lane four adjacent columns
+ * (16-byte loads and stores) and request rows 2 or 3 rows ahead where the
+ * width is a multiple of 4, and are 3 (ID) or 1 (XY) for other widths; -1
+ * restores the default
  * (3 for ID labels, 1 for XY labels).  Variants differ in speed only: every
  * variant writes the same labels. */
 int vd_set_flood_variant(vd_sim *sim, int variant);

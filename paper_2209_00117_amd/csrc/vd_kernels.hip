@@ -90,6 +90,54 @@ __global__ void __launch_bounds__(kBlock) k_relabel(uint32_t *__restrict__ map,
     }
 }
 
+// k_relabel for widths divisible by 4: each lane relabels four adjacent
+// pixels per row (16-byte loads and stores) and walks a strip of 1024
+// columns down `rows` rows, so the pixels of one Voronoi cell -- which carry
+// one label -- are handled by one workgroup close in time.  A pixel whose
+// label equals its left neighbour's, or (for the first of the four) the
+// label of the same column one row up, reuses that result; the gather of a
+// reusing lane goes to an index past the map, which the hardware answers
+// without a memory access.
+__global__ void __launch_bounds__(kBlock) k_relabel4(uint32_t *__restrict__ map,
+                                                     const uint32_t *__restrict__ idx,
+                                                     int32_t W, int32_t H, int32_t rows)
+{
+    const int32_t strips = (W + kTWQ - 1) / kTWQ;
+    const int32_t strip = (int32_t)blockIdx.x % strips;
+    const int32_t y0 = ((int32_t)blockIdx.x / strips) * rows;
+    const int32_t y1 = min(y0 + rows, H);
+    const int32_t off = 4 * (strip * kTWQ + kQuad * (int32_t)threadIdx.x);
+    const __amdgpu_buffer_rsrc_t ir = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)idx, 0, (int32_t)min((int64_t)W * H * 4, (int64_t)0x7FFFFFFF), kRsrcWord3);
+    const uint32_t base = (kOff << 16) | kOff;
+    uint32_t prev_l = kEmpty, prev_n = kEmpty;   // column x of the row above
+    // the next row's labels are requested before this row's gathers
+    u32x4 next = y0 < y1 ? load4(row_rsrc(map, y0, W, H), off) : u32x4{0u, 0u, 0u, 0u};
+    for (int32_t y = y0; y < y1; ++y) {
+        const u32x4 l = next;
+        next = load4(row_rsrc(map, y + 1 < y1 ? y + 1 : H, W, H), off);
+        u32x4 n;
+        uint32_t left_l = prev_l, left_n = prev_n;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const uint32_t le = l[e];
+            const int32_t lx = (int32_t)(le & 0xFFFFu) - (int32_t)kOff;
+            const int32_t ly = (int32_t)(le >> 16) - (int32_t)kOff;
+            const bool valid = le != kEmpty && lx >= 0 && lx < W && ly >= 0 && ly < H;
+            const bool reuse = le == left_l;
+            const int32_t at = (valid && !reuse) ? 4 * (ly * W + lx) : -1;
+            const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(ir, at, 0, 0);
+            const uint32_t np = valid ? (v >= base ? v : kEmpty) : kEmpty;
+            n[e] = reuse ? left_n : np;
+            left_l = le;
+            left_n = n[e];
+        }
+        store4(n, row_rsrc(map, y, W, H), off);
+        prev_l = l[0];
+        prev_n = n[0];
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_export(const uint32_t *__restrict__ map,
                                                    uint32_t *__restrict__ out, int64_t n,
                                                    int32_t label)
@@ -125,15 +173,16 @@ __global__ void __launch_bounds__(kTW) k_flood_lds(const uint32_t *__restrict__ 
                                          xcd_logical(blockIdx.x, g.nblocks), lds);
 }
 
-template <int METRIC, int VN, int KC>
+template <int METRIC, int VN, int KC, int NS>
 __global__ void __launch_bounds__(kBlock) k_flood_quad_xy(const uint32_t *__restrict__ src,
                                                           uint32_t *__restrict__ dst, int32_t W,
                                                           int32_t H, int32_t k, FloodGrid g)
 {
-    flood_quad_xy_tile<METRIC, VN, KC>(src, dst, W, H, k, g, xcd_logical(blockIdx.x, g.nblocks));
+    flood_quad_xy_tile<METRIC, VN, KC, NS>(src, dst, W, H, k, g,
+                                           xcd_logical(blockIdx.x, g.nblocks));
 }
 
-template <int METRIC, int VN, int KC>
+template <int METRIC, int VN, int KC, int NS>
 __global__ void __launch_bounds__(kBlock) k_flood_quad_id(const uint32_t *__restrict__ src,
                                                           uint32_t *__restrict__ dst,
                                                           const uint32_t *__restrict__ table,
@@ -141,19 +190,19 @@ __global__ void __launch_bounds__(kBlock) k_flood_quad_id(const uint32_t *__rest
                                                           int32_t k, FloodGrid g)
 {
     __shared__ QuadRow lds[2];
-    flood_quad_id_tile<METRIC, VN, KC>(src, dst, table_rsrc(table, S), W, H, k, g,
-                                       xcd_logical(blockIdx.x, g.nblocks), lds);
+    flood_quad_id_tile<METRIC, VN, KC, NS>(src, dst, table_rsrc(table, S), W, H, k, g,
+                                           xcd_logical(blockIdx.x, g.nblocks), lds);
 }
 
-template <int METRIC, int VN>
+template <int METRIC, int VN, int NS>
 __global__ void __launch_bounds__(kBlock) k_flood_quad_idd(const uint32_t *__restrict__ src,
                                                            uint32_t *__restrict__ dst,
                                                            const uint32_t *__restrict__ table,
                                                            uint32_t S, int32_t W, int32_t H,
                                                            int32_t k, FloodGrid g)
 {
-    flood_quad_id_direct_tile<METRIC, VN>(src, dst, table_rsrc(table, S), W, H, k, g,
-                                          xcd_logical(blockIdx.x, g.nblocks));
+    flood_quad_id_direct_tile<METRIC, VN, NS>(src, dst, table_rsrc(table, S), W, H, k, g,
+                                              xcd_logical(blockIdx.x, g.nblocks));
 }
 
 inline dim3 grid1d(int64_t n, int64_t cap = 1 << 20)
@@ -210,8 +259,15 @@ hipError_t launch_index_old(uint32_t *idx, const uint32_t *old_table, const uint
 hipError_t launch_relabel(uint32_t *map, const uint32_t *idx, int32_t W, int32_t H,
                           hipStream_t s)
 {
-    hipLaunchKernelGGL(k_relabel, grid1d((int64_t)W * H, 8192), dim3(kBlock), 0, s, map, idx, W,
-                       H);
+    if (W % kQuad == 0) {
+        const int32_t rows = 16;
+        const int64_t blocks = (int64_t)((W + kTWQ - 1) / kTWQ) * ((H + rows - 1) / rows);
+        hipLaunchKernelGGL(k_relabel4, dim3((unsigned)blocks), dim3(kBlock), 0, s, map, idx, W,
+                           H, rows);
+    } else {
+        hipLaunchKernelGGL(k_relabel, grid1d((int64_t)W * H, 8192), dim3(kBlock), 0, s, map,
+                           idx, W, H);
+    }
     return hipGetLastError();
 }
 
@@ -279,30 +335,34 @@ hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *tabl
 {
     if (variant < 0 || variant >= kFloodVariants) return hipErrorInvalidValue;
     uint32_t uS = (uint32_t)S;
-    if (variant == 4) {
+    if (variant >= 4) {
         if (!quad_ok(W, k)) {
             variant = label == kLabelId ? 3 : 1;   // same labels, single-column kernels
         } else {
             FloodGrid g = flood_grid_quad(W, H, k, seg_rows);
             if (g.nblocks == 0) return hipErrorInvalidValue;
             dim3 grid(g.nblocks), block(kBlock);
-#define VD_QUAD(MT, V, KC)                                                                     \
+#define VD_QUAD(MT, V, KC, NS)                                                                 \
     do {                                                                                       \
         if (label == kLabelId && k > kMaxLdsStep)                                              \
-            hipLaunchKernelGGL((k_flood_quad_idd<MT, V>), grid, block, 0, s, src, dst, table,    \
-                               uS, W, H, k, g);                                                \
+            hipLaunchKernelGGL((k_flood_quad_idd<MT, V, NS>), grid, block, 0, s, src, dst,       \
+                               table, uS, W, H, k, g);                                         \
         else if (label == kLabelId)                                                            \
-            hipLaunchKernelGGL((k_flood_quad_id<MT, V, KC>), grid, block, 0, s, src, dst, table, \
-                               uS, W, H, k, g);                                                \
+            hipLaunchKernelGGL((k_flood_quad_id<MT, V, KC, NS>), grid, block, 0, s, src, dst,    \
+                               table, uS, W, H, k, g);                                         \
         else                                                                                   \
-            hipLaunchKernelGGL((k_flood_quad_xy<MT, V, KC>), grid, block, 0, s, src, dst, W, H,  \
-                               k, g);                                                          \
+            hipLaunchKernelGGL((k_flood_quad_xy<MT, V, KC, NS>), grid, block, 0, s, src, dst, W, \
+                               H, k, g);                                                       \
+    } while (0)
+#define VD_QUAD_NS(MT, V, KC)                                                                  \
+    do {                                                                                       \
+        if (variant == 4) VD_QUAD(MT, V, KC, 3); else VD_QUAD(MT, V, KC, 4);                   \
     } while (0)
 #define VD_QUAD_K(MT, V)                                                                       \
     do {                                                                                       \
-        if (k == 1) VD_QUAD(MT, V, 1);                                                         \
-        else if (k == 2) VD_QUAD(MT, V, 2);                                                    \
-        else VD_QUAD(MT, V, 0);                                                                \
+        if (k == 1) VD_QUAD_NS(MT, V, 1);                                                      \
+        else if (k == 2) VD_QUAD_NS(MT, V, 2);                                                 \
+        else VD_QUAD_NS(MT, V, 0);                                                             \
     } while (0)
             if (metric == kEuclid) {
                 if (vn) VD_QUAD_K(kEuclid, 1); else VD_QUAD_K(kEuclid, 0);
@@ -310,6 +370,7 @@ hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *tabl
                 if (vn) VD_QUAD_K(kManhattan, 1); else VD_QUAD_K(kManhattan, 0);
             }
 #undef VD_QUAD_K
+#undef VD_QUAD_NS
 #undef VD_QUAD
             return hipGetLastError();
         }

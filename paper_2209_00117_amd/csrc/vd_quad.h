@@ -129,19 +129,28 @@ __device__ __forceinline__ TileQ decode_tile_q(uint32_t logical, const FloodGrid
 template <int N>
 using IC = std::integral_constant<int, N>;
 
-// The walk shared by both label kinds.  Input row s of the segment is grid
+// Request phase of input row s: the first two rows may lie above the grid
+// (phase 0 and 1 address them directly); later rows come from the cursor.
+// Rows requested in the prologue carry their index (for the lookups that
+// trail the requests); rows requested in the loop carry kSteady.
+constexpr int kSteady = 1 << 20;
+
+// The walk shared by all quad tiles.  Input row s of the segment is grid
 // row y0 + (s - 1) k, and output row j (grid row y0 + j k) takes input rows
-// j, j + 1 and j + 2.  Input rows rotate through three slots (row s in slot
-// s % 3).  `request(s, Slot, Phase)` starts fetching row s into its slot
-// (Phase 0 and 1: the first two rows, which may lie above the grid; Phase
-// 2: any later row); `fetch(Slot)` returns the row in a slot as a Three.
-// Rows are requested two rows ahead of their use.  Every slot and phase is
-// a compile-time constant, so the ring lives in registers.
-template <int METRIC, int VN, int KC, class Request, class Fetch>
+// j, j + 1 and j + 2.  Input rows rotate through NS slots (row s in slot
+// s % NS) and are requested NS - 1 rows ahead of their use:
+// `request(s, Slot, Phase)` starts fetching row s into its slot, and
+// `fetch(Slot)` returns the row in a slot as a Three.  The loop is unrolled
+// lcm(3, NS) times, so every slot and accumulator index is a compile-time
+// constant and the ring lives in registers.
+template <int METRIC, int VN, int KC, int NS, class Request, class Fetch>
 __device__ __forceinline__ void quad_walk(uint32_t *dst, int32_t W, int32_t H, int32_t k,
                                           const TileQ &tl, int32_t oc, Request &request,
                                           Fetch &fetch)
 {
+    static_assert(NS == 3 || NS == 4, "ring of 3 or 4 rows");
+    constexpr int A = NS - 1;                 // rows requested ahead of use
+    constexpr int U = NS == 3 ? 3 : 12;       // lcm(3, NS)
     const int32_t nout = tl.jend - tl.j0;
     const int32_t x = tl.x0 + kQuad * (int32_t)threadIdx.x;
     const uint32_t pk = (uint32_t)k << 16;
@@ -152,16 +161,18 @@ __device__ __forceinline__ void quad_walk(uint32_t *dst, int32_t W, int32_t H, i
     Cursor out = cursor_at(dst, tl.y0, W);
     const uint32_t step_bytes = 4u * (uint32_t)k * (uint32_t)W;
 
-    request(0, IC<0>{}, IC<0>{});
-    request(1, IC<1>{}, IC<1>{});
-    request(2, IC<2>{}, IC<2>{});
+    auto pre = [&](auto M) { request(decltype(M)::value, IC<decltype(M)::value % NS>{}, M); };
+    pre(IC<0>{});
+    pre(IC<1>{});
+    pre(IC<2>{});
+    if constexpr (A >= 3) pre(IC<3>{});
     // input rows 0 and 1 open output rows 0 and 1
     {
         prow[0] = u32x4{p0, p0 + 1, p0 + 2, p0 + 3};
         const Three t = fetch(IC<0>{});
         fold<METRIC, KC, VN != 0, true>(acc[0], prow[0], t);
     }
-    request(3, IC<0>{}, IC<2>{});
+    pre(IC<A + 1>{});
     {
         prow[1] = prow[0] + pk;
         const Three t = fetch(IC<1>{});
@@ -171,13 +182,13 @@ __device__ __forceinline__ void quad_walk(uint32_t *dst, int32_t W, int32_t H, i
     // Input row s (s >= 2) closes output row s - 2, continues s - 1 and
     // opens s (rows opened past the segment are never stored).
     int32_t s = 2;
-    auto step = [&](auto U) -> bool {
-        constexpr int u = decltype(U)::value;   // s % 3
-        constexpr int c0 = (u + 1) % 3, c1 = (u + 2) % 3, c2 = u;
+    auto step = [&](auto I) -> bool {
+        constexpr int u = (decltype(I)::value + 2) % U;   // s mod U
+        constexpr int c0 = (u + 1) % 3, c1 = (u + 2) % 3, c2 = u % 3;
         if (s - 2 >= nout) return false;
-        request(s + 2, IC<(u + 2) % 3>{}, IC<2>{});
+        request(s + A, IC<(u + A) % NS>{}, IC<kSteady>{});
         prow[c2] = prow[c1] + pk;
-        const Three t = fetch(IC<u>{});
+        const Three t = fetch(IC<u % NS>{});
         fold<METRIC, KC, VN != 0, false>(acc[c0], prow[c0], t);
         store4(labels_of(acc[c0]), cursor_rsrc(out, W, H), oc);
         fold<METRIC, KC, false, false>(acc[c1], prow[c1], t);
@@ -186,15 +197,15 @@ __device__ __forceinline__ void quad_walk(uint32_t *dst, int32_t W, int32_t H, i
         ++s;
         return true;
     };
-    // s % 3 runs 2, 0, 1, 2, 0, 1, ...
-    while (step(IC<2>{}) && step(IC<0>{}) && step(IC<1>{})) {
+    auto round = [&](auto... I) -> bool { return (step(I) && ...); };
+    while (expand<U>(round)) {
     }
 }
 
 // XY labels: positions are the labels, so a lane loads its three groups of
 // each row directly (the neighbouring groups come from L2) and needs no
-// exchange.  Input rows are requested two rows ahead into a ring of three.
-template <int METRIC, int VN, int KC>
+// exchange.  Input rows are requested NS - 1 rows ahead into a ring of NS.
+template <int METRIC, int VN, int KC, int NS>
 __device__ __forceinline__ void flood_quad_xy_tile(const uint32_t *src, uint32_t *dst,
                                                    int32_t W, int32_t H, int32_t k,
                                                    const FloodGrid &g, uint32_t logical)
@@ -205,7 +216,7 @@ __device__ __forceinline__ void flood_quad_xy_tile(const uint32_t *src, uint32_t
     const int32_t x = tl.x0 + kQuad * (int32_t)threadIdx.x;
     const int32_t oc = 4 * x, oa = 4 * (x - h), ob = 4 * (x + h);
     const uint32_t step_bytes = 4u * (uint32_t)k * (uint32_t)W;
-    u32x4 ring[3][3];
+    u32x4 ring[NS][3];
     // input row s of the segment is grid row y0 + (s - 1) k; rows above the
     // grid only occur among the first two
     Cursor in = cursor_at(src, tl.y0 + k, W);   // input row 2
@@ -226,26 +237,27 @@ __device__ __forceinline__ void flood_quad_xy_tile(const uint32_t *src, uint32_t
         const u32x4 *q = ring[decltype(Slot)::value];
         return Three{{q[0], q[0]}, {q[1], q[1]}, {q[2], q[2]}};
     };
-    quad_walk<METRIC, VN, KC>(dst, W, H, k, tl, oc, request, fetch);
+    quad_walk<METRIC, VN, KC, NS>(dst, W, H, k, tl, oc, request, fetch);
 }
 
 // ID labels at large steps (k > kMaxLdsStep, a multiple of 4): the groups
 // at x - k and x + k belong to other workgroups' columns, so each lane loads
 // its three groups itself and looks up all twelve positions (each reused
-// where the label repeats k rows up).  Labels are requested two rows
-// ahead, positions one row ahead.
-template <int METRIC, int VN>
+// where the label repeats k rows up).  Labels are requested NS - 1 rows
+// ahead of use and looked up one row ahead of use.
+template <int METRIC, int VN, int NS>
 __device__ __forceinline__ void flood_quad_id_direct_tile(const uint32_t *src, uint32_t *dst,
                                                           i32x4 tab, int32_t W, int32_t H,
                                                           int32_t k, const FloodGrid &g,
                                                           uint32_t logical)
 {
+    constexpr int D = NS - 2;   // rows between a row's label request and its lookups
     const TileQ tl = decode_tile_q(logical, g, k, H);
     if (tl.j0 >= tl.jend) return;
     const int32_t x = tl.x0 + kQuad * (int32_t)threadIdx.x;
     const int32_t oc = 4 * x, oa = 4 * (x - k), ob = 4 * (x + k);
     const uint32_t step_bytes = 4u * (uint32_t)k * (uint32_t)W;
-    Three ring[3];
+    Three ring[NS];
     const Three none = {};   // labels 0 -> sentinel position 0
     Cursor in = cursor_at(src, tl.y0 + k, W);   // input row 2
     auto request = [&](int32_t s, auto Slot, auto Phase) {
@@ -261,16 +273,16 @@ __device__ __forceinline__ void flood_quad_id_direct_tile(const uint32_t *src, u
         q.a.l = load4(r, oa);
         q.b.l = load4(r, oc);
         q.c.l = load4(r, ob);
-        if (phase >= 1) {
-            Three &n = ring[(slot + 2) % 3];
-            const Three &up = phase >= 2 ? ring[(slot + 1) % 3] : none;
+        if (phase >= D) {   // positions of row s - D, reusing row s - D - 1's
+            Three &n = ring[(slot + NS - D) % NS];
+            const Three &up = phase >= D + 1 ? ring[(slot + NS - D - 1) % NS] : none;
             n.a.s = seed_pos4(n.a.l, up.a, tab);
             n.b.s = seed_pos4(n.b.l, up.b, tab);
             n.c.s = seed_pos4(n.c.l, up.c, tab);
         }
     };
     auto fetch = [&](auto Slot) -> Three { return ring[decltype(Slot)::value]; };
-    quad_walk<METRIC, VN, 0>(dst, W, H, k, tl, oc, request, fetch);
+    quad_walk<METRIC, VN, 0, NS>(dst, W, H, k, tl, oc, request, fetch);
 }
 
 // Shared rows of the ID tile, in groups of four entries: entry e is column
@@ -285,11 +297,11 @@ struct QuadRow {
 // needs are fetched once -- group t by lane t, the 2h / 4 groups past the
 // end by the first lanes of wave 0 -- their positions looked up once, and
 // the three groups each lane needs are read back from LDS.  Labels are
-// requested two rows ahead and looked up one row ahead; two LDS rows
+// requested NS - 1 rows ahead and looked up one row ahead; two LDS rows
 // alternate, and the barrier of each exchange also orders the reuse of the
 // row written two exchanges earlier.  Callers must not let a previous use
 // of `lds` overlap the first exchange (a barrier between tiles suffices).
-template <int METRIC, int VN, int KC>
+template <int METRIC, int VN, int KC, int NS>
 __device__ __forceinline__ void flood_quad_id_tile(const uint32_t *src, uint32_t *dst, i32x4 tab,
                                                    int32_t W, int32_t H, int32_t k,
                                                    const FloodGrid &g, uint32_t logical,
@@ -304,15 +316,16 @@ __device__ __forceinline__ void flood_quad_id_tile(const uint32_t *src, uint32_t
     const int32_t o2 = t < h / 2 ? 4 * (tl.x0 - h + kTWQ + kQuad * t) : INT32_MIN;
     const bool wave2 = __builtin_amdgcn_readfirstlane(t & ~63) < h / 2;   // any lane of the wave
     const uint32_t step_bytes = 4u * (uint32_t)k * (uint32_t)W;
+    constexpr int D = NS - 2;   // rows between a row's label request and its lookups
     struct Slot_ {
         G4 g1, g2;   // groups t and 256 + t
     };
-    Slot_ ring[3];
+    Slot_ ring[NS];
     const G4 none = {u32x4{0u, 0u, 0u, 0u}, u32x4{0u, 0u, 0u, 0u}};   // label 0 -> sentinel 0
     Cursor in = cursor_at(src, tl.y0 + k, W);   // input row 2
     uint32_t lds_sel = 0;
 
-    // Labels of input row s, and positions of input row s - 1.
+    // Labels of input row s, and positions of input row s - D.
     auto request = [&](int32_t s, auto Slot, auto Phase) {
         constexpr int slot = decltype(Slot)::value, phase = decltype(Phase)::value;
         __amdgpu_buffer_rsrc_t r;
@@ -325,9 +338,9 @@ __device__ __forceinline__ void flood_quad_id_tile(const uint32_t *src, uint32_t
         Slot_ &q = ring[slot];
         q.g1.l = load4(r, o1);
         q.g2.l = wave2 ? load4(r, o2) : u32x4{0u, 0u, 0u, 0u};
-        if (phase >= 1) {
-            Slot_ &n = ring[(slot + 2) % 3];
-            const G4 &up1 = phase >= 2 ? ring[(slot + 1) % 3].g1 : none;
+        if (phase >= D) {
+            Slot_ &n = ring[(slot + NS - D) % NS];
+            const G4 &up1 = phase >= D + 1 ? ring[(slot + NS - D - 1) % NS].g1 : none;
             n.g1.s = seed_pos4(n.g1.l, up1, tab);
             // The few halo groups are looked up without reuse: their loads
             // then write the positions directly under the wave-uniform
@@ -361,7 +374,7 @@ __device__ __forceinline__ void flood_quad_id_tile(const uint32_t *src, uint32_t
         th.c.s = row->s[gc];
         return th;
     };
-    quad_walk<METRIC, VN, KC>(dst, W, H, k, tl, oc, request, fetch);
+    quad_walk<METRIC, VN, KC, NS>(dst, W, H, k, tl, oc, request, fetch);
 }
 
 }  // namespace

@@ -132,7 +132,7 @@ size_t footprint(const vd_config *c)
 
 namespace {
 
-int record(vd_sim *s, int kind, bool begin, size_t *slot)
+int record(vd_sim *s, int kind, bool begin, size_t *slot, int count = 1)
 {
     if (!s->timing) return VD_OK;
     if (begin) {
@@ -144,6 +144,7 @@ int record(vd_sim *s, int kind, bool begin, size_t *slot)
         }
         *slot = s->used++;
         s->pool[*slot].kind = kind;
+        s->pool[*slot].count = count;
         VD_HIP(hipEventRecord(s->pool[*slot].a, s->stream));
     } else {
         VD_HIP(hipEventRecord(s->pool[*slot].b, s->stream));
@@ -159,9 +160,9 @@ int harvest(vd_sim *s)
         float ms = 0.f;
         VD_HIP(hipEventElapsedTime(&ms, s->pool[i].a, s->pool[i].b));
         if (s->pool[i].kind == 0) {
-            s->acc.flood_launches += 1;
+            s->acc.flood_launches += s->pool[i].count;
             s->acc.flood_ms += ms;
-            s->acc.flood_pixels += (int64_t)s->cfg.width * s->cfg.height;
+            s->acc.flood_pixels += (int64_t)s->pool[i].count * s->cfg.width * s->cfg.height;
         } else {
             s->acc.step_count += 1;
             s->acc.step_ms += ms;
@@ -171,22 +172,26 @@ int harvest(vd_sim *s)
     return VD_OK;
 }
 
+// The passes of one step run back to back between one pair of timing
+// events (events around every launch would add their own latency to each
+// short pass).
 int run_passes(vd_sim *s, const std::vector<Pass> &passes)
 {
+    if (passes.empty()) return VD_OK;
+    size_t slot = 0;
+    int r = record(s, 0, true, &slot, (int)passes.size());
+    if (r) return r;
     for (const Pass &p : passes) {
-        size_t slot = 0;
-        int r = record(s, 0, true, &slot);
-        if (r) return r;
         VD_HIP(vd::launch_flood(s->map[s->cur], s->map[s->cur ^ 1], s->pos, s->cfg.num_seeds,
                                 s->cfg.width, s->cfg.height, p.k, p.vn, s->cfg.label,
                                 s->cfg.metric, p.variant, p.seg_rows, s->stream));
-        r = record(s, 0, false, &slot);
-        if (r) return r;
         s->cur ^= 1;
-        if (s->timing && s->used >= 4096) {
-            r = harvest(s);
-            if (r) return r;
-        }
+    }
+    r = record(s, 0, false, &slot);
+    if (r) return r;
+    if (s->timing && s->used >= 4096) {
+        r = harvest(s);
+        if (r) return r;
     }
     return VD_OK;
 }

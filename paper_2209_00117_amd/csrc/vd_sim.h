@@ -20,7 +20,8 @@ struct Pass {
 
 struct EventPair {
     hipEvent_t a = nullptr, b = nullptr;
-    int kind = 0;   // 0: flood pass, 1: whole step
+    int kind = 0;     // 0: flood passes, 1: whole step
+    int count = 1;    // kind 0: passes between the two events
 };
 
 // Sets this thread's vd_last_error() message; returns status.

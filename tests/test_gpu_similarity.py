@@ -4,7 +4,7 @@ sim_bf: share of (sampled) pixels whose label's seed is at the exact nearest
 distance, from the oracle's exact nearest-seed search (all pixels of the
 small workload; 2^20 sampled pixels of the single and large workloads).
 sim_jfa: share of pixels whose dJFA label equals the JFA label (the paper's
-metric).  The paper reports dJFAe "nearly 100%" against JFA (Sec. VI-B);
+metric).  The paper finds dJFAe agreeing with JFA on close to all pixels (Sec. VI-B);
 the assertions hold the GPU to 99%.  The numbers are printed and written
 to gpurun_out/similarity.json when that folder exists.
 """

@@ -379,7 +379,7 @@ def test_djfa_reduces_to_jfa(orc):
 def test_djfa_small_workload(orc, label_mode):
     """512^2, 256 seeds, 5 steps of moves in [-1, 1]: every step covers the
     grid, keeps each seed's own pixel, and stays close to JFA and to the
-    exact diagram ("nearly 100%" for dJFAe, Sec. VI-B)."""
+    exact diagram (close to all pixels for dJFAe, Sec. VI-B)."""
     spec = inputs.small().sims[0]
     xy = spec.positions()
     d = orc.Sim(spec.width, spec.height, xy, spec.sim_seed, spec.disp_lo, spec.disp_hi,
