@@ -178,8 +178,9 @@ int vd_get_timing(vd_sim *sim, vd_timing *out);
  * written; 3 shares each row across a workgroup through LDS for steps up to
  * 128 (and is 1 above); 4 and 5 give each lane four adjacent columns
  * (16-byte loads and stores) and request rows 2 or 3 rows ahead where the
- * width is a multiple of 4, and are 3 (ID) or 1 (XY) for other widths; -1
- * restores the default
+ * width is a multiple of 4, and are 3 (ID) or 1 (XY) for other widths;
+ * 6-11 are 0-5 with non-temporal stores of the output map (faster when the
+ * two maps exceed the 256 MB Infinity Cache); -1 restores the default
  * (3 for ID labels, 1 for XY labels).  Variants differ in speed only: every
  * variant writes the same labels. */
 int vd_set_flood_variant(vd_sim *sim, int variant);
@@ -187,8 +188,11 @@ int vd_set_flood_variant(vd_sim *sim, int variant);
 /* Chooses, by timing, the kernel variant and the segment length of every
  * flood pass of this simulation's JFA and dJFA steps.  One JFA step (from
  * scratch on the current seeds) and one dJFA step (from the current
- * diagram) are replayed; before each pass every candidate runs reps times
- * (after one warm-up launch) on that pass's actual input.  The diagram is
+ * diagram) are replayed; before each pass every candidate with ordinary
+ * stores (variants 0-5) runs reps times (after one warm-up launch) on that
+ * pass's actual input.  Then each step kind's passes are replayed whole
+ * with the chosen kernels, with ordinary and with non-temporal stores, and
+ * the faster store policy is kept for all of them.  The diagram is
  * saved first and put back after (device scratch of width*height*4 bytes,
  * plus the seed table in XY mode, is allocated and freed), so the
  * simulation's state does not change.  The choices also enter a

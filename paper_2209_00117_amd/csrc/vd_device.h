@@ -46,6 +46,11 @@ constexpr int kTW = 256;           // flood pass: columns per workgroup (one per
 constexpr int kMaxSegRows = 32;    // flood pass: rows of one chain segment, at most
 constexpr int kLdsRow = kTW + 2 * kMaxLdsStep;   // entries of one shared row
 constexpr int32_t kRsrcWord3 = 0x00020000;   // buffer descriptor word 3 on gfx9 parts
+// Cache-policy operand of a buffer store: 0, or non-temporal (streamed past
+// the caches).  An output map is not read again within its pass; when the
+// maps do not fit in the Infinity Cache, non-temporal stores keep the
+// caches for the input rows and let HBM see long write streams.
+constexpr int kStoreNT = 2;
 
 typedef short short2_t __attribute__((ext_vector_type(2)));
 typedef vd_i32x4 i32x4;
@@ -80,7 +85,7 @@ __device__ __forceinline__ int32_t draw(uint64_t seed, uint64_t n, int32_t lo, u
 // workgroup owns 256 adjacent columns of a segment of one chain and walks it
 // downwards with a window of three input rows held in registers, so each
 // input row is fetched once per segment (plus two rows of overlap between
-// segments) whatever k is.  The next row is requested one iteration ahead.
+// segments) whatever k is.  Rows are requested P + 1 rows ahead of use.
 // Horizontal neighbours (x - k, x + k) are separate loads of the same row;
 // for k < 256 they fall in lines the workgroup fetches anyway, for larger k
 // in lines the workgroups of the neighbouring column tiles fetch.
@@ -215,7 +220,7 @@ __device__ __forceinline__ double cand_key(uint32_t p, const Ent &e)
 // y), c (row y + k), stored through `out` at byte offset oc.  A row off the
 // grid reads as unclaimed labels, whose sentinel keys lose to every claimed
 // candidate and tie with each other, so the edge rows need no special case.
-template <int METRIC, int VN>
+template <int METRIC, int VN, int ST>
 __device__ __forceinline__ void emit(__amdgpu_buffer_rsrc_t out, const Row &a, const Row &b,
                                      const Row &c, uint32_t p, int32_t oc)
 {
@@ -230,7 +235,7 @@ __device__ __forceinline__ void emit(__amdgpu_buffer_rsrc_t out, const Row &a, c
         best = __builtin_fmin(best, cand_key<METRIC>(p, c.w));
         best = __builtin_fmin(best, cand_key<METRIC>(p, c.e));
     }
-    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)__double2loint(best), out, oc, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b32((uint32_t)__double2loint(best), out, oc, 0, ST);
 }
 
 struct Tile {
@@ -276,7 +281,7 @@ __device__ __forceinline__ i32x4 table_rsrc(const uint32_t *table, uint32_t S)
 
 // One tile of a pass: 256 columns of one segment of one chain, walked with
 // a three-row register window (see the note above).
-template <int LABEL, int METRIC, int VN, int P>
+template <int LABEL, int METRIC, int VN, int P, int ST = 0>
 __device__ __forceinline__ void flood_chain_tile(const uint32_t *src, uint32_t *dst, i32x4 tab,
                                                  int32_t W, int32_t H, int32_t k,
                                                  const FloodGrid &g, uint32_t logical)
@@ -316,7 +321,7 @@ __device__ __forceinline__ void flood_chain_tile(const uint32_t *src, uint32_t *
         if (j >= jend) return false;
         load_labels(R[(u + NR - 1) % NR], cursor_rsrc(in, W, H), ow, oc, oe);
         lookup_positions<LABEL>(R[(u + NR - 2) % NR], R[(u + NR - 3) % NR], tab);
-        emit<METRIC, VN>(cursor_rsrc(out, W, H), R[u % NR], R[(u + 1) % NR], R[(u + 2) % NR], p,
+        emit<METRIC, VN, ST>(cursor_rsrc(out, W, H), R[u % NR], R[(u + 1) % NR], R[(u + 2) % NR], p,
                          oc);
         advance(in, step_bytes, k);
         advance(out, step_bytes, k);
@@ -350,7 +355,7 @@ struct Slot {
 // One tile of a pass with shared rows; `lds` holds two rows of kLdsRow
 // entries.  Callers must not let a previous use of `lds` overlap the first
 // exchange (a barrier between tiles suffices).
-template <int LABEL, int METRIC, int VN, int P>
+template <int LABEL, int METRIC, int VN, int P, int ST = 0>
 __device__ __forceinline__ void flood_lds_tile(const uint32_t *src, uint32_t *dst, i32x4 tab,
                                                int32_t W, int32_t H, int32_t k,
                                                const FloodGrid &g, uint32_t logical,
@@ -435,7 +440,7 @@ __device__ __forceinline__ void flood_lds_tile(const uint32_t *src, uint32_t *ds
         load(R[(u + NR - 1) % NR], cursor_rsrc(in, W, H));
         lookup(R[(u + NR - 2) % NR], R[(u + NR - 3) % NR].raw);
         exchange(R[(u + 2) % NR]);
-        emit<METRIC, VN>(cursor_rsrc(out, W, H), R[u % NR].win, R[(u + 1) % NR].win,
+        emit<METRIC, VN, ST>(cursor_rsrc(out, W, H), R[u % NR].win, R[(u + 1) % NR].win,
                          R[(u + 2) % NR].win, p, oc);
         advance(in, step_bytes, k);
         advance(out, step_bytes, k);

@@ -132,7 +132,7 @@ __global__ void __launch_bounds__(kBlock) k_relabel4(uint32_t *__restrict__ map,
             left_l = le;
             left_n = n[e];
         }
-        store4(n, row_rsrc(map, y, W, H), off);
+        store4<0>(n, row_rsrc(map, y, W, H), off);
         prev_l = l[0];
         prev_n = n[0];
     }
@@ -151,17 +151,17 @@ __global__ void __launch_bounds__(kBlock) k_export(const uint32_t *__restrict__ 
     }
 }
 
-template <int LABEL, int METRIC, int VN, int P>
+template <int LABEL, int METRIC, int VN, int P, int ST>
 __global__ void __launch_bounds__(kTW) k_flood(const uint32_t *__restrict__ src,
                                                uint32_t *__restrict__ dst,
                                                const uint32_t *__restrict__ table, uint32_t S,
                                                int32_t W, int32_t H, int32_t k, FloodGrid g)
 {
-    flood_chain_tile<LABEL, METRIC, VN, P>(src, dst, table_rsrc(table, S), W, H, k, g,
+    flood_chain_tile<LABEL, METRIC, VN, P, ST>(src, dst, table_rsrc(table, S), W, H, k, g,
                                            xcd_logical(blockIdx.x, g.nblocks));
 }
 
-template <int LABEL, int METRIC, int VN, int P>
+template <int LABEL, int METRIC, int VN, int P, int ST>
 __global__ void __launch_bounds__(kTW) k_flood_lds(const uint32_t *__restrict__ src,
                                                    uint32_t *__restrict__ dst,
                                                    const uint32_t *__restrict__ table,
@@ -169,20 +169,20 @@ __global__ void __launch_bounds__(kTW) k_flood_lds(const uint32_t *__restrict__ 
                                                    FloodGrid g)
 {
     __shared__ uint2 lds[2][kLdsRow];
-    flood_lds_tile<LABEL, METRIC, VN, P>(src, dst, table_rsrc(table, S), W, H, k, g,
+    flood_lds_tile<LABEL, METRIC, VN, P, ST>(src, dst, table_rsrc(table, S), W, H, k, g,
                                          xcd_logical(blockIdx.x, g.nblocks), lds);
 }
 
-template <int METRIC, int VN, int KC, int NS>
+template <int METRIC, int VN, int KC, int NS, int ST>
 __global__ void __launch_bounds__(kBlock) k_flood_quad_xy(const uint32_t *__restrict__ src,
                                                           uint32_t *__restrict__ dst, int32_t W,
                                                           int32_t H, int32_t k, FloodGrid g)
 {
-    flood_quad_xy_tile<METRIC, VN, KC, NS>(src, dst, W, H, k, g,
+    flood_quad_xy_tile<METRIC, VN, KC, NS, ST>(src, dst, W, H, k, g,
                                            xcd_logical(blockIdx.x, g.nblocks));
 }
 
-template <int METRIC, int VN, int KC, int NS>
+template <int METRIC, int VN, int KC, int NS, int ST>
 __global__ void __launch_bounds__(kBlock) k_flood_quad_id(const uint32_t *__restrict__ src,
                                                           uint32_t *__restrict__ dst,
                                                           const uint32_t *__restrict__ table,
@@ -190,18 +190,18 @@ __global__ void __launch_bounds__(kBlock) k_flood_quad_id(const uint32_t *__rest
                                                           int32_t k, FloodGrid g)
 {
     __shared__ QuadRow lds[2];
-    flood_quad_id_tile<METRIC, VN, KC, NS>(src, dst, table_rsrc(table, S), W, H, k, g,
+    flood_quad_id_tile<METRIC, VN, KC, NS, ST>(src, dst, table_rsrc(table, S), W, H, k, g,
                                            xcd_logical(blockIdx.x, g.nblocks), lds);
 }
 
-template <int METRIC, int VN, int NS>
+template <int METRIC, int VN, int NS, int ST>
 __global__ void __launch_bounds__(kBlock) k_flood_quad_idd(const uint32_t *__restrict__ src,
                                                            uint32_t *__restrict__ dst,
                                                            const uint32_t *__restrict__ table,
                                                            uint32_t S, int32_t W, int32_t H,
                                                            int32_t k, FloodGrid g)
 {
-    flood_quad_id_direct_tile<METRIC, VN, NS>(src, dst, table_rsrc(table, S), W, H, k, g,
+    flood_quad_id_direct_tile<METRIC, VN, NS, ST>(src, dst, table_rsrc(table, S), W, H, k, g,
                                               xcd_logical(blockIdx.x, g.nblocks));
 }
 
@@ -329,11 +329,14 @@ ItemGrid item_grid(int32_t W, int32_t H, int32_t k)
     return it;
 }
 
-hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *table, int32_t S,
-                        int32_t W, int32_t H, int32_t k, int32_t vn, int32_t label,
-                        int32_t metric, int32_t variant, int32_t seg_rows, hipStream_t s)
+namespace {
+
+// Variants 0-5 with store cache policy ST.
+template <int ST>
+hipError_t launch_flood_st(const uint32_t *src, uint32_t *dst, const uint32_t *table, int32_t S,
+                           int32_t W, int32_t H, int32_t k, int32_t vn, int32_t label,
+                           int32_t metric, int32_t variant, int32_t seg_rows, hipStream_t s)
 {
-    if (variant < 0 || variant >= kFloodVariants) return hipErrorInvalidValue;
     uint32_t uS = (uint32_t)S;
     if (variant >= 4) {
         if (!quad_ok(W, k)) {
@@ -345,13 +348,13 @@ hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *tabl
 #define VD_QUAD(MT, V, KC, NS)                                                                 \
     do {                                                                                       \
         if (label == kLabelId && k > kMaxLdsStep)                                              \
-            hipLaunchKernelGGL((k_flood_quad_idd<MT, V, NS>), grid, block, 0, s, src, dst,       \
+            hipLaunchKernelGGL((k_flood_quad_idd<MT, V, NS, ST>), grid, block, 0, s, src, dst,       \
                                table, uS, W, H, k, g);                                         \
         else if (label == kLabelId)                                                            \
-            hipLaunchKernelGGL((k_flood_quad_id<MT, V, KC, NS>), grid, block, 0, s, src, dst,    \
+            hipLaunchKernelGGL((k_flood_quad_id<MT, V, KC, NS, ST>), grid, block, 0, s, src, dst,    \
                                table, uS, W, H, k, g);                                         \
         else                                                                                   \
-            hipLaunchKernelGGL((k_flood_quad_xy<MT, V, KC, NS>), grid, block, 0, s, src, dst, W, \
+            hipLaunchKernelGGL((k_flood_quad_xy<MT, V, KC, NS, ST>), grid, block, 0, s, src, dst, W, \
                                H, k, g);                                                       \
     } while (0)
 #define VD_QUAD_NS(MT, V, KC)                                                                  \
@@ -379,10 +382,10 @@ hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *tabl
     if (g.nblocks == 0) return hipErrorInvalidValue;
     dim3 grid(g.nblocks), block(kTW);
 #define VD_LAUNCH(LB, MT, V, P)                                                              \
-    hipLaunchKernelGGL((k_flood<LB, MT, V, P>), grid, block, 0, s, src, dst, table, uS, W, H,  \
+    hipLaunchKernelGGL((k_flood<LB, MT, V, P, ST>), grid, block, 0, s, src, dst, table, uS, W, H,  \
                        k, g)
 #define VD_LAUNCH_LDS(LB, MT, V, P)                                                           \
-    hipLaunchKernelGGL((k_flood_lds<LB, MT, V, P>), grid, block, 0, s, src, dst, table, uS, W,  \
+    hipLaunchKernelGGL((k_flood_lds<LB, MT, V, P, ST>), grid, block, 0, s, src, dst, table, uS, W,  \
                        H, k, g)
 #define VD_LAUNCH_P(LB, MT, V)                                                                \
     do {                                                                                      \
@@ -408,6 +411,20 @@ hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *tabl
 #undef VD_LAUNCH_LDS
 #undef VD_LAUNCH
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *table, int32_t S,
+                        int32_t W, int32_t H, int32_t k, int32_t vn, int32_t label,
+                        int32_t metric, int32_t variant, int32_t seg_rows, hipStream_t s)
+{
+    if (variant < 0 || variant >= kFloodVariants) return hipErrorInvalidValue;
+    if (variant >= kFloodVariants / 2)
+        return launch_flood_st<kStoreNT>(src, dst, table, S, W, H, k, vn, label, metric,
+                                         variant - kFloodVariants / 2, seg_rows, s);
+    return launch_flood_st<0>(src, dst, table, S, W, H, k, vn, label, metric, variant, seg_rows,
+                              s);
 }
 
 }  // namespace vd

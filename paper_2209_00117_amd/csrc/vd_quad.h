@@ -91,9 +91,10 @@ __device__ __forceinline__ u32x4 load4(__amdgpu_buffer_rsrc_t r, int32_t off)
     return __builtin_bit_cast(u32x4, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
 
+template <int ST>
 __device__ __forceinline__ void store4(u32x4 v, __amdgpu_buffer_rsrc_t r, int32_t off)
 {
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, v), r, off, 0, ST);
 }
 
 // Seed positions of four ID labels, reusing those of the same columns k
@@ -143,7 +144,7 @@ constexpr int kSteady = 1 << 20;
 // `fetch(Slot)` returns the row in a slot as a Three.  The loop is unrolled
 // lcm(3, NS) times, so every slot and accumulator index is a compile-time
 // constant and the ring lives in registers.
-template <int METRIC, int VN, int KC, int NS, class Request, class Fetch>
+template <int METRIC, int VN, int KC, int NS, int ST, class Request, class Fetch>
 __device__ __forceinline__ void quad_walk(uint32_t *dst, int32_t W, int32_t H, int32_t k,
                                           const TileQ &tl, int32_t oc, Request &request,
                                           Fetch &fetch)
@@ -190,7 +191,7 @@ __device__ __forceinline__ void quad_walk(uint32_t *dst, int32_t W, int32_t H, i
         prow[c2] = prow[c1] + pk;
         const Three t = fetch(IC<u % NS>{});
         fold<METRIC, KC, VN != 0, false>(acc[c0], prow[c0], t);
-        store4(labels_of(acc[c0]), cursor_rsrc(out, W, H), oc);
+        store4<ST>(labels_of(acc[c0]), cursor_rsrc(out, W, H), oc);
         fold<METRIC, KC, false, false>(acc[c1], prow[c1], t);
         fold<METRIC, KC, VN != 0, true>(acc[c2], prow[c2], t);
         advance(out, step_bytes, k);
@@ -205,7 +206,7 @@ __device__ __forceinline__ void quad_walk(uint32_t *dst, int32_t W, int32_t H, i
 // XY labels: positions are the labels, so a lane loads its three groups of
 // each row directly (the neighbouring groups come from L2) and needs no
 // exchange.  Input rows are requested NS - 1 rows ahead into a ring of NS.
-template <int METRIC, int VN, int KC, int NS>
+template <int METRIC, int VN, int KC, int NS, int ST>
 __device__ __forceinline__ void flood_quad_xy_tile(const uint32_t *src, uint32_t *dst,
                                                    int32_t W, int32_t H, int32_t k,
                                                    const FloodGrid &g, uint32_t logical)
@@ -237,7 +238,7 @@ __device__ __forceinline__ void flood_quad_xy_tile(const uint32_t *src, uint32_t
         const u32x4 *q = ring[decltype(Slot)::value];
         return Three{{q[0], q[0]}, {q[1], q[1]}, {q[2], q[2]}};
     };
-    quad_walk<METRIC, VN, KC, NS>(dst, W, H, k, tl, oc, request, fetch);
+    quad_walk<METRIC, VN, KC, NS, ST>(dst, W, H, k, tl, oc, request, fetch);
 }
 
 // ID labels at large steps (k > kMaxLdsStep, a multiple of 4): the groups
@@ -245,7 +246,7 @@ __device__ __forceinline__ void flood_quad_xy_tile(const uint32_t *src, uint32_t
 // its three groups itself and looks up all twelve positions (each reused
 // where the label repeats k rows up).  Labels are requested NS - 1 rows
 // ahead of use and looked up one row ahead of use.
-template <int METRIC, int VN, int NS>
+template <int METRIC, int VN, int NS, int ST>
 __device__ __forceinline__ void flood_quad_id_direct_tile(const uint32_t *src, uint32_t *dst,
                                                           i32x4 tab, int32_t W, int32_t H,
                                                           int32_t k, const FloodGrid &g,
@@ -282,7 +283,7 @@ __device__ __forceinline__ void flood_quad_id_direct_tile(const uint32_t *src, u
         }
     };
     auto fetch = [&](auto Slot) -> Three { return ring[decltype(Slot)::value]; };
-    quad_walk<METRIC, VN, 0, NS>(dst, W, H, k, tl, oc, request, fetch);
+    quad_walk<METRIC, VN, 0, NS, ST>(dst, W, H, k, tl, oc, request, fetch);
 }
 
 // Shared rows of the ID tile, in groups of four entries: entry e is column
@@ -301,7 +302,7 @@ struct QuadRow {
 // alternate, and the barrier of each exchange also orders the reuse of the
 // row written two exchanges earlier.  Callers must not let a previous use
 // of `lds` overlap the first exchange (a barrier between tiles suffices).
-template <int METRIC, int VN, int KC, int NS>
+template <int METRIC, int VN, int KC, int NS, int ST>
 __device__ __forceinline__ void flood_quad_id_tile(const uint32_t *src, uint32_t *dst, i32x4 tab,
                                                    int32_t W, int32_t H, int32_t k,
                                                    const FloodGrid &g, uint32_t logical,
@@ -374,7 +375,7 @@ __device__ __forceinline__ void flood_quad_id_tile(const uint32_t *src, uint32_t
         th.c.s = row->s[gc];
         return th;
     };
-    quad_walk<METRIC, VN, KC, NS>(dst, W, H, k, tl, oc, request, fetch);
+    quad_walk<METRIC, VN, KC, NS, ST>(dst, W, H, k, tl, oc, request, fetch);
 }
 
 }  // namespace

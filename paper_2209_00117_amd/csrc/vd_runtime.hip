@@ -332,8 +332,14 @@ int vd_autotune(vd_sim *s, int32_t reps)
     struct Cand {
         int32_t variant, seg_rows;
     };
+    // Kernel and segment length are chosen per pass among the variants with
+    // ordinary stores; whether the output maps are stored non-temporally is
+    // then chosen per step kind from whole replayed steps, because it
+    // changes the speed of the next pass (which finds, or does not find,
+    // its input in the Infinity Cache), not of the pass that stores.
+    constexpr int32_t kBase = vd::kFloodVariants / 2;
     std::vector<Cand> cands;
-    for (int32_t v = 0; v < vd::kFloodVariants; ++v)
+    for (int32_t v = 0; v < kBase; ++v)
         for (int32_t L : kSegRows) cands.push_back({v, L});
     const std::string arch = arch_name();
     const size_t npix = (size_t)c.width * c.height;
@@ -349,6 +355,7 @@ int vd_autotune(vd_sim *s, int32_t reps)
         return fail(VD_ENOMEM, "autotune needs %zu bytes of device scratch", npix * 4 + tab_bytes);
     }
     std::vector<std::string> keys;     // distinct passes, in replay order
+    std::vector<int> key_dyn;          // their step kind (1: dJFA)
     std::vector<hipEvent_t> ev;        // two per (pass, candidate)
     int r = VD_OK;
     auto hip = [&](hipError_t e, const char *what) {
@@ -388,6 +395,7 @@ int vd_autotune(vd_sim *s, int32_t reps)
             };
             if (fresh) {
                 keys.push_back(key);
+                key_dyn.push_back(dyn);
                 for (const Cand &cd : cands) {
                     hipEvent_t e0 = nullptr, e1 = nullptr;
                     if (!hip(hipEventCreate(&e0), "hipEventCreate")) break;
@@ -405,8 +413,9 @@ int vd_autotune(vd_sim *s, int32_t reps)
         }
     }
     hip(hipStreamSynchronize(s->stream), "hipStreamSynchronize");
+    std::map<std::string, Cand> picks;
+    std::map<std::string, float> pick_us;
     if (r == VD_OK && ev.size() == 2 * keys.size() * cands.size()) {
-        std::lock_guard<std::mutex> lock(g_tune_mu);
         for (size_t i = 0; i < keys.size(); ++i) {
             float best = 1e30f;
             Cand pick = cands[0];
@@ -418,8 +427,56 @@ int vd_autotune(vd_sim *s, int32_t reps)
                     pick = cands[j];
                 }
             }
-            g_tune[keys[i]] = {pick.variant, pick.seg_rows};
-            g_tune_us[keys[i]] = 1e3f * best / reps;
+            picks[keys[i]] = pick;
+            pick_us[keys[i]] = 1e3f * best / reps;
+        }
+    }
+    // Store policy per step kind: replay the step's passes with the picks,
+    // with ordinary and with non-temporal stores, twice each; keep the faster.
+    bool nt[2] = {false, false};
+    for (int dyn = 0; dyn < 2 && r == VD_OK; ++dyn) {
+        const std::vector<Pass> &passes = dyn ? s->djfa_passes : s->jfa_passes;
+        float best[2] = {1e30f, 1e30f};
+        for (int trial = 0; trial < 4 && r == VD_OK; ++trial) {
+            const int policy = trial & 1;
+            hip(hipMemcpyAsync(s->map[s->cur], save, npix * 4, hipMemcpyDeviceToDevice,
+                               s->stream), "restore");
+            if (save_pm)
+                hip(hipMemcpyAsync(s->pos_map, save_pm, tab_bytes, hipMemcpyDeviceToDevice,
+                                   s->stream), "restore");
+            if (r == VD_OK) {
+                int pr = dyn ? djfa_prologue(s) : jfa_prologue(s);
+                if (pr) r = pr;
+            }
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (!hip(hipEventCreate(&e0), "hipEventCreate")) break;
+            ev.push_back(e0);
+            if (!hip(hipEventCreate(&e1), "hipEventCreate")) break;
+            ev.push_back(e1);
+            hip(hipEventRecord(e0, s->stream), "hipEventRecord");
+            for (const Pass &p : passes) {
+                if (r != VD_OK) break;
+                const Cand &c0 = picks[tune_key(arch, c, p, dyn != 0)];
+                const int32_t v = c0.variant + (policy ? kBase : 0);
+                if (hip(vd::launch_flood(s->map[s->cur], s->map[s->cur ^ 1], s->pos,
+                                         c.num_seeds, c.width, c.height, p.k, p.vn, c.label,
+                                         c.metric, v, c0.seg_rows, s->stream), "launch"))
+                    s->cur ^= 1;
+            }
+            hip(hipEventRecord(e1, s->stream), "hipEventRecord");
+            float ms = 0.f;
+            if (hip(hipEventSynchronize(e1), "hipEventSynchronize") &&
+                hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime") && ms < best[policy])
+                best[policy] = ms;
+        }
+        nt[dyn] = best[1] < best[0];
+    }
+    if (r == VD_OK && !picks.empty()) {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        for (size_t i = 0; i < keys.size(); ++i) {
+            const Cand &pk = picks[keys[i]];
+            g_tune[keys[i]] = {pk.variant + (nt[key_dyn[i]] ? kBase : 0), pk.seg_rows};
+            g_tune_us[keys[i]] = pick_us[keys[i]];
         }
     }
     // put the diagram back where the simulation expects it

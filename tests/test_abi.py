@@ -95,5 +95,5 @@ def test_tuning_table_round_trip():
     t = V.tuning_export()
     assert t["gfx950 64x64 S10 id euclid k32 moore"] == [3, 16]
     assert t["gfx950 64x64 S10 xy euclid k1 vn"] == [1, 0]
-    for bad in ("no separators\n", "k|9|0\n", "k|1|999\n"):
+    for bad in ("no separators\n", "k|99|0\n", "k|-1|0\n", "k|1|999\n"):
         assert V.lib().vd_tuning_import(bad.encode()) == -1

@@ -108,7 +108,7 @@ def test_ragged_and_degenerate(V, W, H, S, steps, lo, hi, label):
     run_twin(V, W, H, xy, steps, lo, hi, sim_seed=W + H, label=label, tag="ragged")
 
 
-@pytest.mark.parametrize("variant", [None, 4, 5])
+@pytest.mark.parametrize("variant", [None, 4, 5, 10])
 @pytest.mark.parametrize("metric,vn,extra", [
     (1, 2, 0), (0, 0, 0), (0, 1, 1), (0, 2, 2), (1, 1, 2), (0, 5, 0),
 ])
@@ -122,7 +122,7 @@ def test_pass_options(V, metric, vn, extra, variant):
 # Widths: below, at and across the 256- and 1024-column tiles, one not a
 # multiple of 4 (the four-column kernels then fall back); heights with
 # ragged chains.
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5, 6, 9, 10, 11])
 @pytest.mark.parametrize("W,H,S", [(100, 90, 40), (700, 450, 900), (1100, 300, 5000),
                                    (257, 1200, 600), (2060, 340, 3000), (1024, 1030, 700)])
 def test_flood_variants(V, variant, W, H, S):
@@ -181,7 +181,7 @@ def test_autotune_keeps_results(V, label):
     V.autotune(a.handle, 2)
     assert np.array_equal(a.read_map(), m_before)          # tuning leaves the state alone
     tuned = V.get_tuning(a.handle)
-    assert all(0 <= v < 6 and r in (0, 8, 16, 64) for v, r in tuned)
+    assert all(0 <= v < 12 and r in (0, 8, 16, 64) for v, r in tuned)
     assert all(us > 0 for us in V.get_tuning_us(a.handle))
     c = V.Sim(W, H, xy, **kw)                               # adopts the process-wide table
     assert V.get_tuning(c.handle) == tuned
