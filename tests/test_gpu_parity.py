@@ -108,6 +108,26 @@ def test_ragged_and_degenerate(V, W, H, S, steps, lo, hi, label):
     run_twin(V, W, H, xy, steps, lo, hi, sim_seed=W + H, label=label, tag="ragged")
 
 
+# Degenerate shapes for the four-column kernels (widths divisible by 4):
+# one column group, one row, short chains (k >= H), a second tile holding a
+# single group, every pixel a seed, seeds piled on the borders by drift.
+@pytest.mark.parametrize("variant", [4, 5, 10, 11])
+@pytest.mark.parametrize("W,H,S,steps,lo,hi", [
+    (4, 4, 1, 2, -1, 1),
+    (4, 37, 5, 3, -1, 1),
+    (8, 1, 3, 3, -2, 2),
+    (1024, 3, 50, 2, -2, 2),
+    (1028, 64, 500, 2, -1, 1),
+    (64, 64, 4096, 2, -1, 1),
+    (260, 129, 300, 5, -1, 3),
+])
+@pytest.mark.parametrize("label", [0, 1])
+def test_quad_degenerate(V, W, H, S, steps, lo, hi, label, variant):
+    xy = inputs.place_seeds(W, H, S, W * 5 + H)
+    run_twin(V, W, H, xy, steps, lo, hi, sim_seed=W + 2 * H, label=label, variant=variant,
+             tag="quad")
+
+
 @pytest.mark.parametrize("variant", [None, 4, 5, 10])
 @pytest.mark.parametrize("metric,vn,extra", [
     (1, 2, 0), (0, 0, 0), (0, 1, 1), (0, 2, 2), (1, 1, 2), (0, 5, 0),
