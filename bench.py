@@ -12,6 +12,11 @@ width*height*(JFA passes + dJFA passes) per step, divided by the measured
 time of the whole step (moves, fills and splats included).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload single]
+                  [--label id|xy] [--with-djfam] [--no-tune]
+
+--with-djfam adds a "djfam" block: a Manhattan-metric dJFA twin (Sec. V-C)
+timed in a loop of its own, with T_dJFAe/T_dJFAm and its similarity to the
+Euclidean JFA map.
 """
 from __future__ import annotations
 
@@ -272,6 +277,37 @@ def bench_serving(torch, inputs, V, args):
     print(json.dumps(line), flush=True)
 
 
+def bench_djfam(torch, V, args, W, H, xy, kw, stream, map_jfa, djfae_ms, jfa_ms):
+    """dJFAm (Sec. V-C): a twin with the Manhattan metric and the same seed
+    trajectory, stepped as many times as the main twins (tuned, warmed up
+    and timed the same way, in a loop of its own), then compared with the
+    Euclidean JFA map of the same step."""
+    km = dict(kw, metric=V.MANHATTAN)
+    sm = V.Sim(W, H, xy, stream=stream, **km)
+    if not args.no_tune:
+        V.autotune(sm.handle, 3)
+    for _ in range(args.warmup):
+        sm.move_seeds()
+        sm.djfa_step()
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(2)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    for i in range(args.steps):
+        sm.move_seeds()
+        ev[i][0].record(stream)
+        sm.djfa_step()
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    ms = [e[0].elapsed_time(e[1]) for e in ev]
+    mm = sm.read_map()
+    info = sm.info()
+    sm.close()
+    t = float(np.mean(ms))
+    return {"ms_per_step": t, "p50_ms": pct(ms, 50), "p99_ms": pct(ms, 99),
+            "pixel_updates_per_s": W * H * info.passes_djfa / (t / 1e3),
+            "speedup_vs_jfa": jfa_ms / t, "speedup_djfae_vs_djfam": djfae_ms / t,
+            "similarity_vs_jfa": float((mm == map_jfa).mean())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -286,6 +322,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-pass-timing", action="store_true")
+    ap.add_argument("--with-djfam", action="store_true",
+                    help="also time a Manhattan dJFA twin (dJFAm, Sec. V-C) after the main "
+                         "loop and report T_dJFAe/T_dJFAm and its similarity to JFA")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (run every pass with the default kernel variant)")
     ap.add_argument("--calibrate", action="store_true",
@@ -427,6 +466,9 @@ def main():
         "cpu_baseline": None,
         "tuning": tuning,
     }
+    if args.with_djfam:
+        out["djfam"] = bench_djfam(torch, V, args, W, H, xy, kw, stream, mj,
+                                   float(np.mean(djfa_ms)), float(np.mean(jfa_ms)))
     sj.close(), sd.close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec, xy, args.cpu_budget)

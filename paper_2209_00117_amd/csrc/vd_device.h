@@ -204,15 +204,20 @@ __device__ __forceinline__ bool expand(F &f)
 template <int METRIC>
 __device__ __forceinline__ double cand_key(uint32_t p, const Ent &e)
 {
-    short2_t dv = __builtin_bit_cast(short2_t, p) - __builtin_bit_cast(short2_t, e.s);
     int32_t d;
-    // The clamped form cannot saturate (d < 2^31, see above); it makes the
-    // compiler emit the three-operand v_dot2 with an inline zero rather
-    // than the accumulating form plus a move of zero into the accumulator.
-    if (METRIC == kEuclid)
+    if (METRIC == kEuclid) {
+        // The clamped form cannot saturate (d < 2^31, see above); it makes
+        // the compiler emit the three-operand v_dot2 with an inline zero
+        // rather than the accumulating form plus a move of zero into the
+        // accumulator.
+        short2_t dv = __builtin_bit_cast(short2_t, p) - __builtin_bit_cast(short2_t, e.s);
         d = __builtin_amdgcn_sdot2(dv, dv, 0, true);
-    else
-        d = abs((int32_t)dv.x) + abs((int32_t)dv.y);
+    } else {
+        // v_sad_u16 sums the absolute differences of both 16-bit halves, and
+        // both halves of a packed position are a coordinate plus 16384, so
+        // one instruction gives |dx| + |dy| exactly.
+        d = (int32_t)__builtin_amdgcn_sad_u16(p, e.s, 0);
+    }
     return __hiloint2double(d, (int32_t)e.l);
 }
 

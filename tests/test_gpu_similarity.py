@@ -4,7 +4,8 @@ sim_bf: share of (sampled) pixels whose label's seed is at the exact nearest
 distance, from the oracle's exact nearest-seed search (all pixels of the
 small workload; 2^20 sampled pixels of the single and large workloads).
 sim_jfa: share of pixels whose dJFA label equals the JFA label (the paper's
-metric).  The paper finds dJFAe agreeing with JFA on close to all pixels (Sec. VI-B);
+metric).  The same two figures are reported for dJFAm, a Manhattan-metric
+dJFA twin on the same seed trajectory, against the Euclidean references.  The paper finds dJFAe agreeing with JFA on close to all pixels (Sec. VI-B);
 the assertions hold the GPU to 99%.  The numbers are printed and written
 to gpurun_out/similarity.json when that folder exists.
 """
@@ -41,6 +42,7 @@ def test_similarity_per_workload(V, name, steps):
     xy = spec.positions()
     kw = dict(disp_lo=spec.disp_lo, disp_hi=spec.disp_hi, sim_seed=spec.sim_seed)
     sj, sd = V.Sim(W, H, xy, **kw), V.Sim(W, H, xy, **kw)
+    sm = V.Sim(W, H, xy, metric=V.MANHATTAN, **kw)      # dJFAm (Sec. V-C), same trajectory
     if wl.sample_pixels:
         px, py = inputs.sample_pixels(W, H, wl.sample_pixels, seed=7)
     else:
@@ -48,18 +50,25 @@ def test_similarity_per_workload(V, name, steps):
         px, py = xx.ravel().astype(np.int32), yy.ravel().astype(np.int32)
     rows = []
     for t in range(1, steps + 1):
-        sj.move_seeds(), sd.move_seeds()
-        sj.jfa_step(), sd.djfa_step()
+        sj.move_seeds(), sd.move_seeds(), sm.move_seeds()
+        sj.jfa_step(), sd.djfa_step(), sm.djfa_step()
         pos = sd.read_seeds()
         _, nd = O.nearest(pos, W, H, px, py)
-        md, mj = sd.read_map(), sj.read_map()
+        md, mj, mm = sd.read_map(), sj.read_map(), sm.read_map()
         bf_d = O.count_exact(md, pos, px, py, nd) / len(px)
         bf_j = O.count_exact(mj, pos, px, py, nd) / len(px)
+        bf_m = O.count_exact(mm, pos, px, py, nd) / len(px)
         sim_jfa = O.count_equal(md, mj) / md.size
-        rows.append({"t": t, "djfa_vs_exact": bf_d, "jfa_vs_exact": bf_j, "djfa_vs_jfa": sim_jfa})
+        sim_m = O.count_equal(mm, mj) / mm.size
+        rows.append({"t": t, "djfa_vs_exact": bf_d, "jfa_vs_exact": bf_j, "djfa_vs_jfa": sim_jfa,
+                     "djfam_vs_exact": bf_m, "djfam_vs_jfa": sim_m})
         print(f"[similarity] {name} t={t} dJFA vs exact {100 * bf_d:.4f}%  JFA vs exact "
-              f"{100 * bf_j:.4f}%  dJFA vs JFA {100 * sim_jfa:.4f}%", flush=True)
+              f"{100 * bf_j:.4f}%  dJFA vs JFA {100 * sim_jfa:.4f}%  dJFAm vs exact "
+              f"{100 * bf_m:.4f}%  dJFAm vs JFA {100 * sim_m:.4f}%", flush=True)
         assert bf_d >= 0.99 and sim_jfa >= 0.99
+        # dJFAm is reported, not held to a bound from the paper (which shows it
+        # well below dJFAe); this only catches a broken diagram
+        assert bf_m >= 0.5 and sim_m >= 0.5
     RESULTS[name] = {"workload": wl.name, "sampled_pixels": int(len(px)), "steps": rows}
     out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
     if os.path.isdir(out):
