@@ -119,10 +119,12 @@ def calibrate(torch, nbytes=512 << 20, reps=20):
 
 def bench_batched(torch, inputs, V, args):
     """64 simulations of uneven sizes.  Timed three ways on the same GPU,
-    each over args.steps time steps (move + step): fused batched dJFA and
-    fused batched JFA (one persistent launch per pass level, replayed as a
-    hipGraph), and the same 64 simulations run one at a time with plain JFA
-    (per-simulation launches).  Every batched member's map equals its
+    each over args.steps time steps (move + step): batched dJFA and batched
+    JFA (batched moves, fills and splats, one persistent launch per pass
+    level over the members that the batch autotuner keeps together, the
+    larger members' passes with their own launches; the whole step replayed
+    as a hipGraph), and the same 64 simulations run one at a time with plain
+    JFA (per-simulation launches, default kernel variants).  Every batched member's map equals its
     one-at-a-time run bit for bit (tests/test_gpu_batch.py)."""
     wl = inputs.batched()
     stream = torch.cuda.current_stream()
@@ -138,6 +140,8 @@ def bench_batched(torch, inputs, V, args):
     for name, mode in (("batched_djfa", V.STEP_DJFA), ("batched_jfa", V.STEP_JFA)):
         sims = make()
         b = V.Batch(sims, stream=stream)
+        if not args.no_tune:
+            b.autotune(3)   # untimed: persistent grid and which members run solo
         b.set_graph(not args.no_graph)
         lj, ld, grid = b.info()
         upd = sum(s.width * s.height * (sm.info().passes_djfa if mode == V.STEP_DJFA

@@ -180,9 +180,11 @@ int vd_get_timing(vd_sim *sim, vd_timing *out);
  * (16-byte loads and stores) and request rows 2 or 3 rows ahead where the
  * width is a multiple of 4, and are 3 (ID) or 1 (XY) for other widths;
  * 6-11 are 0-5 with non-temporal stores of the output map (faster when the
- * two maps exceed the 256 MB Infinity Cache); -1 restores the default
- * (3 for ID labels, 1 for XY labels).  Variants differ in speed only: every
- * variant writes the same labels. */
+ * two maps exceed the 256 MB Infinity Cache); -1 restores the defaults:
+ * per pass, 4 in JFA and 3 in dJFA steps for ID labels, 4 for JFA steps of
+ * k >= 512 and 1 otherwise for XY labels, plus 6 where the two maps exceed
+ * 192 MiB.  Variants differ in speed only: every variant writes the same
+ * labels. */
 int vd_set_flood_variant(vd_sim *sim, int variant);
 
 /* Chooses, by timing, the kernel variant and the segment length of every
@@ -267,11 +269,22 @@ int vd_batch_set_graph(vd_batch *b, int enable);
 int vd_batch_set_shape(vd_batch *b, int32_t wg_per_cu);
 
 /* Chooses by timing, separately for JFA and dJFA steps, the persistent
- * grid (1, 2, 4 or 8 workgroups per compute unit, or as many as fit): each
- * candidate runs every pass level reps times reading the current diagrams
- * and writing the idle buffers, so no simulation changes.  Drops captured
- * graphs.  Waits for the stream. */
+ * grid (1, 2, 4 or 8 workgroups per compute unit, or as many as fit) and
+ * which members run solo (none, or all members of at least one of the
+ * members' sizes; see vd_batch_set_solo): each candidate runs the step's
+ * flood work reps times reading the current diagrams and writing the idle
+ * buffers, so no simulation changes.  Drops captured graphs.  Waits for the
+ * stream. */
 int vd_batch_autotune(vd_batch *b, int32_t reps);
+
+/* Members of at least min_pixels pixels (<= 0: none) run the passes of
+ * `mode` steps solo: with their own launches and kernel variants (as
+ * chosen by vd_autotune / vd_set_flood_variant), one member after another,
+ * so each member's maps stay in the Infinity Cache across its passes; the
+ * others share one persistent launch per pass level.  Move, fill, splat and
+ * the step's bookkeeping stay batched.  Results do not change.  Drops
+ * captured graphs; waits for the stream. */
+int vd_batch_set_solo(vd_batch *b, int32_t mode, int64_t min_pixels);
 
 /* Per-level flood and per-step timing with HIP events, as for a single
  * simulation (not recorded inside captured graphs: with graphs on, only

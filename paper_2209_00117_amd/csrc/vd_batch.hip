@@ -20,6 +20,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <functional>
+#include <limits>
+#include <map>
 #include <new>
 #include <vector>
 
@@ -260,8 +263,21 @@ struct vd_batch {
     int32_t grid[2] = {0, 0};     // persistent flood workgroups per mode
     int32_t fit = 1;              // flood workgroups that fit on one CU
     int32_t cus = 1;
+    // Members of at least solo_px[mode] pixels run that step kind's passes
+    // with their own launches (their tuned kernels, their maps kept in the
+    // Infinity Cache across passes) instead of joining the persistent
+    // levels; the batch's move, fill, splat and end kernels cover everyone.
+    int64_t solo_px[2] = {std::numeric_limits<int64_t>::max(),
+                          std::numeric_limits<int64_t>::max()};
+    std::vector<char> solo[2];
+    int64_t solo_pixels[2] = {0, 0};   // pixel-updates of the solo passes of a step
+    int32_t solo_passes[2] = {0, 0};
     bool use_graph = false;
-    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [mode][moved]
+    // Captured steps, keyed by (mode, moved, current map of each solo
+    // member): solo launches name their maps directly, so a step is
+    // captured once per parity configuration it meets (at most two in a
+    // loop of one step kind).
+    std::map<std::vector<char>, hipGraphExec_t> graphs;
     hipStream_t capture = nullptr;   // private stream to capture on (the caller's may be
                                      // the null stream, which cannot be captured)
     bool timing = false;
@@ -313,7 +329,12 @@ int batch_harvest(vd_batch *b)
         float ms = 0.f;
         VD_HIP(hipEventElapsedTime(&ms, b->pool[i].a, b->pool[i].b));
         int kind = b->pool[i].kind;
-        if (kind >= 2) {   // flood level: kind = 2 + mode * kMaxLevels + level
+        if (kind >= 2 + 2 * vd::kMaxLevels) {   // solo passes of a step: 2 + 2 kMaxLevels + mode
+            const int mode = kind - 2 - 2 * vd::kMaxLevels;
+            b->acc.flood_launches += b->solo_passes[mode];
+            b->acc.flood_ms += ms;
+            b->acc.flood_pixels += b->solo_pixels[mode];
+        } else if (kind >= 2) {   // flood level: kind = 2 + mode * kMaxLevels + level
             int mode = (kind - 2) / vd::kMaxLevels, level = (kind - 2) % vd::kMaxLevels;
             b->acc.flood_launches += 1;
             b->acc.flood_ms += ms;
@@ -348,6 +369,27 @@ hipError_t launch_level(vd_batch *b, int mode, int32_t lvl, int32_t parity_level
     return hipGetLastError();
 }
 
+// The passes of the solo members, each with its own kernels, from the map
+// the host mirror names current (the batch keeps the mirror in step with
+// the device state).  `tuning`: every pass reads the current map and writes
+// the idle one, so nothing changes.
+int enqueue_solo(vd_batch *b, int mode, bool tuning, hipStream_t stream)
+{
+    for (size_t i = 0; i < b->sims.size(); ++i) {
+        if (!b->solo[mode][i]) continue;
+        const vd_sim *s = b->sims[i];
+        const vd_config &c = s->cfg;
+        int cur = s->cur;
+        for (const vd::Pass &p : mode == VD_STEP_DJFA ? s->djfa_passes : s->jfa_passes) {
+            VD_HIP(vd::launch_flood(s->map[cur], s->map[cur ^ 1], s->pos, c.num_seeds, c.width,
+                                    c.height, p.k, p.vn, c.label, c.metric, p.variant,
+                                    p.seg_rows, stream));
+            if (!tuning) cur ^= 1;
+        }
+    }
+    return VD_OK;
+}
+
 // Enqueues one batch step on `stream` (b->stream, or the capture stream
 // while a graph is recorded; then timing is off).
 int enqueue_step(vd_batch *b, int mode, int moved, hipStream_t stream)
@@ -380,6 +422,15 @@ int enqueue_step(vd_batch *b, int mode, int moved, hipStream_t stream)
     hipLaunchKernelGGL(vd::k_batch_splat<false>, gseeds, blk, 0, stream, sims,
                        (const vd::DevState *)st);
     VD_HIP(hipGetLastError());
+    if (b->solo_passes[mode] > 0) {
+        size_t slot = 0;
+        int r = batch_record(b, 2 + 2 * vd::kMaxLevels + mode, true, &slot);
+        if (r) return r;
+        r = enqueue_solo(b, mode, false, stream);
+        if (r) return r;
+        r = batch_record(b, 0, false, &slot);
+        if (r) return r;
+    }
     for (int32_t lvl = 0; lvl < b->levels[mode]; ++lvl) {
         size_t slot = 0;
         int r = batch_record(b, 2 + mode * vd::kMaxLevels + lvl, true, &slot);
@@ -417,12 +468,121 @@ int32_t grid_for(const vd_batch *b, int32_t wg_per_cu)
 
 void drop_graphs(vd_batch *b)
 {
-    for (auto &row : b->graph)
-        for (hipGraphExec_t &g : row)
-            if (g) {
-                (void)hipGraphExecDestroy(g);
-                g = nullptr;
+    for (auto &kv : b->graphs)
+        if (kv.second) (void)hipGraphExecDestroy(kv.second);
+    b->graphs.clear();
+}
+
+// Key of the captured step: mode, moved, and the current map of each solo
+// member.
+std::vector<char> graph_key(const vd_batch *b, int mode, int moved)
+{
+    std::vector<char> key = {(char)mode, (char)moved};
+    for (size_t i = 0; i < b->sims.size(); ++i)
+        if (b->solo[mode][i]) key.push_back((char)b->sims[i]->cur);
+    return key;
+}
+
+// Builds and uploads the device tables from the members' host state: the
+// members, their current map and time step, and per step kind the levels of
+// the persistent passes over the members that do not run solo.  Waits for
+// the batch's stream (no step may be in flight while the tables change).
+int build_tables(vd_batch *b)
+{
+    const int32_t n = (int32_t)b->sims.size();
+    VD_HIP(hipStreamSynchronize(b->stream));
+    std::vector<vd::BatchSim> hs((size_t)n);
+    std::vector<vd::DevState> hst((size_t)n);
+    std::vector<vd::LevelInfo> hinfo[2];
+    std::vector<vd::LevelSim> hls[2];
+    std::vector<int32_t> hnp[2];
+    for (int32_t i = 0; i < n; ++i) {
+        const vd_sim *s = b->sims[(size_t)i];
+        vd::BatchSim &d = hs[(size_t)i];
+        memset(&d, 0, sizeof d);
+        d.map[0] = s->map[0];
+        d.map[1] = s->map[1];
+        d.table = s->pos;
+        d.W = s->cfg.width;
+        d.H = s->cfg.height;
+        d.S = s->cfg.num_seeds;
+        d.lo = s->cfg.disp_lo;
+        d.span = (uint32_t)(s->cfg.disp_hi - s->cfg.disp_lo + 1);
+        d.move_seed = s->move_seed;
+        hst[(size_t)i] = vd::DevState{s->cur, 0, (uint64_t)s->t};
+    }
+    for (int m = 0; m < 2; ++m) {
+        b->solo[m].assign((size_t)n, 0);
+        b->solo_pixels[m] = 0;
+        b->solo_passes[m] = 0;
+        int32_t levels = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            const vd_sim *s = b->sims[(size_t)i];
+            const int32_t np = (int32_t)(m ? s->djfa_passes : s->jfa_passes).size();
+            if (np > vd::kMaxLevels) return fail(VD_EINVAL, "too many passes per step (%d)", np);
+            if ((int64_t)s->cfg.width * s->cfg.height >= b->solo_px[m]) {
+                b->solo[m][(size_t)i] = 1;
+                b->solo_pixels[m] += (int64_t)s->cfg.width * s->cfg.height * np;
+                b->solo_passes[m] += np;
+            } else {
+                levels = std::max(levels, np);
             }
+        }
+        b->levels[m] = levels;
+        hinfo[m].assign(vd::kMaxLevels, vd::LevelInfo{});
+        hls[m].assign((size_t)vd::kMaxLevels * n, vd::LevelSim{});
+        hnp[m].resize((size_t)n);
+        b->level_pixels[m].assign(vd::kMaxLevels, 0);
+        for (int32_t lvl = 0; lvl < levels; ++lvl) {
+            uint32_t first = 0;
+            for (int32_t i = 0; i < n; ++i) {
+                const vd_sim *s = b->sims[(size_t)i];
+                const std::vector<vd::Pass> &ps = m ? s->djfa_passes : s->jfa_passes;
+                vd::LevelSim &e = hls[m][(size_t)lvl * n + i];
+                e.first = first;   // a member without items shares its first with the next
+                if (!b->solo[m][(size_t)i] && lvl < (int32_t)ps.size()) {
+                    e.k = ps[(size_t)lvl].k;
+                    e.vn = ps[(size_t)lvl].vn;
+                    const vd::ItemGrid ig = vd::item_grid(s->cfg.width, s->cfg.height, e.k);
+                    e.g = ig.g;
+                    e.per = ig.per;
+                    if (ig.items == 0 || (uint64_t)first + ig.items > 0xFFFFFFF0ull)
+                        return fail(VD_EINVAL, "level %d of the batch is too large", lvl);
+                    first += ig.items;
+                    b->level_pixels[m][(size_t)lvl] += (int64_t)s->cfg.width * s->cfg.height;
+                }
+            }
+            vd::LevelInfo &li = hinfo[m][(size_t)lvl];
+            li.total = first;
+            for (int c = 0; c <= 8; ++c) li.chunk[c] = (uint32_t)((uint64_t)first * c / 8);
+        }
+        for (int32_t i = 0; i < n; ++i)
+            hnp[m][(size_t)i] =
+                (int32_t)(m ? b->sims[(size_t)i]->djfa_passes : b->sims[(size_t)i]->jfa_passes)
+                    .size();
+    }
+    const vd::Layout &lay = b->lay;
+    hipStream_t stream = b->stream;
+    hipError_t e = hipMemcpyAsync(b->base + lay.sims, hs.data(), sizeof(vd::BatchSim) * n,
+                                  hipMemcpyHostToDevice, stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->base + lay.state, hst.data(), sizeof(vd::DevState) * n,
+                           hipMemcpyHostToDevice, stream);
+    for (int m = 0; m < 2 && e == hipSuccess; ++m) {
+        e = hipMemcpyAsync(b->base + lay.info[m], hinfo[m].data(),
+                           sizeof(vd::LevelInfo) * vd::kMaxLevels, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->base + lay.ls[m], hls[m].data(),
+                               sizeof(vd::LevelSim) * hls[m].size(), hipMemcpyHostToDevice,
+                               stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(b->base + lay.npasses[m], hnp[m].data(), sizeof(int32_t) * n,
+                               hipMemcpyHostToDevice, stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);   // the host images are locals
+    if (e != hipSuccess)
+        return fail(VD_EDEVICE, "uploading the batch tables failed: %s", hipGetErrorString(e));
+    return VD_OK;
 }
 
 }  // namespace
@@ -470,91 +630,8 @@ int vd_batch_create(vd_sim *const *sims, int32_t n, void *dev_workspace, size_t 
     b->metric = sims[0]->cfg.metric;
     b->base = (uint8_t *)(((uintptr_t)dev_workspace + 255) / 256 * 256);
 
-    // host images of the device tables
-    std::vector<vd::BatchSim> hs((size_t)n);
-    std::vector<vd::DevState> hst((size_t)n);
-    std::vector<vd::LevelInfo> hinfo[2];
-    std::vector<vd::LevelSim> hls[2];
-    std::vector<int32_t> hnp[2];
-    for (int32_t i = 0; i < n; ++i) {
-        const vd_sim *s = sims[i];
-        vd::BatchSim &d = hs[(size_t)i];
-        memset(&d, 0, sizeof d);
-        d.map[0] = s->map[0];
-        d.map[1] = s->map[1];
-        d.table = s->pos;
-        d.W = s->cfg.width;
-        d.H = s->cfg.height;
-        d.S = s->cfg.num_seeds;
-        d.lo = s->cfg.disp_lo;
-        d.span = (uint32_t)(s->cfg.disp_hi - s->cfg.disp_lo + 1);
-        d.move_seed = s->move_seed;
-        hst[(size_t)i] = vd::DevState{s->cur, 0, (uint64_t)s->t};
-    }
-    for (int m = 0; m < 2; ++m) {
-        int32_t levels = 0;
-        for (vd_sim *s : b->sims)
-            levels = std::max<int32_t>(levels, (int32_t)(m ? s->djfa_passes : s->jfa_passes).size());
-        if (levels > vd::kMaxLevels) {
-            delete b;
-            return fail(VD_EINVAL, "too many passes per step (%d)", levels);
-        }
-        b->levels[m] = levels;
-        hinfo[m].assign(vd::kMaxLevels, vd::LevelInfo{});
-        hls[m].assign((size_t)vd::kMaxLevels * n, vd::LevelSim{});
-        hnp[m].resize((size_t)n);
-        b->level_pixels[m].assign(vd::kMaxLevels, 0);
-        for (int32_t lvl = 0; lvl < levels; ++lvl) {
-            uint32_t first = 0;
-            for (int32_t i = 0; i < n; ++i) {
-                const vd_sim *s = sims[i];
-                const std::vector<vd::Pass> &ps = m ? s->djfa_passes : s->jfa_passes;
-                vd::LevelSim &e = hls[m][(size_t)lvl * n + i];
-                e.first = first;
-                if (lvl < (int32_t)ps.size()) {
-                    e.k = ps[(size_t)lvl].k;
-                    e.vn = ps[(size_t)lvl].vn;
-                    const vd::ItemGrid ig = vd::item_grid(s->cfg.width, s->cfg.height, e.k);
-                    e.g = ig.g;
-                    e.per = ig.per;
-                    if (ig.items == 0 || (uint64_t)first + ig.items > 0xFFFFFFF0ull) {
-                        delete b;
-                        return fail(VD_EINVAL, "level %d of the batch is too large", lvl);
-                    }
-                    first += ig.items;
-                    b->level_pixels[m][(size_t)lvl] +=
-                        (int64_t)s->cfg.width * s->cfg.height;
-                }
-            }
-            vd::LevelInfo &li = hinfo[m][(size_t)lvl];
-            li.total = first;
-            for (int c = 0; c <= 8; ++c) li.chunk[c] = (uint32_t)((uint64_t)first * c / 8);
-        }
-        for (int32_t i = 0; i < n; ++i)
-            hnp[m][(size_t)i] = (int32_t)(m ? sims[i]->djfa_passes : sims[i]->jfa_passes).size();
-    }
-    hipError_t e = hipMemcpyAsync(b->base + lay.sims, hs.data(), sizeof(vd::BatchSim) * n,
-                                  hipMemcpyHostToDevice, stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b->base + lay.state, hst.data(), sizeof(vd::DevState) * n,
-                           hipMemcpyHostToDevice, stream);
-    for (int m = 0; m < 2 && e == hipSuccess; ++m) {
-        e = hipMemcpyAsync(b->base + lay.info[m], hinfo[m].data(),
-                           sizeof(vd::LevelInfo) * vd::kMaxLevels, hipMemcpyHostToDevice, stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(b->base + lay.ls[m], hls[m].data(),
-                               sizeof(vd::LevelSim) * hls[m].size(), hipMemcpyHostToDevice,
-                               stream);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(b->base + lay.npasses[m], hnp[m].data(), sizeof(int32_t) * n,
-                               hipMemcpyHostToDevice, stream);
-    }
-    if (e == hipSuccess) e = hipStreamSynchronize(stream);   // the host images are locals
-    if (e != hipSuccess) {
-        delete b;
-        return fail(VD_EDEVICE, "uploading the batch tables failed: %s", hipGetErrorString(e));
-    }
-    int r = query_fit(b);
+    int r = build_tables(b);
+    if (r == VD_OK) r = query_fit(b);
     if (r) {
         delete b;
         return r;
@@ -576,7 +653,9 @@ int vd_batch_step(vd_batch *b, int32_t mode, int32_t move)
     int r = batch_record(b, 1, true, &slot);
     if (r) return r;
     if (b->use_graph) {
-        hipGraphExec_t &g = b->graph[mode][moved];
+        const std::vector<char> key = graph_key(b, mode, moved);
+        if (!b->graphs.count(key) && b->graphs.size() >= 16) drop_graphs(b);   // bound the cache
+        hipGraphExec_t &g = b->graphs[key];
         if (!g) {
             hipGraph_t graph = nullptr;
             const bool was_timing = b->timing;
@@ -652,52 +731,108 @@ int vd_batch_autotune(vd_batch *b, int32_t reps)
     if (!b) return fail(VD_EINVAL, "batch is NULL");
     if (b->broken) return fail(VD_ESTATE, "batch unusable after an earlier device error");
     if (reps < 1 || reps > 1000) return fail(VD_EINVAL, "reps must be in [1, 1000], got %d", reps);
-    std::vector<int32_t> cand;
-    for (int32_t w : {1, 2, 4, 8, 0}) {
-        int32_t g = grid_for(b, w);
-        if (std::find(cand.begin(), cand.end(), g) == cand.end()) cand.push_back(g);
-    }
     uint32_t *ctr = at<uint32_t>(b, b->lay.ctr);
-    for (int mode = 0; mode < 2; ++mode) {
-        if (b->levels[mode] == 0) continue;
-        std::vector<hipEvent_t> ev(2 * cand.size(), nullptr);
+    // The flood work of one step of `mode` in tuning form: every persistent
+    // level and every solo pass reads the current maps and writes the idle
+    // ones, so the members' state does not change.
+    auto flood_work = [&](int mode, int32_t grid) -> hipError_t {
+        hipError_t e = hipSuccess;
+        for (int32_t lvl = 0; lvl < b->levels[mode] && e == hipSuccess; ++lvl) {
+            hipLaunchKernelGGL(vd::k_batch_begin, dim3(1), dim3(vd::kBlock), 0, b->stream, ctr,
+                               8 * vd::kMaxLevels);
+            e = hipGetLastError();
+            if (e == hipSuccess) e = launch_level(b, mode, lvl, 0, grid, b->stream);
+        }
+        if (e == hipSuccess && b->solo_passes[mode] > 0 &&
+            enqueue_solo(b, mode, true, b->stream) != VD_OK)
+            e = hipErrorUnknown;
+        return e;
+    };
+    // Times `cands.size()` configurations of one mode; set(c) installs
+    // candidate c.  Returns the index of the fastest (-1 on failure).
+    auto pick = [&](int mode, size_t ncand, const std::function<int(size_t)> &set,
+                    const std::function<int32_t()> &grid) -> long {
+        std::vector<hipEvent_t> ev(2 * ncand, nullptr);
         int r = VD_OK;
         for (hipEvent_t &e : ev)
             if (hipEventCreate(&e) != hipSuccess) r = fail(VD_EDEVICE, "hipEventCreate failed");
-        for (size_t c = 0; r == VD_OK && c <= cand.size(); ++c) {
-            // c == 0 is a warm-up of the first candidate, untimed
-            const size_t ci = c == 0 ? 0 : c - 1;
-            hipError_t e = c ? hipEventRecord(ev[2 * ci], b->stream) : hipSuccess;
-            for (int32_t k = 0; k < reps && e == hipSuccess; ++k)
-                for (int32_t lvl = 0; lvl < b->levels[mode] && e == hipSuccess; ++lvl) {
-                    hipLaunchKernelGGL(vd::k_batch_begin, dim3(1), dim3(vd::kBlock), 0,
-                                       b->stream, ctr, 8 * vd::kMaxLevels);
-                    e = hipGetLastError();
-                    if (e == hipSuccess) e = launch_level(b, mode, lvl, 0, cand[ci], b->stream);
-                }
-            if (e == hipSuccess && c) e = hipEventRecord(ev[2 * ci + 1], b->stream);
-            if (e != hipSuccess)
-                r = fail(VD_EDEVICE, "batch autotune launch failed: %s", hipGetErrorString(e));
-        }
-        if (r == VD_OK && hipStreamSynchronize(b->stream) != hipSuccess)
-            r = fail(VD_EDEVICE, "hipStreamSynchronize failed");
-        if (r == VD_OK) {
-            float best = 1e30f;
-            for (size_t c = 0; c < cand.size(); ++c) {
-                float ms = 0.f;
-                if (hipEventElapsedTime(&ms, ev[2 * c], ev[2 * c + 1]) == hipSuccess &&
-                    ms < best) {
-                    best = ms;
-                    b->grid[mode] = cand[c];
-                }
+        float best = 1e30f;
+        long win = -1;
+        for (size_t c = 0; r == VD_OK && c < ncand; ++c) {
+            r = set(c);
+            if (r) break;
+            hipError_t e = flood_work(mode, grid());   // warm-up
+            if (e == hipSuccess) e = hipEventRecord(ev[2 * c], b->stream);
+            for (int32_t k = 0; k < reps && e == hipSuccess; ++k) e = flood_work(mode, grid());
+            if (e == hipSuccess) e = hipEventRecord(ev[2 * c + 1], b->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev[2 * c], ev[2 * c + 1]);
+            if (e != hipSuccess) {
+                r = fail(VD_EDEVICE, "batch autotune failed: %s", hipGetErrorString(e));
+                break;
+            }
+            if (ms < best) {
+                best = ms;
+                win = (long)c;
             }
         }
         for (hipEvent_t e : ev)
             if (e) (void)hipEventDestroy(e);
-        if (r) return r;
+        return r == VD_OK ? win : -1;
+    };
+    // 1. persistent grid per mode (all members in the levels)
+    std::vector<int32_t> grids;
+    for (int32_t w : {1, 2, 4, 8, 0}) {
+        int32_t g = grid_for(b, w);
+        if (std::find(grids.begin(), grids.end(), g) == grids.end()) grids.push_back(g);
     }
+    const int64_t none = std::numeric_limits<int64_t>::max();
+    b->solo_px[0] = b->solo_px[1] = none;
+    int r = build_tables(b);
+    if (r) return r;
+    for (int mode = 0; mode < 2; ++mode) {
+        if (b->levels[mode] == 0) continue;
+        size_t cur = 0;
+        long w = pick(mode, grids.size(), [&](size_t c) { cur = c; return VD_OK; },
+                      [&]() { return grids[cur]; });
+        if (w < 0) return VD_EDEVICE;
+        b->grid[mode] = grids[(size_t)w];
+    }
+    // 2. which members run solo: none, or every member of at least one of
+    //    the members' sizes
+    std::vector<int64_t> th = {none};
+    for (vd_sim *s : b->sims) {
+        const int64_t px = (int64_t)s->cfg.width * s->cfg.height;
+        if (std::find(th.begin(), th.end(), px) == th.end()) th.push_back(px);
+    }
+    for (int mode = 0; mode < 2; ++mode) {
+        long w = pick(mode, th.size(),
+                      [&](size_t c) {
+                          b->solo_px[mode] = th[c];
+                          return build_tables(b);
+                      },
+                      [&]() { return b->grid[mode]; });
+        if (w < 0) {
+            b->solo_px[mode] = none;
+            (void)build_tables(b);
+            return VD_EDEVICE;
+        }
+        b->solo_px[mode] = th[(size_t)w];
+    }
+    r = build_tables(b);
     drop_graphs(b);
-    return VD_OK;
+    return r;
+}
+
+int vd_batch_set_solo(vd_batch *b, int32_t mode, int64_t min_pixels)
+{
+    if (!b) return fail(VD_EINVAL, "batch is NULL");
+    if (mode != VD_STEP_JFA && mode != VD_STEP_DJFA)
+        return fail(VD_EINVAL, "mode must be VD_STEP_JFA or VD_STEP_DJFA, got %d", mode);
+    b->solo_px[mode] = min_pixels <= 0 ? std::numeric_limits<int64_t>::max() : min_pixels;
+    drop_graphs(b);
+    return build_tables(b);
 }
 
 int vd_batch_set_timing(vd_batch *b, int enable)

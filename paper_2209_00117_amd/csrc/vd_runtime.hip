@@ -66,10 +66,29 @@ int32_t first_delta(int32_t W, int32_t H, int32_t S, int32_t dmax)
     return P < k1 ? (int32_t)P : k1;
 }
 
-// Measured on MI355X: ID labels run fastest with rows shared through LDS
-// (fewer seed-table lookups), XY labels with the plain chain walk that
-// requests rows two ahead.
-int32_t default_variant(int32_t label) { return label == VD_LABEL_ID32 ? 3 : 1; }
+// Kernel variant of a pass before any tuning, from measurements on MI355X
+// (4096^2 and 8192^2 maps, the autotuner's choices): ID labels take the
+// four-column kernel in JFA steps (many distinct labels: fewer, wider
+// loads win) and LDS-shared rows in dJFA steps (few distinct labels); XY
+// labels take the four-column kernel for JFA's long jumps and the chain
+// walk otherwise.  When the two maps exceed what the 256 MB Infinity Cache
+// can keep (here: 192 MiB), the output maps are stored non-temporally.
+int32_t default_variant(const vd_config &c, bool dynamic, int32_t k)
+{
+    int32_t v;
+    if (c.label == VD_LABEL_ID32)
+        v = dynamic ? 3 : 4;
+    else
+        v = !dynamic && k >= 512 ? 4 : 1;
+    if (8 * (int64_t)c.width * c.height > (int64_t)192 << 20) v += vd::kFloodVariants / 2;
+    return v;
+}
+
+void set_default_variants(vd_sim *s)
+{
+    for (Pass &p : s->jfa_passes) p.variant = default_variant(s->cfg, false, p.k);
+    for (Pass &p : s->djfa_passes) p.variant = default_variant(s->cfg, true, p.k);
+}
 
 // Pass list of one step: k = first, first/2, ..., 1; the first vn of them
 // Von Neumann (clamped so the last main pass is Moore); extra passes k = 1
@@ -645,9 +664,9 @@ int vd_init_sim(const vd_config *cfg, const int32_t *host_xy, void *dev_workspac
                                                                               : abs(cfg->disp_hi));
     s->k1 = first_k(cfg->width, cfg->height);
     s->delta1 = first_delta(cfg->width, cfg->height, S, s->dmax);
-    s->jfa_passes = schedule(s->k1, 0, cfg->extra_passes, default_variant(cfg->label));
-    s->djfa_passes = schedule(s->delta1, cfg->vn_passes, cfg->extra_passes,
-                              default_variant(cfg->label));
+    s->jfa_passes = schedule(s->k1, 0, cfg->extra_passes, 0);
+    s->djfa_passes = schedule(s->delta1, cfg->vn_passes, cfg->extra_passes, 0);
+    set_default_variants(s);
     s->move_seed = mix64(cfg->sim_seed ^ 0x6D6F7665ull);
     apply_tuning(s);
     hipError_t e = hipMemcpyAsync(s->pos, packed.data(), ((size_t)S + 1) * 4,
@@ -781,9 +800,12 @@ int vd_set_flood_variant(vd_sim *s, int variant)
     if (variant < -1 || variant >= vd::kFloodVariants)
         return fail(VD_EINVAL, "variant must be -1 or in [0, %d), got %d", vd::kFloodVariants,
                     variant);
-    int32_t v = variant < 0 ? default_variant(s->cfg.label) : variant;
-    for (Pass &p : s->jfa_passes) p.variant = v;
-    for (Pass &p : s->djfa_passes) p.variant = v;
+    if (variant < 0) {
+        set_default_variants(s);
+        return VD_OK;
+    }
+    for (Pass &p : s->jfa_passes) p.variant = variant;
+    for (Pass &p : s->djfa_passes) p.variant = variant;
     return VD_OK;
 }
 

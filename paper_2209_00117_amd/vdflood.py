@@ -89,6 +89,7 @@ SIGNATURES = {
                                      ctypes.POINTER(ctypes.c_int32)]),
     "vd_batch_destroy": (None, [_P]),
     "vd_batch_autotune": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "vd_batch_set_solo": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int64]),
     "vd_autotune": (ctypes.c_int, [_P, ctypes.c_int32]),
     "vd_get_tuning": (ctypes.c_int, [_P, _P, _P, ctypes.c_int32]),
     "vd_get_tuning_us": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
@@ -418,6 +419,11 @@ class Batch:
 
     def autotune(self, reps: int = 3):
         batch_autotune(self.handle, reps)
+
+    def set_solo(self, mode: int, min_pixels: int):
+        """Members of at least min_pixels pixels (<= 0: none) run `mode`
+        steps' passes with their own launches."""
+        _check(lib().vd_batch_set_solo(self.handle, mode, int(min_pixels)))
 
     def info(self):
         return batch_info(self.handle)

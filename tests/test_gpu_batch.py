@@ -36,13 +36,19 @@ def _make(V, specs, metric=0):
     return out
 
 
-def _run(V, specs, plan, metric=0, graph=False, tune=False):
+def _run(V, specs, plan, metric=0, graph=False, tune=False, solo=None, variant=None):
     made = _make(V, specs, metric)
     members = [V.Sim(s[0], s[1], xy, **kw) for s, (xy, kw) in zip(specs, made)]
     alone = [V.Sim(s[0], s[1], xy, **kw) for s, (xy, kw) in zip(specs, made)]
+    if variant is not None:
+        for m in members:
+            V.set_flood_variant(m.handle, variant)
     b = V.Batch(members)
     if tune:
         b.autotune(2)
+    if solo is not None:
+        for mode in (V.STEP_JFA, V.STEP_DJFA):
+            b.set_solo(mode, solo)
     b.set_graph(graph)
     for t, (mode, move) in enumerate(plan):
         print(f"[batch] n={len(specs)} step={t} mode={mode} move={move} graph={graph}", flush=True)
@@ -75,6 +81,18 @@ def test_batch_graph_replays(V):
 def test_batch_autotuned(V):
     """The tuned persistent grid changes speed only."""
     _run(V, SHAPES, [(1, True), (0, True), (1, True)], graph=True, tune=True)
+
+
+@pytest.mark.parametrize("graph", [False, True])
+@pytest.mark.parametrize("solo", [1, 100000])
+def test_batch_solo_members(V, graph, solo):
+    """Members of at least `solo` pixels run their passes with their own
+    launches (all members for 1; the larger ones for 100000, the rest in the
+    persistent levels).  Mixed step kinds change which maps are current, so
+    graphs are captured per parity configuration; every step still equals
+    the alone runs."""
+    plan = [(1, True), (1, True), (0, True), (1, True), (0, False), (1, True), (1, True)]
+    _run(V, SHAPES, plan, graph=graph, solo=solo, variant=4)
 
 
 def test_batch_manhattan(V):
