@@ -281,6 +281,61 @@ def bench_serving(torch, inputs, V, args):
     print(json.dumps(line), flush=True)
 
 
+def bench_sweep(torch, V, args, wl, label):
+    """JFA+e and dJFA with v leading Von Neumann passes and e extra passes
+    (Sec. IV-V: JFA+1/+2 and the VN/Moore mix), v, e in {0, 1, 2}: ms per
+    step (default kernel variants, no tuning) and, at the last step, the
+    share of pixels equal to JFA+e's map and to plain JFA's map.  All
+    simulations follow the same seed trajectory."""
+    spec = wl.sims[0]
+    W, H = spec.width, spec.height
+    xy = spec.positions()
+    stream = torch.cuda.current_stream()
+    kw = dict(disp_lo=spec.disp_lo, disp_hi=spec.disp_hi, sim_seed=spec.sim_seed, label=label)
+
+    def run(sim, dynamic):
+        for _ in range(args.warmup):
+            sim.move_seeds()
+            sim.djfa_step() if dynamic else sim.jfa_step()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * args.steps)]
+        torch.cuda.synchronize()
+        for i in range(args.steps):
+            sim.move_seeds()
+            ev[2 * i].record(stream)
+            sim.djfa_step() if dynamic else sim.jfa_step()
+            ev[2 * i + 1].record(stream)
+        torch.cuda.synchronize()
+        return float(np.mean([ev[2 * i].elapsed_time(ev[2 * i + 1])
+                              for i in range(args.steps)]))
+
+    jfa_maps, jfa_ms = {}, {}
+    for e in (0, 1, 2):
+        sj = V.Sim(W, H, xy, stream=stream, extra_passes=e, **kw)
+        jfa_ms[e] = run(sj, False)
+        jfa_maps[e] = sj.read_map()
+        sj.close()
+    rows = []
+    for v in (0, 1, 2):
+        for e in (0, 1, 2):
+            sd = V.Sim(W, H, xy, stream=stream, vn_passes=v, extra_passes=e, **kw)
+            ms = run(sd, True)
+            md = sd.read_map()
+            info = sd.info()
+            sd.close()
+            rows.append({"vn_passes": v, "extra_passes": e, "passes_djfa": info.passes_djfa,
+                         "djfa_ms": ms, "jfa_extra_ms": jfa_ms[e],
+                         "sim_vs_jfa_same_extra": float((md == jfa_maps[e]).mean()),
+                         "sim_vs_plain_jfa": float((md == jfa_maps[0]).mean())})
+            print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    line = {"metric": METRIC, "value": None, "unit": "pixel-updates/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+            "data": "synthetic (uniform random seeds and moves, splitmix64)",
+            "config": {"workload": wl.name, "label": args.label, "mode": "sweep"},
+            "sweep": rows}
+    print(json.dumps(line), flush=True)
+
+
 def bench_djfam(torch, V, args, W, H, xy, kw, stream, map_jfa, djfae_ms, jfa_ms):
     """dJFAm (Sec. V-C): a twin with the Manhattan metric and the same seed
     trajectory, stepped as many times as the main twins (tuned, warmed up
@@ -329,6 +384,9 @@ def main():
     ap.add_argument("--with-djfam", action="store_true",
                     help="also time a Manhattan dJFA twin (dJFAm, Sec. V-C) after the main "
                          "loop and report T_dJFAe/T_dJFAm and its similarity to JFA")
+    ap.add_argument("--sweep", action="store_true",
+                    help="time dJFA for vn_passes in {0,1,2} x extra_passes in {0,1,2} (and "
+                         "JFA+extra) on the workload, with similarities to JFA")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (run every pass with the default kernel variant)")
     ap.add_argument("--calibrate", action="store_true",
@@ -359,6 +417,9 @@ def main():
     spec = wl.sims[0]
     W, H = spec.width, spec.height
     label = V.LABEL_ID32 if args.label == "id" else V.LABEL_XY16
+    if args.sweep:
+        bench_sweep(torch, V, args, wl, label)
+        return
     xy = spec.positions()
     kw = dict(disp_lo=spec.disp_lo, disp_hi=spec.disp_hi, sim_seed=spec.sim_seed, label=label)
     stream = torch.cuda.current_stream()

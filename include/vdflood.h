@@ -60,6 +60,10 @@ enum { VD_EUCLID = 0, VD_MANHATTAN = 1 };
 #define VD_MAX_SIDE 16368
 #define VD_MAX_EXTRA_PASSES 2
 
+/* dmax_override value: d_max measured per dJFA step instead of configured
+ * (see vd_config). */
+#define VD_DMAX_MEASURED (-1)
+
 /* Parameters of one simulation (Sec. II: grid X, seed set S; Sec. V-A: the
  * move bound d_max; Sec. V-B/V-C: neighbourhood and distance choices). */
 typedef struct vd_config {
@@ -71,7 +75,11 @@ typedef struct vd_config {
     int32_t metric;          /* VD_EUCLID (dJFAe) or VD_MANHATTAN (dJFAm), Sec. V-C */
     int32_t vn_passes;       /* dJFA: leading Von Neumann passes, Sec. V-B; default 2 */
     int32_t extra_passes;    /* 0, 1 (k = 1) or 2 (k = 2, 1) appended to each step (JFA+1/+2) */
-    int32_t dmax_override;   /* d_max of Eq. (5); <= 0 means max(|disp_lo|, |disp_hi|) */
+    int32_t dmax_override;   /* d_max of Eq. (5): > 0 that value; 0 max(|disp_lo|, |disp_hi|);
+                                VD_DMAX_MEASURED: per dJFA step, the sum over the moves
+                                since the previous step of each move's largest per-axis
+                                displacement after clamping, measured on the device (the
+                                dJFA step then waits for its stream; not for capture) */
     uint64_t sim_seed;       /* seeds the move stream (splitmix64) */
 } vd_config;
 
@@ -105,8 +113,9 @@ void vd_config_default(vd_config *cfg);
 
 /* Device bytes vd_init_sim needs for cfg: two ping-pong label maps
  * (4 B per pixel each), the seed table (4 B per seed plus one sentinel
- * entry; in XY mode also the positions the diagram refers to) and 256 B of
- * alignment slack.  Returns 0 if cfg is invalid. */
+ * entry; in XY mode also the positions the diagram refers to), 256 B of
+ * step counters and 256 B of alignment slack, each part 256-B aligned.
+ * Returns 0 if cfg is invalid. */
 size_t vd_footprint_bytes(const vd_config *cfg);
 
 /* Creates a simulation (Sec. IV: the diagram VD and the seed set S are the
@@ -131,6 +140,14 @@ int vd_init_sim(const vd_config *cfg, const int32_t *host_xy, void *dev_workspac
  * the range by ((r >> 32) * span) >> 32; positions clamp to the grid.
  * Does not touch the diagram. */
 int vd_move_seeds(vd_sim *sim);
+
+/* Seed movement of any kind (the generalisation Sec. VII leaves open): t
+ * += 1, then seed i moves to (host_xy[2i], host_xy[2i+1]); count must be
+ * 2*S and every position on the grid (VD_EINVAL otherwise, nothing
+ * changed).  With dmax_override = VD_DMAX_MEASURED the next dJFA step sizes
+ * its first jump from the displacement.  Does not touch the diagram; waits
+ * for the stream (the positions are copied before it returns). */
+int vd_set_seeds(vd_sim *sim, const int32_t *host_xy, size_t count);
 
 /* JFA on the current positions (Sec. III): every pixel EMPTY, each seed's
  * own pixel labelled (lowest index where seeds coincide), then flood passes

@@ -23,6 +23,7 @@ import numpy as np
 EMPTY = -1
 EUCLID, MANHATTAN = 0, 1
 LABEL_ID, LABEL_XY = 0, 1
+DMAX_MEASURED = -1
 MOORE, VN = 0, 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -247,24 +248,45 @@ class Sim:
         self.sim_seed, self.lo, self.hi = sim_seed, disp_lo, disp_hi
         self.label_mode, self.metric = label_mode, metric
         self.vn_passes, self.extra_passes = vn_passes, extra_passes
+        # dmax == DMAX_MEASURED: each dJFA step takes d_max from the moves
+        # since the previous step (the sum of each move's largest per-axis
+        # displacement), the bound on how far a seed got from the position
+        # the diagram refers to
+        self.measured = dmax == DMAX_MEASURED
         self.dmax = max(abs(disp_lo), abs(disp_hi)) if dmax is None or dmax <= 0 else dmax
+        self.moved = 0
         self.nthreads = nthreads or default_threads()
         self.t = 0
         self.map = jfa(self.xy, W, H, metric, label_mode, extra_passes, self.nthreads)
         self.map_xy = self.xy          # positions the current diagram's labels refer to
 
+    def _displace(self, new_xy):
+        self.moved += int(np.abs(new_xy.astype(np.int64) - self.xy).max()) if self.S else 0
+        self.xy = new_xy
+
     def move(self):
         self.t += 1
-        self.xy = move_seeds(self.xy, self.W, self.H, self.sim_seed, self.t, self.lo, self.hi)
+        self._displace(move_seeds(self.xy, self.W, self.H, self.sim_seed, self.t, self.lo,
+                                  self.hi))
+
+    def set_positions(self, xy):
+        """Moves every seed to caller-given positions: one time step."""
+        a = _xy(xy).copy()
+        assert a.shape == self.xy.shape
+        self.t += 1
+        self._displace(a)
 
     def jfa_step(self):
         self.map = jfa(self.xy, self.W, self.H, self.metric, self.label_mode,
                        self.extra_passes, self.nthreads)
         self.map_xy = self.xy
+        self.moved = 0
         return self.map
 
     def djfa_step(self):
-        self.map = djfa(self.map, self.map_xy, self.xy, self.dmax, self.metric,
+        dmax = self.moved if self.measured else self.dmax
+        self.map = djfa(self.map, self.map_xy, self.xy, dmax, self.metric,
                         self.label_mode, self.vn_passes, self.extra_passes, self.nthreads)
         self.map_xy = self.xy
+        self.moved = 0
         return self.map

@@ -41,9 +41,16 @@ hipError_t launch_splat_id(uint32_t *map, const uint32_t *table, int32_t S, int3
 hipError_t launch_splat_xy(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
                            hipStream_t s);
 
-// Uniform random integer moves of every seed, clamped to the grid.
+// Uniform random integer moves of every seed, clamped to the grid.  With
+// disp (two device words) non-null, disp[0] then grows by the move's
+// largest per-axis displacement.
 hipError_t launch_move(uint32_t *table, int32_t S, int32_t W, int32_t H, uint64_t move_seed,
-                       int64_t t, int32_t lo, int32_t hi, hipStream_t s);
+                       int64_t t, int32_t lo, int32_t hi, uint32_t *disp, hipStream_t s);
+
+// Seeds moved to the S packed positions in `staged` (device memory); disp
+// as for launch_move.
+hipError_t launch_set_seeds(uint32_t *table, const uint32_t *staged, int32_t S, uint32_t *disp,
+                            hipStream_t s);
 
 // XY labels after a move.  idx[old position] = new position of the lowest
 // seed that sat there (old_table: the positions the map refers to, table:

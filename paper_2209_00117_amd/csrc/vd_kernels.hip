@@ -43,19 +43,68 @@ __global__ void __launch_bounds__(kBlock) k_splat_xy(uint32_t *__restrict__ map,
     }
 }
 
+// Largest per-axis displacement between two packed positions.
+__device__ __forceinline__ uint32_t cheb(uint32_t a, uint32_t b)
+{
+    const int32_t dx = abs((int32_t)(a & 0xFFFFu) - (int32_t)(b & 0xFFFFu));
+    const int32_t dy = abs((int32_t)(a >> 16) - (int32_t)(b >> 16));
+    return (uint32_t)max(dx, dy);
+}
+
+// The wave's largest value into *word (one atomic per wave); every lane of
+// the wave must call it.
+__device__ __forceinline__ void wave_max_into(uint32_t *word, uint32_t v)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, (uint32_t)__shfl_xor((int)v, o, 64));
+    if ((threadIdx.x & 63u) == 0u && v) atomicMax(word, v);
+}
+
+// `disp` (optional): disp[1] receives the largest per-axis displacement of
+// this move (after clamping).
 __global__ void __launch_bounds__(kBlock) k_move(uint32_t *__restrict__ table, int32_t S,
                                                  int32_t W, int32_t H, uint64_t move_seed,
-                                                 uint64_t t, int32_t lo, uint32_t span)
+                                                 uint64_t t, int32_t lo, uint32_t span,
+                                                 uint32_t *__restrict__ disp)
 {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= S) return;
-    uint64_t n = ((t - 1) * (uint64_t)S + (uint64_t)i) * 2u;
-    uint32_t p = table[i + 1];
-    int32_t x = (int32_t)(p & 0xFFFFu) - (int32_t)kOff + draw(move_seed, n + 0, lo, span);
-    int32_t y = (int32_t)(p >> 16) - (int32_t)kOff + draw(move_seed, n + 1, lo, span);
-    x = min(max(x, 0), W - 1);
-    y = min(max(y, 0), H - 1);
-    table[i + 1] = ((uint32_t)(y + (int32_t)kOff) << 16) | (uint32_t)(x + (int32_t)kOff);
+    uint32_t moved = 0;
+    if (i < S) {
+        uint64_t n = ((t - 1) * (uint64_t)S + (uint64_t)i) * 2u;
+        uint32_t p = table[i + 1];
+        int32_t x = (int32_t)(p & 0xFFFFu) - (int32_t)kOff + draw(move_seed, n + 0, lo, span);
+        int32_t y = (int32_t)(p >> 16) - (int32_t)kOff + draw(move_seed, n + 1, lo, span);
+        x = min(max(x, 0), W - 1);
+        y = min(max(y, 0), H - 1);
+        const uint32_t q = ((uint32_t)(y + (int32_t)kOff) << 16) | (uint32_t)(x + (int32_t)kOff);
+        table[i + 1] = q;
+        moved = cheb(p, q);
+    }
+    if (disp) wave_max_into(&disp[1], moved);
+}
+
+// Seeds moved to caller-given positions (packed, staged in device memory).
+__global__ void __launch_bounds__(kBlock) k_set_seeds(uint32_t *__restrict__ table,
+                                                      const uint32_t *__restrict__ staged,
+                                                      int32_t S, uint32_t *__restrict__ disp)
+{
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t moved = 0;
+    if (i < S) {
+        const uint32_t p = table[i + 1], q = staged[i];
+        table[i + 1] = q;
+        moved = cheb(p, q);
+    }
+    if (disp) wave_max_into(&disp[1], moved);
+}
+
+// disp[0] += disp[1] (this move's largest displacement), disp[1] = 0.
+__global__ void k_disp_acc(uint32_t *__restrict__ disp)
+{
+    if (threadIdx.x == 0) {
+        disp[0] += disp[1];
+        disp[1] = 0u;
+    }
 }
 
 // After k_splat_reset / k_splat_min on the old positions, idx[old position]
@@ -239,10 +288,23 @@ hipError_t launch_splat_xy(uint32_t *map, const uint32_t *table, int32_t S, int3
 }
 
 hipError_t launch_move(uint32_t *table, int32_t S, int32_t W, int32_t H, uint64_t move_seed,
-                       int64_t t, int32_t lo, int32_t hi, hipStream_t s)
+                       int64_t t, int32_t lo, int32_t hi, uint32_t *disp, hipStream_t s)
 {
     hipLaunchKernelGGL(k_move, grid1d(S), dim3(kBlock), 0, s, table, S, W, H, move_seed,
-                       (uint64_t)t, lo, (uint32_t)(hi - lo + 1));
+                       (uint64_t)t, lo, (uint32_t)(hi - lo + 1), disp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !disp) return e;
+    hipLaunchKernelGGL(k_disp_acc, dim3(1), dim3(64), 0, s, disp);
+    return hipGetLastError();
+}
+
+hipError_t launch_set_seeds(uint32_t *table, const uint32_t *staged, int32_t S, uint32_t *disp,
+                            hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_seeds, grid1d(S), dim3(kBlock), 0, s, table, staged, S, disp);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !disp) return e;
+    hipLaunchKernelGGL(k_disp_acc, dim3(1), dim3(64), 0, s, disp);
     return hipGetLastError();
 }
 

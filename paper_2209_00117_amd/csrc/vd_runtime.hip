@@ -133,8 +133,9 @@ int validate(const vd_config *c)
         return fail(VD_EINVAL, "vn_passes must be in [0, 64], got %d", c->vn_passes);
     if (c->extra_passes < 0 || c->extra_passes > VD_MAX_EXTRA_PASSES)
         return fail(VD_EINVAL, "extra_passes must be 0, 1 or 2, got %d", c->extra_passes);
-    if (c->dmax_override > 2 * VD_MAX_SIDE)
-        return fail(VD_EINVAL, "dmax_override too large: %d", c->dmax_override);
+    if (c->dmax_override > 2 * VD_MAX_SIDE || c->dmax_override < VD_DMAX_MEASURED)
+        return fail(VD_EINVAL, "dmax_override must be in [%d, %d], got %d", VD_DMAX_MEASURED,
+                    2 * VD_MAX_SIDE, c->dmax_override);
     return VD_OK;
 }
 
@@ -144,6 +145,7 @@ size_t footprint(const vd_config *c)
     size_t seeds = (size_t)c->num_seeds * 4;
     size_t b = 2 * align_up(npix * 4) + align_up(seeds + 4);   // + the sentinel entry
     if (c->label == VD_LABEL_XY16) b += align_up(seeds + 4);
+    b += align_up(8);   // step counters (measured displacement)
     return b + kAlign;
 }
 
@@ -273,15 +275,49 @@ int do_djfa(vd_sim *s)
     return r;
 }
 
+void apply_tuning(vd_sim *s);
+
+// Measured d_max (dmax_override = VD_DMAX_MEASURED): the dJFA schedule of
+// this step from the displacement the moves since the last step recorded
+// on the device.  Reads it back, so the step waits for the stream here.
+int measured_schedule(vd_sim *s)
+{
+    uint32_t d = 0;
+    VD_HIP(hipMemcpyAsync(&d, s->disp, 4, hipMemcpyDeviceToHost, s->stream));
+    VD_HIP(hipStreamSynchronize(s->stream));
+    const int32_t dmax = (int32_t)std::min<uint32_t>(d, 2u * VD_MAX_SIDE);
+    const vd_config &c = s->cfg;
+    const int32_t delta1 = first_delta(c.width, c.height, c.num_seeds, dmax);
+    s->dmax = dmax;
+    if (delta1 == s->delta1 && !s->djfa_passes.empty()) return VD_OK;
+    s->delta1 = delta1;
+    s->djfa_passes = schedule(delta1, c.vn_passes, c.extra_passes, 0);
+    for (Pass &p : s->djfa_passes)
+        p.variant = s->forced_variant >= 0 ? s->forced_variant : default_variant(c, true, p.k);
+    if (s->forced_variant < 0) apply_tuning(s);
+    return VD_OK;
+}
+
 int step(vd_sim *s, bool dynamic)
 {
     if (!s) return fail(VD_EINVAL, "sim is NULL");
     if (s->broken) return fail(VD_ESTATE, "simulation unusable after an earlier device error");
     if (s->batch) return fail(VD_ESTATE, "simulation is driven by a batch (vd_batch_step)");
+    int r = VD_OK;
+    if (dynamic && s->measured) r = measured_schedule(s);
+    if (r) {
+        s->broken = true;
+        return r;
+    }
     size_t slot = 0;
-    int r = record(s, 1, true, &slot);
+    r = record(s, 1, true, &slot);
     if (r) return r;
     r = dynamic ? do_djfa(s) : do_jfa(s);
+    // the diagram now refers to the current positions
+    if (r == VD_OK && s->measured) {
+        hipError_t e = vd::launch_fill(s->disp, 1, 0u, s->stream);
+        if (e != hipSuccess) r = fail(VD_EDEVICE, "counter reset failed: %s", hipGetErrorString(e));
+    }
     if (r == VD_OK) r = record(s, 1, false, &slot);
     if (r == VD_EDEVICE) s->broken = true;
     return r;
@@ -658,7 +694,12 @@ int vd_init_sim(const vd_config *cfg, const int32_t *host_xy, void *dev_workspac
     base += align_up(npix * 4);
     s->pos = (uint32_t *)base;
     base += align_up((size_t)S * 4 + 4);
-    if (cfg->label == VD_LABEL_XY16) s->pos_map = (uint32_t *)base;
+    if (cfg->label == VD_LABEL_XY16) {
+        s->pos_map = (uint32_t *)base;
+        base += align_up((size_t)S * 4 + 4);
+    }
+    s->disp = (uint32_t *)base;
+    s->measured = cfg->dmax_override == VD_DMAX_MEASURED;
     s->dmax = cfg->dmax_override > 0 ? cfg->dmax_override
                                      : (abs(cfg->disp_lo) > abs(cfg->disp_hi) ? abs(cfg->disp_lo)
                                                                               : abs(cfg->disp_hi));
@@ -672,6 +713,7 @@ int vd_init_sim(const vd_config *cfg, const int32_t *host_xy, void *dev_workspac
     hipError_t e = hipMemcpyAsync(s->pos, packed.data(), ((size_t)S + 1) * 4,
                                   hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);   // packed is a local buffer
+    if (e == hipSuccess) e = vd::launch_fill(s->disp, 2, 0u, s->stream);
     if (e != hipSuccess) {
         delete s;
         return fail(VD_EDEVICE, "copying seed positions failed: %s", hipGetErrorString(e));
@@ -692,11 +734,48 @@ int vd_move_seeds(vd_sim *s)
     if (s->batch) return fail(VD_ESTATE, "simulation is driven by a batch (vd_batch_step)");
     s->t += 1;
     hipError_t e = vd::launch_move(s->pos, s->cfg.num_seeds, s->cfg.width, s->cfg.height,
-                                   s->move_seed, s->t, s->cfg.disp_lo, s->cfg.disp_hi, s->stream);
+                                   s->move_seed, s->t, s->cfg.disp_lo, s->cfg.disp_hi,
+                                   s->measured ? s->disp : nullptr, s->stream);
     if (e != hipSuccess) {
         s->broken = true;
         return fail(VD_EDEVICE, "move launch failed: %s", hipGetErrorString(e));
     }
+    return VD_OK;
+}
+
+int vd_set_seeds(vd_sim *s, const int32_t *host_xy, size_t count)
+{
+    if (!s || !host_xy) return fail(VD_EINVAL, "NULL argument");
+    if (s->broken) return fail(VD_ESTATE, "simulation unusable after an earlier device error");
+    if (s->batch) return fail(VD_ESTATE, "simulation is driven by a batch (vd_batch_step)");
+    const int32_t S = s->cfg.num_seeds;
+    if (count != 2 * (size_t)S)
+        return fail(VD_EINVAL, "count %zu != 2 * num_seeds %zu", count, 2 * (size_t)S);
+    std::vector<uint32_t> packed;
+    try {
+        packed.resize((size_t)S);
+    } catch (...) {
+        return fail(VD_ENOMEM, "host allocation of %d seeds failed", S);
+    }
+    for (int32_t i = 0; i < S; ++i) {
+        const int32_t x = host_xy[2 * i], y = host_xy[2 * i + 1];
+        if (x < 0 || x >= s->cfg.width || y < 0 || y >= s->cfg.height)
+            return fail(VD_EINVAL, "seed %d at (%d, %d) is outside the %d x %d grid", i, x, y,
+                        s->cfg.width, s->cfg.height);
+        packed[(size_t)i] = vd::pack_pos(x, y);
+    }
+    // staged in the idle ping-pong map (W*H >= S entries; no step is running)
+    uint32_t *staged = s->map[s->cur ^ 1];
+    hipError_t e = hipMemcpyAsync(staged, packed.data(), (size_t)S * 4, hipMemcpyHostToDevice,
+                                  s->stream);
+    if (e == hipSuccess)
+        e = vd::launch_set_seeds(s->pos, staged, S, s->measured ? s->disp : nullptr, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);   // packed is a local buffer
+    if (e != hipSuccess) {
+        s->broken = true;
+        return fail(VD_EDEVICE, "setting seed positions failed: %s", hipGetErrorString(e));
+    }
+    s->t += 1;
     return VD_OK;
 }
 
@@ -800,6 +879,7 @@ int vd_set_flood_variant(vd_sim *s, int variant)
     if (variant < -1 || variant >= vd::kFloodVariants)
         return fail(VD_EINVAL, "variant must be -1 or in [0, %d), got %d", vd::kFloodVariants,
                     variant);
+    s->forced_variant = variant < 0 ? -1 : variant;
     if (variant < 0) {
         set_default_variants(s);
         return VD_OK;

@@ -609,6 +609,9 @@ int vd_server_add_sim(vd_server *sv, const vd_config *cfg, const int32_t *host_x
     if (cfg->metric != sv->metric)
         return fail(VD_EINVAL, "simulation metric %d differs from the server's %d", cfg->metric,
                     sv->metric);
+    if (cfg->dmax_override == VD_DMAX_MEASURED)
+        return fail(VD_EINVAL, "served simulations take a fixed d_max (the schedule of each "
+                               "request is planned ahead)");
     size_t bytes = vd_footprint_bytes(cfg);
     if (bytes == 0) return VD_EINVAL;   // message set by the validation
     for (int64_t i = 0; i < 2 * (int64_t)cfg->num_seeds; i += 2)

@@ -41,6 +41,9 @@ struct vd_sim {
     uint32_t *pos_map = nullptr; // XY mode: the table the diagram's labels refer to
     int64_t t = 0;
     int32_t dmax = 0;
+    uint32_t *disp = nullptr;    // [0]: displacement bound since the last step, [1]: scratch of a move
+    bool measured = false;       // d_max of each dJFA step from disp[0]
+    int32_t forced_variant = -1; // vd_set_flood_variant's choice, -1: defaults and tuning
     int32_t k1 = 0, delta1 = 0;
     uint64_t move_seed = 0;
     std::vector<vd::Pass> jfa_passes, djfa_passes;

@@ -19,6 +19,7 @@ LABEL_ID32, LABEL_XY16 = 0, 1
 EUCLID, MANHATTAN = 0, 1
 EMPTY = -1
 MAX_SIDE = 16368
+DMAX_MEASURED = -1     # dmax_override: d_max measured per dJFA step
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libvdflood.so")
@@ -65,6 +66,7 @@ SIGNATURES = {
     "vd_init_sim": (ctypes.c_int, [ctypes.POINTER(Config), _P, _P, ctypes.c_size_t, _P,
                                    ctypes.POINTER(_P)]),
     "vd_move_seeds": (ctypes.c_int, [_P]),
+    "vd_set_seeds": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
     "vd_jfa_step": (ctypes.c_int, [_P]),
     "vd_djfa_step": (ctypes.c_int, [_P]),
     "vd_read_map": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
@@ -189,6 +191,12 @@ def init_sim(cfg: Config, xy: np.ndarray, workspace, stream=None) -> ctypes.c_vo
 
 def move_seeds(h):
     _check(lib().vd_move_seeds(h))
+
+
+def set_seeds(h, xy):
+    """Moves every seed to the given (S, 2) positions (one time step)."""
+    a = np.ascontiguousarray(np.asarray(xy, dtype=np.int32).reshape(-1, 2))
+    _check(lib().vd_set_seeds(h, a.ctypes.data_as(_P), a.size))
 
 
 def jfa_step(h):
@@ -322,6 +330,9 @@ class Sim:
 
     def move_seeds(self):
         move_seeds(self.handle)
+
+    def set_seeds(self, xy):
+        set_seeds(self.handle, xy)
 
     def jfa_step(self):
         jfa_step(self.handle)

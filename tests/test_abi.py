@@ -37,12 +37,13 @@ def test_binding_struct_layout_matches_header():
 def test_footprint():
     c = V.config(512, 512, 256)
     npix = 512 * 512 * 4
-    # two maps, the seed table with its sentinel entry (256-B aligned), slack
-    assert V.footprint_bytes(c) == 2 * npix + 1280 + 256
+    # two maps, the seed table with its sentinel entry (256-B aligned), step
+    # counters (256 B), slack (256 B)
+    assert V.footprint_bytes(c) == 2 * npix + 1280 + 256 + 256
     cx = V.config(512, 512, 256, label=V.LABEL_XY16)
-    assert V.footprint_bytes(cx) == 2 * npix + 1280 + 1280 + 256
+    assert V.footprint_bytes(cx) == 2 * npix + 1280 + 1280 + 256 + 256
     big = V.config(8192, 8192, 1 << 20)
-    assert V.footprint_bytes(big) == 2 * 8192 * 8192 * 4 + 4 * (1 << 20) + 256 + 256
+    assert V.footprint_bytes(big) == 2 * 8192 * 8192 * 4 + 4 * (1 << 20) + 256 + 256 + 256
     assert V.footprint_bytes(V.config(16368, 16368, 1)) > 0
     assert V.footprint_bytes(V.config(16369, 8, 1)) == 0
 
@@ -54,6 +55,7 @@ def test_footprint():
     dict(width=8, height=8, num_seeds=2, label=7), dict(width=8, height=8, num_seeds=2, metric=3),
     dict(width=8, height=8, num_seeds=2, extra_passes=3),
     dict(width=8, height=8, num_seeds=2, vn_passes=-1),
+    dict(width=8, height=8, num_seeds=2, dmax_override=-2),
 ])
 def test_invalid_config_rejected_before_device_work(kw):
     w, h, s = kw.pop("width"), kw.pop("height"), kw.pop("num_seeds")

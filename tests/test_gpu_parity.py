@@ -215,3 +215,56 @@ def test_autotune_keeps_results(V, label):
         o.djfa_step() if mode else o.jfa_step()
         for s in (a, b, c):
             assert np.array_equal(s.read_map(), o.map)
+
+
+@pytest.mark.parametrize("label", [0, 1])
+def test_measured_dmax_and_set_seeds(V, label):
+    """dmax_override = DMAX_MEASURED: every dJFA step takes d_max from the
+    displacement the moves since the previous step recorded on the device
+    (vd_set_seeds moves seeds anywhere).  Positions, maps and the chosen
+    first jump equal the oracle's at every step."""
+    W, H, S = 600, 400, 800
+    xy = inputs.place_seeds(W, H, S, 21)
+    g = V.Sim(W, H, xy, disp_lo=-2, disp_hi=2, sim_seed=5, label=label,
+              dmax_override=V.DMAX_MEASURED)
+    o = O.Sim(W, H, xy, 5, -2, 2, label_mode=label, dmax=O.DMAX_MEASURED)
+    rng = np.random.default_rng(3)
+
+    def jump(n, reach):
+        a = o.xy.copy()
+        idx = rng.choice(S, n, replace=False)
+        a[idx, 0] = np.clip(a[idx, 0] + rng.integers(-reach, reach + 1, n), 0, W - 1)
+        a[idx, 1] = np.clip(a[idx, 1] + rng.integers(-reach, reach + 1, n), 0, H - 1)
+        return a
+
+    plan = ["move", "djfa", "jump150", "djfa", "move", "move", "djfa", "djfa", "jump3",
+            "jfa", "move", "djfa", "jump40", "move", "djfa"]
+    for i, op in enumerate(plan):
+        print(f"[parity] measured label={label} op {i} {op}", flush=True)
+        if op == "move":
+            g.move_seeds(), o.move()
+        elif op.startswith("jump"):
+            a = jump(10, int(op[4:]))
+            g.set_seeds(a), o.set_positions(a)
+        elif op == "djfa":
+            want = O.delta1(W, H, S, o.moved)
+            g.djfa_step(), o.djfa_step()
+            assert g.info().delta1 == want, (i, g.info().delta1, want)
+        else:
+            g.jfa_step(), o.jfa_step()
+        assert np.array_equal(g.read_seeds(), o.xy), f"positions differ after op {i}"
+        if op in ("djfa", "jfa"):
+            diff = int((g.read_map() != o.map).sum())
+            assert diff == 0, f"map differs after op {i} ({op}) on {diff} px"
+        assert g.info().t == o.t
+
+
+def test_set_seeds_rejects_bad_input(V):
+    g = V.Sim(64, 64, inputs.place_seeds(64, 64, 10, 1))
+    with pytest.raises(V.VdError):
+        g.set_seeds(np.zeros((9, 2), np.int32))                      # wrong count
+    bad = g.read_seeds().copy()
+    bad[3] = (64, 0)                                                 # off the grid
+    with pytest.raises(V.VdError):
+        g.set_seeds(bad)
+    assert g.info().t == 0                                           # nothing changed

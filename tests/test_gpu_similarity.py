@@ -74,3 +74,44 @@ def test_similarity_per_workload(V, name, steps):
     if os.path.isdir(out):
         with open(os.path.join(out, "similarity.json"), "w") as f:
             json.dump(RESULTS, f, indent=1)
+
+
+def test_similarity_sweep_vn_extra(V):
+    """Similarity to the exact diagram of JFA+e and of dJFA with v leading
+    Von Neumann passes and e extra passes, v, e in {0, 1, 2} (small and
+    single workloads, 3 steps).  Reported, and written to
+    gpurun_out/sweep.json; each configuration is held to 99%."""
+    out = {}
+    for name, steps in (("small", 3), ("single", 3)):
+        wl = inputs.WORKLOADS[name]()
+        spec = wl.sims[0]
+        W, H = spec.width, spec.height
+        xy = spec.positions()
+        kw = dict(disp_lo=spec.disp_lo, disp_hi=spec.disp_hi, sim_seed=spec.sim_seed)
+        if wl.sample_pixels:
+            px, py = inputs.sample_pixels(W, H, wl.sample_pixels, seed=7)
+        else:
+            yy, xx = np.mgrid[0:H, 0:W]
+            px, py = xx.ravel().astype(np.int32), yy.ravel().astype(np.int32)
+        rows = []
+        for e in (0, 1, 2):
+            sims = {("jfa", 0): V.Sim(W, H, xy, extra_passes=e, **kw)}
+            for v in (0, 1, 2):
+                sims[("djfa", v)] = V.Sim(W, H, xy, vn_passes=v, extra_passes=e, **kw)
+            for _ in range(steps):
+                for (kind, _v), sm in sims.items():
+                    sm.move_seeds()
+                    sm.djfa_step() if kind == "djfa" else sm.jfa_step()
+            pos = sims[("jfa", 0)].read_seeds()
+            _, nd = O.nearest(pos, W, H, px, py)
+            for (kind, v), sm in sims.items():
+                r = O.count_exact(sm.read_map(), pos, px, py, nd) / len(px)
+                rows.append({"kind": kind, "vn_passes": v, "extra_passes": e, "vs_exact": r})
+                print(f"[sweep] {name} {kind} vn={v} extra={e}: {100 * r:.4f}% exact", flush=True)
+                assert r >= 0.99
+                sm.close()
+        out[name] = rows
+    d = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
+    if os.path.isdir(d):
+        with open(os.path.join(d, "sweep.json"), "w") as f:
+            json.dump(out, f, indent=1)

@@ -465,3 +465,33 @@ def test_manhattan_similarity_band(orc):
     ce = orc.count_exact(me, e.xy, xx.ravel(), yy.ravel(), nd)
     cm = orc.count_exact(mm, m.xy, xx.ravel(), yy.ravel(), nd)
     assert cm < ce
+
+
+def test_measured_dmax_rule(orc):
+    """d_max measured per dJFA step: the sum over the moves since the last
+    step of each move's largest per-axis displacement, written out here for
+    hand-made moves; a step resets it; a dJFA step then uses the schedule
+    of Eq. (5) for that d_max."""
+    W, H = 64, 48
+    xy = np.array([[10, 10], [20, 30], [63, 47]], np.int32)
+    s = orc.Sim(W, H, xy, 1, -1, 1, dmax=orc.DMAX_MEASURED)
+    assert s.measured and s.moved == 0
+    s.set_positions(np.array([[17, 8], [20, 30], [63, 47]], np.int32))     # |dx| 7, |dy| 2
+    assert s.moved == 7 and s.t == 1
+    s.set_positions(np.array([[17, 8], [20, 19], [60, 47]], np.int32))     # |dy| 11 dominates
+    assert s.moved == 18 and s.t == 2
+    # the dJFA step runs the schedule of d_max 18 and resets the sum
+    before = orc.schedule(W, H, 3, True, 18)
+    assert before[0][0] == orc.delta1(W, H, 3, 18) == 32
+    m = s.djfa_step()
+    assert s.moved == 0
+    # the result equals the plain dJFA of the same maps and d_max
+    s2 = orc.Sim(W, H, xy, 1, -1, 1)
+    s2.xy = np.array([[17, 8], [20, 19], [60, 47]], np.int32)
+    m2 = orc.djfa(s2.map, xy, s2.xy, 18)
+    assert np.array_equal(m, m2)
+    # uniform moves add their own largest displacement (at most max(|lo|, |hi|))
+    s.move()
+    assert 0 <= s.moved <= 1
+    s.jfa_step()
+    assert s.moved == 0
