@@ -75,6 +75,12 @@ def _declare(L):
         "orc_run_passes": (None, [_i32, _i32, _p, _p, _p, _p, _i32, _i32, _i32, _i32]),
         "orc_jfa_step": (None, [_i32, _i32, _i32, _p, _i32, _i32, _i32, _p, _i32]),
         "orc_djfa_step": (None, [_i32, _i32, _i32, _p, _p, _i32, _i32, _i32, _i32, _i32, _p, _i32]),
+        "orc_splat_active": (None, [_i32, _i32, _p, _p, _i32, _p]),
+        "orc_relabel_xy_active": (None, [_i32, _i32, _i32, _p, _p, _p, _p]),
+        "orc_purge_id": (None, [_i64, _p, _p]),
+        "orc_jfa_step_active": (None, [_i32, _i32, _i32, _p, _p, _i32, _i32, _i32, _p, _i32]),
+        "orc_djfa_step_active": (_i32, [_i32, _i32, _i32, _p, _p, _p, _p, _i32, _i32, _i32,
+                                        _i32, _i32, _p, _i32]),
         "orc_count_equal": (_i64, [_i64, _p, _p]),
         "orc_count_exact": (_i64, [_i32, _p, _i32, _p, _i64, _p, _p, _p]),
     }
@@ -216,6 +222,67 @@ def djfa(prev_map, old_xy, xy, dmax, metric=EUCLID, label_mode=LABEL_ID, vn_pass
     return m
 
 
+# --- a changing seed set (insertion and removal) ----------------------------
+def _mask(m, S):
+    if m is None:
+        return None
+    a = np.ascontiguousarray(m, dtype=np.uint8)
+    assert a.shape == (S,), "a seed mask holds one byte per seed"
+    return a
+
+
+def splat_active(m: np.ndarray, xy, active, label_mode=LABEL_ID) -> np.ndarray:
+    a = _xy(xy)
+    act = _mask(active, a.shape[0])
+    out = np.ascontiguousarray(m, np.int32).copy()
+    lib().orc_splat_active(out.shape[1], a.shape[0], _ptr(a), None if act is None else _ptr(act),
+                           label_mode, _ptr(out))
+    return out
+
+
+def relabel_xy_active(m: np.ndarray, old_xy, keep, new_xy) -> np.ndarray:
+    o, n = _xy(old_xy), _xy(new_xy)
+    kp = _mask(keep, o.shape[0])
+    out = np.ascontiguousarray(m, np.int32).copy()
+    H, W = out.shape
+    lib().orc_relabel_xy_active(W, H, o.shape[0], _ptr(o), None if kp is None else _ptr(kp),
+                                _ptr(n), _ptr(out))
+    return out
+
+
+def purge_id(m: np.ndarray, keep) -> np.ndarray:
+    kp = np.ascontiguousarray(keep, dtype=np.uint8)
+    out = np.ascontiguousarray(m, np.int32).copy()
+    lib().orc_purge_id(out.size, _ptr(kp), _ptr(out))
+    return out
+
+
+def jfa_active(xy, active, W, H, metric=EUCLID, label_mode=LABEL_ID, extra_passes=0,
+               nthreads=None):
+    a = _xy(xy)
+    act = _mask(active, a.shape[0])
+    m = np.empty((H, W), np.int32)
+    lib().orc_jfa_step_active(W, H, a.shape[0], _ptr(a), None if act is None else _ptr(act),
+                              metric, label_mode, extra_passes, _ptr(m),
+                              nthreads or default_threads())
+    return m
+
+
+def djfa_active(prev_map, old_xy, xy, keep, active, dmax, metric=EUCLID, label_mode=LABEL_ID,
+                vn_passes=2, extra_passes=0, nthreads=None):
+    """dJFA step after the seed set changed; returns (map, fell_back)."""
+    o, a = _xy(old_xy), _xy(xy)
+    kp, act = _mask(keep, a.shape[0]), _mask(active, a.shape[0])
+    m = np.ascontiguousarray(prev_map, np.int32).copy()
+    H, W = m.shape
+    fb = lib().orc_djfa_step_active(W, H, a.shape[0], _ptr(o), _ptr(a),
+                                    None if kp is None else _ptr(kp),
+                                    None if act is None else _ptr(act), dmax, metric,
+                                    label_mode, vn_passes, extra_passes, _ptr(m),
+                                    nthreads or default_threads())
+    return m, bool(fb)
+
+
 def count_equal(a: np.ndarray, b: np.ndarray) -> int:
     a = np.ascontiguousarray(a, np.int32)
     b = np.ascontiguousarray(b, np.int32)
@@ -259,15 +326,47 @@ class Sim:
         self.t = 0
         self.map = jfa(self.xy, W, H, metric, label_mode, extra_passes, self.nthreads)
         self.map_xy = self.xy          # positions the current diagram's labels refer to
+        # The seed set: active[i] -- seed i is present now; keep[i] -- present
+        # when the diagram was made and ever since; changed -- a seed was
+        # inserted or removed since then.  A seed index is a slot of a table
+        # of S entries; removal frees the slot, insertion takes the lowest
+        # free ones.  Removed seeds neither move nor take part in a step.
+        self.active = np.ones(self.S, bool)
+        self.keep = np.ones(self.S, bool)
+        self.changed = False
+        self.fell_back = False
 
     def _displace(self, new_xy):
-        self.moved += int(np.abs(new_xy.astype(np.int64) - self.xy).max()) if self.S else 0
+        d = np.abs(new_xy.astype(np.int64) - self.xy)[self.active]
+        self.moved += int(d.max()) if d.size else 0
         self.xy = new_xy
 
     def move(self):
         self.t += 1
-        self._displace(move_seeds(self.xy, self.W, self.H, self.sim_seed, self.t, self.lo,
-                                  self.hi))
+        new = move_seeds(self.xy, self.W, self.H, self.sim_seed, self.t, self.lo, self.hi)
+        new[~self.active] = self.xy[~self.active]
+        self._displace(new)
+
+    def remove(self, ids):
+        """Removes the given present seeds (distinct indices)."""
+        ids = np.asarray(ids, np.int64)
+        assert len(set(ids.tolist())) == ids.size and self.active[ids].all()
+        assert self.active.sum() > ids.size, "at least one seed stays"
+        self.active[ids] = False
+        self.keep[ids] = False
+        self.changed = True
+
+    def insert(self, xy):
+        """Inserts seeds at the given positions into the lowest free slots, in
+        ascending order; returns their indices."""
+        a = _xy(xy)
+        free = np.flatnonzero(~self.active)[:a.shape[0]]
+        assert free.size == a.shape[0], "not enough free slots"
+        self.xy = self.xy.copy()
+        self.xy[free] = a
+        self.active[free] = True
+        self.changed = True
+        return free.astype(np.int32)
 
     def set_positions(self, xy):
         """Moves every seed to caller-given positions: one time step."""
@@ -276,17 +375,29 @@ class Sim:
         self.t += 1
         self._displace(a)
 
-    def jfa_step(self):
-        self.map = jfa(self.xy, self.W, self.H, self.metric, self.label_mode,
-                       self.extra_passes, self.nthreads)
+    def _settle(self):
         self.map_xy = self.xy
         self.moved = 0
+        self.keep = self.active.copy()
+        self.changed = False
+
+    def jfa_step(self):
+        act = None if self.active.all() else self.active
+        self.map = jfa_active(self.xy, act, self.W, self.H, self.metric, self.label_mode,
+                              self.extra_passes, self.nthreads)
+        self.fell_back = False
+        self._settle()
         return self.map
 
     def djfa_step(self):
         dmax = self.moved if self.measured else self.dmax
-        self.map = djfa(self.map, self.map_xy, self.xy, dmax, self.metric,
-                        self.label_mode, self.vn_passes, self.extra_passes, self.nthreads)
-        self.map_xy = self.xy
-        self.moved = 0
+        if self.changed or not self.active.all():
+            self.map, self.fell_back = djfa_active(
+                self.map, self.map_xy, self.xy, self.keep, self.active, dmax, self.metric,
+                self.label_mode, self.vn_passes, self.extra_passes, self.nthreads)
+        else:
+            self.map = djfa(self.map, self.map_xy, self.xy, dmax, self.metric,
+                            self.label_mode, self.vn_passes, self.extra_passes, self.nthreads)
+            self.fell_back = False
+        self._settle()
         return self.map

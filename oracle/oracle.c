@@ -256,25 +256,37 @@ void orc_fill_empty(int64_t npix, int32_t *map)
 /* Seeds are the starting points of the floods (Sec. III).  Each seed's own
  * pixel gets that seed's label; where several seeds share a pixel the lowest
  * index wins (ID mode).  In XY mode the label is the pixel's own position. */
-void orc_splat(int32_t W, int32_t S, const int32_t *xy, int32_t label_mode, int32_t *map)
+void orc_splat_active(int32_t W, int32_t S, const int32_t *xy, const uint8_t *active,
+                      int32_t label_mode, int32_t *map)
 {
     for (int32_t i = S - 1; i >= 0; --i) {     /* descending: the lowest index is written last */
+        if (active && !active[i]) continue;    /* a removed seed is no flood start */
         int64_t p = (int64_t)xy[2 * i + 1] * W + xy[2 * i];
         map[p] = label_mode == ORC_LABEL_XY ? pack_xy(xy[2 * i], xy[2 * i + 1]) : i;
     }
+}
+
+void orc_splat(int32_t W, int32_t S, const int32_t *xy, int32_t label_mode, int32_t *map)
+{
+    orc_splat_active(W, S, xy, NULL, label_mode, map);
 }
 
 /* XY mode only: after a move, a label of the previous map is an old seed
  * position.  It becomes the new position of the lowest-index seed that sat
  * there.  (ID labels survive a move unchanged, so ID mode needs nothing.)
  * A label that is no old seed position becomes EMPTY. */
-void orc_relabel_xy(int32_t W, int32_t H, int32_t S, const int32_t *old_xy,
-                    const int32_t *new_xy, int32_t *map)
+void orc_relabel_xy_active(int32_t W, int32_t H, int32_t S, const int32_t *old_xy,
+                           const uint8_t *keep, const int32_t *new_xy, int32_t *map)
 {
+    /* label l (an old position) -> the moved position of the lowest-index
+     * seed that sat at l when the diagram was made and has stayed in the
+     * seed set since (keep[i] != 0; NULL: every seed); unclaimed if there
+     * is none */
     int64_t npix = (int64_t)W * H;
     int32_t *at = (int32_t *)malloc(sizeof(int32_t) * (size_t)npix);
     for (int64_t p = 0; p < npix; ++p) at[p] = ORC_EMPTY;
-    for (int32_t i = S - 1; i >= 0; --i) at[(int64_t)old_xy[2 * i + 1] * W + old_xy[2 * i]] = i;
+    for (int32_t i = S - 1; i >= 0; --i)
+        if (!keep || keep[i]) at[(int64_t)old_xy[2 * i + 1] * W + old_xy[2 * i]] = i;
     for (int64_t p = 0; p < npix; ++p) {
         int32_t l = map[p];
         if (l == ORC_EMPTY) continue;
@@ -283,6 +295,21 @@ void orc_relabel_xy(int32_t W, int32_t H, int32_t S, const int32_t *old_xy,
         map[p] = i == ORC_EMPTY ? ORC_EMPTY : pack_xy(new_xy[2 * i], new_xy[2 * i + 1]);
     }
     free(at);
+}
+
+void orc_relabel_xy(int32_t W, int32_t H, int32_t S, const int32_t *old_xy,
+                    const int32_t *new_xy, int32_t *map)
+{
+    orc_relabel_xy_active(W, H, S, old_xy, NULL, new_xy, map);
+}
+
+/* ID labels of seeds that have left the seed set since the diagram was
+ * made (keep[i] == 0: removed, or removed and inserted again) become
+ * unclaimed. */
+void orc_purge_id(int64_t npix, const uint8_t *keep, int32_t *map)
+{
+    for (int64_t p = 0; p < npix; ++p)
+        if (map[p] != ORC_EMPTY && !keep[map[p]]) map[p] = ORC_EMPTY;
 }
 
 /* ---------------------------------------------------------------------- */
@@ -422,14 +449,61 @@ void orc_run_passes(int32_t W, int32_t H, const int32_t *xy, int32_t *map,
 
 /* Full JFA on the current seed positions (Sec. III): an empty grid, the
  * seeds as flood starting points, then the passes of Eq. (2). */
-void orc_jfa_step(int32_t W, int32_t H, int32_t S, const int32_t *xy, int32_t metric,
-                  int32_t label_mode, int32_t extra_passes, int32_t *map, int32_t nthreads)
+void orc_jfa_step_active(int32_t W, int32_t H, int32_t S, const int32_t *xy,
+                         const uint8_t *active, int32_t metric, int32_t label_mode,
+                         int32_t extra_passes, int32_t *map, int32_t nthreads)
 {
     int32_t ks[80], nb[80];
     int32_t n = orc_schedule(W, H, S, 0, 0, 0, extra_passes, ks, nb, 80);
     orc_fill_empty((int64_t)W * H, map);
-    orc_splat(W, S, xy, label_mode, map);
+    orc_splat_active(W, S, xy, active, label_mode, map);
     orc_run_passes(W, H, xy, map, ks, nb, n, metric, label_mode, nthreads);
+}
+
+void orc_jfa_step(int32_t W, int32_t H, int32_t S, const int32_t *xy, int32_t metric,
+                  int32_t label_mode, int32_t extra_passes, int32_t *map, int32_t nthreads)
+{
+    orc_jfa_step_active(W, H, S, xy, NULL, metric, label_mode, extra_passes, map, nthreads);
+}
+
+/* dJFA after the seed set has changed (insertion and removal of seeds, a
+ * case the paper leaves to future work, Sec. VII).  keep[i] != 0 marks the
+ * seeds present when the diagram was made and ever since; active[i] != 0
+ * the seeds present now (both NULL: the plain step).  Labels of the other
+ * seeds leave the diagram first (ID: purged to unclaimed; XY: by the
+ * relabel), only present seeds are splatted, and Eq. (5) takes the number
+ * of present seeds.  A removed seed's cell must be refilled by its
+ * neighbours within the passes; if a pixel is still unclaimed afterwards,
+ * the step becomes a full JFA step instead.  Returns 1 in that case. */
+int32_t orc_djfa_step_active(int32_t W, int32_t H, int32_t S, const int32_t *old_xy,
+                             const int32_t *xy, const uint8_t *keep, const uint8_t *active,
+                             int32_t dmax, int32_t metric, int32_t label_mode,
+                             int32_t vn_passes, int32_t extra_passes, int32_t *map,
+                             int32_t nthreads)
+{
+    int32_t ks[80], nb[80];
+    int32_t S_on = S;
+    if (active) {
+        S_on = 0;
+        for (int32_t i = 0; i < S; ++i) S_on += active[i] ? 1 : 0;
+    }
+    int32_t n = orc_schedule(W, H, S_on, 1, dmax, vn_passes, extra_passes, ks, nb, 80);
+    int64_t npix = (int64_t)W * H;
+    if (label_mode == ORC_LABEL_XY)
+        orc_relabel_xy_active(W, H, S, old_xy, keep, xy, map);
+    else if (keep)
+        orc_purge_id(npix, keep, map);
+    orc_splat_active(W, S, xy, active, label_mode, map);
+    orc_run_passes(W, H, xy, map, ks, nb, n, metric, label_mode, nthreads);
+    if (!keep) return 0;
+    for (int64_t p = 0; p < npix; ++p) {
+        if (map[p] == ORC_EMPTY) {
+            orc_jfa_step_active(W, H, S, xy, active, metric, label_mode, extra_passes, map,
+                                nthreads);
+            return 1;
+        }
+    }
+    return 0;
 }
 
 /* One dJFA time step (Alg. 1, after SimulateParticles): start from the
@@ -439,11 +513,8 @@ void orc_djfa_step(int32_t W, int32_t H, int32_t S, const int32_t *old_xy, const
                    int32_t dmax, int32_t metric, int32_t label_mode, int32_t vn_passes,
                    int32_t extra_passes, int32_t *map, int32_t nthreads)
 {
-    int32_t ks[80], nb[80];
-    int32_t n = orc_schedule(W, H, S, 1, dmax, vn_passes, extra_passes, ks, nb, 80);
-    if (label_mode == ORC_LABEL_XY) orc_relabel_xy(W, H, S, old_xy, xy, map);
-    orc_splat(W, S, xy, label_mode, map);
-    orc_run_passes(W, H, xy, map, ks, nb, n, metric, label_mode, nthreads);
+    orc_djfa_step_active(W, H, S, old_xy, xy, NULL, NULL, dmax, metric, label_mode, vn_passes,
+                         extra_passes, map, nthreads);
 }
 
 /* ---------------------------------------------------------------------- */
