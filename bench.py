@@ -367,6 +367,56 @@ def bench_djfam(torch, V, args, W, H, xy, kw, stream, map_jfa, djfae_ms, jfa_ms)
             "similarity_vs_jfa": float((mm == map_jfa).mean())}
 
 
+def bench_churn(torch, V, args, W, H, xy, kw, stream, djfa_ms):
+    """A changing seed set: before each step, a share `args.with_churn` of
+    the seeds is removed and as many are inserted at uniform random
+    positions (the same script for a JFA and a dJFA twin).  Reports the
+    dJFA step time (purge, splat, passes, the unclaimed-pixel count and its
+    read-back), the host time of the two seed-set calls, the number of steps
+    redone as JFA, and the similarity to the JFA twin at the last step."""
+    S = len(xy)
+    n = max(1, int(round(args.with_churn * S)))
+    cj = V.Sim(W, H, xy, stream=stream, **kw)
+    cd = V.Sim(W, H, xy, stream=stream, **kw)
+    rng = np.random.default_rng(17)
+    steps = min(args.steps, 50)
+    upd_ms, step_ms, wall_ms = [], [], []
+    for i in range(args.warmup + steps):
+        present = np.flatnonzero(cd.seed_set()[0])
+        gone = rng.choice(present, size=min(n, present.size - 1), replace=False).astype(np.int32)
+        new = np.stack([rng.integers(0, W, gone.size), rng.integers(0, H, gone.size)],
+                       1).astype(np.int32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cd.remove_seeds(gone)
+        cd.insert_seeds(new)
+        t1 = time.perf_counter()
+        cj.remove_seeds(gone)
+        cj.insert_seeds(new)
+        cj.move_seeds(), cd.move_seeds()
+        cj.jfa_step()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        e0.record(stream)
+        cd.djfa_step()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        if i >= args.warmup:
+            upd_ms.append(1e3 * (t1 - t0))
+            step_ms.append(e0.elapsed_time(e1))
+            wall_ms.append(1e3 * (t3 - t2))
+    sim = float((cj.read_map() == cd.read_map()).mean())
+    fallbacks = cd.seed_set()[2]
+    cj.close(), cd.close()
+    return {"churn_per_step": n, "steps": steps, "djfa_ms_per_step": float(np.mean(step_ms)),
+            "djfa_wall_ms_per_step": float(np.mean(wall_ms)),
+            "plain_djfa_ms_per_step": djfa_ms,
+            "host_update_ms": float(np.mean(upd_ms)), "fallbacks": int(fallbacks),
+            "similarity_vs_jfa": sim}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -384,6 +434,9 @@ def main():
     ap.add_argument("--with-djfam", action="store_true",
                     help="also time a Manhattan dJFA twin (dJFAm, Sec. V-C) after the main "
                          "loop and report T_dJFAe/T_dJFAm and its similarity to JFA")
+    ap.add_argument("--with-churn", type=float, default=0.0, metavar="FRACTION",
+                    help="also time dJFA steps after removing and inserting FRACTION of the "
+                         "seeds before each step (a changing seed set)")
     ap.add_argument("--sweep", action="store_true",
                     help="time dJFA for vn_passes in {0,1,2} x extra_passes in {0,1,2} (and "
                          "JFA+extra) on the workload, with similarities to JFA")
@@ -534,6 +587,8 @@ def main():
     if args.with_djfam:
         out["djfam"] = bench_djfam(torch, V, args, W, H, xy, kw, stream, mj,
                                    float(np.mean(djfa_ms)), float(np.mean(jfa_ms)))
+    if args.with_churn > 0:
+        out["churn"] = bench_churn(torch, V, args, W, H, xy, kw, stream, float(np.mean(djfa_ms)))
     sj.close(), sd.close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec, xy, args.cpu_budget)

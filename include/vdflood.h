@@ -114,7 +114,8 @@ void vd_config_default(vd_config *cfg);
 /* Device bytes vd_init_sim needs for cfg: two ping-pong label maps
  * (4 B per pixel each), the seed table (4 B per seed plus one sentinel
  * entry; in XY mode also the positions the diagram refers to), 256 B of
- * step counters and 256 B of alignment slack, each part 256-B aligned.
+ * step counters, the seed-set state (1 B per seed) and 256 B of alignment
+ * slack, each part 256-B aligned.
  * Returns 0 if cfg is invalid. */
 size_t vd_footprint_bytes(const vd_config *cfg);
 
@@ -134,7 +135,8 @@ int vd_init_sim(const vd_config *cfg, const int32_t *host_xy, void *dev_workspac
                 size_t ws_bytes, void *hip_stream, vd_sim **out);
 
 /* SimulateParticles of Alg. 1 (Sec. V-A: uniform random moves of up to
- * d_max units): t += 1, then every seed i moves by (dx, dy), each drawn
+ * d_max units): t += 1, then every present seed i (see vd_remove_seeds)
+ * moves by (dx, dy), each drawn
  * uniformly from [disp_lo, disp_hi] as output ((t-1)*S + i)*2 + axis of the
  * splitmix64 stream seeded with mix64(sim_seed ^ 0x6D6F7665), mapped onto
  * the range by ((r >> 32) * span) >> 32; positions clamp to the grid.
@@ -148,6 +150,44 @@ int vd_move_seeds(vd_sim *sim);
  * its first jump from the displacement.  Does not touch the diagram; waits
  * for the stream (the positions are copied before it returns). */
 int vd_set_seeds(vd_sim *sim, const int32_t *host_xy, size_t count);
+
+/* A changing seed set: insertion and removal of seeds between time steps
+ * (named as future work in Sec. VII).  The seed table of a simulation has
+ * num_seeds slots, all present after vd_init_sim; a seed keeps its index
+ * (its ID label) while present.  Removed seeds neither move nor take part in
+ * a step; vd_read_seeds still reports their last positions.  Neither call is
+ * a time step (t is unchanged) nor touches the diagram; the next step takes
+ * the change into account:
+ *  - vd_jfa_step floods from the present seeds only;
+ *  - vd_djfa_step first drops the labels of every seed that has not been
+ *    present without a break since the diagram was made (ID: those pixels
+ *    become unclaimed; XY: a label resolves to the lowest-index such seed
+ *    that sat at the labelled position, else unclaimed), splats the present
+ *    seeds, and runs the Eq. (5) schedule for the number of present seeds.
+ *    If a pixel is still unclaimed after its passes (a removed cell too wide
+ *    for them to refill), the step is redone as a full JFA step.  Such a
+ *    step counts the unclaimed pixels on the device and waits for its
+ *    stream.
+ * Batches (vd_batch_create) refuse a simulation once a seed has been
+ * inserted or removed, and both calls return VD_ESTATE for a batch member.
+ * Both wait for the stream (the host buffers are copied before return).
+ *
+ * vd_remove_seeds: host_ids holds n distinct indices of present seeds; at
+ * least one seed must stay present (VD_EINVAL otherwise, nothing changed). */
+int vd_remove_seeds(vd_sim *sim, const int32_t *host_ids, size_t n);
+
+/* vd_insert_seeds: n new seeds at (host_xy[2j], host_xy[2j+1]) take the n
+ * lowest-index free slots in ascending order; host_ids[j] receives the index
+ * of seed j.  VD_ESTATE if fewer than n slots are free, VD_EINVAL for a
+ * position off the grid (nothing changed in either case). */
+int vd_insert_seeds(vd_sim *sim, const int32_t *host_xy, size_t n, int32_t *host_ids);
+
+/* The seed set: host_present (NULL: skipped; else count == num_seeds bytes)
+ * receives 1 for a present seed and 0 for a free slot; *num_present the
+ * number of present seeds; *fallbacks the number of dJFA steps redone as
+ * JFA steps (either pointer may be NULL). */
+int vd_get_seed_set(const vd_sim *sim, uint8_t *host_present, size_t count,
+                    int32_t *num_present, int64_t *fallbacks);
 
 /* JFA on the current positions (Sec. III): every pixel EMPTY, each seed's
  * own pixel labelled (lowest index where seeds coincide), then flood passes

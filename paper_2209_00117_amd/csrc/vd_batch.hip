@@ -619,6 +619,9 @@ int vd_batch_create(vd_sim *const *sims, int32_t n, void *dev_workspace, size_t 
             return fail(VD_EINVAL, "all simulations of a batch share one metric");
         if (s->measured)
             return fail(VD_EINVAL, "batches take a fixed d_max (simulation %d measures it)", i);
+        if (s->masked)
+            return fail(VD_EINVAL, "batches take simulations with every seed present and kept "
+                        "(simulation %d has inserted or removed seeds)", i);
         if (s->stream != stream)
             return fail(VD_EINVAL, "simulation %d runs on another stream than the batch", i);
         for (int32_t j = 0; j < i; ++j)

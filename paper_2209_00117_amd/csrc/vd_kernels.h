@@ -29,36 +29,58 @@ inline uint32_t pack_pos(int32_t x, int32_t y)
     return ((uint32_t)(y + (int32_t)kOff) << 16) | (uint32_t)(x + (int32_t)kOff);
 }
 
+// Seed-set state, one byte per seed (a changing seed set: insertion and
+// removal).  kPresent: the seed is in the set now; kKept: it has been in
+// the set since the current diagram was made.  Launchers take a null state
+// when every seed is present and kept.
+constexpr uint32_t kPresent = 1u;
+constexpr uint32_t kKept = 2u;
+
 // map[0 .. n) = value.
 hipError_t launch_fill(uint32_t *map, int64_t n, uint32_t value, hipStream_t s);
 
-// Seed pixels (Sec. III, flood starting points); `table` is the seed table
-// (sentinel first).  ID labels take the lowest index among coincident seeds
-// in two launches: set the seed pixels to all ones, then an unsigned atomic
-// minimum of the labels.  XY labels write the pixel's own packed position.
+// Seed pixels (Sec. III, flood starting points) of the present seeds;
+// `table` is the seed table (sentinel first).  ID labels take the lowest
+// index among coincident seeds in two launches: set the seed pixels to all
+// ones, then an unsigned atomic minimum of the labels.  XY labels write the
+// pixel's own packed position.
 hipError_t launch_splat_id(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
-                           hipStream_t s);
+                           const uint8_t *state, hipStream_t s);
 hipError_t launch_splat_xy(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
-                           hipStream_t s);
+                           const uint8_t *state, hipStream_t s);
 
-// Uniform random integer moves of every seed, clamped to the grid.  With
-// disp (two device words) non-null, disp[0] then grows by the move's
+// Uniform random integer moves of every present seed, clamped to the grid.
+// With disp (two device words) non-null, disp[0] then grows by the move's
 // largest per-axis displacement.
 hipError_t launch_move(uint32_t *table, int32_t S, int32_t W, int32_t H, uint64_t move_seed,
-                       int64_t t, int32_t lo, int32_t hi, uint32_t *disp, hipStream_t s);
+                       int64_t t, int32_t lo, int32_t hi, const uint8_t *state, uint32_t *disp,
+                       hipStream_t s);
 
 // Seeds moved to the S packed positions in `staged` (device memory); disp
-// as for launch_move.
-hipError_t launch_set_seeds(uint32_t *table, const uint32_t *staged, int32_t S, uint32_t *disp,
-                            hipStream_t s);
+// as for launch_move (present seeds only).
+hipError_t launch_set_seeds(uint32_t *table, const uint32_t *staged, int32_t S,
+                            const uint8_t *state, uint32_t *disp, hipStream_t s);
+
+// Inserted seeds: n (index, packed position) pairs staged in device memory.
+hipError_t launch_place(uint32_t *table, const uint32_t *staged, int32_t n, hipStream_t s);
+
+// ID labels of seeds without kKept become unclaimed.
+hipError_t launch_purge(uint32_t *map, const uint8_t *state, int64_t n, hipStream_t s);
+
+// *count = number of unclaimed pixels of map[0 .. n).
+hipError_t launch_count_empty(const uint32_t *map, int64_t n, uint32_t *count, hipStream_t s);
+
+// After a step: present seeds become kept, absent ones lose kKept.
+hipError_t launch_settle(uint8_t *state, int32_t S, hipStream_t s);
 
 // XY labels after a move.  idx[old position] = new position of the lowest
-// seed that sat there (old_table: the positions the map refers to, table:
-// the current ones, both sentinel first); then every label, an old position,
-// becomes idx of it.  idx is a width*height scratch map; only entries at old
-// positions are written or read.
+// kept seed that sat there, all ones if none did (old_table: the positions
+// the map refers to, table: the current ones, both sentinel first); then
+// every label, an old position, becomes idx of it (unclaimed for all
+// ones).  idx is a width*height scratch map; only entries at old positions
+// are written or read.
 hipError_t launch_index_old(uint32_t *idx, const uint32_t *old_table, const uint32_t *table,
-                            int32_t S, int32_t W, hipStream_t s);
+                            int32_t S, int32_t W, const uint8_t *state, hipStream_t s);
 hipError_t launch_relabel(uint32_t *map, const uint32_t *idx, int32_t W, int32_t H,
                           hipStream_t s);
 

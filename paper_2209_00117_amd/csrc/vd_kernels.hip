@@ -16,28 +16,42 @@ __global__ void __launch_bounds__(kBlock) k_fill(uint32_t *__restrict__ map, int
         map[i] = value;
 }
 
+// `state` (optional, one byte per seed): a seed takes part only if its
+// byte has a bit of `need` (kPresent: in the seed set now; kKept: in it
+// since the diagram was made).  Null: every seed takes part.
+__device__ __forceinline__ bool takes_part(const uint8_t *state, int32_t i, uint32_t need)
+{
+    return !state || (state[i] & need) != 0u;
+}
+
 __global__ void __launch_bounds__(kBlock) k_splat_reset(uint32_t *__restrict__ map,
                                                         const uint32_t *__restrict__ table,
-                                                        int32_t S, int32_t W)
+                                                        int32_t S, int32_t W,
+                                                        const uint8_t *__restrict__ state,
+                                                        uint32_t need)
 {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < S) map[pixel_of(table[i + 1], W)] = 0xFFFFFFFFu;
+    if (i < S && takes_part(state, i, need)) map[pixel_of(table[i + 1], W)] = 0xFFFFFFFFu;
 }
 
 __global__ void __launch_bounds__(kBlock) k_splat_min(uint32_t *__restrict__ map,
                                                       const uint32_t *__restrict__ table,
-                                                      int32_t S, int32_t W)
+                                                      int32_t S, int32_t W,
+                                                      const uint8_t *__restrict__ state,
+                                                      uint32_t need)
 {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < S) atomicMin(&map[pixel_of(table[i + 1], W)], (uint32_t)(i + 1));
+    if (i < S && takes_part(state, i, need))
+        atomicMin(&map[pixel_of(table[i + 1], W)], (uint32_t)(i + 1));
 }
 
 __global__ void __launch_bounds__(kBlock) k_splat_xy(uint32_t *__restrict__ map,
                                                      const uint32_t *__restrict__ table,
-                                                     int32_t S, int32_t W)
+                                                     int32_t S, int32_t W,
+                                                     const uint8_t *__restrict__ state)
 {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < S) {
+    if (i < S && takes_part(state, i, kPresent)) {
         uint32_t p = table[i + 1];
         map[pixel_of(p, W)] = p;
     }
@@ -60,16 +74,18 @@ __device__ __forceinline__ void wave_max_into(uint32_t *word, uint32_t v)
     if ((threadIdx.x & 63u) == 0u && v) atomicMax(word, v);
 }
 
-// `disp` (optional): disp[1] receives the largest per-axis displacement of
-// this move (after clamping).
+// Seeds absent from the seed set (state) stay where they are.  `disp`
+// (optional): disp[1] receives the largest per-axis displacement of this
+// move (after clamping).
 __global__ void __launch_bounds__(kBlock) k_move(uint32_t *__restrict__ table, int32_t S,
                                                  int32_t W, int32_t H, uint64_t move_seed,
                                                  uint64_t t, int32_t lo, uint32_t span,
+                                                 const uint8_t *__restrict__ state,
                                                  uint32_t *__restrict__ disp)
 {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t moved = 0;
-    if (i < S) {
+    if (i < S && takes_part(state, i, kPresent)) {
         uint64_t n = ((t - 1) * (uint64_t)S + (uint64_t)i) * 2u;
         uint32_t p = table[i + 1];
         int32_t x = (int32_t)(p & 0xFFFFu) - (int32_t)kOff + draw(move_seed, n + 0, lo, span);
@@ -83,19 +99,61 @@ __global__ void __launch_bounds__(kBlock) k_move(uint32_t *__restrict__ table, i
     if (disp) wave_max_into(&disp[1], moved);
 }
 
-// Seeds moved to caller-given positions (packed, staged in device memory).
+// Seeds moved to caller-given positions (packed, staged in device memory);
+// only present seeds count towards the displacement.
 __global__ void __launch_bounds__(kBlock) k_set_seeds(uint32_t *__restrict__ table,
                                                       const uint32_t *__restrict__ staged,
-                                                      int32_t S, uint32_t *__restrict__ disp)
+                                                      int32_t S, const uint8_t *__restrict__ state,
+                                                      uint32_t *__restrict__ disp)
 {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t moved = 0;
     if (i < S) {
         const uint32_t p = table[i + 1], q = staged[i];
         table[i + 1] = q;
-        moved = cheb(p, q);
+        if (takes_part(state, i, kPresent)) moved = cheb(p, q);
     }
     if (disp) wave_max_into(&disp[1], moved);
+}
+
+// Inserted seeds: staged[2j] is a seed index, staged[2j + 1] its packed
+// position, j < n.
+__global__ void __launch_bounds__(kBlock) k_place(uint32_t *__restrict__ table,
+                                                  const uint32_t *__restrict__ staged, int32_t n)
+{
+    int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) table[staged[2 * j] + 1] = staged[2 * j + 1];
+}
+
+// ID labels of seeds not kept since the diagram was made become unclaimed.
+__global__ void __launch_bounds__(kBlock) k_purge(uint32_t *__restrict__ map,
+                                                  const uint8_t *__restrict__ state, int64_t n)
+{
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
+        const uint32_t l = map[p];
+        if (l != kEmpty && (state[l - 1] & kKept) == 0u) map[p] = kEmpty;
+    }
+}
+
+// *count += the number of unclaimed pixels (one atomic per wave).
+__global__ void __launch_bounds__(kBlock) k_count_empty(const uint32_t *__restrict__ map,
+                                                        int64_t n, uint32_t *__restrict__ count)
+{
+    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    uint32_t c = 0;
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride)
+        c += map[p] == kEmpty ? 1u : 0u;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) c += (uint32_t)__shfl_xor((int)c, o, 64);
+    if ((threadIdx.x & 63u) == 0u && c) atomicAdd(count, c);
+}
+
+// After a step: every present seed is kept from now on, absent ones not.
+__global__ void __launch_bounds__(kBlock) k_settle(uint8_t *__restrict__ state, int32_t S)
+{
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < S) state[i] = (state[i] & kPresent) ? (uint8_t)(kPresent | kKept) : (uint8_t)0;
 }
 
 // disp[0] += disp[1] (this move's largest displacement), disp[1] = 0.
@@ -108,17 +166,19 @@ __global__ void k_disp_acc(uint32_t *__restrict__ disp)
 }
 
 // After k_splat_reset / k_splat_min on the old positions, idx[old position]
-// holds the lowest seed label (index + 1) sitting there.  That seed writes
-// its new position over it; positions are >= (kOff << 16 | kOff), above
-// every label, so no other seed of the same old position can mistake the
-// overwritten entry for its own label.
+// holds the lowest kept seed label (index + 1) sitting there, or all ones
+// if no kept seed sat there.  That seed writes its new position over it;
+// positions are >= (kOff << 16 | kOff), above every label, so no other seed
+// of the same old position can mistake the overwritten entry for its own
+// label.
 __global__ void __launch_bounds__(kBlock) k_index_resolve(uint32_t *__restrict__ idx,
                                                           const uint32_t *__restrict__ old_table,
                                                           const uint32_t *__restrict__ table,
-                                                          int32_t S, int32_t W)
+                                                          int32_t S, int32_t W,
+                                                          const uint8_t *__restrict__ state)
 {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= S) return;
+    if (i >= S || !takes_part(state, i, kKept)) return;
     uint32_t *e = &idx[pixel_of(old_table[i + 1], W)];
     if (*e == (uint32_t)(i + 1)) *e = table[i + 1];
 }
@@ -135,7 +195,8 @@ __global__ void __launch_bounds__(kBlock) k_relabel(uint32_t *__restrict__ map,
         int32_t lx = (int32_t)(l & 0xFFFFu) - (int32_t)kOff;
         int32_t ly = (int32_t)(l >> 16) - (int32_t)kOff;
         uint32_t np = (lx >= 0 && lx < W && ly >= 0 && ly < H) ? idx[(int64_t)ly * W + lx] : 0u;
-        map[p] = np >= ((kOff << 16) | kOff) ? np : kEmpty;
+        // a position, not a leftover label nor the all-ones of "no kept seed"
+        map[p] = (int32_t)np >= (int32_t)((kOff << 16) | kOff) ? np : kEmpty;
     }
 }
 
@@ -158,7 +219,7 @@ __global__ void __launch_bounds__(kBlock) k_relabel4(uint32_t *__restrict__ map,
     const int32_t off = 4 * (strip * kTWQ + kQuad * (int32_t)threadIdx.x);
     const __amdgpu_buffer_rsrc_t ir = __builtin_amdgcn_make_buffer_rsrc(
         (void *)idx, 0, (int32_t)min((int64_t)W * H * 4, (int64_t)0x7FFFFFFF), kRsrcWord3);
-    const uint32_t base = (kOff << 16) | kOff;
+    const int32_t base = (int32_t)((kOff << 16) | kOff);
     uint32_t prev_l = kEmpty, prev_n = kEmpty;   // column x of the row above
     // the next row's labels are requested before this row's gathers
     u32x4 next = y0 < y1 ? load4(row_rsrc(map, y0, W, H), off) : u32x4{0u, 0u, 0u, 0u};
@@ -176,7 +237,8 @@ __global__ void __launch_bounds__(kBlock) k_relabel4(uint32_t *__restrict__ map,
             const bool reuse = le == left_l;
             const int32_t at = (valid && !reuse) ? 4 * (ly * W + lx) : -1;
             const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(ir, at, 0, 0);
-            const uint32_t np = valid ? (v >= base ? v : kEmpty) : kEmpty;
+            // a position, not a leftover label nor the all-ones of "no kept seed"
+            const uint32_t np = valid ? ((int32_t)v >= base ? v : kEmpty) : kEmpty;
             n[e] = reuse ? left_n : np;
             left_l = le;
             left_n = n[e];
@@ -270,51 +332,97 @@ hipError_t launch_fill(uint32_t *map, int64_t n, uint32_t value, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_splat_id(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
-                           hipStream_t s)
+namespace {
+
+// k_splat_reset over the seeds with a bit of `reset_need` (state null:
+// all), then k_splat_min over those with a bit of `min_need`.
+hipError_t splat_min_of(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
+                        const uint8_t *reset_state, uint32_t reset_need,
+                        const uint8_t *state, uint32_t min_need, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_splat_reset, grid1d(S), dim3(kBlock), 0, s, map, table, S, W);
+    hipLaunchKernelGGL(k_splat_reset, grid1d(S), dim3(kBlock), 0, s, map, table, S, W,
+                       reset_state, reset_need);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_splat_min, grid1d(S), dim3(kBlock), 0, s, map, table, S, W);
+    hipLaunchKernelGGL(k_splat_min, grid1d(S), dim3(kBlock), 0, s, map, table, S, W, state,
+                       min_need);
     return hipGetLastError();
 }
 
-hipError_t launch_splat_xy(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
-                           hipStream_t s)
+}  // namespace
+
+hipError_t launch_splat_id(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
+                           const uint8_t *state, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_splat_xy, grid1d(S), dim3(kBlock), 0, s, map, table, S, W);
+    return splat_min_of(map, table, S, W, state, kPresent, state, kPresent, s);
+}
+
+hipError_t launch_splat_xy(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
+                           const uint8_t *state, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_splat_xy, grid1d(S), dim3(kBlock), 0, s, map, table, S, W, state);
     return hipGetLastError();
 }
 
 hipError_t launch_move(uint32_t *table, int32_t S, int32_t W, int32_t H, uint64_t move_seed,
-                       int64_t t, int32_t lo, int32_t hi, uint32_t *disp, hipStream_t s)
+                       int64_t t, int32_t lo, int32_t hi, const uint8_t *state, uint32_t *disp,
+                       hipStream_t s)
 {
     hipLaunchKernelGGL(k_move, grid1d(S), dim3(kBlock), 0, s, table, S, W, H, move_seed,
-                       (uint64_t)t, lo, (uint32_t)(hi - lo + 1), disp);
+                       (uint64_t)t, lo, (uint32_t)(hi - lo + 1), state, disp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !disp) return e;
     hipLaunchKernelGGL(k_disp_acc, dim3(1), dim3(64), 0, s, disp);
     return hipGetLastError();
 }
 
-hipError_t launch_set_seeds(uint32_t *table, const uint32_t *staged, int32_t S, uint32_t *disp,
-                            hipStream_t s)
+hipError_t launch_set_seeds(uint32_t *table, const uint32_t *staged, int32_t S,
+                            const uint8_t *state, uint32_t *disp, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_set_seeds, grid1d(S), dim3(kBlock), 0, s, table, staged, S, disp);
+    hipLaunchKernelGGL(k_set_seeds, grid1d(S), dim3(kBlock), 0, s, table, staged, S, state,
+                       disp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !disp) return e;
     hipLaunchKernelGGL(k_disp_acc, dim3(1), dim3(64), 0, s, disp);
+    return hipGetLastError();
+}
+
+hipError_t launch_place(uint32_t *table, const uint32_t *staged, int32_t n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_place, grid1d(n), dim3(kBlock), 0, s, table, staged, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_purge(uint32_t *map, const uint8_t *state, int64_t n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_purge, grid1d(n, 8192), dim3(kBlock), 0, s, map, state, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_empty(const uint32_t *map, int64_t n, uint32_t *count, hipStream_t s)
+{
+    hipError_t e = launch_fill(count, 1, 0u, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_count_empty, grid1d(n, 8192), dim3(kBlock), 0, s, map, n, count);
+    return hipGetLastError();
+}
+
+hipError_t launch_settle(uint8_t *state, int32_t S, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_settle, grid1d(S), dim3(kBlock), 0, s, state, S);
     return hipGetLastError();
 }
 
 hipError_t launch_index_old(uint32_t *idx, const uint32_t *old_table, const uint32_t *table,
-                            int32_t S, int32_t W, hipStream_t s)
+                            int32_t S, int32_t W, const uint8_t *state, hipStream_t s)
 {
-    hipError_t e = launch_splat_id(idx, old_table, S, W, s);
+    // every old position is reset (a label may name a seed not kept), the
+    // minimum is taken over kept seeds only
+    hipError_t e = splat_min_of(idx, old_table, S, W, nullptr, 0u, state, kKept, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_index_resolve, grid1d(S), dim3(kBlock), 0, s, idx, old_table, table, S,
-                       W);
+                       W, state);
     return hipGetLastError();
 }
 

@@ -145,7 +145,8 @@ size_t footprint(const vd_config *c)
     size_t seeds = (size_t)c->num_seeds * 4;
     size_t b = 2 * align_up(npix * 4) + align_up(seeds + 4);   // + the sentinel entry
     if (c->label == VD_LABEL_XY16) b += align_up(seeds + 4);
-    b += align_up(8);   // step counters (measured displacement)
+    b += align_up(12);                     // step counters
+    b += align_up((size_t)c->num_seeds);   // seed-set state bytes
     return b + kAlign;
 }
 
@@ -217,6 +218,10 @@ int run_passes(vd_sim *s, const std::vector<Pass> &passes)
     return VD_OK;
 }
 
+// The seed-set bytes the kernels read: null while every seed is present
+// and kept (the common case costs nothing).
+const uint8_t *seed_state(const vd_sim *s) { return s->masked ? s->state : nullptr; }
+
 // The map a JFA step floods: unclaimed everywhere but the seed pixels.
 int jfa_prologue(vd_sim *s)
 {
@@ -224,14 +229,18 @@ int jfa_prologue(vd_sim *s)
     int64_t npix = (int64_t)c.width * c.height;
     VD_HIP(vd::launch_fill(s->map[s->cur], npix, vd::kEmpty, s->stream));
     if (c.label == VD_LABEL_XY16)
-        VD_HIP(vd::launch_splat_xy(s->map[s->cur], s->pos, c.num_seeds, c.width, s->stream));
+        VD_HIP(vd::launch_splat_xy(s->map[s->cur], s->pos, c.num_seeds, c.width, seed_state(s),
+                                   s->stream));
     else
-        VD_HIP(vd::launch_splat_id(s->map[s->cur], s->pos, c.num_seeds, c.width, s->stream));
+        VD_HIP(vd::launch_splat_id(s->map[s->cur], s->pos, c.num_seeds, c.width, seed_state(s),
+                                   s->stream));
     return VD_OK;
 }
 
 // The map a dJFA step floods: the previous diagram (XY: relabelled to the
-// moved positions) with every seed pixel claimed by its seed.
+// moved positions) with every seed pixel claimed by its seed.  After
+// insertions or removals, labels of seeds not kept since the diagram was
+// made leave it first (ID: purged; XY: the relabel finds no kept seed).
 int djfa_prologue(vd_sim *s)
 {
     const vd_config &c = s->cfg;
@@ -240,11 +249,14 @@ int djfa_prologue(vd_sim *s)
         // The idle ping-pong buffer serves as the old-position index; the
         // first flood pass overwrites it.
         uint32_t *idx = s->map[s->cur ^ 1];
-        VD_HIP(vd::launch_index_old(idx, s->pos_map, s->pos, c.num_seeds, c.width, s->stream));
+        VD_HIP(vd::launch_index_old(idx, s->pos_map, s->pos, c.num_seeds, c.width, seed_state(s),
+                                    s->stream));
         VD_HIP(vd::launch_relabel(cur, idx, c.width, c.height, s->stream));
-        VD_HIP(vd::launch_splat_xy(cur, s->pos, c.num_seeds, c.width, s->stream));
+        VD_HIP(vd::launch_splat_xy(cur, s->pos, c.num_seeds, c.width, seed_state(s), s->stream));
     } else {
-        VD_HIP(vd::launch_splat_id(cur, s->pos, c.num_seeds, c.width, s->stream));
+        if (s->changed)
+            VD_HIP(vd::launch_purge(cur, s->state, (int64_t)c.width * c.height, s->stream));
+        VD_HIP(vd::launch_splat_id(cur, s->pos, c.num_seeds, c.width, seed_state(s), s->stream));
     }
     return VD_OK;
 }
@@ -275,7 +287,50 @@ int do_djfa(vd_sim *s)
     return r;
 }
 
+// After a dJFA step that followed insertions or removals: a removed seed's
+// cell must have been refilled by its neighbours within the passes.  If a
+// pixel is still unclaimed, the step is redone as a full JFA step.  Reads
+// the count back, so the step waits for its stream here.
+int refill_check(vd_sim *s)
+{
+    const vd_config &c = s->cfg;
+    uint32_t n = 0;
+    VD_HIP(vd::launch_count_empty(s->map[s->cur], (int64_t)c.width * c.height, &s->disp[2],
+                                  s->stream));
+    VD_HIP(hipMemcpyAsync(&n, &s->disp[2], 4, hipMemcpyDeviceToHost, s->stream));
+    VD_HIP(hipStreamSynchronize(s->stream));
+    if (n == 0) return VD_OK;
+    s->fallbacks += 1;
+    return do_jfa(s);
+}
+
+// After a step: the diagram holds exactly the present seeds.
+int settle(vd_sim *s)
+{
+    if (!s->masked) return VD_OK;
+    VD_HIP(vd::launch_settle(s->state, s->cfg.num_seeds, s->stream));
+    for (uint8_t &b : s->host_state)
+        b = (b & vd::kPresent) ? (uint8_t)(vd::kPresent | vd::kKept) : (uint8_t)0;
+    s->changed = false;
+    s->masked = s->present < s->cfg.num_seeds;
+    return VD_OK;
+}
+
 void apply_tuning(vd_sim *s);
+
+// The dJFA schedule for the current d_max and number of present seeds
+// (Eq. (5)); passes are rebuilt only when delta_1 changes.
+void replan_djfa(vd_sim *s)
+{
+    const vd_config &c = s->cfg;
+    const int32_t delta1 = first_delta(c.width, c.height, s->present, s->dmax);
+    if (delta1 == s->delta1 && !s->djfa_passes.empty()) return;
+    s->delta1 = delta1;
+    s->djfa_passes = schedule(delta1, c.vn_passes, c.extra_passes, 0);
+    for (Pass &p : s->djfa_passes)
+        p.variant = s->forced_variant >= 0 ? s->forced_variant : default_variant(c, true, p.k);
+    if (s->forced_variant < 0) apply_tuning(s);
+}
 
 // Measured d_max (dmax_override = VD_DMAX_MEASURED): the dJFA schedule of
 // this step from the displacement the moves since the last step recorded
@@ -285,16 +340,8 @@ int measured_schedule(vd_sim *s)
     uint32_t d = 0;
     VD_HIP(hipMemcpyAsync(&d, s->disp, 4, hipMemcpyDeviceToHost, s->stream));
     VD_HIP(hipStreamSynchronize(s->stream));
-    const int32_t dmax = (int32_t)std::min<uint32_t>(d, 2u * VD_MAX_SIDE);
-    const vd_config &c = s->cfg;
-    const int32_t delta1 = first_delta(c.width, c.height, c.num_seeds, dmax);
-    s->dmax = dmax;
-    if (delta1 == s->delta1 && !s->djfa_passes.empty()) return VD_OK;
-    s->delta1 = delta1;
-    s->djfa_passes = schedule(delta1, c.vn_passes, c.extra_passes, 0);
-    for (Pass &p : s->djfa_passes)
-        p.variant = s->forced_variant >= 0 ? s->forced_variant : default_variant(c, true, p.k);
-    if (s->forced_variant < 0) apply_tuning(s);
+    s->dmax = (int32_t)std::min<uint32_t>(d, 2u * VD_MAX_SIDE);
+    replan_djfa(s);
     return VD_OK;
 }
 
@@ -312,7 +359,10 @@ int step(vd_sim *s, bool dynamic)
     size_t slot = 0;
     r = record(s, 1, true, &slot);
     if (r) return r;
+    const bool changed = s->changed;
     r = dynamic ? do_djfa(s) : do_jfa(s);
+    if (r == VD_OK && dynamic && changed) r = refill_check(s);
+    if (r == VD_OK) r = settle(s);
     // the diagram now refers to the current positions
     if (r == VD_OK && s->measured) {
         hipError_t e = vd::launch_fill(s->disp, 1, 0u, s->stream);
@@ -699,6 +749,15 @@ int vd_init_sim(const vd_config *cfg, const int32_t *host_xy, void *dev_workspac
         base += align_up((size_t)S * 4 + 4);
     }
     s->disp = (uint32_t *)base;
+    base += align_up(12);
+    s->state = (uint8_t *)base;
+    try {
+        s->host_state.assign((size_t)S, (uint8_t)(vd::kPresent | vd::kKept));
+    } catch (...) {
+        delete s;
+        return fail(VD_ENOMEM, "host allocation of %d seeds failed", S);
+    }
+    s->present = S;
     s->measured = cfg->dmax_override == VD_DMAX_MEASURED;
     s->dmax = cfg->dmax_override > 0 ? cfg->dmax_override
                                      : (abs(cfg->disp_lo) > abs(cfg->disp_hi) ? abs(cfg->disp_lo)
@@ -712,8 +771,11 @@ int vd_init_sim(const vd_config *cfg, const int32_t *host_xy, void *dev_workspac
     apply_tuning(s);
     hipError_t e = hipMemcpyAsync(s->pos, packed.data(), ((size_t)S + 1) * 4,
                                   hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->state, s->host_state.data(), (size_t)S, hipMemcpyHostToDevice,
+                           s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);   // packed is a local buffer
-    if (e == hipSuccess) e = vd::launch_fill(s->disp, 2, 0u, s->stream);
+    if (e == hipSuccess) e = vd::launch_fill(s->disp, 3, 0u, s->stream);
     if (e != hipSuccess) {
         delete s;
         return fail(VD_EDEVICE, "copying seed positions failed: %s", hipGetErrorString(e));
@@ -735,7 +797,7 @@ int vd_move_seeds(vd_sim *s)
     s->t += 1;
     hipError_t e = vd::launch_move(s->pos, s->cfg.num_seeds, s->cfg.width, s->cfg.height,
                                    s->move_seed, s->t, s->cfg.disp_lo, s->cfg.disp_hi,
-                                   s->measured ? s->disp : nullptr, s->stream);
+                                   seed_state(s), s->measured ? s->disp : nullptr, s->stream);
     if (e != hipSuccess) {
         s->broken = true;
         return fail(VD_EDEVICE, "move launch failed: %s", hipGetErrorString(e));
@@ -769,13 +831,116 @@ int vd_set_seeds(vd_sim *s, const int32_t *host_xy, size_t count)
     hipError_t e = hipMemcpyAsync(staged, packed.data(), (size_t)S * 4, hipMemcpyHostToDevice,
                                   s->stream);
     if (e == hipSuccess)
-        e = vd::launch_set_seeds(s->pos, staged, S, s->measured ? s->disp : nullptr, s->stream);
+        e = vd::launch_set_seeds(s->pos, staged, S, seed_state(s),
+                                 s->measured ? s->disp : nullptr, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);   // packed is a local buffer
     if (e != hipSuccess) {
         s->broken = true;
         return fail(VD_EDEVICE, "setting seed positions failed: %s", hipGetErrorString(e));
     }
     s->t += 1;
+    return VD_OK;
+}
+
+int vd_remove_seeds(vd_sim *s, const int32_t *host_ids, size_t n)
+{
+    if (!s || (!host_ids && n)) return fail(VD_EINVAL, "NULL argument");
+    if (s->broken) return fail(VD_ESTATE, "simulation unusable after an earlier device error");
+    if (s->batch) return fail(VD_ESTATE, "simulation is driven by a batch (vd_batch_step)");
+    if (n == 0) return VD_OK;
+    const int32_t S = s->cfg.num_seeds;
+    if (n >= (size_t)s->present)
+        return fail(VD_EINVAL, "removing %zu of %d present seeds leaves none", n, s->present);
+    std::vector<uint8_t> next = s->host_state;
+    for (size_t j = 0; j < n; ++j) {
+        const int32_t i = host_ids[j];
+        if (i < 0 || i >= S) return fail(VD_EINVAL, "seed index %d outside [0, %d)", i, S);
+        if (!(next[(size_t)i] & vd::kPresent))
+            return fail(VD_EINVAL, "seed %d is not present (or named twice)", i);
+        next[(size_t)i] = 0;
+    }
+    hipError_t e = hipMemcpyAsync(s->state, next.data(), (size_t)S, hipMemcpyHostToDevice,
+                                  s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);   // next is a local buffer
+    if (e != hipSuccess) {
+        s->broken = true;
+        return fail(VD_EDEVICE, "updating the seed set failed: %s", hipGetErrorString(e));
+    }
+    s->host_state.swap(next);
+    s->present -= (int32_t)n;
+    s->changed = s->masked = true;
+    replan_djfa(s);
+    return VD_OK;
+}
+
+int vd_insert_seeds(vd_sim *s, const int32_t *host_xy, size_t n, int32_t *host_ids)
+{
+    if (!s || ((!host_xy || !host_ids) && n)) return fail(VD_EINVAL, "NULL argument");
+    if (s->broken) return fail(VD_ESTATE, "simulation unusable after an earlier device error");
+    if (s->batch) return fail(VD_ESTATE, "simulation is driven by a batch (vd_batch_step)");
+    if (n == 0) return VD_OK;
+    const vd_config &c = s->cfg;
+    const int32_t S = c.num_seeds;
+    if (n > (size_t)(S - s->present))
+        return fail(VD_ESTATE, "%zu seeds to insert, %d free slots", n, S - s->present);
+    for (size_t j = 0; j < n; ++j) {
+        const int32_t x = host_xy[2 * j], y = host_xy[2 * j + 1];
+        if (x < 0 || x >= c.width || y < 0 || y >= c.height)
+            return fail(VD_EINVAL, "inserted seed %zu at (%d, %d) is outside the %d x %d grid", j,
+                        x, y, c.width, c.height);
+    }
+    std::vector<uint8_t> next = s->host_state;
+    std::vector<uint32_t> pairs;
+    try {
+        pairs.resize(2 * n);
+    } catch (...) {
+        return fail(VD_ENOMEM, "host allocation of %zu seeds failed", n);
+    }
+    // the lowest free slots, in ascending order
+    size_t j = 0;
+    for (int32_t i = 0; i < S && j < n; ++i) {
+        if (next[(size_t)i] & vd::kPresent) continue;
+        next[(size_t)i] = (uint8_t)vd::kPresent;   // not kept: its old labels are stale
+        pairs[2 * j] = (uint32_t)i;
+        pairs[2 * j + 1] = vd::pack_pos(host_xy[2 * j], host_xy[2 * j + 1]);
+        ++j;
+    }
+    // staged in the idle ping-pong map, at most width*height words at a time
+    uint32_t *staged = s->map[s->cur ^ 1];
+    const size_t chunk = std::max<size_t>(1, (size_t)c.width * c.height / 2);
+    hipError_t e = hipSuccess;
+    for (size_t at = 0; at < n && e == hipSuccess; at += chunk) {
+        const size_t m = std::min(chunk, n - at);
+        e = hipMemcpyAsync(staged, &pairs[2 * at], m * 8, hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) e = vd::launch_place(s->pos, staged, (int32_t)m, s->stream);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->state, next.data(), (size_t)S, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);   // local buffers
+    if (e != hipSuccess) {
+        s->broken = true;
+        return fail(VD_EDEVICE, "inserting seeds failed: %s", hipGetErrorString(e));
+    }
+    for (size_t k = 0; k < n; ++k) host_ids[k] = (int32_t)pairs[2 * k];
+    s->host_state.swap(next);
+    s->present += (int32_t)n;
+    s->changed = s->masked = true;
+    replan_djfa(s);
+    return VD_OK;
+}
+
+int vd_get_seed_set(const vd_sim *s, uint8_t *host_present, size_t count, int32_t *num_present,
+                    int64_t *fallbacks)
+{
+    if (!s) return fail(VD_EINVAL, "sim is NULL");
+    if (host_present) {
+        if (count != (size_t)s->cfg.num_seeds)
+            return fail(VD_EINVAL, "count %zu != num_seeds %d", count, s->cfg.num_seeds);
+        for (size_t i = 0; i < count; ++i)
+            host_present[i] = (s->host_state[i] & vd::kPresent) ? 1 : 0;
+    }
+    if (num_present) *num_present = s->present;
+    if (fallbacks) *fallbacks = s->fallbacks;
     return VD_OK;
 }
 

@@ -41,7 +41,16 @@ struct vd_sim {
     uint32_t *pos_map = nullptr; // XY mode: the table the diagram's labels refer to
     int64_t t = 0;
     int32_t dmax = 0;
-    uint32_t *disp = nullptr;    // [0]: displacement bound since the last step, [1]: scratch of a move
+    uint32_t *disp = nullptr;    // [0]: displacement bound since the last step, [1]: scratch
+                                 // of a move, [2]: unclaimed-pixel count of a step
+    // The seed set (insertion and removal): one byte per seed, kPresent |
+    // kKept, on the device and mirrored here.
+    uint8_t *state = nullptr;
+    std::vector<uint8_t> host_state;
+    int32_t present = 0;         // seeds in the set now
+    bool changed = false;        // a seed inserted or removed since the diagram was made
+    bool masked = false;         // changed, or some seed absent: kernels read `state`
+    int64_t fallbacks = 0;       // dJFA steps replaced by a JFA step (unrefilled pixels)
     bool measured = false;       // d_max of each dJFA step from disp[0]
     int32_t forced_variant = -1; // vd_set_flood_variant's choice, -1: defaults and tuning
     int32_t k1 = 0, delta1 = 0;

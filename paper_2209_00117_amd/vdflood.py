@@ -67,6 +67,9 @@ SIGNATURES = {
                                    ctypes.POINTER(_P)]),
     "vd_move_seeds": (ctypes.c_int, [_P]),
     "vd_set_seeds": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
+    "vd_remove_seeds": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
+    "vd_insert_seeds": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
+    "vd_get_seed_set": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P, _P]),
     "vd_jfa_step": (ctypes.c_int, [_P]),
     "vd_djfa_step": (ctypes.c_int, [_P]),
     "vd_read_map": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
@@ -197,6 +200,32 @@ def set_seeds(h, xy):
     """Moves every seed to the given (S, 2) positions (one time step)."""
     a = np.ascontiguousarray(np.asarray(xy, dtype=np.int32).reshape(-1, 2))
     _check(lib().vd_set_seeds(h, a.ctypes.data_as(_P), a.size))
+
+
+def remove_seeds(h, ids):
+    """Removes the given present seeds from the seed set."""
+    a = np.ascontiguousarray(np.asarray(ids, dtype=np.int32).reshape(-1))
+    _check(lib().vd_remove_seeds(h, a.ctypes.data_as(_P), a.size))
+
+
+def insert_seeds(h, xy) -> np.ndarray:
+    """Inserts seeds at the given (n, 2) positions into the lowest free
+    slots; returns their indices."""
+    a = np.ascontiguousarray(np.asarray(xy, dtype=np.int32).reshape(-1, 2))
+    ids = np.empty(a.shape[0], np.int32)
+    _check(lib().vd_insert_seeds(h, a.ctypes.data_as(_P), a.shape[0], ids.ctypes.data_as(_P)))
+    return ids
+
+
+def seed_set(h):
+    """(present mask as bool array, number present, JFA fallbacks so far)."""
+    info = get_info(h)
+    m = np.empty(info.num_seeds, np.uint8)
+    n = ctypes.c_int32()
+    fb = ctypes.c_int64()
+    _check(lib().vd_get_seed_set(h, m.ctypes.data_as(_P), m.size, ctypes.byref(n),
+                                 ctypes.byref(fb)))
+    return m.astype(bool), int(n.value), int(fb.value)
 
 
 def jfa_step(h):
@@ -333,6 +362,15 @@ class Sim:
 
     def set_seeds(self, xy):
         set_seeds(self.handle, xy)
+
+    def remove_seeds(self, ids):
+        remove_seeds(self.handle, ids)
+
+    def insert_seeds(self, xy) -> np.ndarray:
+        return insert_seeds(self.handle, xy)
+
+    def seed_set(self):
+        return seed_set(self.handle)
 
     def jfa_step(self):
         jfa_step(self.handle)

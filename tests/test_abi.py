@@ -38,12 +38,13 @@ def test_footprint():
     c = V.config(512, 512, 256)
     npix = 512 * 512 * 4
     # two maps, the seed table with its sentinel entry (256-B aligned), step
-    # counters (256 B), slack (256 B)
-    assert V.footprint_bytes(c) == 2 * npix + 1280 + 256 + 256
+    # counters (256 B), seed-set state (1 B per seed, 256-B aligned), slack
+    assert V.footprint_bytes(c) == 2 * npix + 1280 + 256 + 256 + 256
     cx = V.config(512, 512, 256, label=V.LABEL_XY16)
-    assert V.footprint_bytes(cx) == 2 * npix + 1280 + 1280 + 256 + 256
+    assert V.footprint_bytes(cx) == 2 * npix + 1280 + 1280 + 256 + 256 + 256
     big = V.config(8192, 8192, 1 << 20)
-    assert V.footprint_bytes(big) == 2 * 8192 * 8192 * 4 + 4 * (1 << 20) + 256 + 256 + 256
+    assert V.footprint_bytes(big) == (2 * 8192 * 8192 * 4 + 4 * (1 << 20) + 256 + 256
+                                      + (1 << 20) + 256)
     assert V.footprint_bytes(V.config(16368, 16368, 1)) > 0
     assert V.footprint_bytes(V.config(16369, 8, 1)) == 0
 
@@ -87,6 +88,11 @@ def test_null_and_small_workspace():
     assert "outside" in V.last_error()
     for fn in ("vd_move_seeds", "vd_jfa_step", "vd_djfa_step"):
         assert getattr(L, fn)(None) == -1
+    ids = (ctypes.c_int32 * 2)(0, 1)
+    assert L.vd_remove_seeds(None, ctypes.cast(ids, ctypes.c_void_p), 2) == -1
+    assert L.vd_insert_seeds(None, ctypes.cast(xy, ctypes.c_void_p), 2,
+                             ctypes.cast(ids, ctypes.c_void_p)) == -1
+    assert L.vd_get_seed_set(None, None, 0, None, None) == -1
     L.vd_destroy(None)
 
 
