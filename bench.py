@@ -370,51 +370,68 @@ def bench_djfam(torch, V, args, W, H, xy, kw, stream, map_jfa, djfae_ms, jfa_ms)
 def bench_churn(torch, V, args, W, H, xy, kw, stream, djfa_ms):
     """A changing seed set: before each step, a share `args.with_churn` of
     the seeds is removed and as many are inserted at uniform random
-    positions (the same script for a JFA and a dJFA twin).  Reports the
-    dJFA step time (purge, splat, passes, the unclaimed-pixel count and its
-    read-back), the host time of the two seed-set calls, the number of steps
-    redone as JFA, and the similarity to the JFA twin at the last step."""
+    positions (the same script for a JFA and a dJFA twin).  Two tables:
+    "full" (num_seeds slots, all present: insertions reuse the slots just
+    freed, so each dJFA step also purges their old labels) and "headroom"
+    (as many spare slots as a step inserts: insertions take slots freed a
+    step earlier, no purge).  Reports the dJFA step time (splat, passes, the
+    unclaimed-pixel count and its read-back; the purge where needed), the
+    host time of the two seed-set calls, the steps redone as JFA, and the
+    similarity to the JFA twin at the last step."""
     S = len(xy)
     n = max(1, int(round(args.with_churn * S)))
-    cj = V.Sim(W, H, xy, stream=stream, **kw)
-    cd = V.Sim(W, H, xy, stream=stream, **kw)
-    rng = np.random.default_rng(17)
-    steps = min(args.steps, 50)
-    upd_ms, step_ms, wall_ms = [], [], []
-    for i in range(args.warmup + steps):
-        present = np.flatnonzero(cd.seed_set()[0])
-        gone = rng.choice(present, size=min(n, present.size - 1), replace=False).astype(np.int32)
-        new = np.stack([rng.integers(0, W, gone.size), rng.integers(0, H, gone.size)],
-                       1).astype(np.int32)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        cd.remove_seeds(gone)
-        cd.insert_seeds(new)
-        t1 = time.perf_counter()
-        cj.remove_seeds(gone)
-        cj.insert_seeds(new)
-        cj.move_seeds(), cd.move_seeds()
-        cj.jfa_step()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        e0.record(stream)
-        cd.djfa_step()
-        e1.record(stream)
-        torch.cuda.synchronize()
-        t3 = time.perf_counter()
-        if i >= args.warmup:
-            upd_ms.append(1e3 * (t1 - t0))
-            step_ms.append(e0.elapsed_time(e1))
-            wall_ms.append(1e3 * (t3 - t2))
-    sim = float((cj.read_map() == cd.read_map()).mean())
-    fallbacks = cd.seed_set()[2]
-    cj.close(), cd.close()
-    return {"churn_per_step": n, "steps": steps, "djfa_ms_per_step": float(np.mean(step_ms)),
-            "djfa_wall_ms_per_step": float(np.mean(wall_ms)),
-            "plain_djfa_ms_per_step": djfa_ms,
-            "host_update_ms": float(np.mean(upd_ms)), "fallbacks": int(fallbacks),
-            "similarity_vs_jfa": sim}
+    out = {"churn_per_step": n, "plain_djfa_ms_per_step": djfa_ms}
+    for mode in ("full", "headroom"):
+        rng = np.random.default_rng(17)
+        if mode == "headroom":
+            extra = np.stack([rng.integers(0, W, n), rng.integers(0, H, n)], 1).astype(np.int32)
+            xy0 = np.concatenate([xy, extra])
+        else:
+            xy0 = xy
+        cj = V.Sim(W, H, xy0, stream=stream, **kw)
+        cd = V.Sim(W, H, xy0, stream=stream, **kw)
+        if mode == "headroom":
+            spare = np.arange(S, S + n, dtype=np.int32)
+            for sim in (cj, cd):
+                sim.remove_seeds(spare)
+                sim.jfa_step()
+        steps = min(args.steps, 50)
+        upd_ms, step_ms, wall_ms = [], [], []
+        for i in range(args.warmup + steps):
+            present = np.flatnonzero(cd.seed_set()[0])
+            gone = rng.choice(present, size=min(n, present.size - 1),
+                              replace=False).astype(np.int32)
+            new = np.stack([rng.integers(0, W, gone.size), rng.integers(0, H, gone.size)],
+                           1).astype(np.int32)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cd.remove_seeds(gone)
+            cd.insert_seeds(new)
+            t1 = time.perf_counter()
+            cj.remove_seeds(gone)
+            cj.insert_seeds(new)
+            cj.move_seeds(), cd.move_seeds()
+            cj.jfa_step()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            e0.record(stream)
+            cd.djfa_step()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            if i >= args.warmup:
+                upd_ms.append(1e3 * (t1 - t0))
+                step_ms.append(e0.elapsed_time(e1))
+                wall_ms.append(1e3 * (t3 - t2))
+        sim = float((cj.read_map() == cd.read_map()).mean())
+        fallbacks = cd.seed_set()[2]
+        cj.close(), cd.close()
+        out[mode] = {"steps": steps, "djfa_ms_per_step": float(np.mean(step_ms)),
+                     "djfa_wall_ms_per_step": float(np.mean(wall_ms)),
+                     "host_update_ms": float(np.mean(upd_ms)), "fallbacks": int(fallbacks),
+                     "similarity_vs_jfa": sim}
+    return out
 
 
 def main():

@@ -114,8 +114,9 @@ void vd_config_default(vd_config *cfg);
 /* Device bytes vd_init_sim needs for cfg: two ping-pong label maps
  * (4 B per pixel each), the seed table (4 B per seed plus one sentinel
  * entry; in XY mode also the positions the diagram refers to), 256 B of
- * step counters, the seed-set state (1 B per seed) and 256 B of alignment
- * slack, each part 256-B aligned.
+ * step counters, the seed-set state (1 B per seed; in ID mode also 4 B per
+ * seed for the positions of removed seeds) and 256 B of alignment slack,
+ * each part 256-B aligned.
  * Returns 0 if cfg is invalid. */
 size_t vd_footprint_bytes(const vd_config *cfg);
 
@@ -176,10 +177,13 @@ int vd_set_seeds(vd_sim *sim, const int32_t *host_xy, size_t count);
  * least one seed must stay present (VD_EINVAL otherwise, nothing changed). */
 int vd_remove_seeds(vd_sim *sim, const int32_t *host_ids, size_t n);
 
-/* vd_insert_seeds: n new seeds at (host_xy[2j], host_xy[2j+1]) take the n
- * lowest-index free slots in ascending order; host_ids[j] receives the index
- * of seed j.  VD_ESTATE if fewer than n slots are free, VD_EINVAL for a
- * position off the grid (nothing changed in either case). */
+/* vd_insert_seeds: n new seeds at (host_xy[2j], host_xy[2j+1]) take free
+ * slots in ascending index order, first the slots free since before the
+ * last step, then slots removed since (only the latter make the next dJFA
+ * step purge their old labels, one extra pass over the map in ID mode);
+ * host_ids[j] receives the index of seed j.  VD_ESTATE if fewer than n
+ * slots are free, VD_EINVAL for a position off the grid (nothing changed in
+ * either case). */
 int vd_insert_seeds(vd_sim *sim, const int32_t *host_xy, size_t n, int32_t *host_ids);
 
 /* The seed set: host_present (NULL: skipped; else count == num_seeds bytes)

@@ -329,10 +329,11 @@ class Sim:
         # The seed set: active[i] -- seed i is present now; keep[i] -- present
         # when the diagram was made and ever since; changed -- a seed was
         # inserted or removed since then.  A seed index is a slot of a table
-        # of S entries; removal frees the slot, insertion takes the lowest
-        # free ones.  Removed seeds neither move nor take part in a step.
+        # of S entries; removal frees the slot, insertion takes free ones
+        # (see insert).  Removed seeds neither move nor take part in a step.
         self.active = np.ones(self.S, bool)
         self.keep = np.ones(self.S, bool)
+        self.removed = np.zeros(self.S, bool)     # removed since the diagram was made
         self.changed = False
         self.fell_back = False
 
@@ -354,13 +355,18 @@ class Sim:
         assert self.active.sum() > ids.size, "at least one seed stays"
         self.active[ids] = False
         self.keep[ids] = False
+        self.removed[ids] = True
         self.changed = True
 
     def insert(self, xy):
-        """Inserts seeds at the given positions into the lowest free slots, in
-        ascending order; returns their indices."""
+        """Inserts seeds at the given positions into free slots, in ascending
+        index order: first the slots free since before the diagram was made,
+        then (if those run out) slots removed since, whose old labels the
+        next dJFA step must purge; returns their indices."""
         a = _xy(xy)
-        free = np.flatnonzero(~self.active)[:a.shape[0]]
+        cold = np.flatnonzero(~self.active & ~self.removed)
+        hot = np.flatnonzero(~self.active & self.removed)
+        free = np.concatenate([cold, hot])[:a.shape[0]]
         assert free.size == a.shape[0], "not enough free slots"
         self.xy = self.xy.copy()
         self.xy[free] = a
@@ -379,6 +385,7 @@ class Sim:
         self.map_xy = self.xy
         self.moved = 0
         self.keep = self.active.copy()
+        self.removed[:] = False
         self.changed = False
 
     def jfa_step(self):

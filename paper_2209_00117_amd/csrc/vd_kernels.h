@@ -31,10 +31,12 @@ inline uint32_t pack_pos(int32_t x, int32_t y)
 
 // Seed-set state, one byte per seed (a changing seed set: insertion and
 // removal).  kPresent: the seed is in the set now; kKept: it has been in
-// the set since the current diagram was made.  Launchers take a null state
+// the set since the current diagram was made; kGone: it was removed since
+// then (host bookkeeping; kernels ignore it).  Launchers take a null state
 // when every seed is present and kept.
 constexpr uint32_t kPresent = 1u;
 constexpr uint32_t kKept = 2u;
+constexpr uint32_t kGone = 4u;
 
 // map[0 .. n) = value.
 hipError_t launch_fill(uint32_t *map, int64_t n, uint32_t value, hipStream_t s);
@@ -57,18 +59,29 @@ hipError_t launch_move(uint32_t *table, int32_t S, int32_t W, int32_t H, uint64_
                        hipStream_t s);
 
 // Seeds moved to the S packed positions in `staged` (device memory); disp
-// as for launch_move (present seeds only).
+// as for launch_move (present seeds only).  `parked` (ID labels, else null)
+// receives the positions of absent seeds.
 hipError_t launch_set_seeds(uint32_t *table, const uint32_t *staged, int32_t S,
-                            const uint8_t *state, uint32_t *disp, hipStream_t s);
+                            const uint8_t *state, uint32_t *parked, uint32_t *disp, hipStream_t s);
 
 // Inserted seeds: n (index, packed position) pairs staged in device memory.
 hipError_t launch_place(uint32_t *table, const uint32_t *staged, int32_t n, hipStream_t s);
 
-// ID labels of seeds without kKept become unclaimed.
-hipError_t launch_purge(uint32_t *map, const uint8_t *state, int64_t n, hipStream_t s);
+// Removed seeds with ID labels (n indices staged in device memory): the
+// position is kept in parked[i], the table entry becomes the sentinel.
+hipError_t launch_park(uint32_t *table, uint32_t *parked, const uint32_t *ids, int32_t n,
+                       hipStream_t s);
 
-// *count = number of unclaimed pixels of map[0 .. n).
-hipError_t launch_count_empty(const uint32_t *map, int64_t n, uint32_t *count, hipStream_t s);
+// ID labels of seeds without kKept become unclaimed (state: S bytes; the
+// map's n pixels, 16-byte aligned).
+hipError_t launch_purge(uint32_t *map, const uint8_t *state, int32_t S, int64_t n,
+                        hipStream_t s);
+
+// *count = number of unclaimed pixels of map[0 .. n) (16-byte aligned):
+// label 0, or with state (S bytes) non-null, ID labels of seeds without
+// kPresent.
+hipError_t launch_count_unclaimed(const uint32_t *map, int64_t n, const uint8_t *state,
+                                  int32_t S, uint32_t *count, hipStream_t s);
 
 // After a step: present seeds become kept, absent ones lose kKept.
 hipError_t launch_settle(uint8_t *state, int32_t S, hipStream_t s);

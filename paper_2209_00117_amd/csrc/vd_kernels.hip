@@ -100,18 +100,27 @@ __global__ void __launch_bounds__(kBlock) k_move(uint32_t *__restrict__ table, i
 }
 
 // Seeds moved to caller-given positions (packed, staged in device memory);
-// only present seeds count towards the displacement.
+// only present seeds count towards the displacement.  With `parked`
+// non-null (ID labels), an absent seed's position goes there: its table
+// entry holds the sentinel.
 __global__ void __launch_bounds__(kBlock) k_set_seeds(uint32_t *__restrict__ table,
                                                       const uint32_t *__restrict__ staged,
                                                       int32_t S, const uint8_t *__restrict__ state,
+                                                      uint32_t *__restrict__ parked,
                                                       uint32_t *__restrict__ disp)
 {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t moved = 0;
     if (i < S) {
-        const uint32_t p = table[i + 1], q = staged[i];
-        table[i + 1] = q;
-        if (takes_part(state, i, kPresent)) moved = cheb(p, q);
+        const uint32_t q = staged[i];
+        if (takes_part(state, i, kPresent)) {
+            moved = cheb(table[i + 1], q);
+            table[i + 1] = q;
+        } else if (parked) {
+            parked[i] = q;
+        } else {
+            table[i + 1] = q;
+        }
     }
     if (disp) wave_max_into(&disp[1], moved);
 }
@@ -125,25 +134,136 @@ __global__ void __launch_bounds__(kBlock) k_place(uint32_t *__restrict__ table,
     if (j < n) table[staged[2 * j] + 1] = staged[2 * j + 1];
 }
 
-// ID labels of seeds not kept since the diagram was made become unclaimed.
-__global__ void __launch_bounds__(kBlock) k_purge(uint32_t *__restrict__ map,
-                                                  const uint8_t *__restrict__ state, int64_t n)
+// Removed seeds (ID labels): the position moves to `parked` and the table
+// entry becomes the sentinel position, so every flood pass finds the seed's
+// labels farther than any present seed's -- exactly as if they were
+// unclaimed pixels (label 0 also reads the sentinel; a tie between the two
+// only decides which unclaimed label a pixel holds).
+__global__ void __launch_bounds__(kBlock) k_park(uint32_t *__restrict__ table,
+                                                 uint32_t *__restrict__ parked,
+                                                 const uint32_t *__restrict__ ids, int32_t n)
 {
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
-        const uint32_t l = map[p];
-        if (l != kEmpty && (state[l - 1] & kKept) == 0u) map[p] = kEmpty;
+    int32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) {
+        const uint32_t i = ids[j];
+        parked[i] = table[i + 1];
+        table[i + 1] = 0u;
     }
 }
 
-// *count += the number of unclaimed pixels (one atomic per wave).
-__global__ void __launch_bounds__(kBlock) k_count_empty(const uint32_t *__restrict__ map,
-                                                        int64_t n, uint32_t *__restrict__ count)
+// Whole-map scans of the seed-set code (purge, unclaimed count): each lane
+// takes kScanVec 16-byte vectors, kScanVec * (lanes in the grid) apart,
+// and requests them all before using any; a label's state byte is fetched
+// only where it differs from the label to its left (the fetch of a reusing
+// lane goes to offset -1, which the hardware answers without a memory
+// access).  Each 16-byte vector covers four pixels; n & 3 tail pixels are
+// handled one per lane.
+constexpr int kScanVec = 4;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t bytes_rsrc(const uint8_t *p, int32_t n)
 {
-    int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    return __builtin_amdgcn_make_buffer_rsrc((void *)p, 0, p ? n : 0, kRsrcWord3);
+}
+
+// State bytes of the four labels of v (0 for label 0 and for a label equal
+// to its left neighbour; `left` is the label left of v[0]).
+__device__ __forceinline__ u32x4 state4(__amdgpu_buffer_rsrc_t sr, const u32x4 &v, uint32_t left)
+{
+    u32x4 b;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const uint32_t l = v[e], lft = e == 0 ? left : v[e - 1];
+        const int32_t at = (l != kEmpty && l != lft) ? (int32_t)l - 1 : -1;
+        b[e] = __builtin_amdgcn_raw_buffer_load_b8(sr, at, 0, 0);
+    }
+    return b;
+}
+
+// ID labels of seeds not kept since the diagram was made become unclaimed
+// (vectors where nothing changes are not written).
+__global__ void __launch_bounds__(kBlock) k_purge(uint32_t *__restrict__ map, int64_t n,
+                                                  const uint8_t *__restrict__ state, int32_t S)
+{
+    const int64_t n4 = n >> 2;
+    const int64_t T = (int64_t)gridDim.x * blockDim.x;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const __amdgpu_buffer_rsrc_t sr = bytes_rsrc(state, S);
+    u32x4 *m4 = reinterpret_cast<u32x4 *>(map);
+    for (int64_t q0 = g; q0 < n4; q0 += kScanVec * T) {
+        u32x4 v[kScanVec];
+#pragma unroll
+        for (int u = 0; u < kScanVec; ++u) {
+            const int64_t q = q0 + u * T;
+            v[u] = q < n4 ? m4[q] : u32x4{0u, 0u, 0u, 0u};
+        }
+#pragma unroll
+        for (int u = 0; u < kScanVec; ++u) {
+            const u32x4 b = state4(sr, v[u], kEmpty);
+            u32x4 o = v[u];
+            bool dirty = false;
+            bool gone = false;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                // a label equal to its left neighbour shares its verdict
+                gone = (e > 0 && v[u][e] == v[u][e - 1]) ? gone
+                                                         : (v[u][e] != kEmpty && (b[e] & kKept) == 0u);
+                o[e] = gone ? kEmpty : v[u][e];
+                dirty = dirty || gone;
+            }
+            const int64_t q = q0 + u * T;
+            if (dirty && q < n4) m4[q] = o;
+        }
+    }
+    const int64_t tail = 4 * n4 + g;
+    if (tail < n) {
+        const uint32_t l = map[tail];
+        if (l != kEmpty && (state[l - 1] & kKept) == 0u) map[tail] = kEmpty;
+    }
+}
+
+// *count += the number of unclaimed pixels of map[0 .. n): label 0, or with
+// state non-null (ID labels) the label of an absent seed; one atomic per
+// wave that found any.
+__global__ void __launch_bounds__(kBlock) k_count_unclaimed(const uint32_t *__restrict__ map,
+                                                            int64_t n,
+                                                            const uint8_t *__restrict__ state,
+                                                            int32_t S,
+                                                            uint32_t *__restrict__ count)
+{
+    const int64_t n4 = n >> 2;
+    const int64_t T = (int64_t)gridDim.x * blockDim.x;
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const __amdgpu_buffer_rsrc_t sr = bytes_rsrc(state, S);
+    const u32x4 *m4 = reinterpret_cast<const u32x4 *>(map);
     uint32_t c = 0;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride)
-        c += map[p] == kEmpty ? 1u : 0u;
+    for (int64_t q0 = g; q0 < n4; q0 += kScanVec * T) {
+        u32x4 v[kScanVec];
+#pragma unroll
+        for (int u = 0; u < kScanVec; ++u) {
+            const int64_t q = q0 + u * T;
+            // past the end: a claimed label (state byte 1 is never fetched for it)
+            v[u] = q < n4 ? m4[q] : u32x4{1u, 1u, 1u, 1u};
+        }
+#pragma unroll
+        for (int u = 0; u < kScanVec; ++u) {
+            const int64_t q = q0 + u * T;
+            if (q >= n4) continue;
+            const u32x4 b = state4(sr, v[u], kEmpty);
+            uint32_t un = 0;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                un = (e > 0 && v[u][e] == v[u][e - 1])
+                         ? un
+                         : ((v[u][e] == kEmpty || (state && (b[e] & kPresent) == 0u)) ? 1u : 0u);
+                c += un;
+            }
+        }
+    }
+    const int64_t tail = 4 * n4 + g;
+    if (tail < n) {
+        const uint32_t l = map[tail];
+        c += (l == kEmpty || (state && (state[l - 1] & kPresent) == 0u)) ? 1u : 0u;
+    }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) c += (uint32_t)__shfl_xor((int)c, o, 64);
     if ((threadIdx.x & 63u) == 0u && c) atomicAdd(count, c);
@@ -377,10 +497,10 @@ hipError_t launch_move(uint32_t *table, int32_t S, int32_t W, int32_t H, uint64_
 }
 
 hipError_t launch_set_seeds(uint32_t *table, const uint32_t *staged, int32_t S,
-                            const uint8_t *state, uint32_t *disp, hipStream_t s)
+                            const uint8_t *state, uint32_t *parked, uint32_t *disp, hipStream_t s)
 {
     hipLaunchKernelGGL(k_set_seeds, grid1d(S), dim3(kBlock), 0, s, table, staged, S, state,
-                       disp);
+                       parked, disp);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !disp) return e;
     hipLaunchKernelGGL(k_disp_acc, dim3(1), dim3(64), 0, s, disp);
@@ -394,17 +514,41 @@ hipError_t launch_place(uint32_t *table, const uint32_t *staged, int32_t n, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_purge(uint32_t *map, const uint8_t *state, int64_t n, hipStream_t s)
+hipError_t launch_park(uint32_t *table, uint32_t *parked, const uint32_t *ids, int32_t n,
+                       hipStream_t s)
 {
-    hipLaunchKernelGGL(k_purge, grid1d(n, 8192), dim3(kBlock), 0, s, map, state, n);
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_park, grid1d(n), dim3(kBlock), 0, s, table, parked, ids, n);
     return hipGetLastError();
 }
 
-hipError_t launch_count_empty(const uint32_t *map, int64_t n, uint32_t *count, hipStream_t s)
+namespace {
+
+// Grid of a whole-map scan: one round of kScanVec vectors per lane where
+// the map allows, at most 8192 workgroups, and every tail pixel covered.
+dim3 scan_grid(int64_t n)
+{
+    const int64_t per_block = (int64_t)kBlock * kScanVec;
+    int64_t blocks = ((n >> 2) + per_block - 1) / per_block;
+    return dim3((unsigned)std::min<int64_t>(std::max<int64_t>(blocks, 1), 8192));
+}
+
+}  // namespace
+
+hipError_t launch_purge(uint32_t *map, const uint8_t *state, int32_t S, int64_t n,
+                        hipStream_t s)
+{
+    hipLaunchKernelGGL(k_purge, scan_grid(n), dim3(kBlock), 0, s, map, n, state, S);
+    return hipGetLastError();
+}
+
+hipError_t launch_count_unclaimed(const uint32_t *map, int64_t n, const uint8_t *state,
+                                  int32_t S, uint32_t *count, hipStream_t s)
 {
     hipError_t e = launch_fill(count, 1, 0u, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_count_empty, grid1d(n, 8192), dim3(kBlock), 0, s, map, n, count);
+    hipLaunchKernelGGL(k_count_unclaimed, scan_grid(n), dim3(kBlock), 0, s, map, n, state, S,
+                       count);
     return hipGetLastError();
 }
 

@@ -147,6 +147,7 @@ size_t footprint(const vd_config *c)
     if (c->label == VD_LABEL_XY16) b += align_up(seeds + 4);
     b += align_up(12);                     // step counters
     b += align_up((size_t)c->num_seeds);   // seed-set state bytes
+    if (c->label == VD_LABEL_ID32) b += align_up(seeds);   // parked positions
     return b + kAlign;
 }
 
@@ -240,7 +241,11 @@ int jfa_prologue(vd_sim *s)
 // The map a dJFA step floods: the previous diagram (XY: relabelled to the
 // moved positions) with every seed pixel claimed by its seed.  After
 // insertions or removals, labels of seeds not kept since the diagram was
-// made leave it first (ID: purged; XY: the relabel finds no kept seed).
+// made leave it first.  XY: the relabel finds no kept seed for them.  ID: a
+// removed seed's table entry holds the sentinel position, so the passes
+// treat its labels like unclaimed pixels without touching the map; only a
+// slot removed and inserted again (whose entry is a live position) needs
+// its old labels purged.
 int djfa_prologue(vd_sim *s)
 {
     const vd_config &c = s->cfg;
@@ -254,8 +259,9 @@ int djfa_prologue(vd_sim *s)
         VD_HIP(vd::launch_relabel(cur, idx, c.width, c.height, s->stream));
         VD_HIP(vd::launch_splat_xy(cur, s->pos, c.num_seeds, c.width, seed_state(s), s->stream));
     } else {
-        if (s->changed)
-            VD_HIP(vd::launch_purge(cur, s->state, (int64_t)c.width * c.height, s->stream));
+        if (s->reinserted)
+            VD_HIP(vd::launch_purge(cur, s->state, c.num_seeds, (int64_t)c.width * c.height,
+                                    s->stream));
         VD_HIP(vd::launch_splat_id(cur, s->pos, c.num_seeds, c.width, seed_state(s), s->stream));
     }
     return VD_OK;
@@ -287,16 +293,18 @@ int do_djfa(vd_sim *s)
     return r;
 }
 
-// After a dJFA step that followed insertions or removals: a removed seed's
-// cell must have been refilled by its neighbours within the passes.  If a
-// pixel is still unclaimed, the step is redone as a full JFA step.  Reads
-// the count back, so the step waits for its stream here.
+// After a dJFA step that followed removals: a removed seed's cell must
+// have been refilled by its neighbours within the passes.  If a pixel is
+// still unclaimed (label 0, or in ID mode an absent seed's label), the step
+// is redone as a full JFA step.  Reads the count back, so the step waits
+// for its stream here.
 int refill_check(vd_sim *s)
 {
     const vd_config &c = s->cfg;
     uint32_t n = 0;
-    VD_HIP(vd::launch_count_empty(s->map[s->cur], (int64_t)c.width * c.height, &s->disp[2],
-                                  s->stream));
+    VD_HIP(vd::launch_count_unclaimed(s->map[s->cur], (int64_t)c.width * c.height,
+                                      c.label == VD_LABEL_ID32 ? s->state : nullptr,
+                                      c.num_seeds, &s->disp[2], s->stream));
     VD_HIP(hipMemcpyAsync(&n, &s->disp[2], 4, hipMemcpyDeviceToHost, s->stream));
     VD_HIP(hipStreamSynchronize(s->stream));
     if (n == 0) return VD_OK;
@@ -311,7 +319,7 @@ int settle(vd_sim *s)
     VD_HIP(vd::launch_settle(s->state, s->cfg.num_seeds, s->stream));
     for (uint8_t &b : s->host_state)
         b = (b & vd::kPresent) ? (uint8_t)(vd::kPresent | vd::kKept) : (uint8_t)0;
-    s->changed = false;
+    s->changed = s->removed = s->reinserted = false;
     s->masked = s->present < s->cfg.num_seeds;
     return VD_OK;
 }
@@ -359,9 +367,9 @@ int step(vd_sim *s, bool dynamic)
     size_t slot = 0;
     r = record(s, 1, true, &slot);
     if (r) return r;
-    const bool changed = s->changed;
+    const bool removed = s->removed;
     r = dynamic ? do_djfa(s) : do_jfa(s);
-    if (r == VD_OK && dynamic && changed) r = refill_check(s);
+    if (r == VD_OK && dynamic && removed) r = refill_check(s);
     if (r == VD_OK) r = settle(s);
     // the diagram now refers to the current positions
     if (r == VD_OK && s->measured) {
@@ -751,6 +759,8 @@ int vd_init_sim(const vd_config *cfg, const int32_t *host_xy, void *dev_workspac
     s->disp = (uint32_t *)base;
     base += align_up(12);
     s->state = (uint8_t *)base;
+    base += align_up((size_t)S);
+    if (cfg->label == VD_LABEL_ID32) s->parked = (uint32_t *)base;
     try {
         s->host_state.assign((size_t)S, (uint8_t)(vd::kPresent | vd::kKept));
     } catch (...) {
@@ -831,7 +841,7 @@ int vd_set_seeds(vd_sim *s, const int32_t *host_xy, size_t count)
     hipError_t e = hipMemcpyAsync(staged, packed.data(), (size_t)S * 4, hipMemcpyHostToDevice,
                                   s->stream);
     if (e == hipSuccess)
-        e = vd::launch_set_seeds(s->pos, staged, S, seed_state(s),
+        e = vd::launch_set_seeds(s->pos, staged, S, seed_state(s), s->parked,
                                  s->measured ? s->disp : nullptr, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);   // packed is a local buffer
     if (e != hipSuccess) {
@@ -857,10 +867,17 @@ int vd_remove_seeds(vd_sim *s, const int32_t *host_ids, size_t n)
         if (i < 0 || i >= S) return fail(VD_EINVAL, "seed index %d outside [0, %d)", i, S);
         if (!(next[(size_t)i] & vd::kPresent))
             return fail(VD_EINVAL, "seed %d is not present (or named twice)", i);
-        next[(size_t)i] = 0;
+        next[(size_t)i] = (uint8_t)vd::kGone;
     }
-    hipError_t e = hipMemcpyAsync(s->state, next.data(), (size_t)S, hipMemcpyHostToDevice,
-                                  s->stream);
+    hipError_t e = hipSuccess;
+    if (s->parked) {
+        // the indices, staged in the idle ping-pong map (n < S <= width*height)
+        uint32_t *staged = s->map[s->cur ^ 1];
+        e = hipMemcpyAsync(staged, host_ids, n * 4, hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess) e = vd::launch_park(s->pos, s->parked, staged, (int32_t)n, s->stream);
+    }
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->state, next.data(), (size_t)S, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);   // next is a local buffer
     if (e != hipSuccess) {
         s->broken = true;
@@ -868,7 +885,7 @@ int vd_remove_seeds(vd_sim *s, const int32_t *host_ids, size_t n)
     }
     s->host_state.swap(next);
     s->present -= (int32_t)n;
-    s->changed = s->masked = true;
+    s->changed = s->removed = s->masked = true;
     replan_djfa(s);
     return VD_OK;
 }
@@ -896,14 +913,21 @@ int vd_insert_seeds(vd_sim *s, const int32_t *host_xy, size_t n, int32_t *host_i
     } catch (...) {
         return fail(VD_ENOMEM, "host allocation of %zu seeds failed", n);
     }
-    // the lowest free slots, in ascending order
+    // Free slots in ascending order, first those free since before the
+    // diagram was made (no label of theirs is left in it), then those
+    // removed since (their old labels must be purged at the next dJFA step).
     size_t j = 0;
-    for (int32_t i = 0; i < S && j < n; ++i) {
-        if (next[(size_t)i] & vd::kPresent) continue;
-        next[(size_t)i] = (uint8_t)vd::kPresent;   // not kept: its old labels are stale
-        pairs[2 * j] = (uint32_t)i;
-        pairs[2 * j + 1] = vd::pack_pos(host_xy[2 * j], host_xy[2 * j + 1]);
-        ++j;
+    bool again = false;
+    for (int pass = 0; pass < 2 && j < n; ++pass) {
+        for (int32_t i = 0; i < S && j < n; ++i) {
+            const uint8_t b = next[(size_t)i];
+            if ((b & vd::kPresent) || ((b & vd::kGone) != 0) != (pass == 1)) continue;
+            again = again || pass == 1;
+            next[(size_t)i] = (uint8_t)vd::kPresent;   // not kept: no label of its own yet
+            pairs[2 * j] = (uint32_t)i;
+            pairs[2 * j + 1] = vd::pack_pos(host_xy[2 * j], host_xy[2 * j + 1]);
+            ++j;
+        }
     }
     // staged in the idle ping-pong map, at most width*height words at a time
     uint32_t *staged = s->map[s->cur ^ 1];
@@ -925,6 +949,7 @@ int vd_insert_seeds(vd_sim *s, const int32_t *host_xy, size_t n, int32_t *host_i
     s->host_state.swap(next);
     s->present += (int32_t)n;
     s->changed = s->masked = true;
+    s->reinserted = s->reinserted || again;
     replan_djfa(s);
     return VD_OK;
 }
@@ -974,6 +999,19 @@ int vd_read_seeds(vd_sim *s, int32_t *host_xy, size_t count)
         return fail(VD_ENOMEM, "host allocation failed");
     }
     VD_HIP(hipMemcpyAsync(packed.data(), s->pos + 1, S * 4, hipMemcpyDeviceToHost, s->stream));
+    if (s->parked && s->present < (int32_t)S) {
+        // absent seeds (ID labels): their positions are parked
+        std::vector<uint32_t> parked;
+        try {
+            parked.resize(S);
+        } catch (...) {
+            return fail(VD_ENOMEM, "host allocation failed");
+        }
+        VD_HIP(hipMemcpyAsync(parked.data(), s->parked, S * 4, hipMemcpyDeviceToHost, s->stream));
+        VD_HIP(hipStreamSynchronize(s->stream));
+        for (size_t i = 0; i < S; ++i)
+            if (!(s->host_state[i] & vd::kPresent)) packed[i] = parked[i];
+    }
     VD_HIP(hipStreamSynchronize(s->stream));
     for (size_t i = 0; i < S; ++i) {
         host_xy[2 * i] = (int32_t)(packed[i] & 0xFFFFu) - (int32_t)vd::kOff;

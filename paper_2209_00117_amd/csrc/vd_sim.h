@@ -47,8 +47,12 @@ struct vd_sim {
     // kKept, on the device and mirrored here.
     uint8_t *state = nullptr;
     std::vector<uint8_t> host_state;
+    uint32_t *parked = nullptr;  // ID labels: positions of absent seeds (their table
+                                 // entries hold the sentinel)
     int32_t present = 0;         // seeds in the set now
     bool changed = false;        // a seed inserted or removed since the diagram was made
+    bool removed = false;        // a seed removed since then
+    bool reinserted = false;     // a slot removed since then was inserted again
     bool masked = false;         // changed, or some seed absent: kernels read `state`
     int64_t fallbacks = 0;       // dJFA steps replaced by a JFA step (unrefilled pixels)
     bool measured = false;       // d_max of each dJFA step from disp[0]

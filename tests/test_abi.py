@@ -38,13 +38,14 @@ def test_footprint():
     c = V.config(512, 512, 256)
     npix = 512 * 512 * 4
     # two maps, the seed table with its sentinel entry (256-B aligned), step
-    # counters (256 B), seed-set state (1 B per seed, 256-B aligned), slack
-    assert V.footprint_bytes(c) == 2 * npix + 1280 + 256 + 256 + 256
+    # counters (256 B), seed-set state (1 B per seed, 256-B aligned), ID
+    # mode: parked positions (4 B per seed), slack (256 B)
+    assert V.footprint_bytes(c) == 2 * npix + 1280 + 256 + 256 + 1024 + 256
     cx = V.config(512, 512, 256, label=V.LABEL_XY16)
     assert V.footprint_bytes(cx) == 2 * npix + 1280 + 1280 + 256 + 256 + 256
     big = V.config(8192, 8192, 1 << 20)
     assert V.footprint_bytes(big) == (2 * 8192 * 8192 * 4 + 4 * (1 << 20) + 256 + 256
-                                      + (1 << 20) + 256)
+                                      + (1 << 20) + 4 * (1 << 20) + 256)
     assert V.footprint_bytes(V.config(16368, 16368, 1)) > 0
     assert V.footprint_bytes(V.config(16369, 8, 1)) == 0
 

@@ -131,6 +131,48 @@ def test_reinserted_slot(V, label):
 
 
 @pytest.mark.parametrize("label", [0, 1])
+def test_insert_prefers_cold_slots(V, label):
+    """Slots free since before the last step are taken first; a slot freed
+    since is reused (and its old labels purged) only when they run out."""
+    W, H = 96, 64
+    xy = inputs.place_seeds(W, H, 10, 2)
+    g, o = _pair(V, W, H, xy, -1, 1, 2, label)
+    g.remove_seeds([8, 4]), o.remove([8, 4])
+    g.djfa_step(), o.djfa_step()
+    g.remove_seeds([1, 6]), o.remove([1, 6])
+    new = np.array([[1, 1], [2, 2], [3, 3]], np.int32)
+    ids = g.insert_seeds(new)
+    assert ids.tolist() == [4, 8, 1] and np.array_equal(ids, o.insert(new))
+    g.move_seeds(), o.move()
+    g.djfa_step(), o.djfa_step()
+    _same(g, o, "cold")
+    g.close()
+
+
+@pytest.mark.parametrize("label", [0, 1])
+def test_set_seeds_with_absent_seeds(V, label):
+    """Caller-given positions for every slot, absent ones included (they
+    keep the new position while absent and count towards no displacement),
+    with measured d_max; then the absent slots are inserted again."""
+    W, H = 160, 120
+    xy = inputs.place_seeds(W, H, 50, 8)
+    g, o = _pair(V, W, H, xy, -1, 1, 8, label, dmax=O.DMAX_MEASURED)
+    g.remove_seeds([1, 2, 40]), o.remove([1, 2, 40])
+    rng = np.random.default_rng(8)
+    for _ in range(2):
+        new = np.clip(o.xy + rng.integers(-3, 4, o.xy.shape), 0, [W - 1, H - 1]).astype(np.int32)
+        g.set_seeds(new), o.set_positions(new)
+        g.djfa_step(), o.djfa_step()
+        _same(g, o, "set_seeds")
+    back = np.array([[5, 5], [150, 110], [80, 60]], np.int32)
+    assert np.array_equal(g.insert_seeds(back), o.insert(back))
+    g.move_seeds(), o.move()
+    g.djfa_step(), o.djfa_step()
+    _same(g, o, "set_seeds+insert")
+    g.close()
+
+
+@pytest.mark.parametrize("label", [0, 1])
 def test_unrefillable_hole_falls_back(V, label):
     W = H = 256
     rng = np.random.default_rng(1)

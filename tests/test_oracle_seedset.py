@@ -102,7 +102,8 @@ def test_djfa_after_removal_and_insertion(orc, label_mode):
         s.remove(gone)
         if step % 2 == 0:
             fresh = np.stack([rng.integers(0, W, 12), rng.integers(0, H, 12)], 1).astype(np.int32)
-            free = np.flatnonzero(~s.active)[:12]
+            free = np.concatenate([np.flatnonzero(~s.active & ~s.removed),
+                                   np.flatnonzero(~s.active & s.removed)])[:12]
             ids = s.insert(fresh)
             assert np.array_equal(ids, free)
             assert np.array_equal(s.xy[ids], fresh)
@@ -117,6 +118,23 @@ def test_djfa_after_removal_and_insertion(orc, label_mode):
         for (x, y), i in first.items():
             assert m[y, x] == (i if label_mode == 0 else (y << 16 | x))
         assert _exact_share(orc, m, s.xy, s.active, W, H, label_mode) >= 0.99
+
+
+def test_insert_prefers_slots_free_before_the_diagram(orc):
+    """Slots free since before the last step come first (their labels are
+    gone from the diagram), then slots removed since, lowest index first."""
+    W = H = 40
+    xy = inputs.place_seeds(W, H, 10, 2)
+    s = orc.Sim(W, H, xy, 1, -1, 1)
+    s.remove([8, 4])
+    s.djfa_step()
+    s.remove([1, 6])
+    ids = s.insert(np.array([[1, 1], [2, 2], [3, 3]], np.int32))
+    assert ids.tolist() == [4, 8, 1]
+    assert not s.keep[[1, 4, 8]].any() and s.active[[1, 4, 8]].all() and not s.active[6]
+    s.djfa_step()
+    s.remove([0])
+    assert s.insert(np.array([[5, 5]], np.int32)).tolist() == [6]
 
 
 def test_insert_takes_lowest_free_slots(orc):
