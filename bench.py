@@ -37,7 +37,8 @@ METRIC = "pixel-updates/s and ms per time step (dJFA vs JFA), % HBM peak; p50/p9
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
 BYTES_PER_PIXEL_UPDATE = 8     # one 4-byte label read + one 4-byte label write per pass
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2209_00117_amd", "csrc", f)
-                  for f in ("vd_device.h", "vd_quad.h", "vd_kernels.hip", "vd_kernels.h")]
+                  for f in ("vd_device.h", "vd_quad.h", "vd_tail.h", "vd_kernels.hip",
+                            "vd_kernels.h")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "flood_traffic.json")
 
 
@@ -457,6 +458,11 @@ def main():
     ap.add_argument("--sweep", action="store_true",
                     help="time dJFA for vn_passes in {0,1,2} x extra_passes in {0,1,2} (and "
                          "JFA+extra) on the workload, with similarities to JFA")
+    ap.add_argument("--tail-fusion", default="auto",
+                    choices=["auto", "on", "off", "16", "24", "32"],
+                    help="run each step's last passes (k = 4, 2, 1) as one LDS-tiled launch "
+                         "(16, 24, 32: the tile height; on: 16); auto = the default or the "
+                         "autotuner's choice")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (run every pass with the default kernel variant)")
     ap.add_argument("--calibrate", action="store_true",
@@ -501,6 +507,11 @@ def main():
         # the process-wide table.  The simulation's state is left unchanged.
         V.autotune(sj.handle, 3)
     sd = V.Sim(W, H, xy, stream=stream, **kw)
+    if args.tail_fusion != "auto":
+        for sim in (sj, sd):
+            mode = {"on": 1, "off": 0}.get(args.tail_fusion)
+            V.set_tail_fusion(sim.handle, int(args.tail_fusion) if mode is None else mode)
+    fused = V.get_tail_fusion(sd.handle)
     info = sd.info()
     pj, pd = info.passes_jfa, info.passes_djfa
     if not args.no_tune:
@@ -586,7 +597,8 @@ def main():
         "data": "synthetic (uniform random seeds and moves, splitmix64)",
         "config": {"workload": wl.name, "width": W, "height": H, "seeds": spec.num_seeds,
                    "disp": [spec.disp_lo, spec.disp_hi], "label": args.label,
-                   "passes_jfa": pj, "passes_djfa": pd, "k1": info.k1, "delta1": info.delta1},
+                   "passes_jfa": pj, "passes_djfa": pd, "k1": info.k1, "delta1": info.delta1,
+                   "fused_tail_passes": {"jfa": fused[0], "djfa": fused[1]}},
         "jfa": {"ms_per_step": float(np.mean(jfa_ms)), "p50_ms": pct(jfa_ms, 50),
                 "p99_ms": pct(jfa_ms, 99),
                 "pixel_updates_per_s": W * H * pj / (np.mean(jfa_ms) / 1e3)},

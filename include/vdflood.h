@@ -248,6 +248,17 @@ int vd_get_timing(vd_sim *sim, vd_timing *out);
  * labels. */
 int vd_set_flood_variant(vd_sim *sim, int variant);
 
+/* Tail fusion: a step's last passes (the longest run of steps 1, 2 or 4
+ * summing to at most 8, at most four passes, e.g. k = 4, 2, 1) run as one
+ * launch that keeps tiles of the map in LDS between them; the map is the
+ * same either way.  mode 16, 24 or 32: on, with tiles of 48 x mode
+ * outputs; 1: on with 16-row tiles; 0: off; -1: the default (off) or the
+ * choice vd_autotune made for the step kind.  VD_EINVAL for another mode. */
+int vd_set_tail_fusion(vd_sim *sim, int mode);
+
+/* Passes each step kind currently runs fused (0: none). */
+int vd_get_tail_fusion(const vd_sim *sim, int32_t *jfa, int32_t *djfa);
+
 /* Chooses, by timing, the kernel variant and the segment length of every
  * flood pass of this simulation's JFA and dJFA steps.  One JFA step (from
  * scratch on the current seeds) and one dJFA step (from the current

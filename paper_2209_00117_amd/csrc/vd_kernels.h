@@ -149,4 +149,21 @@ hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *tabl
                         int32_t W, int32_t H, int32_t k, int32_t vn, int32_t label,
                         int32_t metric, int32_t variant, int32_t seg_rows, hipStream_t s);
 
+// The last n passes of a step in one launch (tiles in LDS, see vd_tail.h):
+// steps ks[0..n) (each 1, 2 or 4, in pass order, summing to at most
+// kTailHalo) with Von Neumann flags vns; 2 <= n <= kTailMaxPasses; tiles of
+// 48 x th outputs, th = 16, 24 or 32.  Gives the same dst as the n passes
+// run one after another.
+constexpr int kTailHalo = 8;
+constexpr int kTailMaxPasses = 4;
+struct TailPlan {
+    int32_t n, halo;
+    int32_t k[kTailMaxPasses], vn[kTailMaxPasses];
+    uint32_t ntx;   // tiles across the map
+};
+hipError_t launch_flood_tail(const uint32_t *src, uint32_t *dst, const uint32_t *table, int32_t S,
+                             int32_t W, int32_t H, const int32_t *ks, const int32_t *vns,
+                             int32_t n, int32_t label, int32_t metric, bool nt, int32_t th,
+                             hipStream_t s);
+
 }  // namespace vd

@@ -3,6 +3,7 @@
 // vd_device.h.
 #include "vd_device.h"
 #include "vd_quad.h"
+#include "vd_tail.h"
 
 namespace vd {
 
@@ -436,6 +437,18 @@ __global__ void __launch_bounds__(kBlock) k_flood_quad_idd(const uint32_t *__res
                                               xcd_logical(blockIdx.x, g.nblocks));
 }
 
+template <int LABEL, int METRIC, int ST, int TH>
+__global__ void __launch_bounds__(kBlock) k_flood_tail(const uint32_t *__restrict__ src,
+                                                       uint32_t *__restrict__ dst,
+                                                       const uint32_t *__restrict__ table,
+                                                       uint32_t S, int32_t W, int32_t H,
+                                                       TailPlan plan)
+{
+    __shared__ TailBuf<TH> buf[2];
+    flood_tail_tile<LABEL, METRIC, ST, TH>(src, dst, table, S, W, H, plan,
+                                           xcd_logical(blockIdx.x, gridDim.x), buf);
+}
+
 inline dim3 grid1d(int64_t n, int64_t cap = 1 << 20)
 {
     int64_t b = (n + kBlock - 1) / kBlock;
@@ -728,6 +741,52 @@ hipError_t launch_flood_st(const uint32_t *src, uint32_t *dst, const uint32_t *t
 }
 
 }  // namespace
+
+hipError_t launch_flood_tail(const uint32_t *src, uint32_t *dst, const uint32_t *table, int32_t S,
+                             int32_t W, int32_t H, const int32_t *ks, const int32_t *vns,
+                             int32_t n, int32_t label, int32_t metric, bool nt, int32_t th,
+                             hipStream_t s)
+{
+    if (n < 2 || n > kTailMaxPasses) return hipErrorInvalidValue;
+    if (th != 16 && th != 24 && th != 32) return hipErrorInvalidValue;
+    TailPlan plan{};
+    plan.n = n;
+    for (int32_t i = 0; i < n; ++i) {
+        if (ks[i] != 1 && ks[i] != 2 && ks[i] != 4) return hipErrorInvalidValue;
+        plan.k[i] = ks[i];
+        plan.vn[i] = vns[i] ? 1 : 0;
+        plan.halo += ks[i];
+    }
+    if (plan.halo > kTailHalo) return hipErrorInvalidValue;
+    plan.ntx = (uint32_t)((W + kTailTW - 1) / kTailTW);
+    const int64_t blocks = (int64_t)plan.ntx * ((H + th - 1) / th);
+    dim3 grid((unsigned)blocks), block(kBlock);
+    const uint32_t uS = (uint32_t)S;
+#define VD_TAIL_TH(LB, MT, ST)                                                                 \
+    do {                                                                                       \
+        if (th == 16)                                                                          \
+            hipLaunchKernelGGL((k_flood_tail<LB, MT, ST, 16>), grid, block, 0, s, src, dst,    \
+                               table, uS, W, H, plan);                                         \
+        else if (th == 24)                                                                     \
+            hipLaunchKernelGGL((k_flood_tail<LB, MT, ST, 24>), grid, block, 0, s, src, dst,    \
+                               table, uS, W, H, plan);                                         \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_flood_tail<LB, MT, ST, 32>), grid, block, 0, s, src, dst,    \
+                               table, uS, W, H, plan);                                         \
+    } while (0)
+#define VD_TAIL(LB, MT)                                                                        \
+    do {                                                                                       \
+        if (nt) VD_TAIL_TH(LB, MT, kStoreNT); else VD_TAIL_TH(LB, MT, 0);                       \
+    } while (0)
+    if (label == kLabelId) {
+        if (metric == kEuclid) VD_TAIL(kLabelId, kEuclid); else VD_TAIL(kLabelId, kManhattan);
+    } else {
+        if (metric == kEuclid) VD_TAIL(kLabelXy, kEuclid); else VD_TAIL(kLabelXy, kManhattan);
+    }
+#undef VD_TAIL
+#undef VD_TAIL_TH
+    return hipGetLastError();
+}
 
 hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *table, int32_t S,
                         int32_t W, int32_t H, int32_t k, int32_t vn, int32_t label,

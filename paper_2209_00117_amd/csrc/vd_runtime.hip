@@ -84,10 +84,40 @@ int32_t default_variant(const vd_config &c, bool dynamic, int32_t k)
     return v;
 }
 
+// Tile height of a step kind's fused last passes before any tuning (0: not
+// fused).  Measured on MI355X at 4096^2 and 8192^2, the fused launch did
+// not beat the separate passes (it recomputes the tile halo and leaves a
+// quarter of the lanes idle in the last pass, and the separate passes are
+// already near the cost of their arithmetic), so it is left to the tuner.
+int32_t default_tail_th(const vd_config &, bool)
+{
+    return 0;
+}
+
+constexpr int32_t kTailHeights[] = {16, 24, 32};
+
 void set_default_variants(vd_sim *s)
 {
     for (Pass &p : s->jfa_passes) p.variant = default_variant(s->cfg, false, p.k);
     for (Pass &p : s->djfa_passes) p.variant = default_variant(s->cfg, true, p.k);
+    for (int dyn = 0; dyn < 2; ++dyn)
+        s->tail_th[dyn] = s->forced_fuse >= 0 ? s->forced_fuse : default_tail_th(s->cfg, dyn != 0);
+}
+
+// Number of trailing passes that can run as one fused launch: the longest
+// suffix of steps 1, 2 or 4 summing to at most kTailHalo, at most
+// kTailMaxPasses long; 0 if shorter than two.
+size_t tail_len(const std::vector<Pass> &passes)
+{
+    size_t m = 0;
+    int32_t sum = 0;
+    while (m < passes.size() && m < (size_t)vd::kTailMaxPasses) {
+        const int32_t k = passes[passes.size() - 1 - m].k;
+        if ((k != 1 && k != 2 && k != 4) || sum + k > vd::kTailHalo) break;
+        sum += k;
+        ++m;
+    }
+    return m >= 2 ? m : 0;
 }
 
 // Pass list of one step: k = first, first/2, ..., 1; the first vn of them
@@ -198,18 +228,43 @@ int harvest(vd_sim *s)
 // The passes of one step run back to back between one pair of timing
 // events (events around every launch would add their own latency to each
 // short pass).
-int run_passes(vd_sim *s, const std::vector<Pass> &passes)
+// With th (a tile height) non-zero, the step's last passes (tail_len) run
+// as one launch with the store policy of the last pass.
+int launch_passes(vd_sim *s, const std::vector<Pass> &passes, int32_t th)
 {
-    if (passes.empty()) return VD_OK;
-    size_t slot = 0;
-    int r = record(s, 0, true, &slot, (int)passes.size());
-    if (r) return r;
-    for (const Pass &p : passes) {
+    const size_t m = th ? tail_len(passes) : 0;
+    const size_t n = passes.size() - m;
+    for (size_t i = 0; i < n; ++i) {
+        const Pass &p = passes[i];
         VD_HIP(vd::launch_flood(s->map[s->cur], s->map[s->cur ^ 1], s->pos, s->cfg.num_seeds,
                                 s->cfg.width, s->cfg.height, p.k, p.vn, s->cfg.label,
                                 s->cfg.metric, p.variant, p.seg_rows, s->stream));
         s->cur ^= 1;
     }
+    if (m) {
+        int32_t ks[vd::kTailMaxPasses], vns[vd::kTailMaxPasses];
+        for (size_t i = 0; i < m; ++i) {
+            ks[i] = passes[n + i].k;
+            vns[i] = passes[n + i].vn;
+        }
+        const bool nt = passes.back().variant >= vd::kFloodVariants / 2;
+        VD_HIP(vd::launch_flood_tail(s->map[s->cur], s->map[s->cur ^ 1], s->pos,
+                                     s->cfg.num_seeds, s->cfg.width, s->cfg.height, ks, vns,
+                                     (int32_t)m, s->cfg.label, s->cfg.metric, nt, th,
+                                     s->stream));
+        s->cur ^= 1;
+    }
+    return VD_OK;
+}
+
+int run_passes(vd_sim *s, const std::vector<Pass> &passes, int32_t th)
+{
+    if (passes.empty()) return VD_OK;
+    size_t slot = 0;
+    int r = record(s, 0, true, &slot, (int)passes.size());
+    if (r) return r;
+    r = launch_passes(s, passes, th);
+    if (r) return r;
     r = record(s, 0, false, &slot);
     if (r) return r;
     if (s->timing && s->used >= 4096) {
@@ -280,7 +335,7 @@ int step_epilogue(vd_sim *s)
 int do_jfa(vd_sim *s)
 {
     int r = jfa_prologue(s);
-    if (r == VD_OK) r = run_passes(s, s->jfa_passes);
+    if (r == VD_OK) r = run_passes(s, s->jfa_passes, s->tail_th[0]);
     if (r == VD_OK) r = step_epilogue(s);
     return r;
 }
@@ -288,7 +343,7 @@ int do_jfa(vd_sim *s)
 int do_djfa(vd_sim *s)
 {
     int r = djfa_prologue(s);
-    if (r == VD_OK) r = run_passes(s, s->djfa_passes);
+    if (r == VD_OK) r = run_passes(s, s->djfa_passes, s->tail_th[1]);
     if (r == VD_OK) r = step_epilogue(s);
     return r;
 }
@@ -416,11 +471,22 @@ std::string tune_key(const std::string &arch, const vd_config &c, const Pass &p,
     return buf;
 }
 
+// Key of a step kind's tail-fusion choice (value: 0 not fused, i > 0 fused
+// with tiles of height kTailHeights[i - 1]).
+std::string fuse_key(const std::string &arch, const vd_config &c, bool dynamic)
+{
+    char buf[192];
+    snprintf(buf, sizeof buf, "%s %dx%d S%d %s %s tail %s", arch.c_str(), c.width, c.height,
+             c.num_seeds, c.label == VD_LABEL_XY16 ? "xy" : "id",
+             c.metric == VD_MANHATTAN ? "manhattan" : "euclid", dynamic ? "djfa" : "jfa");
+    return buf;
+}
+
 void apply_tuning(vd_sim *s)
 {
     const std::string arch = arch_name();
     std::lock_guard<std::mutex> lock(g_tune_mu);
-    for (int dyn = 0; dyn < 2; ++dyn)
+    for (int dyn = 0; dyn < 2; ++dyn) {
         for (Pass &p : dyn ? s->djfa_passes : s->jfa_passes) {
             auto it = g_tune.find(tune_key(arch, s->cfg, p, dyn != 0));
             if (it != g_tune.end()) {
@@ -428,6 +494,14 @@ void apply_tuning(vd_sim *s)
                 p.seg_rows = it->second.second;
             }
         }
+        if (s->forced_fuse < 0) {
+            auto it = g_tune.find(fuse_key(arch, s->cfg, dyn != 0));
+            if (it != g_tune.end()) {
+                const int32_t v = it->second.first;
+                s->tail_th[dyn] = v >= 1 && v <= 3 ? kTailHeights[v - 1] : 0;
+            }
+        }
+    }
 }
 
 }  // namespace
@@ -584,6 +658,51 @@ int vd_autotune(vd_sim *s, int32_t reps)
         }
         nt[dyn] = best[1] < best[0];
     }
+    // Tail fusion per step kind, the same way: whole replayed steps with the
+    // picks and the store policy, the last passes separate or fused with
+    // each tile height (option 0: separate, i: kTailHeights[i - 1]).
+    int32_t fz[2] = {0, 0};
+    for (int dyn = 0; dyn < 2 && r == VD_OK; ++dyn) {
+        std::vector<Pass> passes = dyn ? s->djfa_passes : s->jfa_passes;
+        if (tail_len(passes) == 0) continue;
+        for (Pass &p : passes) {
+            const Cand &c0 = picks[tune_key(arch, c, p, dyn != 0)];
+            p.variant = c0.variant + (nt[dyn] ? kBase : 0);
+            p.seg_rows = c0.seg_rows;
+        }
+        constexpr int kOpts = 1 + (int)(sizeof kTailHeights / sizeof kTailHeights[0]);
+        float best[kOpts];
+        for (float &b : best) b = 1e30f;
+        for (int trial = 0; trial < 2 * kOpts && r == VD_OK; ++trial) {
+            const int policy = trial % kOpts;
+            hip(hipMemcpyAsync(s->map[s->cur], save, npix * 4, hipMemcpyDeviceToDevice,
+                               s->stream), "restore");
+            if (save_pm)
+                hip(hipMemcpyAsync(s->pos_map, save_pm, tab_bytes, hipMemcpyDeviceToDevice,
+                                   s->stream), "restore");
+            if (r == VD_OK) {
+                int pr = dyn ? djfa_prologue(s) : jfa_prologue(s);
+                if (pr) r = pr;
+            }
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (!hip(hipEventCreate(&e0), "hipEventCreate")) break;
+            ev.push_back(e0);
+            if (!hip(hipEventCreate(&e1), "hipEventCreate")) break;
+            ev.push_back(e1);
+            hip(hipEventRecord(e0, s->stream), "hipEventRecord");
+            if (r == VD_OK) {
+                int lr = launch_passes(s, passes, policy ? kTailHeights[policy - 1] : 0);
+                if (lr) r = lr;
+            }
+            hip(hipEventRecord(e1, s->stream), "hipEventRecord");
+            float ms = 0.f;
+            if (hip(hipEventSynchronize(e1), "hipEventSynchronize") &&
+                hip(hipEventElapsedTime(&ms, e0, e1), "hipEventElapsedTime") && ms < best[policy])
+                best[policy] = ms;
+        }
+        for (int o = 1; o < kOpts; ++o)
+            if (best[o] < best[fz[dyn]]) fz[dyn] = o;
+    }
     if (r == VD_OK && !picks.empty()) {
         std::lock_guard<std::mutex> lock(g_tune_mu);
         for (size_t i = 0; i < keys.size(); ++i) {
@@ -591,6 +710,9 @@ int vd_autotune(vd_sim *s, int32_t reps)
             g_tune[keys[i]] = {pk.variant + (nt[key_dyn[i]] ? kBase : 0), pk.seg_rows};
             g_tune_us[keys[i]] = pick_us[keys[i]];
         }
+        for (int dyn = 0; dyn < 2; ++dyn)
+            if (tail_len(dyn ? s->djfa_passes : s->jfa_passes))
+                g_tune[fuse_key(arch, c, dyn != 0)] = {fz[dyn], 0};
     }
     // put the diagram back where the simulation expects it
     s->cur = cur0;
@@ -1089,6 +1211,26 @@ int vd_set_flood_variant(vd_sim *s, int variant)
     }
     for (Pass &p : s->jfa_passes) p.variant = variant;
     for (Pass &p : s->djfa_passes) p.variant = variant;
+    return VD_OK;
+}
+
+int vd_set_tail_fusion(vd_sim *s, int mode)
+{
+    if (!s) return fail(VD_EINVAL, "sim is NULL");
+    if (mode != -1 && mode != 0 && mode != 1 && mode != 16 && mode != 24 && mode != 32)
+        return fail(VD_EINVAL, "mode must be -1, 0, 1, 16, 24 or 32, got %d", mode);
+    s->forced_fuse = mode == 1 ? 16 : mode;
+    for (int dyn = 0; dyn < 2; ++dyn)
+        s->tail_th[dyn] = s->forced_fuse >= 0 ? s->forced_fuse : default_tail_th(s->cfg, dyn != 0);
+    if (mode < 0) apply_tuning(s);
+    return VD_OK;
+}
+
+int vd_get_tail_fusion(const vd_sim *s, int32_t *jfa, int32_t *djfa)
+{
+    if (!s) return fail(VD_EINVAL, "sim is NULL");
+    if (jfa) *jfa = s->tail_th[0] ? (int32_t)tail_len(s->jfa_passes) : 0;
+    if (djfa) *djfa = s->tail_th[1] ? (int32_t)tail_len(s->djfa_passes) : 0;
     return VD_OK;
 }
 

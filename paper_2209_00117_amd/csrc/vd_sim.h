@@ -57,6 +57,10 @@ struct vd_sim {
     int64_t fallbacks = 0;       // dJFA steps replaced by a JFA step (unrefilled pixels)
     bool measured = false;       // d_max of each dJFA step from disp[0]
     int32_t forced_variant = -1; // vd_set_flood_variant's choice, -1: defaults and tuning
+    int32_t tail_th[2] = {0, 0}; // JFA, dJFA: last passes in one launch with tiles of this
+                                 // height (16, 24, 32), 0: not fused
+    int32_t forced_fuse = -1;    // vd_set_tail_fusion's tile height (0: off), -1: defaults
+                                 // and tuning
     int32_t k1 = 0, delta1 = 0;
     uint64_t move_seed = 0;
     std::vector<vd::Pass> jfa_passes, djfa_passes;

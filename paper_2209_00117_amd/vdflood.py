@@ -68,6 +68,8 @@ SIGNATURES = {
     "vd_move_seeds": (ctypes.c_int, [_P]),
     "vd_set_seeds": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
     "vd_remove_seeds": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
+    "vd_set_tail_fusion": (ctypes.c_int, [_P, ctypes.c_int]),
+    "vd_get_tail_fusion": (ctypes.c_int, [_P, _P, _P]),
     "vd_insert_seeds": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
     "vd_get_seed_set": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P, _P]),
     "vd_jfa_step": (ctypes.c_int, [_P]),
@@ -226,6 +228,20 @@ def seed_set(h):
     _check(lib().vd_get_seed_set(h, m.ctypes.data_as(_P), m.size, ctypes.byref(n),
                                  ctypes.byref(fb)))
     return m.astype(bool), int(n.value), int(fb.value)
+
+
+def set_tail_fusion(h, mode: int):
+    """16, 24 or 32: fuse each step's last passes into one launch with tiles
+    of that many rows (1: 16), 0: do not, -1: the default or the autotuner's
+    choice."""
+    _check(lib().vd_set_tail_fusion(h, int(mode)))
+
+
+def get_tail_fusion(h):
+    """(passes fused in a JFA step, in a dJFA step)."""
+    j, d = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().vd_get_tail_fusion(h, ctypes.byref(j), ctypes.byref(d)))
+    return int(j.value), int(d.value)
 
 
 def jfa_step(h):

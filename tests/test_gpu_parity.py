@@ -41,11 +41,16 @@ def _seed_pixels_ok(m, xy, label_mode):
 
 
 def run_twin(V, W, H, xy, steps, lo, hi, sim_seed=1, label=0, metric=0, vn=2, extra=0,
-             dmax=0, tag="", variant=None):
+             dmax=0, tag="", variant=None, fuse=None):
     """Runs a JFA and a dJFA simulation side by side on the GPU and in the
-    oracle; asserts equal positions and maps at every step."""
+    oracle; asserts equal positions and maps at every step.  `variant` runs
+    every pass on one kernel variant; the step's last passes are then fused
+    only if `fuse` is 1 (otherwise `fuse` sets tail fusion, None: default)."""
+    if variant is not None and fuse is None:
+        fuse = 0
     print(f"[parity] {tag} W={W} H={H} S={len(xy)} steps={steps} disp=[{lo},{hi}] "
-          f"label={label} metric={metric} vn={vn} extra={extra} variant={variant}", flush=True)
+          f"label={label} metric={metric} vn={vn} extra={extra} variant={variant} fuse={fuse}",
+          flush=True)
     kw = dict(disp_lo=lo, disp_hi=hi, label=label, metric=metric, vn_passes=vn,
               extra_passes=extra, dmax_override=dmax, sim_seed=sim_seed)
     gj = V.Sim(W, H, xy, **kw)
@@ -53,6 +58,9 @@ def run_twin(V, W, H, xy, steps, lo, hi, sim_seed=1, label=0, metric=0, vn=2, ex
     if variant is not None:
         V.set_flood_variant(gj.handle, variant)
         V.set_flood_variant(gd.handle, variant)
+    if fuse is not None:
+        V.set_tail_fusion(gj.handle, fuse)
+        V.set_tail_fusion(gd.handle, fuse)
     okw = dict(label_mode=label, metric=metric, vn_passes=vn, extra_passes=extra,
                dmax=dmax if dmax > 0 else None)
     oj = O.Sim(W, H, xy, sim_seed, lo, hi, **okw)
@@ -154,6 +162,43 @@ def test_flood_variants(V, variant, W, H, S):
                  tag="variant")
 
 
+# Tail fusion (the last passes of a step in one LDS-tiled launch): tiles of
+# 48 x 32 outputs with up to 8 pixels of halo, so the shapes span one tile,
+# ragged last tiles, grids smaller than the halo, and fused runs whose
+# passes use the Von Neumann neighbourhood (dJFA with delta_1 <= 4).
+@pytest.mark.parametrize("W,H,S,steps,lo,hi", [
+    (1, 1, 1, 2, -1, 1),
+    (2, 1, 2, 2, -1, 1),
+    (3, 5, 4, 2, -1, 1),
+    (7, 40, 9, 3, -1, 1),
+    (48, 32, 30, 3, -1, 1),
+    (49, 33, 60, 3, -2, 2),
+    (100, 90, 40, 3, -2, 2),
+    (64, 64, 1024, 3, -1, 1),         # delta_1 = 4: the fused passes 4, 2 are Von Neumann
+    (333, 77, 1000, 3, -1, 1),
+    (1000, 1000, 50, 2, -2, 2),
+    (64, 64, 4096, 2, -1, 1),
+    (257, 129, 300, 5, -1, 3),
+])
+@pytest.mark.parametrize("label", [0, 1])
+def test_tail_fusion(V, W, H, S, steps, lo, hi, label):
+    xy = inputs.place_seeds(W, H, S, W * 3 + H)
+    run_twin(V, W, H, xy, steps, lo, hi, sim_seed=W + 5 * H, label=label, fuse=1, tag="tail")
+
+
+@pytest.mark.parametrize("metric,vn,extra", [
+    (1, 2, 0), (0, 0, 0), (0, 1, 1), (0, 2, 2), (1, 1, 2), (0, 5, 0), (1, 5, 1),
+])
+def test_tail_fusion_options(V, metric, vn, extra):
+    """Manhattan, every Von Neumann count, JFA+1 / +2 (four fused passes:
+    4, 2, 1, 1 or 2, 1, 2, 1), with the non-temporal store form too."""
+    for S, variant in ((900, None), (5000, 10)):
+        xy = inputs.place_seeds(700, 450, S, 3)
+        for label in (0, 1):
+            run_twin(V, 700, 450, xy, 3, -2, 2, sim_seed=5, label=label, metric=metric, vn=vn,
+                     extra=extra, tag="tail-options", variant=variant, fuse=1)
+
+
 def test_dmax_override(V):
     xy = inputs.place_seeds(512, 512, 4000, 9)
     run_twin(V, 512, 512, xy, 3, -1, 1, dmax=40, tag="dmax")
@@ -205,6 +250,7 @@ def test_autotune_keeps_results(V, label):
     assert all(us > 0 for us in V.get_tuning_us(a.handle))
     c = V.Sim(W, H, xy, **kw)                               # adopts the process-wide table
     assert V.get_tuning(c.handle) == tuned
+    assert V.get_tail_fusion(c.handle) == V.get_tail_fusion(a.handle)
     c.move_seeds()
     c.djfa_step()
     for mode in (1, 1, 0, 1):
