@@ -435,6 +435,45 @@ def bench_churn(torch, V, args, W, H, xy, kw, stream, djfa_ms):
     return out
 
 
+def bench_tail_sweep(torch, V, args):
+    """Tail fusion across map sizes: square maps of 256^2 .. 4096^2 with one
+    seed per 256 pixels (moves in [-2, 2]), ID and XY labels, the last passes
+    of each step separate (0) or fused with 16- or 24-row tiles; ms per JFA
+    step and per dJFA step (move included), 40 steps each after 5 warm-up
+    steps, default kernel variants."""
+    from paper_2209_00117_amd import inputs
+    stream = torch.cuda.current_stream()
+    rows = []
+    for side in (256, 512, 1024, 1536, 2048, 3072, 4096):
+        S = max(16, side * side // 256)
+        xy = inputs.place_seeds(side, side, S, 3)
+        for label in (V.LABEL_ID32, V.LABEL_XY16):
+            row = {"side": side, "seeds": S, "label": "id" if label == V.LABEL_ID32 else "xy"}
+            for mode in (0, 16, 24):
+                sj, sd = (V.Sim(side, side, xy, stream=stream, disp_lo=-2, disp_hi=2, label=label)
+                          for _ in range(2))
+                for sim in (sj, sd):
+                    V.set_tail_fusion(sim.handle, mode)
+                for _ in range(5):
+                    sj.move_seeds(), sd.move_seeds(), sj.jfa_step(), sd.djfa_step()
+                ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+                torch.cuda.synchronize()
+                ev[0].record(stream)
+                for _ in range(40):
+                    sj.jfa_step()
+                ev[1].record(stream)
+                for _ in range(40):
+                    sd.move_seeds(), sd.djfa_step()
+                ev[2].record(stream)
+                torch.cuda.synchronize()
+                row[f"jfa_ms_{mode}"] = round(ev[0].elapsed_time(ev[1]) / 40, 4)
+                row[f"djfa_ms_{mode}"] = round(ev[1].elapsed_time(ev[2]) / 40, 4)
+                sj.close(), sd.close()
+            print(json.dumps(row), file=sys.stderr, flush=True)
+            rows.append(row)
+    print(json.dumps({"tail_sweep": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -463,6 +502,9 @@ def main():
                     help="run each step's last passes (k = 4, 2, 1) as one LDS-tiled launch "
                          "(16, 24, 32: the tile height; on: 16); auto = the default or the "
                          "autotuner's choice")
+    ap.add_argument("--tail-sweep", action="store_true",
+                    help="time steps with the last passes separate and fused (16- and 24-row "
+                         "tiles) on square maps of 256^2 .. 4096^2, ID and XY labels")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (run every pass with the default kernel variant)")
     ap.add_argument("--calibrate", action="store_true",
@@ -483,6 +525,9 @@ def main():
         calibrate(torch)
         return
     V.lib()
+    if args.tail_sweep:
+        bench_tail_sweep(torch, V, args)
+        return
     if args.workload == "batched":
         bench_batched(torch, inputs, V, args)
         return

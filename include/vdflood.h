@@ -252,8 +252,10 @@ int vd_set_flood_variant(vd_sim *sim, int variant);
  * summing to at most 8, at most four passes, e.g. k = 4, 2, 1) run as one
  * launch that keeps tiles of the map in LDS between them; the map is the
  * same either way.  mode 16, 24 or 32: on, with tiles of 48 x mode
- * outputs; 1: on with 16-row tiles; 0: off; -1: the default (off) or the
- * choice vd_autotune made for the step kind.  VD_EINVAL for another mode. */
+ * outputs; 1: on with 16-row tiles; 0: off; -1: the default (on for maps
+ * of up to 2048^2 pixels with ID labels and 1536^2 with XY labels, 16-row
+ * tiles up to 2^19 pixels, else 24) or the choice vd_autotune made for the
+ * step kind.  VD_EINVAL for another mode. */
 int vd_set_tail_fusion(vd_sim *sim, int mode);
 
 /* Passes each step kind currently runs fused (0: none). */

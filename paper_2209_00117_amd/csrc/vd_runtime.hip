@@ -85,13 +85,19 @@ int32_t default_variant(const vd_config &c, bool dynamic, int32_t k)
 }
 
 // Tile height of a step kind's fused last passes before any tuning (0: not
-// fused).  Measured on MI355X at 4096^2 and 8192^2, the fused launch did
-// not beat the separate passes (it recomputes the tile halo and leaves a
-// quarter of the lanes idle in the last pass, and the separate passes are
-// already near the cost of their arithmetic), so it is left to the tuner.
-int32_t default_tail_th(const vd_config &, bool)
+// fused).  Measured on MI355X (square maps, one seed per 256 pixels, both
+// step kinds): the fused launch saves two launches and two map round trips
+// but recomputes the tile halo and leaves up to a quarter of its lanes
+// idle, about 1.6x the arithmetic of the separate passes.  It wins while
+// the passes are short (up to 2048^2 with ID labels, 1536^2 with XY labels:
+// 10-20% per step) and loses on larger maps, whose separate passes are
+// bound by arithmetic and table lookups rather than by launches or bytes.
+int32_t default_tail_th(const vd_config &c, bool)
 {
-    return 0;
+    const int64_t px = (int64_t)c.width * c.height;
+    const int64_t limit = c.label == VD_LABEL_ID32 ? 2048 * 2048 : 1536 * 1536;
+    if (px > limit) return 0;
+    return px <= ((int64_t)1 << 19) ? 16 : 24;
 }
 
 constexpr int32_t kTailHeights[] = {16, 24, 32};
