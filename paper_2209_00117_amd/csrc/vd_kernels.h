@@ -126,8 +126,11 @@ struct ItemGrid {
 };
 ItemGrid item_grid(int32_t W, int32_t H, int32_t k);
 
-// Largest step the shared-row (LDS) kernel handles.
+// Largest step the shared-row (LDS) kernels handle: one column per lane,
+// and four columns per lane (ID labels; two row sizes, the wider one for
+// steps above kMaxLdsStep).
 constexpr int kMaxLdsStep = 128;
+constexpr int kMaxQuadLdsStep = 512;
 
 // Grid of the four-columns-per-lane kernels (1024 columns per workgroup),
 // and whether they handle a pass: width a multiple of 4 and k = 1, 2 or a
@@ -141,7 +144,7 @@ bool quad_ok(int32_t W, int32_t k);
 // gives the same map.  0, 1, 2: the chain walk requesting loads 1, 2 or 3
 // rows ahead; 3: rows shared through LDS for k <= 128 (2 rows ahead),
 // otherwise variant 1; 4, 5: four columns per lane where quad_ok holds (ID
-// labels: rows shared through LDS for k <= 128, direct loads above),
+// labels: rows shared through LDS for k <= 512, direct loads above),
 // requesting rows 2 (4) or 3 (5) rows ahead, otherwise variant 3 (ID) or 1
 // (XY).  Variants 6-11 are 0-5 with non-temporal stores of the output map.
 constexpr int kFloodVariants = 12;

@@ -1,6 +1,8 @@
 // vdflood single-simulation kernels for gfx950 (CDNA4, wave64) and their
 // launchers.  The flood-pass device code (and the reasoning behind it) is in
 // vd_device.h.
+#include <type_traits>
+
 #include "vd_device.h"
 #include "vd_quad.h"
 #include "vd_tail.h"
@@ -414,16 +416,18 @@ __global__ void __launch_bounds__(kBlock) k_flood_quad_xy(const uint32_t *__rest
                                            xcd_logical(blockIdx.x, g.nblocks));
 }
 
-template <int METRIC, int VN, int KC, int NS, int ST>
+// WIDE: shared rows sized for steps up to kMaxQuadLdsStep.
+template <int METRIC, int VN, int KC, int NS, int ST, bool WIDE>
 __global__ void __launch_bounds__(kBlock) k_flood_quad_id(const uint32_t *__restrict__ src,
                                                           uint32_t *__restrict__ dst,
                                                           const uint32_t *__restrict__ table,
                                                           uint32_t S, int32_t W, int32_t H,
                                                           int32_t k, FloodGrid g)
 {
-    __shared__ QuadRow lds[2];
+    using Q = typename std::conditional<WIDE, QuadRowWide, QuadRow>::type;
+    __shared__ Q lds[2];
     flood_quad_id_tile<METRIC, VN, KC, NS, ST>(src, dst, table_rsrc(table, S), W, H, k, g,
-                                           xcd_logical(blockIdx.x, g.nblocks), lds);
+                                               xcd_logical(blockIdx.x, g.nblocks), lds);
 }
 
 template <int METRIC, int VN, int NS, int ST>
@@ -674,12 +678,15 @@ hipError_t launch_flood_st(const uint32_t *src, uint32_t *dst, const uint32_t *t
             dim3 grid(g.nblocks), block(kBlock);
 #define VD_QUAD(MT, V, KC, NS)                                                                 \
     do {                                                                                       \
-        if (label == kLabelId && k > kMaxLdsStep)                                              \
+        if (label == kLabelId && k > kMaxQuadLdsStep)                                          \
             hipLaunchKernelGGL((k_flood_quad_idd<MT, V, NS, ST>), grid, block, 0, s, src, dst,       \
                                table, uS, W, H, k, g);                                         \
+        else if (label == kLabelId && k > kMaxLdsStep)                                         \
+            hipLaunchKernelGGL((k_flood_quad_id<MT, V, 0, NS, ST, true>), grid, block, 0, s, src,    \
+                               dst, table, uS, W, H, k, g);                                    \
         else if (label == kLabelId)                                                            \
-            hipLaunchKernelGGL((k_flood_quad_id<MT, V, KC, NS, ST>), grid, block, 0, s, src, dst,    \
-                               table, uS, W, H, k, g);                                         \
+            hipLaunchKernelGGL((k_flood_quad_id<MT, V, KC, NS, ST, false>), grid, block, 0, s, src,  \
+                               dst, table, uS, W, H, k, g);                                    \
         else                                                                                   \
             hipLaunchKernelGGL((k_flood_quad_xy<MT, V, KC, NS, ST>), grid, block, 0, s, src, dst, W, \
                                H, k, g);                                                       \

@@ -31,6 +31,7 @@ namespace {
 constexpr int kQuad = 4;                             // columns per lane
 constexpr int kTWQ = kBlock * kQuad;                 // columns per workgroup
 constexpr int kQuadLdsRow = kTWQ + 2 * kMaxLdsStep;  // entries of one shared row
+constexpr int kQuadLdsRowWide = kTWQ + 2 * kMaxQuadLdsStep;   // the same for k <= 512
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
@@ -289,10 +290,13 @@ __device__ __forceinline__ void flood_quad_id_direct_tile(const uint32_t *src, u
 // Shared rows of the ID tile, in groups of four entries: entry e is column
 // x0 - h + e.  Labels and positions are kept apart so that a lane moves 16
 // contiguous bytes of each array per group.
-struct QuadRow {
-    u32x4 l[kQuadLdsRow / kQuad];
-    u32x4 s[kQuadLdsRow / kQuad];
+template <int ROW>
+struct QuadRowT {
+    u32x4 l[ROW / kQuad];
+    u32x4 s[ROW / kQuad];
 };
+using QuadRow = QuadRowT<kQuadLdsRow>;           // steps up to kMaxLdsStep: 20 KiB for two
+using QuadRowWide = QuadRowT<kQuadLdsRowWide>;   // steps up to kMaxQuadLdsStep: 32 KiB
 
 // ID labels (steps k <= kMaxLdsStep): the 1024 + 2h columns a workgroup
 // needs are fetched once -- group t by lane t, the 2h / 4 groups past the
@@ -302,11 +306,11 @@ struct QuadRow {
 // alternate, and the barrier of each exchange also orders the reuse of the
 // row written two exchanges earlier.  Callers must not let a previous use
 // of `lds` overlap the first exchange (a barrier between tiles suffices).
-template <int METRIC, int VN, int KC, int NS, int ST>
+template <int METRIC, int VN, int KC, int NS, int ST, class Q>
 __device__ __forceinline__ void flood_quad_id_tile(const uint32_t *src, uint32_t *dst, i32x4 tab,
                                                    int32_t W, int32_t H, int32_t k,
                                                    const FloodGrid &g, uint32_t logical,
-                                                   QuadRow *lds)
+                                                   Q *lds)
 {
     const TileQ tl = decode_tile_q(logical, g, k, H);
     if (tl.j0 >= tl.jend) return;
@@ -355,8 +359,8 @@ __device__ __forceinline__ void flood_quad_id_tile(const uint32_t *src, uint32_t
     };
     auto fetch = [&](auto Slot) -> Three {
         const Slot_ &q = ring[decltype(Slot)::value];
-        QuadRow *row = (QuadRow *)((char *)lds + lds_sel);
-        lds_sel ^= (uint32_t)sizeof(QuadRow);
+        Q *row = (Q *)((char *)lds + lds_sel);
+        lds_sel ^= (uint32_t)sizeof(Q);
         row->l[t] = q.g1.l;
         row->s[t] = q.g1.s;
         if (wave2) {
