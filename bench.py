@@ -206,9 +206,11 @@ def bench_serving(torch, inputs, V, args):
     """256 resident simulations of mixed sizes; Poisson arrivals of time-step
     requests (move + dJFA) at args.rate per second, uniformly over the
     simulations, for 1 s of warm-up and args.seconds measured.  Latency runs
-    from submission to the request's completion on the GPU.  The same
-    arrival stream is then served one request at a time with plain JFA
-    (move + JFA per request, each waited for before the next starts)."""
+    from submission to the request's completion on the GPU.  Served twice:
+    whole steps (the server's default policy) and continuous batching by
+    passes.  The same arrival stream is then served one request at a time
+    with plain JFA (move + JFA per request, each waited for before the next
+    starts)."""
     wl = inputs.serving()
     specs = wl.sims
     stream = torch.cuda.current_stream()
@@ -216,10 +218,6 @@ def bench_serving(torch, inputs, V, args):
     fp = sum((V.footprint_bytes(V.config(s.width, s.height, s.num_seeds)) + 255) // 256 * 256
              for s in specs)
     pool = V.Server.footprint_bytes(len(specs)) + fp + (1 << 20)
-    sv = V.Server(len(specs), pool, stream=stream)
-    ids = [sv.add_sim(s.width, s.height, xy, disp_lo=s.disp_lo, disp_hi=s.disp_hi,
-                      sim_seed=s.sim_seed) for s, xy in made]
-    sv.drain()
     warm = 1.0
     times, targets = inputs.poisson_arrivals(args.rate, warm + args.seconds, len(specs))
 
@@ -229,25 +227,35 @@ def bench_serving(torch, inputs, V, args):
                 pass
             submit(int(tgt), at)
 
-    t_start = time.perf_counter()
-    reset_done = [False]
+    def run_server(policy):
+        sv = V.Server(len(specs), pool, stream=stream)
+        sv.set_policy(policy)
+        ids = [sv.add_sim(s.width, s.height, xy, disp_lo=s.disp_lo, disp_hi=s.disp_hi,
+                          sim_seed=s.sim_seed) for s, xy in made]
+        sv.drain()
+        t_start = time.perf_counter()
+        reset_done = [False]
 
-    def submit_server(tgt, at):
-        if not reset_done[0] and at >= warm:
-            sv.stats(reset=True)
-            reset_done[0] = True
-        sv.submit(ids[tgt], V.STEP_DJFA)
+        def submit_server(tgt, at):
+            if not reset_done[0] and at >= warm:
+                sv.stats(reset=True)
+                reset_done[0] = True
+            sv.submit(ids[tgt], V.STEP_DJFA)
 
-    serve(submit_server, t_start)
-    sv.drain()
-    st = sv.stats()
+        serve(submit_server, t_start)
+        sv.drain()
+        st = sv.stats()
+        sv.close()
+        return {"requests": st["completed"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
+                "mean_ms": st["mean_ms"], "max_ms": st["max_ms"],
+                "pixel_updates_per_s": st["pixel_updates"] / st["elapsed_s"],
+                "requests_per_s": st["completed"] / st["elapsed_s"], "ticks": st["ticks"],
+                "elapsed_s": st["elapsed_s"]}
+
+    # whole steps (the default policy), then continuous batching by passes
+    served = run_server(V.SERVE_STEPS)
+    served_passes = run_server(V.SERVE_PASSES)
     px = sum(s.width * s.height for s in specs)
-    served = {"requests": st["completed"], "p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"],
-              "mean_ms": st["mean_ms"], "max_ms": st["max_ms"],
-              "pixel_updates_per_s": st["pixel_updates"] / st["elapsed_s"],
-              "requests_per_s": st["completed"] / st["elapsed_s"], "ticks": st["ticks"],
-              "elapsed_s": st["elapsed_s"]}
-    sv.close()
 
     # one request at a time, plain JFA, same arrivals
     sims = [V.Sim(s.width, s.height, xy, stream=stream, disp_lo=s.disp_lo, disp_hi=s.disp_hi,
@@ -278,7 +286,8 @@ def bench_serving(torch, inputs, V, args):
             "data": "synthetic (uniform random seeds and moves, Poisson arrivals, splitmix64)",
             "config": {"workload": wl.name, "sims": len(specs), "pixels": px,
                        "rate_per_s": args.rate, "seconds": args.seconds, "pool_bytes": pool},
-            "served_djfa": served, "one_at_a_time_jfa": plain}
+            "served_djfa": served, "served_djfa_by_passes": served_passes,
+            "one_at_a_time_jfa": plain}
     print(json.dumps(line), flush=True)
 
 

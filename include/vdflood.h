@@ -377,8 +377,8 @@ void vd_batch_destroy(vd_batch *b);
 const char *vd_last_error(void);
 
 /* ---------------------------------------------------------------------- */
-/* Serving: time-step requests of many resident simulations, continuously  */
-/* batched at flood-pass granularity by a scheduler thread.                */
+/* Serving: time-step requests of many resident simulations, run by a      */
+/* scheduler thread either as whole steps or batched at pass granularity.  */
 /* ---------------------------------------------------------------------- */
 
 typedef struct vd_server vd_server;   /* opaque; owned by the library */
@@ -387,7 +387,7 @@ typedef struct vd_server_stats {
     int64_t submitted;        /* requests submitted since the last reset */
     int64_t completed;        /* requests finished since the last reset */
     int64_t pixel_updates;    /* flood pixel-updates of finished ticks */
-    int64_t ticks;            /* fused launches issued */
+    int64_t ticks;            /* ticks issued (whole-step groups or batched pass launches) */
     double elapsed_s;         /* wall time since the last reset */
     double mean_ms, p50_ms, p99_ms, max_ms;   /* request latency: submit -> done */
     int32_t resident;         /* simulations with device state */
@@ -412,6 +412,16 @@ int vd_server_create(int32_t max_sims, int32_t metric, void *dev_pool, size_t po
  * simulations wait for memory in registration order.  host_xy is copied. */
 int vd_server_add_sim(vd_server *sv, const vd_config *cfg, const int32_t *host_xy,
                       int32_t *sim_id);
+
+/* How requests started from now on run.  VD_SERVE_STEPS (the default): each
+ * as its simulation's move and step with that simulation's own launches
+ * (tuned kernel variants, fused tail), one simulation after another.
+ * VD_SERVE_PASSES: continuous batching at pass granularity -- every started
+ * request joins the next tick, and one persistent launch per tick runs the
+ * next pass of every running request.  Results are identical either way.
+ * VD_EINVAL for another value. */
+enum { VD_SERVE_STEPS = 0, VD_SERVE_PASSES = 1 };
+int vd_server_set_policy(vd_server *sv, int32_t policy);
 
 /* Queues one time step of a simulation: a move, then a JFA (VD_STEP_JFA) or
  * dJFA (VD_STEP_DJFA) step.  Requests of one simulation run in submission

@@ -69,6 +69,7 @@ SIGNATURES = {
     "vd_set_seeds": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
     "vd_remove_seeds": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
     "vd_set_tail_fusion": (ctypes.c_int, [_P, ctypes.c_int]),
+    "vd_server_set_policy": (ctypes.c_int, [_P, ctypes.c_int32]),
     "vd_get_tail_fusion": (ctypes.c_int, [_P, _P, _P]),
     "vd_insert_seeds": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
     "vd_get_seed_set": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P, _P]),
@@ -105,6 +106,7 @@ SIGNATURES = {
 }
 
 STEP_JFA, STEP_DJFA = 0, 1
+SERVE_STEPS, SERVE_PASSES = 0, 1
 
 
 class ServerStats(ctypes.Structure):
@@ -508,8 +510,9 @@ class Batch:
 # --- serving ----------------------------------------------------------------
 class Server:
     """A serving loop over resident simulations (vd_server_*): time-step
-    requests are queued per simulation and continuously batched on the GPU
-    by the library's scheduler thread."""
+    requests are queued per simulation and run on the GPU by the library's
+    scheduler thread, as whole steps (SERVE_STEPS, the default) or batched
+    at pass granularity (SERVE_PASSES)."""
 
     def __init__(self, max_sims: int, pool_bytes: int, metric=EUCLID, device="cuda",
                  stream=None):
@@ -533,6 +536,9 @@ class Server:
                                        ctypes.byref(sid)))
         self.shapes[sid.value] = (height, width)
         return sid.value
+
+    def set_policy(self, policy: int):
+        _check(lib().vd_server_set_policy(self.handle, int(policy)))
 
     def submit(self, sim_id: int, mode: int) -> int:
         t = ctypes.c_int64()

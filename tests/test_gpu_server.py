@@ -1,7 +1,8 @@
-"""Serving (vd_server_*): requests of many simulations are batched on the
-GPU while others run; each simulation's result equals a lone simulation
-given the same request sequence, bit for bit, and admission by memory
-footprint holds simulations back until memory frees."""
+"""Serving (vd_server_*): requests of many simulations run on the GPU while
+others are queued, as whole steps or batched by passes (and with the policy
+switched while requests run); each simulation's result equals a lone
+simulation given the same request sequence, bit for bit, and admission by
+memory footprint holds simulations back until memory frees."""
 import random
 
 import numpy as np
@@ -44,24 +45,29 @@ def _alone(V, W, H, xy, kw, modes):
     return a.read_map()
 
 
-def test_server_mix_equals_alone(V):
+@pytest.mark.parametrize("policy", ["steps", "passes", "switch"])
+def test_server_mix_equals_alone(V, policy):
     made = _sims(SHAPES)
     sv = V.Server(len(made), 1 << 30)
+    sv.set_policy(V.SERVE_PASSES if policy == "passes" else V.SERVE_STEPS)
     ids = [sv.add_sim(W, H, xy, **kw) for W, H, xy, kw in made]
     rng = random.Random(5)
     plan = {i: [] for i in ids}
     tickets = []
-    for _ in range(60):                      # interleaved bursts: work overlaps on the GPU
+    for r in range(60):                      # interleaved bursts: work overlaps on the GPU
+        if policy == "switch" and r % 15 == 0:
+            sv.set_policy(V.SERVE_PASSES if (r // 15) % 2 == 0 else V.SERVE_STEPS)
         i = rng.choice(ids)
         m = V.STEP_DJFA if rng.random() < 0.75 else V.STEP_JFA
         plan[i].append(m)
         tickets.append(sv.submit(i, m))
-    print(f"[server] {len(tickets)} requests over {len(ids)} sims", flush=True)
+    print(f"[server] {policy}: {len(tickets)} requests over {len(ids)} sims", flush=True)
     lat = [sv.wait(t, 60000) for t in tickets]
     assert all(x > 0 for x in lat)
     st = sv.stats()
     assert st["completed"] == st["submitted"] == 60 and st["resident"] == len(ids)
-    assert st["ticks"] < 60 * 13             # requests shared launches
+    if policy == "passes":
+        assert st["ticks"] < 60 * 13         # requests shared launches
     for (W, H, xy, kw), i in zip(made, ids):
         got = sv.read_map(i)
         assert sv.sim_state(i)["t"] == len(plan[i])
@@ -110,6 +116,8 @@ def test_server_rejects_misuse(V):
         sv.submit(i, 7)
     with pytest.raises(V.VdError):
         sv.submit(99, V.STEP_DJFA)
+    with pytest.raises(V.VdError):
+        sv.set_policy(2)
     t = sv.submit(i, V.STEP_DJFA)
     sv.wait(t, 60000)
     with pytest.raises(V.VdError):
