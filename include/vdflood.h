@@ -255,7 +255,9 @@ int vd_set_flood_variant(vd_sim *sim, int variant);
  * outputs; 1: on with 16-row tiles; 0: off; -1: the default (on for maps
  * of up to 2048^2 pixels with ID labels and 1536^2 with XY labels, 16-row
  * tiles up to 2^19 pixels, else 24) or the choice vd_autotune made for the
- * step kind.  VD_EINVAL for another mode. */
+ * step kind.  VD_EINVAL for another mode; VD_ESTATE for a batch member (a
+ * batch runs its solo members' steps with the fusion they had when it was
+ * built). */
 int vd_set_tail_fusion(vd_sim *sim, int mode);
 
 /* Passes each step kind currently runs fused (0: none). */

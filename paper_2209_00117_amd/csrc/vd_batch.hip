@@ -373,17 +373,46 @@ hipError_t launch_level(vd_batch *b, int mode, int32_t lvl, int32_t parity_level
 // the host mirror names current (the batch keeps the mirror in step with
 // the device state).  `tuning`: every pass reads the current map and writes
 // the idle one, so nothing changes.
+// A solo member's passes, as its own step would run them: its kernel
+// variants, and its last passes fused where the member fuses them (each
+// launch flips its current map; step_launches counts them).
+// Map flips of member i in a step of kind `mode`: one per pass level when
+// it runs fused with the others, one per launch of its own when solo.
+int32_t flips(const vd_batch *b, int mode, int32_t i)
+{
+    const vd_sim *s = b->sims[(size_t)i];
+    const bool dyn = mode == VD_STEP_DJFA;
+    if (b->solo[mode][(size_t)i]) return vd::step_launches(s, dyn);
+    return (int32_t)(dyn ? s->djfa_passes : s->jfa_passes).size();
+}
+
 int enqueue_solo(vd_batch *b, int mode, bool tuning, hipStream_t stream)
 {
     for (size_t i = 0; i < b->sims.size(); ++i) {
         if (!b->solo[mode][i]) continue;
         const vd_sim *s = b->sims[i];
         const vd_config &c = s->cfg;
+        const std::vector<vd::Pass> &ps = mode == VD_STEP_DJFA ? s->djfa_passes : s->jfa_passes;
+        const int32_t th = s->tail_th[mode == VD_STEP_DJFA ? 1 : 0];
+        const size_t m = th ? vd::tail_len(ps) : 0;
         int cur = s->cur;
-        for (const vd::Pass &p : mode == VD_STEP_DJFA ? s->djfa_passes : s->jfa_passes) {
+        for (size_t j = 0; j + m < ps.size(); ++j) {
+            const vd::Pass &p = ps[j];
             VD_HIP(vd::launch_flood(s->map[cur], s->map[cur ^ 1], s->pos, c.num_seeds, c.width,
                                     c.height, p.k, p.vn, c.label, c.metric, p.variant,
                                     p.seg_rows, stream));
+            if (!tuning) cur ^= 1;
+        }
+        if (m) {
+            int32_t ks[vd::kTailMaxPasses], vns[vd::kTailMaxPasses];
+            for (size_t j = 0; j < m; ++j) {
+                ks[j] = ps[ps.size() - m + j].k;
+                vns[j] = ps[ps.size() - m + j].vn;
+            }
+            const bool nt = ps.back().variant >= vd::kFloodVariants / 2;
+            VD_HIP(vd::launch_flood_tail(s->map[cur], s->map[cur ^ 1], s->pos, c.num_seeds,
+                                         c.width, c.height, ks, vns, (int32_t)m, c.label,
+                                         c.metric, nt, th, stream));
             if (!tuning) cur ^= 1;
         }
     }
@@ -556,10 +585,9 @@ int build_tables(vd_batch *b)
             li.total = first;
             for (int c = 0; c <= 8; ++c) li.chunk[c] = (uint32_t)((uint64_t)first * c / 8);
         }
+        // map flips per step: one per level, or per launch of a solo member
         for (int32_t i = 0; i < n; ++i)
-            hnp[m][(size_t)i] =
-                (int32_t)(m ? b->sims[(size_t)i]->djfa_passes : b->sims[(size_t)i]->jfa_passes)
-                    .size();
+            hnp[m][(size_t)i] = flips(b, m, i);
     }
     const vd::Layout &lay = b->lay;
     hipStream_t stream = b->stream;
@@ -704,9 +732,9 @@ int vd_batch_step(vd_batch *b, int32_t mode, int32_t move)
     }
     r = batch_record(b, 1, false, &slot);
     if (r) return r;
-    for (vd_sim *s : b->sims) {   // host mirror of the device-side state
-        const size_t np = (mode == VD_STEP_DJFA ? s->djfa_passes : s->jfa_passes).size();
-        s->cur ^= (int)(np & 1);
+    for (size_t i = 0; i < b->sims.size(); ++i) {   // host mirror of the device-side state
+        vd_sim *s = b->sims[i];
+        s->cur ^= (int)(flips(b, mode, (int32_t)i) & 1);
         s->t += moved;
     }
     if (b->timing && b->used >= 4096) return batch_harvest(b);

@@ -110,21 +110,6 @@ void set_default_variants(vd_sim *s)
         s->tail_th[dyn] = s->forced_fuse >= 0 ? s->forced_fuse : default_tail_th(s->cfg, dyn != 0);
 }
 
-// Number of trailing passes that can run as one fused launch: the longest
-// suffix of steps 1, 2 or 4 summing to at most kTailHalo, at most
-// kTailMaxPasses long; 0 if shorter than two.
-size_t tail_len(const std::vector<Pass> &passes)
-{
-    size_t m = 0;
-    int32_t sum = 0;
-    while (m < passes.size() && m < (size_t)vd::kTailMaxPasses) {
-        const int32_t k = passes[passes.size() - 1 - m].k;
-        if ((k != 1 && k != 2 && k != 4) || sum + k > vd::kTailHalo) break;
-        sum += k;
-        ++m;
-    }
-    return m >= 2 ? m : 0;
-}
 
 // Pass list of one step: k = first, first/2, ..., 1; the first vn of them
 // Von Neumann (clamped so the last main pass is Moore); extra passes k = 1
@@ -238,7 +223,7 @@ int harvest(vd_sim *s)
 // as one launch with the store policy of the last pass.
 int launch_passes(vd_sim *s, const std::vector<Pass> &passes, int32_t th)
 {
-    const size_t m = th ? tail_len(passes) : 0;
+    const size_t m = th ? vd::tail_len(passes) : 0;
     const size_t n = passes.size() - m;
     for (size_t i = 0; i < n; ++i) {
         const Pass &p = passes[i];
@@ -670,7 +655,7 @@ int vd_autotune(vd_sim *s, int32_t reps)
     int32_t fz[2] = {0, 0};
     for (int dyn = 0; dyn < 2 && r == VD_OK; ++dyn) {
         std::vector<Pass> passes = dyn ? s->djfa_passes : s->jfa_passes;
-        if (tail_len(passes) == 0) continue;
+        if (vd::tail_len(passes) == 0) continue;
         for (Pass &p : passes) {
             const Cand &c0 = picks[tune_key(arch, c, p, dyn != 0)];
             p.variant = c0.variant + (nt[dyn] ? kBase : 0);
@@ -717,7 +702,7 @@ int vd_autotune(vd_sim *s, int32_t reps)
             g_tune_us[keys[i]] = pick_us[keys[i]];
         }
         for (int dyn = 0; dyn < 2; ++dyn)
-            if (tail_len(dyn ? s->djfa_passes : s->jfa_passes))
+            if (vd::tail_len(dyn ? s->djfa_passes : s->jfa_passes))
                 g_tune[fuse_key(arch, c, dyn != 0)] = {fz[dyn], 0};
     }
     // put the diagram back where the simulation expects it
@@ -1223,6 +1208,7 @@ int vd_set_flood_variant(vd_sim *s, int variant)
 int vd_set_tail_fusion(vd_sim *s, int mode)
 {
     if (!s) return fail(VD_EINVAL, "sim is NULL");
+    if (s->batch) return fail(VD_ESTATE, "simulation is driven by a batch (vd_batch_step)");
     if (mode != -1 && mode != 0 && mode != 1 && mode != 16 && mode != 24 && mode != 32)
         return fail(VD_EINVAL, "mode must be -1, 0, 1, 16, 24 or 32, got %d", mode);
     s->forced_fuse = mode == 1 ? 16 : mode;
@@ -1235,8 +1221,8 @@ int vd_set_tail_fusion(vd_sim *s, int mode)
 int vd_get_tail_fusion(const vd_sim *s, int32_t *jfa, int32_t *djfa)
 {
     if (!s) return fail(VD_EINVAL, "sim is NULL");
-    if (jfa) *jfa = s->tail_th[0] ? (int32_t)tail_len(s->jfa_passes) : 0;
-    if (djfa) *djfa = s->tail_th[1] ? (int32_t)tail_len(s->djfa_passes) : 0;
+    if (jfa) *jfa = s->tail_th[0] ? (int32_t)vd::tail_len(s->jfa_passes) : 0;
+    if (djfa) *djfa = s->tail_th[1] ? (int32_t)vd::tail_len(s->djfa_passes) : 0;
     return VD_OK;
 }
 

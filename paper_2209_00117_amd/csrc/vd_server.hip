@@ -238,6 +238,7 @@ struct Served {
     Request req{};
     int32_t pass = 0, npasses = 0;
     int32_t inflight = 0;         // enqueued ticks touching it, not yet finished
+    int32_t running = 0;          // requests started and not yet completed
 };
 
 struct Tick {
@@ -373,6 +374,7 @@ void reap(vd_server *sv, bool wait_one)
         }
         const vd::Clock::time_point now = vd::Clock::now();
         for (auto &c : t.completes) {
+            sv->sims[c.first].running -= 1;
             double ms = vd::ms_between(c.second.submitted, now);
             sv->finished[c.second.ticket] = ms;
             sv->latencies.push_back(ms);
@@ -424,6 +426,7 @@ bool tick(vd_server *sv)
         if (!s.active && !s.fifo.empty() && !s.removing) {
             s.req = s.fifo.front();
             s.fifo.pop_front();
+            s.running += 1;
             if (sv->policy == VD_SERVE_STEPS) {
                 whole.push_back(id);
                 continue;
@@ -803,7 +806,7 @@ int vd_server_read_map(vd_server *sv, int32_t sim_id, int32_t *host_dst, size_t 
     if (it == sv->sims.end()) return fail(VD_EINVAL, "no simulation %d", sim_id);
     Served &s = it->second;
     if (!s.sim) return fail(VD_ESTATE, "simulation %d is not resident yet", sim_id);
-    if (s.active || !s.fifo.empty())
+    if (s.running || !s.fifo.empty())
         return fail(VD_ESTATE, "simulation %d has requests in progress", sim_id);
     return vd_read_map(s.sim, host_dst, count);
 }
@@ -818,7 +821,7 @@ int vd_server_sim_state(vd_server *sv, int32_t sim_id, int32_t *resident, int64_
     const Served &s = it->second;
     if (resident) *resident = s.sim != nullptr;
     if (t) *t = s.sim ? s.sim->t : 0;
-    if (pending) *pending = (int32_t)s.fifo.size() + (s.active ? 1 : 0);
+    if (pending) *pending = (int32_t)s.fifo.size() + s.running;
     return VD_OK;
 }
 

@@ -27,6 +27,22 @@ struct EventPair {
 // Sets this thread's vd_last_error() message; returns status.
 int fail(int status, const char *fmt, ...);
 
+// Number of trailing passes that can run as one fused launch: the longest
+// suffix of steps 1, 2 or 4 summing to at most kTailHalo, at most
+// kTailMaxPasses long; 0 if shorter than two.
+inline size_t tail_len(const std::vector<Pass> &passes)
+{
+    size_t m = 0;
+    int32_t sum = 0;
+    while (m < passes.size() && m < (size_t)kTailMaxPasses) {
+        const int32_t k = passes[passes.size() - 1 - m].k;
+        if ((k != 1 && k != 2 && k != 4) || sum + k > kTailHalo) break;
+        sum += k;
+        ++m;
+    }
+    return m >= 2 ? m : 0;
+}
+
 }  // namespace vd
 
 struct vd_batch;
@@ -71,3 +87,14 @@ struct vd_sim {
     bool broken = false;
     vd_batch *batch = nullptr;   // set while a batch drives this simulation
 };
+
+namespace vd {
+// Launches of a step of kind `dynamic` run by the simulation's own pass
+// driver (the fused tail counts once); each flips the current map.
+inline int32_t step_launches(const vd_sim *s, bool dynamic)
+{
+    const std::vector<Pass> &ps = dynamic ? s->djfa_passes : s->jfa_passes;
+    const size_t m = s->tail_th[dynamic ? 1 : 0] ? tail_len(ps) : 0;
+    return (int32_t)(ps.size() - (m ? m - 1 : 0));
+}
+}  // namespace vd

@@ -36,13 +36,16 @@ def _make(V, specs, metric=0):
     return out
 
 
-def _run(V, specs, plan, metric=0, graph=False, tune=False, solo=None, variant=None):
+def _run(V, specs, plan, metric=0, graph=False, tune=False, solo=None, variant=None, fuse=None):
     made = _make(V, specs, metric)
     members = [V.Sim(s[0], s[1], xy, **kw) for s, (xy, kw) in zip(specs, made)]
     alone = [V.Sim(s[0], s[1], xy, **kw) for s, (xy, kw) in zip(specs, made)]
     if variant is not None:
         for m in members:
             V.set_flood_variant(m.handle, variant)
+    if fuse is not None:                 # solo members run their last passes fused or not
+        for m in members:
+            V.set_tail_fusion(m.handle, fuse)
     b = V.Batch(members)
     if tune:
         b.autotune(2)
@@ -83,16 +86,18 @@ def test_batch_autotuned(V):
     _run(V, SHAPES, [(1, True), (0, True), (1, True)], graph=True, tune=True)
 
 
+@pytest.mark.parametrize("fuse", [None, 0, 24])
 @pytest.mark.parametrize("graph", [False, True])
 @pytest.mark.parametrize("solo", [1, 100000])
-def test_batch_solo_members(V, graph, solo):
+def test_batch_solo_members(V, graph, solo, fuse):
     """Members of at least `solo` pixels run their passes with their own
     launches (all members for 1; the larger ones for 100000, the rest in the
-    persistent levels).  Mixed step kinds change which maps are current, so
-    graphs are captured per parity configuration; every step still equals
-    the alone runs."""
+    persistent levels), their last passes fused as the member's own steps
+    would fuse them (default, off, 24-row tiles).  Mixed step kinds change
+    which maps are current, so graphs are captured per parity
+    configuration; every step still equals the alone runs."""
     plan = [(1, True), (1, True), (0, True), (1, True), (0, False), (1, True), (1, True)]
-    _run(V, SHAPES, plan, graph=graph, solo=solo, variant=4)
+    _run(V, SHAPES, plan, graph=graph, solo=solo, variant=4, fuse=fuse)
 
 
 def test_batch_manhattan(V):
@@ -118,6 +123,8 @@ def test_batch_rejects_misuse(V):
         a.djfa_step()                      # driven by the batch
     with pytest.raises(V.VdError):
         V.Batch([a])                       # already in a batch
+    with pytest.raises(V.VdError):
+        V.set_tail_fusion(a.handle, 0)     # fixed while batched
     b.close()
     a.djfa_step()                          # free again
     x = V.Sim(100, 100, xy, label=V.LABEL_XY16)
