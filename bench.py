@@ -123,10 +123,11 @@ def bench_batched(torch, inputs, V, args):
     each over args.steps time steps (move + step): batched dJFA and batched
     JFA (batched moves, fills and splats, one persistent launch per pass
     level over the members that the batch autotuner keeps together, the
-    larger members' passes with their own launches; the whole step replayed
-    as a hipGraph), and the same 64 simulations run one at a time with plain
-    JFA (per-simulation launches, default kernel variants).  Every batched member's map equals its
-    one-at-a-time run bit for bit (tests/test_gpu_batch.py)."""
+    larger members' passes with their own launches and fused last passes;
+    the whole step replayed as a hipGraph), and the same 64 simulations run
+    one at a time with plain JFA (per-simulation launches, default kernel
+    variants).  Every batched member's map equals its one-at-a-time run bit
+    for bit (tests/test_gpu_batch.py)."""
     wl = inputs.batched()
     stream = torch.cuda.current_stream()
     specs = wl.sims

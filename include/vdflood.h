@@ -354,8 +354,9 @@ int vd_batch_set_shape(vd_batch *b, int32_t wg_per_cu);
 int vd_batch_autotune(vd_batch *b, int32_t reps);
 
 /* Members of at least min_pixels pixels (<= 0: none) run the passes of
- * `mode` steps solo: with their own launches and kernel variants (as
- * chosen by vd_autotune / vd_set_flood_variant), one member after another,
+ * `mode` steps solo: with their own launches, kernel variants and tail
+ * fusion (as chosen by vd_autotune / vd_set_flood_variant /
+ * vd_set_tail_fusion before the batch was built), one member after another,
  * so each member's maps stay in the Infinity Cache across its passes; the
  * others share one persistent launch per pass level.  Move, fill, splat and
  * the step's bookkeeping stay batched.  Results do not change.  Drops
