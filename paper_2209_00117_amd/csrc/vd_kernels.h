@@ -50,6 +50,12 @@ hipError_t launch_splat_id(uint32_t *map, const uint32_t *table, int32_t S, int3
                            const uint8_t *state, hipStream_t s);
 hipError_t launch_splat_xy(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
                            const uint8_t *state, hipStream_t s);
+// The ID splat on a map filled with all ones (a JFA step's start): the
+// atomic minimum alone.  All ones is no label: it indexes past the seed
+// table, whose answer is the sentinel position, so the flood passes treat
+// such pixels exactly as unclaimed ones (and a JFA step claims every pixel).
+hipError_t launch_splat_id_over_ones(uint32_t *map, const uint32_t *table, int32_t S,
+                                     int32_t W, const uint8_t *state, hipStream_t s);
 
 // Uniform random integer moves of every present seed, clamped to the grid.
 // With disp (two device words) non-null, disp[0] then grows by the move's

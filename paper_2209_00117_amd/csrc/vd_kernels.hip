@@ -220,7 +220,7 @@ __global__ void __launch_bounds__(kBlock) k_purge(uint32_t *__restrict__ map, in
     const int64_t tail = 4 * n4 + g;
     if (tail < n) {
         const uint32_t l = map[tail];
-        if (l != kEmpty && (state[l - 1] & kKept) == 0u) map[tail] = kEmpty;
+        if (l != kEmpty && (l > (uint32_t)S || (state[l - 1] & kKept) == 0u)) map[tail] = kEmpty;
     }
 }
 
@@ -265,7 +265,9 @@ __global__ void __launch_bounds__(kBlock) k_count_unclaimed(const uint32_t *__re
     const int64_t tail = 4 * n4 + g;
     if (tail < n) {
         const uint32_t l = map[tail];
-        c += (l == kEmpty || (state && (state[l - 1] & kPresent) == 0u)) ? 1u : 0u;
+        c += (l == kEmpty || (state && (l > (uint32_t)S || (state[l - 1] & kPresent) == 0u)))
+                 ? 1u
+                 : 0u;
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) c += (uint32_t)__shfl_xor((int)c, o, 64);
@@ -492,6 +494,14 @@ hipError_t launch_splat_id(uint32_t *map, const uint32_t *table, int32_t S, int3
                            const uint8_t *state, hipStream_t s)
 {
     return splat_min_of(map, table, S, W, state, kPresent, state, kPresent, s);
+}
+
+hipError_t launch_splat_id_over_ones(uint32_t *map, const uint32_t *table, int32_t S,
+                                     int32_t W, const uint8_t *state, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_splat_min, grid1d(S), dim3(kBlock), 0, s, map, table, S, W, state,
+                       kPresent);
+    return hipGetLastError();
 }
 
 hipError_t launch_splat_xy(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,

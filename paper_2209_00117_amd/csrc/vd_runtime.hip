@@ -269,18 +269,23 @@ int run_passes(vd_sim *s, const std::vector<Pass> &passes, int32_t th)
 // and kept (the common case costs nothing).
 const uint8_t *seed_state(const vd_sim *s) { return s->masked ? s->state : nullptr; }
 
-// The map a JFA step floods: unclaimed everywhere but the seed pixels.
+// The map a JFA step floods: unclaimed everywhere but the seed pixels.  ID
+// maps are filled with all ones rather than label 0 (both read as the
+// sentinel position in the passes, and every pixel is claimed by the end
+// of the step), so the atomic minimum of the seed labels needs no reset.
 int jfa_prologue(vd_sim *s)
 {
     const vd_config &c = s->cfg;
     int64_t npix = (int64_t)c.width * c.height;
-    VD_HIP(vd::launch_fill(s->map[s->cur], npix, vd::kEmpty, s->stream));
-    if (c.label == VD_LABEL_XY16)
+    if (c.label == VD_LABEL_XY16) {
+        VD_HIP(vd::launch_fill(s->map[s->cur], npix, vd::kEmpty, s->stream));
         VD_HIP(vd::launch_splat_xy(s->map[s->cur], s->pos, c.num_seeds, c.width, seed_state(s),
                                    s->stream));
-    else
-        VD_HIP(vd::launch_splat_id(s->map[s->cur], s->pos, c.num_seeds, c.width, seed_state(s),
-                                   s->stream));
+    } else {
+        VD_HIP(vd::launch_fill(s->map[s->cur], npix, 0xFFFFFFFFu, s->stream));
+        VD_HIP(vd::launch_splat_id_over_ones(s->map[s->cur], s->pos, c.num_seeds, c.width,
+                                             seed_state(s), s->stream));
+    }
     return VD_OK;
 }
 
