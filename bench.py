@@ -490,7 +490,7 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="single",
-                    choices=["small", "single", "large", "batched", "serving"])
+                    choices=["small", "single", "large", "band", "batched", "serving"])
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: requests per second")
     ap.add_argument("--seconds", type=float, default=10.0, help="serving: measured seconds")
     ap.add_argument("--no-graph", action="store_true", help="batched: launch kernels directly")

@@ -126,6 +126,17 @@ def large() -> Workload:
                     [SimSpec(8192, 8192, 1 << 20, -4, 4, 1, 50)], sample_pixels=1 << 20)
 
 
+def band() -> Workload:
+    """One GPU's share of the 8192 x 8192 grid split into eight row bands:
+    1024 rows plus 16 halo rows on each side (delta_1 = 16 at that density),
+    with seeds at the same density (2^20 / 8 per 1024 rows), moves in
+    [-4, 4]."""
+    rows = 8192 // 8 + 2 * 16
+    return Workload(f"band 8192x{rows} S={128 * rows} disp[-4,4] (one of 8 row bands of "
+                    f"8192^2 with its 16-row halos)",
+                    [SimSpec(8192, rows, 128 * rows, -4, 4, 1, 50)], sample_pixels=1 << 20)
+
+
 def batched(n_sims: int = 64, steps: int = 20) -> Workload:
     """64 independent simulations; side drawn from {256, ..., 4096}, seed
     count uniform in [2^6, 2^16] (at most side^2), moves in [-1, 3]."""
@@ -169,5 +180,5 @@ def poisson_arrivals(rate_per_s: float, duration_s: float, n_sims: int, seed: in
     return np.array(times), np.array(targets, dtype=np.int64)
 
 
-WORKLOADS = {"small": small, "single": single, "large": large, "batched": batched,
-             "serving": serving}
+WORKLOADS = {"small": small, "single": single, "large": large, "band": band,
+             "batched": batched, "serving": serving}

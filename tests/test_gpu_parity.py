@@ -41,20 +41,26 @@ def _seed_pixels_ok(m, xy, label_mode):
 
 
 def run_twin(V, W, H, xy, steps, lo, hi, sim_seed=1, label=0, metric=0, vn=2, extra=0,
-             dmax=0, tag="", variant=None, fuse=None):
+             dmax=0, tag="", variant=None, fuse=None, tune=False):
     """Runs a JFA and a dJFA simulation side by side on the GPU and in the
     oracle; asserts equal positions and maps at every step.  `variant` runs
     every pass on one kernel variant; the step's last passes are then fused
-    only if `fuse` is 1 (otherwise `fuse` sets tail fusion, None: default)."""
+    only if `fuse` is 1 (otherwise `fuse` sets tail fusion, None: default).
+    `tune` autotunes the first simulation before the second is made (which
+    adopts the table), as bench.py does before it times."""
     if variant is not None and fuse is None:
         fuse = 0
     print(f"[parity] {tag} W={W} H={H} S={len(xy)} steps={steps} disp=[{lo},{hi}] "
-          f"label={label} metric={metric} vn={vn} extra={extra} variant={variant} fuse={fuse}",
-          flush=True)
+          f"label={label} metric={metric} vn={vn} extra={extra} variant={variant} fuse={fuse} "
+          f"tune={tune}", flush=True)
     kw = dict(disp_lo=lo, disp_hi=hi, label=label, metric=metric, vn_passes=vn,
               extra_passes=extra, dmax_override=dmax, sim_seed=sim_seed)
     gj = V.Sim(W, H, xy, **kw)
+    if tune:
+        V.autotune(gj.handle, 1)
     gd = V.Sim(W, H, xy, **kw)
+    if tune:
+        assert V.get_tuning(gd.handle) == V.get_tuning(gj.handle)
     if variant is not None:
         V.set_flood_variant(gj.handle, variant)
         V.set_flood_variant(gd.handle, variant)
@@ -204,16 +210,25 @@ def test_dmax_override(V):
     run_twin(V, 512, 512, xy, 3, -1, 1, dmax=40, tag="dmax")
 
 
-def _full_size(V, spec, steps, label=0):
+def _full_size(V, spec, steps, label=0, tune=False):
     """A full-size workload for a few steps; positions and maps compared in
     full against the threaded oracle."""
     return run_twin(V, spec.width, spec.height, spec.positions(), steps, spec.disp_lo,
-                    spec.disp_hi, sim_seed=spec.sim_seed, label=label, tag=spec.width)
+                    spec.disp_hi, sim_seed=spec.sim_seed, label=label,
+                    tag=f"{spec.width}x{spec.height}", tune=tune)
 
 
 def test_single_full_size(V):
-    oj, od = _full_size(V, inputs.single().sims[0], 2)
+    """The 4096^2 workload with the autotuned kernels bench.py times."""
+    oj, od = _full_size(V, inputs.single().sims[0], 2, tune=True)
     print(f"[parity] 4096^2: dJFA vs JFA similarity {100 * O.count_equal(oj.map, od.map) / oj.map.size:.4f}%")
+
+
+@pytest.mark.parametrize("label", [0, 1])
+def test_band_full_size(V, label):
+    """One of eight row bands of 8192^2 with its halo rows (8192 x 1056),
+    autotuned as bench.py runs it."""
+    _full_size(V, inputs.band().sims[0], 2, label=label, tune=True)
 
 
 def test_large_full_size(V):

@@ -39,3 +39,14 @@ def test_workload_recipes():
     assert all(256 <= s.num_seeds <= min(1 << 18, s.width ** 2) for s in v.sims)
     t, tgt = inputs.poisson_arrivals(2000.0, 0.5, 256)
     assert 800 < len(t) < 1200 and (np.diff(t) > 0).all() and tgt.max() < 256
+
+
+def test_band_recipe_is_one_eighth_of_the_large_grid(orc):
+    """The band has the large workload's width, seed density, moves and
+    first dJFA jump, and 1024 rows plus delta_1 halo rows on each side."""
+    band, large = inputs.band().sims[0], inputs.large().sims[0]
+    d1 = orc.delta1(large.width, large.height, large.num_seeds, 4)
+    assert band.width == large.width and band.height == large.height // 8 + 2 * d1
+    assert band.num_seeds * large.pixels == large.num_seeds * band.pixels
+    assert (band.disp_lo, band.disp_hi) == (large.disp_lo, large.disp_hi)
+    assert orc.delta1(band.width, band.height, band.num_seeds, 4) == d1 == 16
