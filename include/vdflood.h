@@ -445,7 +445,8 @@ int vd_server_drain(vd_server *sv, double timeout_ms);
 int vd_server_remove_sim(vd_server *sv, int32_t sim_id);
 
 /* The current diagram of an idle resident simulation (VD_ESTATE while it
- * has requests in progress or is not resident); as vd_read_map. */
+ * has requests in progress or is not resident; the server's error once a
+ * launch or tick has failed); as vd_read_map. */
 int vd_server_read_map(vd_server *sv, int32_t sim_id, int32_t *host_dst, size_t count);
 
 /* Whether a simulation is resident, its time step and its pending requests. */

@@ -806,6 +806,7 @@ int vd_server_read_map(vd_server *sv, int32_t sim_id, int32_t *host_dst, size_t 
     if (it == sv->sims.end()) return fail(VD_EINVAL, "no simulation %d", sim_id);
     Served &s = it->second;
     if (!s.sim) return fail(VD_ESTATE, "simulation %d is not resident yet", sim_id);
+    if (sv->error) return server_error(sv);   // its steps may never complete
     if (s.running || !s.fifo.empty())
         return fail(VD_ESTATE, "simulation %d has requests in progress", sim_id);
     return vd_read_map(s.sim, host_dst, count);

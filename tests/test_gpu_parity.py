@@ -240,6 +240,38 @@ def test_large_full_size_xy(V):
 
 
 @pytest.mark.parametrize("label", [0, 1])
+def test_max_side_full_size(V, label):
+    """The largest grid the library accepts (16368^2, 1 GiB per map): the
+    squared distance from the sentinel to the far corner is the largest key
+    the passes see, and byte offsets reach 2^30.  2^20 seeds; VD_0 (a full
+    JFA step) and one dJFA step, compared in full."""
+    W = H = 16368
+    xy = inputs.place_seeds(W, H, 1 << 20, 17)
+    print(f"[parity] max-side {W}x{H} S={len(xy)} label={label}", flush=True)
+    g = V.Sim(W, H, xy, disp_lo=-4, disp_hi=4, sim_seed=17, label=label)
+    o = O.Sim(W, H, xy, 17, -4, 4, label_mode=label)
+    bad = int((g.read_map() != o.map).sum())            # VD_0: a full JFA step
+    assert bad == 0, f"max-side: VD_0 differs on {bad} pixels"
+    g.move_seeds(), o.move()
+    g.djfa_step(), o.djfa_step()
+    assert np.array_equal(g.read_seeds(), o.xy)
+    bad = int((g.read_map() != o.map).sum())
+    assert bad == 0, f"max-side: dJFA map differs on {bad} pixels"
+    g.close()
+
+
+@pytest.mark.parametrize("W,H", [(16367, 33), (33, 16367), (16368, 2), (1, 16368)])
+def test_max_side_thin_grids(V, W, H):
+    """One side at (or next to) the maximum, the other tiny: the first jump
+    is 8192 along the long side and every candidate across the short side
+    falls off the grid."""
+    S = max(1, min(W * H // 50, 3000))
+    xy = inputs.place_seeds(W, H, S, W + H)
+    for label in (0, 1):
+        run_twin(V, W, H, xy, 3, -3, 3, sim_seed=W, label=label, tag="thin")
+
+
+@pytest.mark.parametrize("label", [0, 1])
 def test_autotune_keeps_results(V, label):
     """Tuned kernel variants and segment lengths change speed only: a tuned
     simulation, a new one that adopts the table, and an untuned one stay
