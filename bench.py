@@ -445,6 +445,42 @@ def bench_churn(torch, V, args, W, H, xy, kw, stream, djfa_ms):
     return out
 
 
+def bench_readback(torch, V, args, W, H, xy, kw, stream, passes_djfa):
+    """The boundary hands diagrams to the host: dJFA steps (move included)
+    each followed by vd_read_map of the whole map, into pinned host memory
+    and into ordinary (pageable) memory, timed by the host clock around the
+    synchronous calls; and the read-back alone.  PCIe-inclusive figures,
+    reported beside the main ones, never as the headline value."""
+    sim = V.Sim(W, H, xy, stream=stream, **kw)
+    npix = W * H
+    pinned = torch.empty(npix, dtype=torch.int32, pin_memory=True)
+    pageable = np.empty(npix, np.int32)
+    targets = {"pinned": pinned.data_ptr(), "pageable": pageable.ctypes.data}
+    steps = min(args.steps, 30)
+    out = {"map_bytes": 4 * npix, "steps": steps}
+    for name, ptr in targets.items():
+        step_ms, copy_ms = [], []
+        for i in range(args.warmup + steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            sim.move_seeds()
+            sim.djfa_step()
+            V.read_map_into(sim.handle, ptr, npix)
+            t1 = time.perf_counter()
+            V.read_map_into(sim.handle, ptr, npix)
+            t2 = time.perf_counter()
+            if i >= args.warmup:
+                step_ms.append(1e3 * (t1 - t0))
+                copy_ms.append(1e3 * (t2 - t1))
+        ms = float(np.mean(step_ms))
+        out[name] = {"djfa_step_with_readback_ms": ms,
+                     "readback_ms": float(np.mean(copy_ms)),
+                     "readback_GBps": 4 * npix / (float(np.mean(copy_ms)) / 1e3) / 1e9,
+                     "pixel_updates_per_s": npix * passes_djfa / (ms / 1e3)}
+    sim.close()
+    return out
+
+
 def bench_tail_sweep(torch, V, args):
     """Tail fusion across map sizes: square maps of 256^2 .. 4096^2 with one
     seed per 256 pixels (moves in [-2, 2]), ID and XY labels, the last passes
@@ -504,6 +540,9 @@ def main():
     ap.add_argument("--with-churn", type=float, default=0.0, metavar="FRACTION",
                     help="also time dJFA steps after removing and inserting FRACTION of the "
                          "seeds before each step (a changing seed set)")
+    ap.add_argument("--with-readback", action="store_true",
+                    help="also time dJFA steps each followed by reading the map back to the "
+                         "host (pinned and pageable memory): PCIe-inclusive figures")
     ap.add_argument("--sweep", action="store_true",
                     help="time dJFA for vn_passes in {0,1,2} x extra_passes in {0,1,2} (and "
                          "JFA+extra) on the workload, with similarities to JFA")
@@ -673,6 +712,8 @@ def main():
                                    float(np.mean(djfa_ms)), float(np.mean(jfa_ms)))
     if args.with_churn > 0:
         out["churn"] = bench_churn(torch, V, args, W, H, xy, kw, stream, float(np.mean(djfa_ms)))
+    if args.with_readback:
+        out["readback"] = bench_readback(torch, V, args, W, H, xy, kw, stream, pd)
     sj.close(), sd.close()
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(spec, xy, args.cpu_budget)

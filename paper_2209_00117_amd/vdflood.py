@@ -267,6 +267,12 @@ def read_map(h) -> np.ndarray:
     return out
 
 
+def read_map_into(h, host_ptr: int, count: int):
+    """vd_read_map into caller-owned host memory of `count` int32 (for
+    instance a pinned tensor's data_ptr())."""
+    _check(lib().vd_read_map(h, ctypes.c_void_p(host_ptr), count))
+
+
 def read_seeds(h) -> np.ndarray:
     info = get_info(h)
     out = np.empty((info.num_seeds, 2), np.int32)
