@@ -361,3 +361,24 @@ def test_set_seeds_rejects_bad_input(V):
     with pytest.raises(V.VdError):
         g.set_seeds(bad)
     assert g.info().t == 0                                           # nothing changed
+
+
+def test_read_map_into_caller_memory(V):
+    """vd_read_map into pinned and pageable caller memory gives the same
+    diagram as the binding's own array (ID and XY labels)."""
+    import torch
+    W, H = 300, 200
+    xy = inputs.place_seeds(W, H, 150, 6)
+    for label in (0, 1):
+        g = V.Sim(W, H, xy, label=label)
+        g.move_seeds(), g.djfa_step()
+        ref = g.read_map()
+        pinned = torch.zeros(W * H, dtype=torch.int32, pin_memory=True)
+        V.read_map_into(g.handle, pinned.data_ptr(), W * H)
+        assert np.array_equal(pinned.numpy().reshape(H, W), ref)
+        plain = np.zeros(W * H, np.int32)
+        V.read_map_into(g.handle, plain.ctypes.data, W * H)
+        assert np.array_equal(plain.reshape(H, W), ref)
+        with pytest.raises(V.VdError):
+            V.read_map_into(g.handle, plain.ctypes.data, W * H - 1)
+        g.close()
