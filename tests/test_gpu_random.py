@@ -6,8 +6,10 @@ label encoding, the metric, the Von Neumann and extra pass counts, d_max
 (bound, measured or overridden), a forced kernel variant or the defaults,
 tail fusion, and a changing seed set or not; a JFA
 and a dJFA twin then run four steps on the GPU and in the oracle, and
-positions, present masks and every map must agree exactly.  The draws are
-fixed by the case number, so a failure names a reproducible configuration.
+positions, present masks and every map must agree exactly.  Random batches
+and random servers are drawn the same way and compared with the oracle
+after every step or drain.  The draws are fixed by the case number, so a
+failure names a reproducible configuration.
 """
 import numpy as np
 import pytest
@@ -93,3 +95,115 @@ def test_random_configuration(V, case):
             bad = int((g.read_map() != o.map).sum())
             assert bad == 0, f"case {case} t={t}: {kind} map differs on {bad} pixels"
     gj.close(), gd.close()
+
+
+N_BATCH_CASES = 64
+
+
+def draw_batch(case: int) -> dict:
+    r = np.random.default_rng(5000 + case)
+    members = []
+    for j in range(int(r.integers(1, 11))):
+        W = int(r.choice([1, 5, 64, 100, 256, 300, 1024, 1030]))
+        H = int(r.choice([1, 7, 64, 200, 333]))
+        lo = int(r.integers(-4, 3))
+        members.append(dict(W=W, H=H, S=int(min(W * H, int(r.integers(1, 3000)))), lo=lo,
+                            hi=int(r.integers(lo, 5)), vn=int(r.integers(0, 4)),
+                            extra=int(r.integers(0, 3)),
+                            dmax=int(r.choice([0, 0, int(r.integers(1, 20))])),
+                            variant=int(r.integers(-1, 12)),
+                            fuse=int(r.choice([-1, 0, 1, 24])),
+                            seed=int(r.integers(1, 1 << 30))))
+    plan = [(int(r.integers(0, 2)), bool(r.integers(0, 4))) for _ in range(6)]
+    return dict(members=members, metric=int(r.integers(0, 2)), graph=bool(r.integers(0, 2)),
+                shape=int(r.choice([0, 1, 2, 4, 8])),
+                solo=int(r.choice([-1, 0, 1, 20000, 60000])), plan=plan)
+
+
+@pytest.mark.parametrize("case", range(N_BATCH_CASES))
+def test_random_batch(V, case):
+    """A batch of 1..10 uneven members (ID labels, one metric) with random
+    per-member options, persistent grid shape, graphs on or off and solo
+    members or not, over six random steps (JFA or dJFA, with or without
+    moves); every member equals its oracle after every step."""
+    c = draw_batch(case)
+    print(f"[random-batch] case {case}: {c}", flush=True)
+    sims, orcs = [], []
+    for m in c["members"]:
+        xy = inputs.place_seeds(m["W"], m["H"], m["S"], m["seed"])
+        g = V.Sim(m["W"], m["H"], xy, disp_lo=m["lo"], disp_hi=m["hi"], metric=c["metric"],
+                  vn_passes=m["vn"], extra_passes=m["extra"], dmax_override=m["dmax"],
+                  sim_seed=m["seed"])
+        V.set_flood_variant(g.handle, m["variant"])
+        V.set_tail_fusion(g.handle, m["fuse"])
+        sims.append(g)
+        orcs.append(O.Sim(m["W"], m["H"], xy, m["seed"], m["lo"], m["hi"], metric=c["metric"],
+                          vn_passes=m["vn"], extra_passes=m["extra"],
+                          dmax=m["dmax"] if m["dmax"] > 0 else None))
+    b = V.Batch(sims)
+    b.set_shape(c["shape"])
+    if c["solo"] >= 0:
+        for mode in (V.STEP_JFA, V.STEP_DJFA):
+            b.set_solo(mode, c["solo"])
+    b.set_graph(c["graph"])
+    for t, (mode, move) in enumerate(c["plan"]):
+        b.step(mode, move)
+        for o in orcs:
+            if move:
+                o.move()
+            o.djfa_step() if mode == V.STEP_DJFA else o.jfa_step()
+        for j, (g, o) in enumerate(zip(sims, orcs)):
+            assert np.array_equal(g.read_seeds(), o.xy), f"case {case} t={t} member {j}"
+            bad = int((g.read_map() != o.map).sum())
+            assert bad == 0, f"case {case} t={t} member {j}: map differs on {bad} pixels"
+    b.close()
+    for g in sims:
+        g.close()
+
+
+N_SERVER_CASES = 12
+
+
+@pytest.mark.parametrize("case", range(N_SERVER_CASES))
+def test_random_server(V, case):
+    """A server with 2..8 uneven simulations (random pass options, one
+    metric) takes 40 random requests in bursts, switching policy at random
+    and draining at random points (every resident simulation is then read
+    and compared); at the end every simulation equals its oracle run of the
+    same request sequence."""
+    r = np.random.default_rng(9000 + case)
+    metric = int(r.integers(0, 2))
+    sv = V.Server(8, 1 << 31, metric=metric)
+    sv.set_policy(int(r.integers(0, 2)))
+    ids, orcs = [], {}
+    for j in range(int(r.integers(2, 9))):
+        W = int(r.choice([1, 40, 256, 300, 1024, 1100]))
+        H = int(r.choice([1, 9, 128, 333]))
+        S = int(min(W * H, int(r.integers(1, 4000))))
+        lo = int(r.integers(-3, 2))
+        hi = int(r.integers(lo, 4))
+        vn, extra = int(r.integers(0, 3)), int(r.integers(0, 3))
+        seed = int(r.integers(1, 1 << 30))
+        xy = inputs.place_seeds(W, H, S, seed)
+        i = sv.add_sim(W, H, xy, disp_lo=lo, disp_hi=hi, metric=metric, vn_passes=vn,
+                       extra_passes=extra, sim_seed=seed)
+        ids.append(i)
+        orcs[i] = O.Sim(W, H, xy, seed, lo, hi, metric=metric, vn_passes=vn,
+                        extra_passes=extra)
+    print(f"[random-server] case {case}: {len(ids)} sims, metric {metric}", flush=True)
+    for n in range(40):
+        if r.random() < 0.1:
+            sv.set_policy(int(r.integers(0, 2)))
+        i = int(r.choice(ids))
+        mode = V.STEP_DJFA if r.random() < 0.7 else V.STEP_JFA
+        sv.submit(i, mode)
+        orcs[i].move()
+        orcs[i].djfa_step() if mode == V.STEP_DJFA else orcs[i].jfa_step()
+        if r.random() < 0.1 or n == 39:
+            sv.drain(60000)
+            for k in ids:
+                bad = int((sv.read_map(k) != orcs[k].map).sum())
+                assert bad == 0, f"case {case} request {n}: sim {k} differs on {bad} pixels"
+    st = sv.stats()
+    assert st["completed"] == st["submitted"] == 40
+    sv.close()
