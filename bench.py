@@ -554,6 +554,11 @@ def main():
     ap.add_argument("--tail-sweep", action="store_true",
                     help="time steps with the last passes separate and fused (16- and 24-row "
                          "tiles) on square maps of 256^2 .. 4096^2, ID and XY labels")
+    ap.add_argument("--save-tuning", metavar="PATH",
+                    help="write the process-wide tuning table (JSON) after autotuning")
+    ap.add_argument("--load-tuning", metavar="PATH",
+                    help="adopt a saved tuning table instead of autotuning (profiled runs: "
+                         "counter collection distorts the timings the tuner compares)")
     ap.add_argument("--no-tune", action="store_true",
                     help="skip the autotuner (run every pass with the default kernel variant)")
     ap.add_argument("--calibrate", action="store_true",
@@ -593,13 +598,19 @@ def main():
     xy = spec.positions()
     kw = dict(disp_lo=spec.disp_lo, disp_hi=spec.disp_hi, sim_seed=spec.sim_seed, label=label)
     stream = torch.cuda.current_stream()
+    if args.load_tuning:
+        # a table saved by an earlier run: its choices are adopted by the
+        # simulations created below, and nothing is timed here
+        V.load_tuning(args.load_tuning)
     sj = V.Sim(W, H, xy, stream=stream, **kw)
     tuning = None
-    if not args.no_tune:
+    if not args.no_tune and not args.load_tuning:
         # Untimed: every pass of both step kinds is timed per kernel variant
         # and segment length on its real input; the twin created next adopts
         # the process-wide table.  The simulation's state is left unchanged.
         V.autotune(sj.handle, 3)
+        if args.save_tuning:
+            V.save_tuning(args.save_tuning)
     sd = V.Sim(W, H, xy, stream=stream, **kw)
     if args.tail_fusion != "auto":
         for sim in (sj, sd):
@@ -614,7 +625,7 @@ def main():
         choice, us = V.get_tuning(sd.handle), V.get_tuning_us(sd.handle)
         rows = [[k, v, r, round(t, 2)] for k, (v, r), t in zip(ks + kd, choice, us)]
         tuning = {"columns": ["k", "variant", "seg_rows", "best_us"], "jfa": rows[:pj],
-                  "djfa": rows[pj:]}
+                  "djfa": rows[pj:], "source": "loaded" if args.load_tuning else "autotuned"}
 
     def one_step(ev=None):
         if ev is not None:
