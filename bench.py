@@ -1,15 +1,18 @@
 #!/usr/bin/env python3
 """Benchmark of the JFA / dJFA hot path on one MI355X.
 
-One benchmark step is one simulation time step of the whole path: every
-seed moves (on the device), a JFA simulation recomputes its diagram from
-scratch, and a dJFA simulation with the same seed trajectory updates its
-diagram from the previous step (Alg. 1).  Inputs are resident in HBM before
-the timed region; nothing leaves the device inside it.
+One benchmark step is one simulation time step of the whole path, run by
+two twins with the same seed trajectory: the seeds move (on the device),
+the JFA twin recomputes its diagram from scratch and the dJFA twin updates
+its diagram from the previous step (Alg. 1).  The timed region runs the
+JFA twin's K steps, then the dJFA twin's K steps, each as a lone
+simulation would run (interleaving the twins step by step would make each
+evict the other's maps from the Infinity Cache).  Inputs are resident in
+HBM before the timed region; nothing leaves the device inside it.
 
 Prints one JSON line.  `value` is pixel-updates/s over the timed region:
 width*height*(JFA passes + dJFA passes) per step, divided by the measured
-time of the whole step (moves, fills and splats included).
+time of both twins' steps (moves, fills and splats included).
 
   python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload single]
                   [--label id|xy] [--with-djfam] [--no-tune]
@@ -520,6 +523,52 @@ def bench_tail_sweep(torch, V, args):
     print(json.dumps({"tail_sweep": rows}), flush=True)
 
 
+def bench_size_sweep(torch, V, args):
+    """Throughput across map sizes: square maps of 1024^2 .. 16368^2 with one
+    seed per 256 pixels and moves in [-2, 2], ID and XY labels, each
+    autotuned; per size the flood-pass rate of JFA and dJFA steps (HIP events
+    around 20 steps of each after 3 warm-up steps) and the share of 8 TB/s
+    that the 8 algorithmic bytes per pixel-update make.  The two maps of a
+    simulation fit in the 256 MB Infinity Cache up to 4096^2 and not from
+    8192^2 on."""
+    from paper_2209_00117_amd import inputs
+    stream = torch.cuda.current_stream()
+    rows = []
+    for side in (1024, 2048, 4096, 8192, 11584, 16368):
+        S = side * side // 256
+        xy = inputs.place_seeds(side, side, S, 7)
+        for label in (V.LABEL_ID32, V.LABEL_XY16):
+            kw = dict(disp_lo=-2, disp_hi=2, label=label)
+            sj = V.Sim(side, side, xy, stream=stream, **kw)
+            V.autotune(sj.handle, 2)
+            sd = V.Sim(side, side, xy, stream=stream, **kw)
+            for _ in range(3):
+                sj.move_seeds(), sd.move_seeds(), sj.jfa_step(), sd.djfa_step()
+            info = sd.info()
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            torch.cuda.synchronize()
+            ev[0].record(stream)
+            for _ in range(20):
+                sj.jfa_step()
+            ev[1].record(stream)
+            for _ in range(20):
+                sd.move_seeds(), sd.djfa_step()
+            ev[2].record(stream)
+            torch.cuda.synchronize()
+            jms, dms = ev[0].elapsed_time(ev[1]) / 20, ev[1].elapsed_time(ev[2]) / 20
+            px = side * side
+            upd = px * (info.passes_jfa + info.passes_djfa) / ((jms + dms) / 1e3)
+            row = {"side": side, "seeds": S, "label": "id" if label == V.LABEL_ID32 else "xy",
+                   "map_MiB": 4 * px / 2**20, "passes_jfa": info.passes_jfa,
+                   "passes_djfa": info.passes_djfa, "jfa_ms": round(jms, 4),
+                   "djfa_ms": round(dms, 4), "G_pixel_updates_per_s": round(upd / 1e9, 1),
+                   "hbm_frac_algorithmic": round(8 * upd / 8e12, 3)}
+            print(json.dumps(row), file=sys.stderr, flush=True)
+            rows.append(row)
+            sj.close(), sd.close()
+    print(json.dumps({"size_sweep": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -551,6 +600,9 @@ def main():
                     help="run each step's last passes (k = 4, 2, 1) as one LDS-tiled launch "
                          "(16, 24, 32: the tile height; on: 16); auto = the default or the "
                          "autotuner's choice")
+    ap.add_argument("--size-sweep", action="store_true",
+                    help="pixel-update rate of JFA and dJFA steps on square maps of 1024^2 .. "
+                         "16368^2 (one seed per 256 pixels), ID and XY labels, autotuned")
     ap.add_argument("--tail-sweep", action="store_true",
                     help="time steps with the last passes separate and fused (16- and 24-row "
                          "tiles) on square maps of 256^2 .. 4096^2, ID and XY labels")
@@ -581,6 +633,9 @@ def main():
     V.lib()
     if args.tail_sweep:
         bench_tail_sweep(torch, V, args)
+        return
+    if args.size_sweep:
+        bench_size_sweep(torch, V, args)
         return
     if args.workload == "batched":
         bench_batched(torch, inputs, V, args)
@@ -627,42 +682,43 @@ def main():
         tuning = {"columns": ["k", "variant", "seg_rows", "best_us"], "jfa": rows[:pj],
                   "djfa": rows[pj:], "source": "loaded" if args.load_tuning else "autotuned"}
 
-    def one_step(ev=None):
+    def twin_step(sim, dynamic, ev=None):
+        # one time step of one twin: its seeds move, then its JFA or dJFA step
         if ev is not None:
             ev[0].record(stream)
-        sj.move_seeds()
-        sd.move_seeds()
+        sim.move_seeds()
         if ev is not None:
             ev[1].record(stream)
-        sj.jfa_step()
+        sim.djfa_step() if dynamic else sim.jfa_step()
         if ev is not None:
             ev[2].record(stream)
-        sd.djfa_step()
-        if ev is not None:
-            ev[3].record(stream)
 
-    for _ in range(args.warmup):
-        one_step()
+    for sim, dynamic in ((sj, False), (sd, True)):
+        for _ in range(args.warmup):
+            twin_step(sim, dynamic)
     torch.cuda.synchronize()
 
     if not args.no_pass_timing:
         V.set_timing(sj.handle, True)
         V.set_timing(sd.handle, True)
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    ev_j, ev_d = ([[torch.cuda.Event(enable_timing=True) for _ in range(3)]
+                   for _ in range(args.steps)] for _ in range(2))
     start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     start.record(stream)
     for i in range(args.steps):
-        one_step(events[i])
+        twin_step(sj, False, ev_j[i])
+    for i in range(args.steps):
+        twin_step(sd, True, ev_d[i])
     stop.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     total_ms = start.elapsed_time(stop)
 
-    jfa_ms = [e[1].elapsed_time(e[2]) for e in events]
-    djfa_ms = [e[2].elapsed_time(e[3]) for e in events]
-    move_ms = [e[0].elapsed_time(e[1]) for e in events]
+    jfa_ms = [e[1].elapsed_time(e[2]) for e in ev_j]
+    djfa_ms = [e[1].elapsed_time(e[2]) for e in ev_d]
+    move_ms = [a[0].elapsed_time(a[1]) + b[0].elapsed_time(b[1]) for a, b in zip(ev_j, ev_d)]
     tj = tdd = None
     if not args.no_pass_timing:
         tj, tdd = V.get_timing(sj.handle), V.get_timing(sd.handle)
