@@ -43,9 +43,9 @@ hipError_t launch_fill(uint32_t *map, int64_t n, uint32_t value, hipStream_t s);
 
 // Seed pixels (Sec. III, flood starting points) of the present seeds;
 // `table` is the seed table (sentinel first).  ID labels take the lowest
-// index among coincident seeds in two launches: set the seed pixels to all
-// ones, then an unsigned atomic minimum of the labels.  XY labels write the
-// pixel's own packed position.
+// index among coincident seeds, in one launch of compare-and-swap loops
+// that replace the labels left from the previous step (see k_splat_swap).
+// XY labels write the pixel's own packed position.
 hipError_t launch_splat_id(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
                            const uint8_t *state, hipStream_t s);
 hipError_t launch_splat_xy(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,

@@ -37,6 +37,34 @@ __global__ void __launch_bounds__(kBlock) k_splat_reset(uint32_t *__restrict__ m
     if (i < S && takes_part(state, i, need)) map[pixel_of(table[i + 1], W)] = 0xFFFFFFFFu;
 }
 
+// ID splat into a diagram that still holds the previous step's labels, in
+// one launch: seed i stores label i + 1 at its pixel unless the pixel holds
+// a label no larger whose seed sits on that pixel now.  A label whose seed
+// is elsewhere (or absent: its table entry is the sentinel), and any value
+// outside 1..S, is stale and gets replaced.  At one pixel the value only
+// goes from stale to a present seed's label and from there to smaller such
+// labels, so every compare-and-swap loop ends, and the final value is the
+// smallest label among the seeds on the pixel.
+__global__ void __launch_bounds__(kBlock) k_splat_swap(uint32_t *__restrict__ map,
+                                                       const uint32_t *__restrict__ table,
+                                                       int32_t S, int32_t W,
+                                                       const uint8_t *__restrict__ state,
+                                                       uint32_t need)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S || !takes_part(state, i, need)) return;
+    const uint32_t p = table[i + 1], me = (uint32_t)(i + 1);
+    uint32_t *const at = &map[pixel_of(p, W)];
+    uint32_t cur = __hip_atomic_load(at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        const bool here = cur - 1u < (uint32_t)S && table[cur] == p;
+        if (here && cur <= me) return;
+        const uint32_t seen = atomicCAS(at, cur, me);
+        if (seen == cur) return;
+        cur = seen;
+    }
+}
+
 __global__ void __launch_bounds__(kBlock) k_splat_min(uint32_t *__restrict__ map,
                                                       const uint32_t *__restrict__ table,
                                                       int32_t S, int32_t W,
@@ -493,7 +521,9 @@ hipError_t splat_min_of(uint32_t *map, const uint32_t *table, int32_t S, int32_t
 hipError_t launch_splat_id(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
                            const uint8_t *state, hipStream_t s)
 {
-    return splat_min_of(map, table, S, W, state, kPresent, state, kPresent, s);
+    hipLaunchKernelGGL(k_splat_swap, grid1d(S), dim3(kBlock), 0, s, map, table, S, W, state,
+                       kPresent);
+    return hipGetLastError();
 }
 
 hipError_t launch_splat_id_over_ones(uint32_t *map, const uint32_t *table, int32_t S,
