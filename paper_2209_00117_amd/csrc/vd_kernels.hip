@@ -27,38 +27,38 @@ __device__ __forceinline__ bool takes_part(const uint8_t *state, int32_t i, uint
     return !state || (state[i] & need) != 0u;
 }
 
-__global__ void __launch_bounds__(kBlock) k_splat_reset(uint32_t *__restrict__ map,
-                                                        const uint32_t *__restrict__ table,
-                                                        int32_t S, int32_t W,
-                                                        const uint8_t *__restrict__ state,
-                                                        uint32_t need)
-{
-    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < S && takes_part(state, i, need)) map[pixel_of(table[i + 1], W)] = 0xFFFFFFFFu;
-}
-
-// ID splat into a diagram that still holds the previous step's labels, in
-// one launch: seed i stores label i + 1 at its pixel unless the pixel holds
-// a label no larger whose seed sits on that pixel now.  A label whose seed
-// is elsewhere (or absent: its table entry is the sentinel), and any value
-// outside 1..S, is stale and gets replaced.  At one pixel the value only
-// goes from stale to a present seed's label and from there to smaller such
-// labels, so every compare-and-swap loop ends, and the final value is the
-// smallest label among the seeds on the pixel.
+// Seed pixels over whatever they held before, in one launch.  Seed i takes
+// part if part_state has a bit of part_need (all seeds for a null
+// part_state); it claims its pixel with label i + 1 if label_state has a
+// bit of label_need, else with all ones (no label).  A pixel's value is
+// settled if it is all ones or the label of a label-claiming seed that sits
+// on that pixel (per `table`); any other value is stale.  A seed leaves a
+// settled value no larger than its own claim and otherwise puts its claim
+// in by compare-and-swap.  At one pixel the value only goes from stale to
+// all ones or a label, from all ones to a label, and from a label to a
+// smaller one, so every loop ends, and the final value is the smallest
+// label of the label-claiming seeds on the pixel, or all ones if every
+// seed there claims without one -- whatever the pixel held before.
 __global__ void __launch_bounds__(kBlock) k_splat_swap(uint32_t *__restrict__ map,
                                                        const uint32_t *__restrict__ table,
                                                        int32_t S, int32_t W,
-                                                       const uint8_t *__restrict__ state,
-                                                       uint32_t need)
+                                                       const uint8_t *__restrict__ part_state,
+                                                       uint32_t part_need,
+                                                       const uint8_t *__restrict__ label_state,
+                                                       uint32_t label_need)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= S || !takes_part(state, i, need)) return;
-    const uint32_t p = table[i + 1], me = (uint32_t)(i + 1);
+    if (i >= S || !takes_part(part_state, i, part_need)) return;
+    const uint32_t p = table[i + 1];
+    const uint32_t me = takes_part(label_state, i, label_need) ? (uint32_t)(i + 1) : 0xFFFFFFFFu;
     uint32_t *const at = &map[pixel_of(p, W)];
     uint32_t cur = __hip_atomic_load(at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     for (;;) {
-        const bool here = cur - 1u < (uint32_t)S && table[cur] == p;
-        if (here && cur <= me) return;
+        const bool settled =
+            cur == 0xFFFFFFFFu ||
+            (cur - 1u < (uint32_t)S && takes_part(label_state, (int32_t)(cur - 1u), label_need) &&
+             table[cur] == p);
+        if (settled && cur <= me) return;
         const uint32_t seen = atomicCAS(at, cur, me);
         if (seen == cur) return;
         cur = seen;
@@ -318,7 +318,7 @@ __global__ void k_disp_acc(uint32_t *__restrict__ disp)
     }
 }
 
-// After k_splat_reset / k_splat_min on the old positions, idx[old position]
+// After k_splat_swap on the old positions, idx[old position]
 // holds the lowest kept seed label (index + 1) sitting there, or all ones
 // if no kept seed sat there.  That seed writes its new position over it;
 // positions are >= (kOff << 16 | kOff), above every label, so no other seed
@@ -499,30 +499,12 @@ hipError_t launch_fill(uint32_t *map, int64_t n, uint32_t value, hipStream_t s)
     return hipGetLastError();
 }
 
-namespace {
-
-// k_splat_reset over the seeds with a bit of `reset_need` (state null:
-// all), then k_splat_min over those with a bit of `min_need`.
-hipError_t splat_min_of(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
-                        const uint8_t *reset_state, uint32_t reset_need,
-                        const uint8_t *state, uint32_t min_need, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_splat_reset, grid1d(S), dim3(kBlock), 0, s, map, table, S, W,
-                       reset_state, reset_need);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_splat_min, grid1d(S), dim3(kBlock), 0, s, map, table, S, W, state,
-                       min_need);
-    return hipGetLastError();
-}
-
-}  // namespace
 
 hipError_t launch_splat_id(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
                            const uint8_t *state, hipStream_t s)
 {
     hipLaunchKernelGGL(k_splat_swap, grid1d(S), dim3(kBlock), 0, s, map, table, S, W, state,
-                       kPresent);
+                       (uint32_t)kPresent, state, (uint32_t)kPresent);
     return hipGetLastError();
 }
 
@@ -618,9 +600,11 @@ hipError_t launch_settle(uint8_t *state, int32_t S, hipStream_t s)
 hipError_t launch_index_old(uint32_t *idx, const uint32_t *old_table, const uint32_t *table,
                             int32_t S, int32_t W, const uint8_t *state, hipStream_t s)
 {
-    // every old position is reset (a label may name a seed not kept), the
-    // minimum is taken over kept seeds only
-    hipError_t e = splat_min_of(idx, old_table, S, W, nullptr, 0u, state, kKept, s);
+    // every seed marks its old position (a label may name a seed not kept):
+    // with the lowest kept label there, else with all ones
+    hipLaunchKernelGGL(k_splat_swap, grid1d(S), dim3(kBlock), 0, s, idx, old_table, S, W,
+                       (const uint8_t *)nullptr, 0u, state, (uint32_t)kKept);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_index_resolve, grid1d(S), dim3(kBlock), 0, s, idx, old_table, table, S,
                        W, state);
