@@ -382,3 +382,27 @@ def test_read_map_into_caller_memory(V):
         with pytest.raises(V.VdError):
             V.read_map_into(g.handle, plain.ctypes.data, W * H - 1)
         g.close()
+
+
+@pytest.mark.parametrize("label", [0, 1])
+def test_djfa_splat_over_stale_labels(V, label):
+    """Seeds moved (vd_set_seeds) onto pixels that hold smaller labels of
+    seeds now elsewhere, and two seeds onto one pixel: the dJFA splat must
+    replace the stale labels and leave the lowest coincident label, as the
+    oracle's splat of the present seeds does."""
+    W = H = 48
+    xy = np.array([[2, 2], [40, 40], [10, 30], [30, 10], [24, 24]], np.int32)
+    g = V.Sim(W, H, xy, label=label, dmax_override=40)
+    o = O.Sim(W, H, xy, 1, -1, 1, label_mode=label, dmax=40)
+    # seed 4 and seed 3 onto the pixel seed 1 labelled, seed 2 onto seed 0's cell
+    new = xy.copy()
+    new[4] = [36, 36]
+    new[3] = [36, 36]
+    new[2] = [4, 3]
+    g.set_seeds(new), o.set_positions(new)
+    g.djfa_step(), o.djfa_step()
+    m = g.read_map()
+    assert np.array_equal(m, o.map)
+    if label == 0:
+        assert m[36, 36] == 3 and m[3, 4] == 2 and m[2, 2] == 0
+    g.close()
