@@ -1,21 +1,28 @@
 #!/usr/bin/env python3
 """Benchmark of the JFA / dJFA hot path on one MI355X.
 
-One benchmark step is one simulation time step of the whole path, run by
-two twins with the same seed trajectory: the seeds move (on the device),
-the JFA twin recomputes its diagram from scratch and the dJFA twin updates
-its diagram from the previous step (Alg. 1).  The timed region runs the
-JFA twin's K steps, then the dJFA twin's K steps, each as a lone
-simulation would run (interleaving the twins step by step would make each
-evict the other's maps from the Infinity Cache).  Inputs are resident in
-HBM before the timed region; nothing leaves the device inside it.
+Default workload: 8192 x 8192 pixels, 2^20 uniform random seeds, moves in
+[-4, 4] per axis (the two maps of a simulation, 2 x 256 MiB, stream from
+HBM).  One benchmark step is one simulation time step of the whole path,
+run by two twins with the same seed trajectory: the seeds move (on the
+device), the JFA twin recomputes its diagram from scratch and the dJFA
+twin updates its diagram from the previous step (Alg. 1).  The timed
+region runs the JFA twin's K steps, then the dJFA twin's K steps, each as
+a lone simulation would run.  Inputs are resident in HBM before the timed
+region; nothing leaves the device inside it.
 
-Prints one JSON line.  `value` is pixel-updates/s over the timed region:
-width*height*(JFA passes + dJFA passes) per step, divided by the measured
-time of both twins' steps (moves, fills and splats included).
+Both label formats (int32 seed IDs and packed 16-bit x/y positions) are
+measured, one after the other, and the line reports the faster one, with
+the other's figures under "labels".  `value` is pixel-updates/s over the
+timed region: width*height*(JFA passes + dJFA passes) per step, divided by
+the measured time of both twins' steps (moves, fills and splats included).
+Similarity to the exact diagram (Sec. VI-A) is checked outside the timed
+region at t = 1, at the end of the timed steps and at the workload's full
+length, and for the 512^2 and 4096^2 workloads over their full lengths.
+The CPU oracle is timed last, on the host's cores (cpu_baseline).
 
-  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload single]
-                  [--label id|xy] [--with-djfam] [--no-tune]
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload large]
+                  [--label id|xy|both] [--with-djfam] [--no-tune] [--no-cpu]
 
 --with-djfam adds a "djfam" block: a Manhattan-metric dJFA twin (Sec. V-C)
 timed in a loop of its own, with T_dJFAe/T_dJFAm and its similarity to the
@@ -24,9 +31,11 @@ Euclidean JFA map.
 from __future__ import annotations
 
 import argparse
+import copy
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -72,32 +81,94 @@ def pct(a, q):
     return float(np.percentile(np.asarray(a), q)) if len(a) else None
 
 
-def cpu_baseline(spec, xy, budget_s: float):
-    """The CPU oracle, as it is, on a bounded sample of the same workload:
-    whole time steps (move, JFA, dJFA) of the same simulation until about
-    budget_s seconds of work have run."""
-    import oracle as O
-    threads = O.default_threads()
-    od = O.Sim(spec.width, spec.height, xy, spec.sim_seed, spec.disp_lo, spec.disp_hi,
-               nthreads=threads)
+def host_cpus():
+    """CPUs this process may use (what `nproc` prints), the cgroup CPU quota
+    if one is set (in cores), and lscpu's model name."""
+    nproc = len(os.sched_getaffinity(0))
+    quota = None
+    try:
+        with open("/sys/fs/cgroup/cpu.max") as f:
+            q, period = f.read().split()[:2]
+        if q != "max":
+            quota = int(q) / int(period)
+    except (OSError, ValueError):
+        pass
+    model = None
+    try:
+        text = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in text.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return nproc, quota, model
+
+
+def oracle_steps(O, spec, xy, build_threads, threads, steps):
+    """The oracle's twins on one workload: VD_0 by its full JFA with
+    build_threads (untimed; the dJFA twin starts from a copy), then `steps`
+    time steps timed with `threads` threads: move both twins, JFA step of
+    one, dJFA step of the other.  Returns per-step seconds."""
     oj = O.Sim(spec.width, spec.height, xy, spec.sim_seed, spec.disp_lo, spec.disp_hi,
-               nthreads=threads)
-    pj = len(O.schedule(spec.width, spec.height, spec.num_seeds, False))
-    pd = len(O.schedule(spec.width, spec.height, spec.num_seeds, True, od.dmax))
-    steps, elapsed = 0, 0.0
-    while elapsed < budget_s and steps < spec.steps:
+               nthreads=build_threads)
+    od = copy.deepcopy(oj)
+    oj.nthreads = od.nthreads = threads
+    move_s, jfa_s, djfa_s = [], [], []
+    for _ in range(steps):
         t0 = time.perf_counter()
-        od.move(), oj.move()
+        oj.move(), od.move()
+        t1 = time.perf_counter()
         oj.jfa_step()
+        t2 = time.perf_counter()
         od.djfa_step()
-        elapsed += time.perf_counter() - t0
-        steps += 1
-    upd = steps * spec.width * spec.height * (pj + pd)
-    return {"value": upd / elapsed, "unit": "pixel-updates/s", "cores": threads,
-            "kind": "oracle",
-            "sample": f"{steps} whole time steps (move + JFA + dJFA) of the same "
-                      f"{spec.width}x{spec.height} S={spec.num_seeds} simulation, "
-                      f"{elapsed:.1f} s, rows split over {threads} threads"}
+        t3 = time.perf_counter()
+        move_s.append(t1 - t0), jfa_s.append(t2 - t1), djfa_s.append(t3 - t2)
+    return move_s, jfa_s, djfa_s
+
+
+def cpu_baseline(args, xy_large=None):
+    """The CPU oracle, as it is, timed on this host's cores: per-step JFA and
+    dJFA ms of the three single-simulation workloads, with the rows of each
+    pass split over every CPU the process may use and single-threaded.
+    Bounded sample: the 8192^2 workload's first 3 time steps (all threads;
+    the headline value), its first step single-threaded, the 4096^2
+    workload's first 3 steps (all threads) and first step (one thread), the
+    512^2 workload's 5 steps both ways.  --cpu-full times every listed
+    workload's first 3 steps single-threaded too."""
+    import oracle as O
+    from paper_2209_00117_amd import inputs
+    nproc, quota, model = host_cpus()
+    threads = max(1, min(nproc, int(quota))) if quota else nproc
+    one_steps = 3 if args.cpu_full else 1
+    rows, value = [], None
+    for name, all_steps, single_steps in (("small", 5, 5), ("single", 3, one_steps),
+                                          ("large", 3, one_steps)):
+        spec = inputs.WORKLOADS[name]().sims[0]
+        xy = xy_large if (name == "large" and xy_large is not None) else spec.positions()
+        pj = len(O.schedule(spec.width, spec.height, spec.num_seeds, False))
+        pd = len(O.schedule(spec.width, spec.height, spec.num_seeds, True,
+                            max(abs(spec.disp_lo), abs(spec.disp_hi))))
+        for n_thr, steps in ((threads, all_steps), (1, single_steps)):
+            mv, js, ds = oracle_steps(O, spec, xy, threads, n_thr, steps)
+            px = spec.width * spec.height
+            tot = sum(mv) + sum(js) + sum(ds)
+            row = {"workload": name, "threads": n_thr, "steps": steps,
+                   "jfa_ms_per_step": 1e3 * float(np.mean(js)),
+                   "djfa_ms_per_step": 1e3 * float(np.mean(ds)),
+                   "move_ms_per_step": 1e3 * float(np.mean(mv)),
+                   "pixel_updates_per_s": steps * px * (pj + pd) / tot}
+            rows.append(row)
+            print(json.dumps({"cpu_oracle": row}), file=sys.stderr, flush=True)
+            if name == "large" and n_thr == threads:
+                value = row["pixel_updates_per_s"]
+    return {"value": value, "unit": "pixel-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"the 8192x8192 S=2^20 workload's first 3 time steps (move both twins, "
+                      f"JFA step, dJFA step; VD_0 untimed), rows of each pass split over "
+                      f"{threads} threads; per-workload rows below, single-threaded rows "
+                      f"over {one_steps} step(s) of the 4096^2 and 8192^2 workloads",
+            "nproc": nproc, "cgroup_cpu_quota": quota, "cpu_model": model,
+            "per_workload": rows}
 
 
 def calibrate(torch, nbytes=512 << 20, reps=20):
@@ -569,18 +640,256 @@ def bench_size_sweep(torch, V, args):
     print(json.dumps({"size_sweep": rows}), flush=True)
 
 
+def seed_positions_of(labels, name, seeds):
+    """(x, y) of each label's seed (int64), and a mask of claimed labels."""
+    labels = labels.astype(np.int64)
+    if name == "id":
+        ok = (labels >= 0) & (labels < len(seeds))
+        at = np.where(ok, labels, 0)
+        return seeds[at, 0].astype(np.int64), seeds[at, 1].astype(np.int64), ok
+    ok = labels >= 0
+    return labels & 0xFFFF, labels >> 16, ok
+
+
+def exact_d2(seeds, px, py):
+    """Squared distance from each sample pixel to its exact nearest seed
+    (Eq. 1), by a k-d tree over the seeds (scipy); which of several
+    equidistant seeds it returns does not matter here."""
+    from scipy.spatial import cKDTree
+    tree = cKDTree(seeds.astype(np.float64))
+    _, idx = tree.query(np.stack([px, py], 1).astype(np.float64), k=1)
+    dx = px.astype(np.int64) - seeds[idx, 0]
+    dy = py.astype(np.int64) - seeds[idx, 1]
+    return dx * dx + dy * dy
+
+
+def similarity_point(inputs, wl, name, t, seeds, map_jfa, map_djfa):
+    """Sec. VI-A similarity at one time step: the share of (sampled) pixels
+    whose dJFA (and JFA) label is a seed at exact nearest distance, and the
+    paper's dJFA-vs-JFA label equality over the whole map."""
+    H, W = map_djfa.shape
+    if wl.sample_pixels:
+        px, py = inputs.sample_pixels(W, H, wl.sample_pixels, 7)
+    else:
+        py, px = np.divmod(np.arange(W * H, dtype=np.int64), W)
+    px, py = px.astype(np.int64), py.astype(np.int64)
+    best = exact_d2(seeds, px, py)
+    out = {"t": t}
+    for key, m in (("djfa_vs_exact", map_djfa), ("jfa_vs_exact", map_jfa)):
+        sx, sy, ok = seed_positions_of(m[py, px], name, seeds)
+        d2 = (px - sx) ** 2 + (py - sy) ** 2
+        out[key] = float(np.mean(ok & (d2 == best)))
+    out["djfa_vs_jfa"] = float((map_djfa == map_jfa).mean())
+    out["pixels"] = int(px.size)
+    return out
+
+
+def measure_label(torch, V, args, wl, spec, xy, name):
+    """The two twins of one label format on one workload: tuning, warm-up,
+    the timed region (the JFA twin's steps, then the dJFA twin's), per-pass
+    timing and the similarity checkpoints (t = 1, the end of the timed
+    steps, and the workload's full length, all outside the timed region)."""
+    from paper_2209_00117_amd import inputs
+    W, H = spec.width, spec.height
+    label = V.LABEL_ID32 if name == "id" else V.LABEL_XY16
+    kw = dict(disp_lo=spec.disp_lo, disp_hi=spec.disp_hi, sim_seed=spec.sim_seed, label=label)
+    stream = torch.cuda.current_stream()
+    sj = V.Sim(W, H, xy, stream=stream, **kw)
+    tuning = None
+    if not args.no_tune and not args.load_tuning:
+        # Untimed: every pass of both step kinds is timed per kernel variant
+        # and segment length on its real input; the twin created next adopts
+        # the process-wide table.  The simulation's state is left unchanged.
+        V.autotune(sj.handle, 3)
+    sd = V.Sim(W, H, xy, stream=stream, **kw)
+    if args.tail_fusion != "auto":
+        for sim in (sj, sd):
+            mode = {"on": 1, "off": 0}.get(args.tail_fusion)
+            V.set_tail_fusion(sim.handle, int(args.tail_fusion) if mode is None else mode)
+    fused = V.get_tail_fusion(sd.handle)
+    info = sd.info()
+    pj, pd = info.passes_jfa, info.passes_djfa
+    if not args.no_tune:
+        ks = [info.k1 >> i for i in range(pj)]
+        kd = [info.delta1 >> i for i in range(pd)]
+        choice, us = V.get_tuning(sd.handle), V.get_tuning_us(sd.handle)
+        rows = [[k, v, r, round(t, 2)] for k, (v, r), t in zip(ks + kd, choice, us)]
+        tuning = {"columns": ["k", "variant", "seg_rows", "best_us"], "jfa": rows[:pj],
+                  "djfa": rows[pj:], "source": "loaded" if args.load_tuning else "autotuned"}
+
+    def twin_step(sim, dynamic, ev=None):
+        # one time step of one twin: its seeds move, then its JFA or dJFA step
+        if ev is not None:
+            ev[0].record(stream)
+        sim.move_seeds()
+        if ev is not None:
+            ev[1].record(stream)
+        sim.djfa_step() if dynamic else sim.jfa_step()
+        if ev is not None:
+            ev[2].record(stream)
+
+    checks = []
+
+    def checkpoint():
+        if args.no_similarity:
+            return
+        t = sd.info().t
+        checks.append(similarity_point(inputs, wl, name, int(t), sd.read_seeds(),
+                                       sj.read_map(), sd.read_map()))
+        print(json.dumps({"label": name, "similarity": checks[-1]}), file=sys.stderr, flush=True)
+
+    for i in range(args.warmup):
+        twin_step(sj, False)
+        twin_step(sd, True)
+        if i == 0:
+            checkpoint()
+    torch.cuda.synchronize()
+
+    if not args.no_pass_timing:
+        V.set_timing(sj.handle, True)
+        V.set_timing(sd.handle, True)
+    ev_j, ev_d = ([[torch.cuda.Event(enable_timing=True) for _ in range(3)]
+                   for _ in range(args.steps)] for _ in range(2))
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    start.record(stream)
+    for i in range(args.steps):
+        twin_step(sj, False, ev_j[i])
+    for i in range(args.steps):
+        twin_step(sd, True, ev_d[i])
+    stop.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = start.elapsed_time(stop)
+
+    jfa_ms = [e[1].elapsed_time(e[2]) for e in ev_j]
+    djfa_ms = [e[1].elapsed_time(e[2]) for e in ev_d]
+    move_ms = [a[0].elapsed_time(a[1]) + b[0].elapsed_time(b[1]) for a, b in zip(ev_j, ev_d)]
+    tj = tdd = None
+    if not args.no_pass_timing:
+        tj, tdd = V.get_timing(sj.handle), V.get_timing(sd.handle)
+        V.set_timing(sj.handle, False)
+        V.set_timing(sd.handle, False)
+
+    # dJFA vs JFA similarity at the last timed step (Sec. VI-A), device maps read back
+    mj, md = sj.read_map(), sd.read_map()
+    sim_jfa = float((mj == md).mean())
+    checkpoint()
+    # on to the workload's full length (untimed), then the last checkpoint
+    done = args.warmup + args.steps
+    if not args.no_similarity and done < spec.steps:
+        for _ in range(spec.steps - done):
+            twin_step(sj, False)
+            twin_step(sd, True)
+        checkpoint()
+
+    px_updates = args.steps * W * H * (pj + pd)
+    value = px_updates / (total_ms / 1e3)
+    roofline = None
+    if tj is not None and tj.flood_launches + tdd.flood_launches > 0:
+        launches = tj.flood_launches + tdd.flood_launches
+        avg_ms = (tj.flood_ms + tdd.flood_ms) / launches
+        achieved = BYTES_PER_PIXEL_UPDATE * W * H / (avg_ms / 1e3) / 1e9
+        traffic = measured_traffic(args.workload + ("" if name == "id" else "-xy"))
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": traffic, "kernel": "flood pass",
+                    "avg_launch_us": round(avg_ms * 1e3, 3), "launches": launches,
+                    "algorithmic_bytes_per_launch": BYTES_PER_PIXEL_UPDATE * W * H,
+                    "jfa_avg_launch_us": round(tj.flood_ms / max(tj.flood_launches, 1) * 1e3, 3),
+                    "djfa_avg_launch_us": round(tdd.flood_ms / max(tdd.flood_launches, 1) * 1e3,
+                                                3)}
+
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "pixel-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic (uniform random seeds and moves, splitmix64)",
+        "config": {"workload": wl.name, "width": W, "height": H, "seeds": spec.num_seeds,
+                   "disp": [spec.disp_lo, spec.disp_hi], "label": name,
+                   "passes_jfa": pj, "passes_djfa": pd, "k1": info.k1, "delta1": info.delta1,
+                   "fused_tail_passes": {"jfa": fused[0], "djfa": fused[1]}},
+        "jfa": {"ms_per_step": float(np.mean(jfa_ms)), "p50_ms": pct(jfa_ms, 50),
+                "p99_ms": pct(jfa_ms, 99),
+                "pixel_updates_per_s": W * H * pj / (np.mean(jfa_ms) / 1e3)},
+        "djfa": {"ms_per_step": float(np.mean(djfa_ms)), "p50_ms": pct(djfa_ms, 50),
+                 "p99_ms": pct(djfa_ms, 99),
+                 "pixel_updates_per_s": W * H * pd / (np.mean(djfa_ms) / 1e3)},
+        "move_ms_per_step": float(np.mean(move_ms)),
+        "speedup_djfa_vs_jfa": float(np.mean(jfa_ms) / np.mean(djfa_ms)),
+        "similarity_djfa_vs_jfa": sim_jfa,
+        "similarity_exact": checks,
+        "wall_s": wall,
+        "roofline": roofline,
+        "cpu_baseline": None,
+        "tuning": tuning,
+    }
+    if args.with_djfam:
+        out["djfam"] = bench_djfam(torch, V, args, W, H, xy, kw, stream, mj,
+                                   float(np.mean(djfa_ms)), float(np.mean(jfa_ms)))
+    if args.with_churn > 0:
+        out["churn"] = bench_churn(torch, V, args, W, H, xy, kw, stream, float(np.mean(djfa_ms)))
+    if args.with_readback:
+        out["readback"] = bench_readback(torch, V, args, W, H, xy, kw, stream, pd)
+    sj.close(), sd.close()
+    return out
+
+
+def similarity_run(torch, V, wl, name):
+    """One workload at its full length with default kernels, both twins;
+    similarity to the exact diagram at the first, middle and last steps
+    (every step of a workload of at most 5 steps)."""
+    from paper_2209_00117_amd import inputs
+    spec = wl.sims[0]
+    xy = spec.positions()
+    label = V.LABEL_ID32 if name == "id" else V.LABEL_XY16
+    stream = torch.cuda.current_stream()
+    kw = dict(disp_lo=spec.disp_lo, disp_hi=spec.disp_hi, sim_seed=spec.sim_seed, label=label)
+    sj, sd = (V.Sim(spec.width, spec.height, xy, stream=stream, **kw) for _ in range(2))
+    at = set(range(1, spec.steps + 1)) if spec.steps <= 5 else {1, spec.steps // 2, spec.steps}
+    points = []
+    for t in range(1, spec.steps + 1):
+        sj.move_seeds(), sd.move_seeds()
+        sj.jfa_step(), sd.djfa_step()
+        if t in at:
+            points.append(similarity_point(inputs, wl, name, t, sd.read_seeds(), sj.read_map(),
+                                           sd.read_map()))
+    sj.close(), sd.close()
+    res = {"workload": wl.name, "label": name, "steps": spec.steps, "points": points}
+    for key in ("djfa_vs_exact", "jfa_vs_exact", "djfa_vs_jfa"):
+        res[key + "_mean"] = float(np.mean([p[key] for p in points]))
+        res[key + "_min"] = float(np.min([p[key] for p in points]))
+    print(json.dumps({"similarity_run": res}), file=sys.stderr, flush=True)
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--workload", default="single",
+    ap.add_argument("--workload", default="large",
                     choices=["small", "single", "large", "band", "batched", "serving"])
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: requests per second")
     ap.add_argument("--seconds", type=float, default=10.0, help="serving: measured seconds")
     ap.add_argument("--no-graph", action="store_true", help="batched: launch kernels directly")
-    ap.add_argument("--label", default="id", choices=["id", "xy"])
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--label", default="both", choices=["id", "xy", "both"],
+                    help="label format; both: measure each, report the faster")
+    ap.add_argument("--cpu-full", action="store_true",
+                    help="CPU oracle: first 3 steps single-threaded as well")
+    ap.add_argument("--no-similarity", action="store_true",
+                    help="skip the similarity checkpoints against the exact diagram")
+    ap.add_argument("--no-similarity-configs", action="store_true",
+                    help="skip the 512^2 and 4096^2 similarity runs")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-pass-timing", action="store_true")
     ap.add_argument("--with-djfam", action="store_true",
@@ -645,145 +954,37 @@ def main():
         return
     wl = inputs.WORKLOADS[args.workload]()
     spec = wl.sims[0]
-    W, H = spec.width, spec.height
-    label = V.LABEL_ID32 if args.label == "id" else V.LABEL_XY16
     if args.sweep:
-        bench_sweep(torch, V, args, wl, label)
+        bench_sweep(torch, V, args, wl, V.LABEL_ID32 if args.label == "id" else V.LABEL_XY16)
         return
     xy = spec.positions()
-    kw = dict(disp_lo=spec.disp_lo, disp_hi=spec.disp_hi, sim_seed=spec.sim_seed, label=label)
-    stream = torch.cuda.current_stream()
     if args.load_tuning:
         # a table saved by an earlier run: its choices are adopted by the
         # simulations created below, and nothing is timed here
         V.load_tuning(args.load_tuning)
-    sj = V.Sim(W, H, xy, stream=stream, **kw)
-    tuning = None
-    if not args.no_tune and not args.load_tuning:
-        # Untimed: every pass of both step kinds is timed per kernel variant
-        # and segment length on its real input; the twin created next adopts
-        # the process-wide table.  The simulation's state is left unchanged.
-        V.autotune(sj.handle, 3)
-        if args.save_tuning:
-            V.save_tuning(args.save_tuning)
-    sd = V.Sim(W, H, xy, stream=stream, **kw)
-    if args.tail_fusion != "auto":
-        for sim in (sj, sd):
-            mode = {"on": 1, "off": 0}.get(args.tail_fusion)
-            V.set_tail_fusion(sim.handle, int(args.tail_fusion) if mode is None else mode)
-    fused = V.get_tail_fusion(sd.handle)
-    info = sd.info()
-    pj, pd = info.passes_jfa, info.passes_djfa
-    if not args.no_tune:
-        ks = [info.k1 >> i for i in range(pj)]
-        kd = [info.delta1 >> i for i in range(pd)]
-        choice, us = V.get_tuning(sd.handle), V.get_tuning_us(sd.handle)
-        rows = [[k, v, r, round(t, 2)] for k, (v, r), t in zip(ks + kd, choice, us)]
-        tuning = {"columns": ["k", "variant", "seg_rows", "best_us"], "jfa": rows[:pj],
-                  "djfa": rows[pj:], "source": "loaded" if args.load_tuning else "autotuned"}
-
-    def twin_step(sim, dynamic, ev=None):
-        # one time step of one twin: its seeds move, then its JFA or dJFA step
-        if ev is not None:
-            ev[0].record(stream)
-        sim.move_seeds()
-        if ev is not None:
-            ev[1].record(stream)
-        sim.djfa_step() if dynamic else sim.jfa_step()
-        if ev is not None:
-            ev[2].record(stream)
-
-    for sim, dynamic in ((sj, False), (sd, True)):
-        for _ in range(args.warmup):
-            twin_step(sim, dynamic)
-    torch.cuda.synchronize()
-
-    if not args.no_pass_timing:
-        V.set_timing(sj.handle, True)
-        V.set_timing(sd.handle, True)
-    ev_j, ev_d = ([[torch.cuda.Event(enable_timing=True) for _ in range(3)]
-                   for _ in range(args.steps)] for _ in range(2))
-    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    start.record(stream)
-    for i in range(args.steps):
-        twin_step(sj, False, ev_j[i])
-    for i in range(args.steps):
-        twin_step(sd, True, ev_d[i])
-    stop.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    total_ms = start.elapsed_time(stop)
-
-    jfa_ms = [e[1].elapsed_time(e[2]) for e in ev_j]
-    djfa_ms = [e[1].elapsed_time(e[2]) for e in ev_d]
-    move_ms = [a[0].elapsed_time(a[1]) + b[0].elapsed_time(b[1]) for a, b in zip(ev_j, ev_d)]
-    tj = tdd = None
-    if not args.no_pass_timing:
-        tj, tdd = V.get_timing(sj.handle), V.get_timing(sd.handle)
-        V.set_timing(sj.handle, False)
-        V.set_timing(sd.handle, False)
-
-    # dJFA vs JFA similarity at the last step (Sec. VI-A), device maps read back
-    mj, md = sj.read_map(), sd.read_map()
-    sim_jfa = float((mj == md).mean())
-
-    px_updates = args.steps * W * H * (pj + pd)
-    value = px_updates / (total_ms / 1e3)
-    roofline = None
-    if tj is not None and tj.flood_launches + tdd.flood_launches > 0:
-        launches = tj.flood_launches + tdd.flood_launches
-        avg_ms = (tj.flood_ms + tdd.flood_ms) / launches
-        achieved = BYTES_PER_PIXEL_UPDATE * W * H / (avg_ms / 1e3) / 1e9
-        traffic = measured_traffic(args.workload + ("" if label == 0 else "-xy"))
-        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                    "traffic": traffic, "kernel": "flood pass",
-                    "avg_launch_us": round(avg_ms * 1e3, 3), "launches": launches,
-                    "algorithmic_bytes_per_launch": BYTES_PER_PIXEL_UPDATE * W * H}
-
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "pixel-updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": total_ms / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "int32",
-        "data": "synthetic (uniform random seeds and moves, splitmix64)",
-        "config": {"workload": wl.name, "width": W, "height": H, "seeds": spec.num_seeds,
-                   "disp": [spec.disp_lo, spec.disp_hi], "label": args.label,
-                   "passes_jfa": pj, "passes_djfa": pd, "k1": info.k1, "delta1": info.delta1,
-                   "fused_tail_passes": {"jfa": fused[0], "djfa": fused[1]}},
-        "jfa": {"ms_per_step": float(np.mean(jfa_ms)), "p50_ms": pct(jfa_ms, 50),
-                "p99_ms": pct(jfa_ms, 99),
-                "pixel_updates_per_s": W * H * pj / (np.mean(jfa_ms) / 1e3)},
-        "djfa": {"ms_per_step": float(np.mean(djfa_ms)), "p50_ms": pct(djfa_ms, 50),
-                 "p99_ms": pct(djfa_ms, 99),
-                 "pixel_updates_per_s": W * H * pd / (np.mean(djfa_ms) / 1e3)},
-        "move_ms_per_step": float(np.mean(move_ms)),
-        "speedup_djfa_vs_jfa": float(np.mean(jfa_ms) / np.mean(djfa_ms)),
-        "similarity_djfa_vs_jfa": sim_jfa,
-        "wall_s": wall,
-        "roofline": roofline,
-        "cpu_baseline": None,
-        "tuning": tuning,
-    }
-    if args.with_djfam:
-        out["djfam"] = bench_djfam(torch, V, args, W, H, xy, kw, stream, mj,
-                                   float(np.mean(djfa_ms)), float(np.mean(jfa_ms)))
-    if args.with_churn > 0:
-        out["churn"] = bench_churn(torch, V, args, W, H, xy, kw, stream, float(np.mean(djfa_ms)))
-    if args.with_readback:
-        out["readback"] = bench_readback(torch, V, args, W, H, xy, kw, stream, pd)
-    sj.close(), sd.close()
+    names = ["id", "xy"] if args.label == "both" else [args.label]
+    results = {name: measure_label(torch, V, args, wl, spec, xy, name) for name in names}
+    if args.save_tuning and not args.load_tuning and not args.no_tune:
+        V.save_tuning(args.save_tuning)
+    # the label format is chosen by measurement: the line reports the faster one
+    chosen = max(names, key=lambda n: results[n]["value"])
+    out = dict(results[chosen])
+    out["config"] = dict(out["config"], label=chosen,
+                         label_choice="measured: the faster of " + " and ".join(names))
+    if len(names) > 1:
+        out["labels"] = {n: {k: results[n][k] for k in
+                             ("value", "ms_per_step", "jfa", "djfa", "move_ms_per_step",
+                              "speedup_djfa_vs_jfa", "similarity_djfa_vs_jfa",
+                              "similarity_exact", "roofline", "tuning")}
+                         for n in names}
+    if not args.no_similarity_configs and args.workload == "large":
+        # dJFA similarity against the exact diagram per workload (Sec. VI-A):
+        # the two smaller workloads at their full lengths, default kernels
+        out["similarity_per_config"] = [
+            similarity_run(torch, V, inputs.WORKLOADS[w](), n)
+            for w in ("small", "single") for n in names]
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(spec, xy, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(args, xy if args.workload == "large" else None)
     print(json.dumps(out), flush=True)
 
 

@@ -300,6 +300,10 @@ int vd_tuning_export(char *buf, size_t cap, size_t *needed);
  * equal keys); simulations created afterwards use them. */
 int vd_tuning_import(const char *text);
 
+/* Empties the process-wide tuning table (simulations that exist keep the
+ * choices they made; later ones start from the defaults). */
+int vd_tuning_clear(void);
+
 /* Releases the handle (never the caller's workspace).  Waits for the
  * simulation's pending work.  NULL is ignored, and so is a simulation that
  * still belongs to a batch (destroy the batch first). */

@@ -791,6 +791,14 @@ int vd_tuning_import(const char *text)
     return VD_OK;
 }
 
+int vd_tuning_clear(void)
+{
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tune.clear();
+    g_tune_us.clear();
+    return VD_OK;
+}
+
 int vd_get_tuning(const vd_sim *s, int32_t *variants, int32_t *seg_rows, int32_t cap)
 {
     if (!s) return fail(VD_EINVAL, "sim is NULL");

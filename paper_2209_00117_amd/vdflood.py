@@ -103,6 +103,7 @@ SIGNATURES = {
     "vd_get_tuning_us": (ctypes.c_int, [_P, _P, ctypes.c_int32]),
     "vd_tuning_export": (ctypes.c_int, [_P, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]),
     "vd_tuning_import": (ctypes.c_int, [ctypes.c_char_p]),
+    "vd_tuning_clear": (ctypes.c_int, []),
 }
 
 STEP_JFA, STEP_DJFA = 0, 1
@@ -340,6 +341,10 @@ def tuning_export() -> dict:
 def tuning_import(table: dict):
     text = "".join(f"{k}|{v[0]}|{v[1]}\n" for k, v in table.items())
     _check(lib().vd_tuning_import(text.encode()))
+
+
+def tuning_clear():
+    _check(lib().vd_tuning_clear())
 
 
 def save_tuning(path: str):

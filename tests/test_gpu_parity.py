@@ -41,7 +41,7 @@ def _seed_pixels_ok(m, xy, label_mode):
 
 
 def run_twin(V, W, H, xy, steps, lo, hi, sim_seed=1, label=0, metric=0, vn=2, extra=0,
-             dmax=0, tag="", variant=None, fuse=None, tune=False):
+             dmax=0, tag="", variant=None, fuse=None, tune=False, tune_reps=1):
     """Runs a JFA and a dJFA simulation side by side on the GPU and in the
     oracle; asserts equal positions and maps at every step.  `variant` runs
     every pass on one kernel variant; the step's last passes are then fused
@@ -57,7 +57,7 @@ def run_twin(V, W, H, xy, steps, lo, hi, sim_seed=1, label=0, metric=0, vn=2, ex
               extra_passes=extra, dmax_override=dmax, sim_seed=sim_seed)
     gj = V.Sim(W, H, xy, **kw)
     if tune:
-        V.autotune(gj.handle, 1)
+        V.autotune(gj.handle, tune_reps)
     gd = V.Sim(W, H, xy, **kw)
     if tune:
         assert V.get_tuning(gd.handle) == V.get_tuning(gj.handle)
@@ -210,12 +210,12 @@ def test_dmax_override(V):
     run_twin(V, 512, 512, xy, 3, -1, 1, dmax=40, tag="dmax")
 
 
-def _full_size(V, spec, steps, label=0, tune=False):
+def _full_size(V, spec, steps, label=0, tune=False, tune_reps=1):
     """A full-size workload for a few steps; positions and maps compared in
     full against the threaded oracle."""
     return run_twin(V, spec.width, spec.height, spec.positions(), steps, spec.disp_lo,
                     spec.disp_hi, sim_seed=spec.sim_seed, label=label,
-                    tag=f"{spec.width}x{spec.height}", tune=tune)
+                    tag=f"{spec.width}x{spec.height}", tune=tune, tune_reps=tune_reps)
 
 
 def test_single_full_size(V):
@@ -231,12 +231,63 @@ def test_band_full_size(V, label):
     _full_size(V, inputs.band().sims[0], 2, label=label, tune=True)
 
 
-def test_large_full_size(V):
-    _full_size(V, inputs.large().sims[0], 1)
+@pytest.mark.parametrize("label", [0, 1])
+def test_large_full_size(V, label):
+    """The 8192^2 workload (2^20 seeds, moves in [-4, 4]) for two steps with
+    the kernels bench.py times there: autotuned with its repetitions."""
+    _full_size(V, inputs.large().sims[0], 2, label=label, tune=True, tune_reps=3)
 
 
-def test_large_full_size_xy(V):
-    _full_size(V, inputs.large().sims[0], 1, label=1)
+def _arch():
+    import torch
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+
+
+@pytest.mark.parametrize("label", [0, 1])
+def test_large_every_kernel(V, label):
+    """Every choice the autotuner has at the 8192^2 workload's full size --
+    kernel variants 0-11 x segment lengths (automatic, 8, 16, 64 rows) -- on
+    real passes: ten runs, each giving the passes of VD_0 and of one JFA and
+    one dJFA step other choices by a cyclic rotation (injected as a tuning
+    table), so that every choice runs on JFA passes at two or more k and on
+    at least one dJFA pass; maps compared in full with the oracle."""
+    spec = inputs.large().sims[0]
+    W, H, S = spec.width, spec.height, spec.num_seeds
+    xy = spec.positions()
+    print(f"[parity] every-kernel {W}x{H} S={S} label={label}", flush=True)
+    oj = O.Sim(W, H, xy, spec.sim_seed, spec.disp_lo, spec.disp_hi, label_mode=label)
+    od = O.Sim(W, H, xy, spec.sim_seed, spec.disp_lo, spec.disp_hi, label_mode=label)
+    map0 = oj.map.copy()
+    oj.move(), od.move()
+    oj.jfa_step(), od.djfa_step()
+    jfa_k = [k for k, _ in O.schedule(W, H, S, False)]
+    djfa = O.schedule(W, H, S, True, od.dmax)
+    choices = [(v, r) for v in range(12) for r in (0, 8, 16, 64)]
+    arch, lab = _arch(), ("xy" if label else "id")
+    kw = dict(disp_lo=spec.disp_lo, disp_hi=spec.disp_hi, sim_seed=spec.sim_seed, label=label)
+    try:
+        for run in range(10):
+            table = {}
+            for i, k in enumerate(jfa_k):
+                c = choices[(run * len(jfa_k) + i) % len(choices)]
+                table[f"{arch} {W}x{H} S{S} {lab} euclid k{k} moore jfa"] = list(c)
+            for j, (k, nb) in enumerate(djfa):
+                c = choices[(run * len(djfa) + j) % len(choices)]
+                table[f"{arch} {W}x{H} S{S} {lab} euclid k{k} {'vn' if nb else 'moore'} djfa"] = \
+                    list(c)
+            V.tuning_import(table)
+            gj, gd = V.Sim(W, H, xy, **kw), V.Sim(W, H, xy, **kw)
+            want = [tuple(table[key]) for key in table]
+            assert V.get_tuning(gd.handle) == want, f"run {run}: table not adopted"
+            assert np.array_equal(gj.read_map(), map0), f"run {run}: VD_0 differs"
+            gj.move_seeds(), gd.move_seeds()
+            gj.jfa_step(), gd.djfa_step()
+            nj = int((gj.read_map() != oj.map).sum())
+            nd = int((gd.read_map() != od.map).sum())
+            gj.close(), gd.close()
+            assert nj == 0 and nd == 0, f"run {run}: JFA differs on {nj}, dJFA on {nd} pixels"
+    finally:
+        V.tuning_clear()
 
 
 @pytest.mark.parametrize("label", [0, 1])
