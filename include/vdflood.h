@@ -120,6 +120,38 @@ void vd_config_default(vd_config *cfg);
  * Returns 0 if cfg is invalid. */
 size_t vd_footprint_bytes(const vd_config *cfg);
 
+/* Bytes of the fixed device array vd_jfa_noalloc takes its scratch from
+ * (one array per GPU, held from the library's first use of that GPU until
+ * the process ends): 72 MiB. */
+#define VD_NOALLOC_SCRATCH_BYTES (72u << 20)
+
+/* For callers that cannot allocate device memory -- code under HIP graph
+ * capture, serving loops (hipMalloc and hipFree can stall every stream of
+ * the device), harnesses that forbid allocation: the diagram vd_init_sim
+ * computes as VD_0 (a full JFA step on the given positions: Sec. III,
+ * Table I, Eq. (2)), written straight into caller memory, with no
+ * simulation, no workspace and no allocation.  The library's scratch (the
+ * seed table, 4 B per seed plus the sentinel entry, 1 B per seed of state,
+ * and the second ping-pong map, 4 B per pixel, each part 256-B aligned)
+ * comes from a fixed device array of VD_NOALLOC_SCRATCH_BYTES, so
+ * width*height is limited to about 18.8 M pixels (4096 x 4096 with up to
+ * 2^20 seeds); a larger request returns VD_EINVAL and launches nothing.
+ *  cfg:     width, height, num_seeds, label, metric and extra_passes are
+ *           used (validated as by vd_init_sim); the rest is ignored.
+ *  dev_xy:  device memory, 2*num_seeds int32: (x, y) of seed i at [2i],
+ *           [2i+1].  A seed off the grid takes no part (its label never
+ *           appears); positions need not be distinct.
+ *  dev_map: device memory, width*height int32, row-major; receives the
+ *           labels in vd_read_map's encoding.  Must not overlap dev_xy.
+ *  hip_stream: hipStream_t the work is queued on (NULL: default stream).
+ * Asynchronous: returns once the work is queued.  Every call on one GPU
+ * shares that GPU's scratch array, so calls whose work overlaps on one GPU
+ * (on different streams or threads, without ordering between them) race;
+ * calls on one stream are ordered.  The first call on a device resolves
+ * the array's address there (hipGetSymbolAddress). */
+int vd_jfa_noalloc(const vd_config *cfg, const int32_t *dev_xy, int32_t *dev_map,
+                   void *hip_stream);
+
 /* Creates a simulation (Sec. IV: the diagram VD and the seed set S are the
  * state carried across time steps) and computes VD_0 by a full JFA on the
  * initial positions; t = 0.

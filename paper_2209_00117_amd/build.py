@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvdflood.so")
-SOURCES = ["vd_kernels.hip", "vd_runtime.hip", "vd_batch.hip", "vd_server.hip"]
+SOURCES = ["vd_kernels.hip", "vd_runtime.hip", "vd_batch.hip", "vd_server.hip",
+           "vd_noalloc.hip"]
 ARCH = "gfx950"
 
 

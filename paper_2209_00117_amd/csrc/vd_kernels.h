@@ -70,6 +70,11 @@ hipError_t launch_move(uint32_t *table, int32_t S, int32_t W, int32_t H, uint64_
 hipError_t launch_set_seeds(uint32_t *table, const uint32_t *staged, int32_t S,
                             const uint8_t *state, uint32_t *parked, uint32_t *disp, hipStream_t s);
 
+// Seed table (S + 1 entries, sentinel first) and state bytes (S) from S
+// (x, y) int32 pairs in device memory; seeds off the grid take no part.
+hipError_t launch_pack_positions(uint32_t *table, uint8_t *state, const int32_t *xy, int32_t S,
+                                 int32_t W, int32_t H, hipStream_t s);
+
 // Inserted seeds: n (index, packed position) pairs staged in device memory.
 hipError_t launch_place(uint32_t *table, const uint32_t *staged, int32_t n, hipStream_t s);
 

@@ -165,6 +165,26 @@ __global__ void __launch_bounds__(kBlock) k_place(uint32_t *__restrict__ table,
     if (j < n) table[staged[2 * j] + 1] = staged[2 * j + 1];
 }
 
+// Seed table and seed-set bytes from caller positions (x, y int32 pairs in
+// device memory): entry 0 is the sentinel and entry i + 1 seed i's packed
+// position; a seed off the grid gets the sentinel and state 0, so it takes
+// no part (it is never splatted, and no pixel ever carries its label).
+__global__ void __launch_bounds__(kBlock) k_pack_positions(uint32_t *__restrict__ table,
+                                                           uint8_t *__restrict__ state,
+                                                           const int32_t *__restrict__ xy,
+                                                           int32_t S, int32_t W, int32_t H)
+{
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) table[0] = 0u;
+    if (i < S) {
+        const int32_t x = xy[2 * i], y = xy[2 * i + 1];
+        const bool in = x >= 0 && x < W && y >= 0 && y < H;
+        table[i + 1] = in ? ((uint32_t)(y + (int32_t)kOff) << 16) | (uint32_t)(x + (int32_t)kOff)
+                          : 0u;
+        state[i] = in ? (uint8_t)(kPresent | kKept) : (uint8_t)0;
+    }
+}
+
 // Removed seeds (ID labels): the position moves to `parked` and the table
 // entry becomes the sentinel position, so every flood pass finds the seed's
 // labels farther than any present seed's -- exactly as if they were
@@ -543,6 +563,13 @@ hipError_t launch_set_seeds(uint32_t *table, const uint32_t *staged, int32_t S,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || !disp) return e;
     hipLaunchKernelGGL(k_disp_acc, dim3(1), dim3(64), 0, s, disp);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_positions(uint32_t *table, uint8_t *state, const int32_t *xy, int32_t S,
+                                 int32_t W, int32_t H, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pack_positions, grid1d(S), dim3(kBlock), 0, s, table, state, xy, S, W, H);
     return hipGetLastError();
 }
 

@@ -45,6 +45,10 @@ constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
+}  // namespace
+
+namespace vd {
+
 // Eq. (2): k1 = 2^(ceil(log2 N) - 1), N = max(W, H); 0 for a 1-pixel grid.
 int32_t first_k(int32_t W, int32_t H)
 {
@@ -100,6 +104,41 @@ int32_t default_tail_th(const vd_config &c, bool)
     return px <= ((int64_t)1 << 19) ? 16 : 24;
 }
 
+int validate(const vd_config *c)
+{
+    if (!c) return fail(VD_EINVAL, "config is NULL");
+    if (c->width < 1 || c->width > VD_MAX_SIDE || c->height < 1 || c->height > VD_MAX_SIDE)
+        return fail(VD_EINVAL, "width and height must be in [1, %d], got %d x %d", VD_MAX_SIDE,
+                    c->width, c->height);
+    if (c->num_seeds < 1 || (int64_t)c->num_seeds > (int64_t)c->width * c->height)
+        return fail(VD_EINVAL, "num_seeds must be in [1, width*height], got %d", c->num_seeds);
+    if (c->disp_lo > c->disp_hi || c->disp_lo < -VD_MAX_SIDE || c->disp_hi > VD_MAX_SIDE)
+        return fail(VD_EINVAL, "need -%d <= disp_lo <= disp_hi <= %d, got [%d, %d]", VD_MAX_SIDE,
+                    VD_MAX_SIDE, c->disp_lo, c->disp_hi);
+    if (c->label != VD_LABEL_ID32 && c->label != VD_LABEL_XY16)
+        return fail(VD_EINVAL, "unknown label mode %d", c->label);
+    if (c->metric != VD_EUCLID && c->metric != VD_MANHATTAN)
+        return fail(VD_EINVAL, "unknown metric %d", c->metric);
+    if (c->vn_passes < 0 || c->vn_passes > 64)
+        return fail(VD_EINVAL, "vn_passes must be in [0, 64], got %d", c->vn_passes);
+    if (c->extra_passes < 0 || c->extra_passes > VD_MAX_EXTRA_PASSES)
+        return fail(VD_EINVAL, "extra_passes must be 0, 1 or 2, got %d", c->extra_passes);
+    if (c->dmax_override > 2 * VD_MAX_SIDE || c->dmax_override < VD_DMAX_MEASURED)
+        return fail(VD_EINVAL, "dmax_override must be in [%d, %d], got %d", VD_DMAX_MEASURED,
+                    2 * VD_MAX_SIDE, c->dmax_override);
+    return VD_OK;
+}
+
+}  // namespace vd
+
+using vd::first_k;
+using vd::first_delta;
+using vd::default_variant;
+using vd::default_tail_th;
+using vd::validate;
+
+namespace {
+
 constexpr int32_t kTailHeights[] = {16, 24, 32};
 
 void set_default_variants(vd_sim *s)
@@ -133,31 +172,6 @@ uint64_t mix64(uint64_t z)
     z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
     z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
     return z ^ (z >> 31);
-}
-
-int validate(const vd_config *c)
-{
-    if (!c) return fail(VD_EINVAL, "config is NULL");
-    if (c->width < 1 || c->width > VD_MAX_SIDE || c->height < 1 || c->height > VD_MAX_SIDE)
-        return fail(VD_EINVAL, "width and height must be in [1, %d], got %d x %d", VD_MAX_SIDE,
-                    c->width, c->height);
-    if (c->num_seeds < 1 || (int64_t)c->num_seeds > (int64_t)c->width * c->height)
-        return fail(VD_EINVAL, "num_seeds must be in [1, width*height], got %d", c->num_seeds);
-    if (c->disp_lo > c->disp_hi || c->disp_lo < -VD_MAX_SIDE || c->disp_hi > VD_MAX_SIDE)
-        return fail(VD_EINVAL, "need -%d <= disp_lo <= disp_hi <= %d, got [%d, %d]", VD_MAX_SIDE,
-                    VD_MAX_SIDE, c->disp_lo, c->disp_hi);
-    if (c->label != VD_LABEL_ID32 && c->label != VD_LABEL_XY16)
-        return fail(VD_EINVAL, "unknown label mode %d", c->label);
-    if (c->metric != VD_EUCLID && c->metric != VD_MANHATTAN)
-        return fail(VD_EINVAL, "unknown metric %d", c->metric);
-    if (c->vn_passes < 0 || c->vn_passes > 64)
-        return fail(VD_EINVAL, "vn_passes must be in [0, 64], got %d", c->vn_passes);
-    if (c->extra_passes < 0 || c->extra_passes > VD_MAX_EXTRA_PASSES)
-        return fail(VD_EINVAL, "extra_passes must be 0, 1 or 2, got %d", c->extra_passes);
-    if (c->dmax_override > 2 * VD_MAX_SIDE || c->dmax_override < VD_DMAX_MEASURED)
-        return fail(VD_EINVAL, "dmax_override must be in [%d, %d], got %d", VD_DMAX_MEASURED,
-                    2 * VD_MAX_SIDE, c->dmax_override);
-    return VD_OK;
 }
 
 size_t footprint(const vd_config *c)

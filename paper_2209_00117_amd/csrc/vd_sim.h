@@ -27,6 +27,17 @@ struct EventPair {
 // Sets this thread's vd_last_error() message; returns status.
 int fail(int status, const char *fmt, ...);
 
+// Eq. (2): the first JFA step k1 (0 for a 1-pixel grid).
+int32_t first_k(int32_t W, int32_t H);
+// Eq. (5): the first dJFA step delta_1, capped at k1.
+int32_t first_delta(int32_t W, int32_t H, int32_t S, int32_t dmax);
+// Kernel variant of a pass and tile height of fused last passes before any
+// tuning (both change speed only).
+int32_t default_variant(const vd_config &c, bool dynamic, int32_t k);
+int32_t default_tail_th(const vd_config &c, bool dynamic);
+// Checks a configuration; sets the error message and returns VD_EINVAL.
+int validate(const vd_config *c);
+
 // Number of trailing passes that can run as one fused launch: the longest
 // suffix of steps 1, 2 or 4 summing to at most kTailHalo, at most
 // kTailMaxPasses long; 0 if shorter than two.

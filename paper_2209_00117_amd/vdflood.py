@@ -66,6 +66,7 @@ SIGNATURES = {
     "vd_init_sim": (ctypes.c_int, [ctypes.POINTER(Config), _P, _P, ctypes.c_size_t, _P,
                                    ctypes.POINTER(_P)]),
     "vd_move_seeds": (ctypes.c_int, [_P]),
+    "vd_jfa_noalloc": (ctypes.c_int, [ctypes.POINTER(Config), _P, _P, _P]),
     "vd_set_seeds": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
     "vd_remove_seeds": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
     "vd_set_tail_fusion": (ctypes.c_int, [_P, ctypes.c_int]),
@@ -183,6 +184,17 @@ def _stream_ptr(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+NOALLOC_SCRATCH_BYTES = 72 << 20
+
+
+def jfa_noalloc(cfg: Config, dev_xy: int, dev_map: int, stream=None):
+    """vd_jfa_noalloc: the JFA diagram of the (x, y) int32 pairs at device
+    address dev_xy into the width*height int32 map at device address
+    dev_map (vd_read_map's encoding), queued on the stream; no allocation."""
+    _check(lib().vd_jfa_noalloc(ctypes.byref(cfg), ctypes.c_void_p(dev_xy),
+                                ctypes.c_void_p(dev_map), _stream_ptr(stream)))
 
 
 def init_sim(cfg: Config, xy: np.ndarray, workspace, stream=None) -> ctypes.c_void_p:
