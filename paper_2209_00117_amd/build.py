@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libvdflood.so")
 SOURCES = ["vd_kernels.hip", "vd_runtime.hip", "vd_batch.hip", "vd_server.hip",
-           "vd_noalloc.hip"]
+           "vd_noalloc.hip", "vd_relabel.hip"]
 ARCH = "gfx950"
 
 

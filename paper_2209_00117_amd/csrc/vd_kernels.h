@@ -50,6 +50,10 @@ hipError_t launch_splat_id(uint32_t *map, const uint32_t *table, int32_t S, int3
                            const uint8_t *state, hipStream_t s);
 hipError_t launch_splat_xy(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
                            const uint8_t *state, hipStream_t s);
+// The same with the top bit set (a seed pixel of this step, which a first
+// pass reading through the old-position index takes as it is).
+hipError_t launch_splat_xy_marked(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
+                                  const uint8_t *state, hipStream_t s);
 // The ID splat on a map filled with all ones (a JFA step's start): the
 // atomic minimum alone.  All ones is no label: it indexes past the seed
 // table, whose answer is the sentinel position, so the flood passes treat
@@ -162,6 +166,19 @@ constexpr int kFloodVariants = 12;
 hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *table, int32_t S,
                         int32_t W, int32_t H, int32_t k, int32_t vn, int32_t label,
                         int32_t metric, int32_t variant, int32_t seg_rows, hipStream_t s);
+
+// The first pass of an XY-label dJFA step, reading the previous diagram
+// through the old-position index instead of after a relabel pass: src holds
+// old positions (and this step's seed pixels, marked with the top bit by
+// launch_splat_xy_marked), idx is the index launch_index_old built (a
+// width*height map of its own).  dst equals the pass run on the relabelled
+// and splatted map.  Available where relabel_fold_ok(W, k) holds (width a
+// multiple of 4, k a multiple of 4 up to kMaxQuadLdsStep); `variant` picks
+// the rows in flight and the store policy as for launch_flood.
+bool relabel_fold_ok(int32_t W, int32_t k);
+hipError_t launch_flood_relabel(const uint32_t *src, uint32_t *dst, const uint32_t *idx,
+                                int32_t W, int32_t H, int32_t k, int32_t vn, int32_t metric,
+                                int32_t variant, int32_t seg_rows, hipStream_t s);
 
 // The last n passes of a step in one launch (tiles in LDS, see vd_tail.h):
 // steps ks[0..n) (each 1, 2 or 4, in pass order, summing to at most

@@ -76,15 +76,17 @@ __global__ void __launch_bounds__(kBlock) k_splat_min(uint32_t *__restrict__ map
         atomicMin(&map[pixel_of(table[i + 1], W)], (uint32_t)(i + 1));
 }
 
+// `mark` is or-ed into the written position (0, or the top bit).
 __global__ void __launch_bounds__(kBlock) k_splat_xy(uint32_t *__restrict__ map,
                                                      const uint32_t *__restrict__ table,
                                                      int32_t S, int32_t W,
-                                                     const uint8_t *__restrict__ state)
+                                                     const uint8_t *__restrict__ state,
+                                                     uint32_t mark)
 {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < S && takes_part(state, i, kPresent)) {
         uint32_t p = table[i + 1];
-        map[pixel_of(p, W)] = p;
+        map[pixel_of(p, W)] = p | mark;
     }
 }
 
@@ -373,17 +375,21 @@ __global__ void __launch_bounds__(kBlock) k_relabel(uint32_t *__restrict__ map,
     }
 }
 
-// k_relabel for widths divisible by 4: each lane relabels four adjacent
-// pixels per row (16-byte loads and stores) and walks a strip of 1024
-// columns down `rows` rows, so the pixels of one Voronoi cell -- which carry
-// one label -- are handled by one workgroup close in time.  A pixel whose
-// label equals its left neighbour's, or (for the first of the four) the
-// label of the same column one row up, reuses that result; the gather of a
-// reusing lane goes to an index past the map, which the hardware answers
-// without a memory access.
-__global__ void __launch_bounds__(kBlock) k_relabel4(uint32_t *__restrict__ map,
-                                                     const uint32_t *__restrict__ idx,
-                                                     int32_t W, int32_t H, int32_t rows)
+// k_relabel for widths divisible by 4, pipelined: each lane relabels four
+// adjacent pixels in each of kRelabelRows rows at once -- all their label
+// loads are requested, then all their gathers, then the results stored --
+// so the gathers of eight rows are in flight together instead of one row's.
+// A pixel whose label equals its left neighbour's in the group reuses that
+// result (its gather goes to an offset past the map, which the hardware
+// answers without a memory access); rows are independent of each other.
+// A workgroup covers 1024 columns of `rows` rows (a multiple of
+// kRelabelRows), where old positions -- near the pixels that carry them --
+// fall in a few lines of the index that neighbouring rows share in L2.
+constexpr int kRelabelRows = 8;
+
+__global__ void __launch_bounds__(kBlock) k_relabel_deep(uint32_t *__restrict__ map,
+                                                         const uint32_t *__restrict__ idx,
+                                                         int32_t W, int32_t H, int32_t rows)
 {
     const int32_t strips = (W + kTWQ - 1) / kTWQ;
     const int32_t strip = (int32_t)blockIdx.x % strips;
@@ -393,32 +399,38 @@ __global__ void __launch_bounds__(kBlock) k_relabel4(uint32_t *__restrict__ map,
     const __amdgpu_buffer_rsrc_t ir = __builtin_amdgcn_make_buffer_rsrc(
         (void *)idx, 0, (int32_t)min((int64_t)W * H * 4, (int64_t)0x7FFFFFFF), kRsrcWord3);
     const int32_t base = (int32_t)((kOff << 16) | kOff);
-    uint32_t prev_l = kEmpty, prev_n = kEmpty;   // column x of the row above
-    // the next row's labels are requested before this row's gathers
-    u32x4 next = y0 < y1 ? load4(row_rsrc(map, y0, W, H), off) : u32x4{0u, 0u, 0u, 0u};
-    for (int32_t y = y0; y < y1; ++y) {
-        const u32x4 l = next;
-        next = load4(row_rsrc(map, y + 1 < y1 ? y + 1 : H, W, H), off);
-        u32x4 n;
-        uint32_t left_l = prev_l, left_n = prev_n;
+    for (int32_t y = y0; y < y1; y += kRelabelRows) {
+        u32x4 l[kRelabelRows], v[kRelabelRows];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const uint32_t le = l[e];
-            const int32_t lx = (int32_t)(le & 0xFFFFu) - (int32_t)kOff;
-            const int32_t ly = (int32_t)(le >> 16) - (int32_t)kOff;
-            const bool valid = le != kEmpty && lx >= 0 && lx < W && ly >= 0 && ly < H;
-            const bool reuse = le == left_l;
-            const int32_t at = (valid && !reuse) ? 4 * (ly * W + lx) : -1;
-            const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(ir, at, 0, 0);
-            // a position, not a leftover label nor the all-ones of "no kept seed"
-            const uint32_t np = valid ? ((int32_t)v >= base ? v : kEmpty) : kEmpty;
-            n[e] = reuse ? left_n : np;
-            left_l = le;
-            left_n = n[e];
+        for (int r = 0; r < kRelabelRows; ++r)   // rows past y1 read as unclaimed (size 0)
+            l[r] = load4(row_rsrc(map, y + r < y1 ? y + r : H, W, H), off);
+#pragma unroll
+        for (int r = 0; r < kRelabelRows; ++r) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t le = l[r][e];
+                const int32_t lx = (int32_t)(le & 0xFFFFu) - (int32_t)kOff;
+                const int32_t ly = (int32_t)(le >> 16) - (int32_t)kOff;
+                const bool valid = le != kEmpty && lx >= 0 && lx < W && ly >= 0 && ly < H;
+                const bool reuse = e > 0 && le == l[r][e > 0 ? e - 1 : 0];
+                const int32_t at = (valid && !reuse) ? 4 * (ly * W + lx) : -1;
+                v[r][e] = __builtin_amdgcn_raw_buffer_load_b32(ir, at, 0, 0);
+            }
         }
-        store4<0>(n, row_rsrc(map, y, W, H), off);
-        prev_l = l[0];
-        prev_n = n[0];
+#pragma unroll
+        for (int r = 0; r < kRelabelRows; ++r) {
+            u32x4 n;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t le = l[r][e];
+                const bool reuse = e > 0 && le == l[r][e > 0 ? e - 1 : 0];
+                // a position, not a leftover label nor the all-ones of "no kept seed"
+                // (label 0 and labels off the grid gathered nothing: 0)
+                const uint32_t np = (int32_t)v[r][e] >= base ? v[r][e] : kEmpty;
+                n[e] = reuse ? n[e > 0 ? e - 1 : 0] : np;
+            }
+            store4<0>(n, row_rsrc(map, y + r < y1 ? y + r : H, W, H), off);
+        }
     }
 }
 
@@ -476,7 +488,8 @@ __global__ void __launch_bounds__(kBlock) k_flood_quad_id(const uint32_t *__rest
 {
     using Q = typename std::conditional<WIDE, QuadRowWide, QuadRow>::type;
     __shared__ Q lds[2];
-    flood_quad_id_tile<METRIC, VN, KC, NS, ST>(src, dst, table_rsrc(table, S), W, H, k, g,
+    const TableLookup lk{table_rsrc(table, S)};
+    flood_quad_id_tile<METRIC, VN, KC, NS, ST>(src, dst, lk, W, H, k, g,
                                                xcd_logical(blockIdx.x, g.nblocks), lds);
 }
 
@@ -539,7 +552,15 @@ hipError_t launch_splat_id_over_ones(uint32_t *map, const uint32_t *table, int32
 hipError_t launch_splat_xy(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
                            const uint8_t *state, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_splat_xy, grid1d(S), dim3(kBlock), 0, s, map, table, S, W, state);
+    hipLaunchKernelGGL(k_splat_xy, grid1d(S), dim3(kBlock), 0, s, map, table, S, W, state, 0u);
+    return hipGetLastError();
+}
+
+hipError_t launch_splat_xy_marked(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
+                                  const uint8_t *state, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_splat_xy, grid1d(S), dim3(kBlock), 0, s, map, table, S, W, state,
+                       kMarked);
     return hipGetLastError();
 }
 
@@ -642,10 +663,10 @@ hipError_t launch_relabel(uint32_t *map, const uint32_t *idx, int32_t W, int32_t
                           hipStream_t s)
 {
     if (W % kQuad == 0) {
-        const int32_t rows = 16;
+        const int32_t rows = 4 * kRelabelRows;
         const int64_t blocks = (int64_t)((W + kTWQ - 1) / kTWQ) * ((H + rows - 1) / rows);
-        hipLaunchKernelGGL(k_relabel4, dim3((unsigned)blocks), dim3(kBlock), 0, s, map, idx, W,
-                           H, rows);
+        hipLaunchKernelGGL(k_relabel_deep, dim3((unsigned)blocks), dim3(kBlock), 0, s, map, idx,
+                           W, H, rows);
     } else {
         hipLaunchKernelGGL(k_relabel, grid1d((int64_t)W * H, 8192), dim3(kBlock), 0, s, map,
                            idx, W, H);

@@ -98,12 +98,21 @@ __device__ __forceinline__ void store4(u32x4 v, __amdgpu_buffer_rsrc_t r, int32_
     __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(i32x4, v), r, off, 0, ST);
 }
 
-// Seed positions of four ID labels, reusing those of the same columns k
-// rows up where the label repeats (see seed_pos).
+// Seed positions of four ID labels, reusing that of the left neighbour in
+// the group or of the same column k rows up where the label repeats (a
+// Voronoi cell spans several pixels of a row); only the other lanes send
+// the table an index (see seed_pos).
 __device__ __forceinline__ u32x4 seed_pos4(u32x4 l, const G4 &up, i32x4 tab)
 {
-    return u32x4{seed_pos(l[0], up.l[0], up.s[0], tab), seed_pos(l[1], up.l[1], up.s[1], tab),
-                 seed_pos(l[2], up.l[2], up.s[2], tab), seed_pos(l[3], up.l[3], up.s[3], tab)};
+    u32x4 r;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const bool left = e > 0 && l[e] == l[e > 0 ? e - 1 : 0];
+        const bool fresh = !left && l[e] != up.l[e];
+        const uint32_t v = vd_struct_buffer_load(tab, fresh ? (int32_t)l[e] : -1, 0, 0, 0);
+        r[e] = fresh ? v : (left ? r[e > 0 ? e - 1 : 0] : up.s[e]);
+    }
+    return r;
 }
 
 struct TileQ {
@@ -287,6 +296,66 @@ __device__ __forceinline__ void flood_quad_id_direct_tile(const uint32_t *src, u
     quad_walk<METRIC, VN, 0, NS, ST>(dst, W, H, k, tl, oc, request, fetch);
 }
 
+// How a shared-row tile finds the position of each label it loads.
+//
+// TableLookup: ID labels; the position comes from the seed table (entry 0,
+// the unclaimed label, is the sentinel), reused where the label repeats k
+// rows up.
+struct TableLookup {
+    i32x4 tab;
+    static constexpr bool kLabelIsPos = false;
+    __device__ __forceinline__ u32x4 pos4(u32x4 l, const G4 &up) const
+    {
+        return seed_pos4(l, up, tab);
+    }
+    __device__ __forceinline__ uint32_t pos1(uint32_t l) const
+    {
+        return vd_struct_buffer_load(tab, (int32_t)l, 0, 0, 0);
+    }
+};
+
+// RelabelLookup: the XY labels of the previous diagram, read by a dJFA
+// step's first pass.  A label is an old position, which stands for the
+// moved position of the lowest kept seed that sat there (the index map
+// holds it at the old position: a position, else a leftover label or all
+// ones for "no such seed", both below every position), or a seed pixel
+// claimed by this step's splat, marked with the top bit, which stands for
+// itself; 0 stays unclaimed.  The translated value is both the label and
+// the position.  Where the label repeats that of the left neighbour in the
+// group or k rows up, that result is reused, and the lane's gather goes to
+// an offset past the map, which the hardware answers without a memory
+// access.
+constexpr uint32_t kMarked = 0x80000000u;
+
+struct RelabelLookup {
+    __amdgpu_buffer_rsrc_t idx;
+    int32_t W;
+    static constexpr bool kLabelIsPos = true;
+    __device__ __forceinline__ uint32_t one(uint32_t l, bool fresh) const
+    {
+        const bool marked = (l & kMarked) != 0u;
+        const int32_t x = (int32_t)(l & 0xFFFFu) - (int32_t)kOff;
+        const int32_t y = (int32_t)(l >> 16) - (int32_t)kOff;
+        const int32_t at = (fresh && !marked && l != kEmpty) ? 4 * (y * W + x) : -1;
+        const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(idx, at, 0, 0);
+        const uint32_t moved = (int32_t)v >= (int32_t)((kOff << 16) | kOff) ? v : kEmpty;
+        return marked ? (l & ~kMarked) : moved;
+    }
+    __device__ __forceinline__ u32x4 pos4(u32x4 l, const G4 &up) const
+    {
+        u32x4 r;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const bool left = e > 0 && l[e] == l[e > 0 ? e - 1 : 0];
+            const bool fresh = !left && l[e] != up.l[e];
+            const uint32_t v = one(l[e], fresh);
+            r[e] = fresh ? v : (left ? r[e > 0 ? e - 1 : 0] : up.s[e]);
+        }
+        return r;
+    }
+    __device__ __forceinline__ uint32_t pos1(uint32_t l) const { return one(l, true); }
+};
+
 // Shared rows of the ID tile, in groups of four entries: entry e is column
 // x0 - h + e.  Labels and positions are kept apart so that a lane moves 16
 // contiguous bytes of each array per group.
@@ -306,11 +375,11 @@ using QuadRowWide = QuadRowT<kQuadLdsRowWide>;   // steps up to kMaxQuadLdsStep:
 // alternate, and the barrier of each exchange also orders the reuse of the
 // row written two exchanges earlier.  Callers must not let a previous use
 // of `lds` overlap the first exchange (a barrier between tiles suffices).
-template <int METRIC, int VN, int KC, int NS, int ST, class Q>
-__device__ __forceinline__ void flood_quad_id_tile(const uint32_t *src, uint32_t *dst, i32x4 tab,
-                                                   int32_t W, int32_t H, int32_t k,
-                                                   const FloodGrid &g, uint32_t logical,
-                                                   Q *lds)
+template <int METRIC, int VN, int KC, int NS, int ST, class Q, class LK>
+__device__ __forceinline__ void flood_quad_id_tile(const uint32_t *src, uint32_t *dst,
+                                                   const LK &lk, int32_t W, int32_t H,
+                                                   int32_t k, const FloodGrid &g,
+                                                   uint32_t logical, Q *lds)
 {
     const TileQ tl = decode_tile_q(logical, g, k, H);
     if (tl.j0 >= tl.jend) return;
@@ -346,14 +415,13 @@ __device__ __forceinline__ void flood_quad_id_tile(const uint32_t *src, uint32_t
         if (phase >= D) {
             Slot_ &n = ring[(slot + NS - D) % NS];
             const G4 &up1 = phase >= D + 1 ? ring[(slot + NS - D - 1) % NS].g1 : none;
-            n.g1.s = seed_pos4(n.g1.l, up1, tab);
+            n.g1.s = lk.pos4(n.g1.l, up1);
             // The few halo groups are looked up without reuse: their loads
             // then write the positions directly under the wave-uniform
             // branch, with no select that would wait for them there.
             if (wave2) {
 #pragma unroll
-                for (int e = 0; e < 4; ++e)
-                    n.g2.s[e] = vd_struct_buffer_load(tab, (int32_t)n.g2.l[e], 0, 0, 0);
+                for (int e = 0; e < 4; ++e) n.g2.s[e] = lk.pos1(n.g2.l[e]);
             }
         }
     };
@@ -361,22 +429,28 @@ __device__ __forceinline__ void flood_quad_id_tile(const uint32_t *src, uint32_t
         const Slot_ &q = ring[decltype(Slot)::value];
         Q *row = (Q *)((char *)lds + lds_sel);
         lds_sel ^= (uint32_t)sizeof(Q);
-        row->l[t] = q.g1.l;
+        if (!LK::kLabelIsPos) row->l[t] = q.g1.l;
         row->s[t] = q.g1.s;
         if (wave2) {
-            row->l[kBlock + t] = q.g2.l;
+            if (!LK::kLabelIsPos) row->l[kBlock + t] = q.g2.l;
             row->s[kBlock + t] = q.g2.s;
         }
         __syncthreads();
         // groups of columns x - h, x and x + h
         const int32_t ga = t, gb = t + h / kQuad, gc = t + 2 * (h / kQuad);
         Three th;
-        th.a.l = row->l[ga];
         th.a.s = row->s[ga];
-        th.b.l = row->l[gb];
         th.b.s = row->s[gb];
-        th.c.l = row->l[gc];
         th.c.s = row->s[gc];
+        if (LK::kLabelIsPos) {
+            th.a.l = th.a.s;
+            th.b.l = th.b.s;
+            th.c.l = th.c.s;
+        } else {
+            th.a.l = row->l[ga];
+            th.b.l = row->l[gb];
+            th.c.l = row->l[gc];
+        }
         return th;
     };
     quad_walk<METRIC, VN, KC, NS, ST>(dst, W, H, k, tl, oc, request, fetch);

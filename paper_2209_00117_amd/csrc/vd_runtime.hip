@@ -179,7 +179,7 @@ size_t footprint(const vd_config *c)
     size_t npix = (size_t)c->width * (size_t)c->height;
     size_t seeds = (size_t)c->num_seeds * 4;
     size_t b = 2 * align_up(npix * 4) + align_up(seeds + 4);   // + the sentinel entry
-    if (c->label == VD_LABEL_XY16) b += align_up(seeds + 4);
+    if (c->label == VD_LABEL_XY16) b += align_up(seeds + 4) + align_up(npix * 4);
     b += align_up(12);                     // step counters
     b += align_up((size_t)c->num_seeds);   // seed-set state bytes
     if (c->label == VD_LABEL_ID32) b += align_up(seeds);   // parked positions
@@ -235,15 +235,24 @@ int harvest(vd_sim *s)
 // short pass).
 // With th (a tile height) non-zero, the step's last passes (tail_len) run
 // as one launch with the store policy of the last pass.
-int launch_passes(vd_sim *s, const std::vector<Pass> &passes, int32_t th)
+// With relabel (an XY dJFA step's old-position index) non-null, the first
+// pass reads the previous diagram through it (launch_flood_relabel).
+int launch_passes(vd_sim *s, const std::vector<Pass> &passes, int32_t th,
+                  const uint32_t *relabel = nullptr)
 {
     const size_t m = th ? vd::tail_len(passes) : 0;
     const size_t n = passes.size() - m;
     for (size_t i = 0; i < n; ++i) {
         const Pass &p = passes[i];
-        VD_HIP(vd::launch_flood(s->map[s->cur], s->map[s->cur ^ 1], s->pos, s->cfg.num_seeds,
-                                s->cfg.width, s->cfg.height, p.k, p.vn, s->cfg.label,
-                                s->cfg.metric, p.variant, p.seg_rows, s->stream));
+        if (i == 0 && relabel)
+            VD_HIP(vd::launch_flood_relabel(s->map[s->cur], s->map[s->cur ^ 1], relabel,
+                                            s->cfg.width, s->cfg.height, p.k, p.vn,
+                                            s->cfg.metric, p.variant, p.seg_rows, s->stream));
+        else
+            VD_HIP(vd::launch_flood(s->map[s->cur], s->map[s->cur ^ 1], s->pos,
+                                    s->cfg.num_seeds, s->cfg.width, s->cfg.height, p.k, p.vn,
+                                    s->cfg.label, s->cfg.metric, p.variant, p.seg_rows,
+                                    s->stream));
         s->cur ^= 1;
     }
     if (m) {
@@ -262,13 +271,14 @@ int launch_passes(vd_sim *s, const std::vector<Pass> &passes, int32_t th)
     return VD_OK;
 }
 
-int run_passes(vd_sim *s, const std::vector<Pass> &passes, int32_t th)
+int run_passes(vd_sim *s, const std::vector<Pass> &passes, int32_t th,
+               const uint32_t *relabel = nullptr)
 {
     if (passes.empty()) return VD_OK;
     size_t slot = 0;
     int r = record(s, 0, true, &slot, (int)passes.size());
     if (r) return r;
-    r = launch_passes(s, passes, th);
+    r = launch_passes(s, passes, th, relabel);
     if (r) return r;
     r = record(s, 0, false, &slot);
     if (r) return r;
@@ -311,11 +321,33 @@ int jfa_prologue(vd_sim *s)
 // treat its labels like unclaimed pixels without touching the map; only a
 // slot removed and inserted again (whose entry is a live position) needs
 // its old labels purged.
-int djfa_prologue(vd_sim *s)
+// Whether an XY dJFA step translates the previous diagram's labels inside
+// its first flood pass (which then reads the map through the index) rather
+// than in a relabel pass of its own: where the four-column shared-row tile
+// runs that pass and it is not part of a fused tail.
+bool fold_for(const vd_sim *s, const std::vector<Pass> &passes, int32_t th)
+{
+    if (s->cfg.label != VD_LABEL_XY16 || !s->idx || passes.empty()) return false;
+    const size_t m = th ? vd::tail_len(passes) : 0;
+    if (m >= passes.size()) return false;
+    return vd::relabel_fold_ok(s->cfg.width, passes[0].k);
+}
+
+bool fold_relabel(const vd_sim *s) { return fold_for(s, s->djfa_passes, s->tail_th[1]); }
+
+int djfa_prologue(vd_sim *s, bool fold)
 {
     const vd_config &c = s->cfg;
     uint32_t *cur = s->map[s->cur];
-    if (c.label == VD_LABEL_XY16) {
+    if (c.label == VD_LABEL_XY16 && fold) {
+        // The index of old positions goes to its own map; the first pass
+        // reads the diagram through it.  This step's seed pixels are marked
+        // so that the first pass takes them as they are.
+        VD_HIP(vd::launch_index_old(s->idx, s->pos_map, s->pos, c.num_seeds, c.width,
+                                    seed_state(s), s->stream));
+        VD_HIP(vd::launch_splat_xy_marked(cur, s->pos, c.num_seeds, c.width, seed_state(s),
+                                          s->stream));
+    } else if (c.label == VD_LABEL_XY16) {
         // The idle ping-pong buffer serves as the old-position index; the
         // first flood pass overwrites it.
         uint32_t *idx = s->map[s->cur ^ 1];
@@ -352,8 +384,9 @@ int do_jfa(vd_sim *s)
 
 int do_djfa(vd_sim *s)
 {
-    int r = djfa_prologue(s);
-    if (r == VD_OK) r = run_passes(s, s->djfa_passes, s->tail_th[1]);
+    const bool fold = fold_relabel(s);
+    int r = djfa_prologue(s, fold);
+    if (r == VD_OK) r = run_passes(s, s->djfa_passes, s->tail_th[1], fold ? s->idx : nullptr);
     if (r == VD_OK) r = step_epilogue(s);
     return r;
 }
@@ -569,6 +602,9 @@ int vd_autotune(vd_sim *s, int32_t reps)
     // diagram).  Before each pass, every candidate runs on the pass's real
     // input (reading it, writing the idle buffer); the pass itself then
     // advances the replay.
+    // The replays run every pass with its own launch; an XY dJFA step's first
+    // pass then reads through the old-position index where it can.
+    const bool fold = fold_for(s, s->djfa_passes, 0);
     for (int dyn = 0; dyn < 2 && r == VD_OK; ++dyn) {
         if (dyn) {
             hip(hipMemcpyAsync(s->map[s->cur], save, npix * 4, hipMemcpyDeviceToDevice,
@@ -578,14 +614,20 @@ int vd_autotune(vd_sim *s, int32_t reps)
                                    s->stream), "restore");
         }
         if (r == VD_OK) {
-            int pr = dyn ? djfa_prologue(s) : jfa_prologue(s);
+            int pr = dyn ? djfa_prologue(s, fold) : jfa_prologue(s);
             if (pr) r = pr;
         }
+        size_t pass_i = 0;
         for (const Pass &p : dyn ? s->djfa_passes : s->jfa_passes) {
             if (r != VD_OK) break;
             std::string key = tune_key(arch, c, p, dyn != 0);
             bool fresh = std::find(keys.begin(), keys.end(), key) == keys.end();
+            const bool relabel = dyn && fold && pass_i++ == 0;
             auto launch = [&](int32_t variant, int32_t seg_rows) {
+                if (relabel)
+                    return vd::launch_flood_relabel(s->map[s->cur], s->map[s->cur ^ 1], s->idx,
+                                                    c.width, c.height, p.k, p.vn, c.metric,
+                                                    variant, seg_rows, s->stream);
                 return vd::launch_flood(s->map[s->cur], s->map[s->cur ^ 1], s->pos, c.num_seeds,
                                         c.width, c.height, p.k, p.vn, c.label, c.metric,
                                         variant, seg_rows, s->stream);
@@ -642,7 +684,7 @@ int vd_autotune(vd_sim *s, int32_t reps)
                 hip(hipMemcpyAsync(s->pos_map, save_pm, tab_bytes, hipMemcpyDeviceToDevice,
                                    s->stream), "restore");
             if (r == VD_OK) {
-                int pr = dyn ? djfa_prologue(s) : jfa_prologue(s);
+                int pr = dyn ? djfa_prologue(s, fold) : jfa_prologue(s);
                 if (pr) r = pr;
             }
             hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -651,14 +693,21 @@ int vd_autotune(vd_sim *s, int32_t reps)
             if (!hip(hipEventCreate(&e1), "hipEventCreate")) break;
             ev.push_back(e1);
             hip(hipEventRecord(e0, s->stream), "hipEventRecord");
+            bool first = true;
             for (const Pass &p : passes) {
                 if (r != VD_OK) break;
                 const Cand &c0 = picks[tune_key(arch, c, p, dyn != 0)];
                 const int32_t v = c0.variant + (policy ? kBase : 0);
-                if (hip(vd::launch_flood(s->map[s->cur], s->map[s->cur ^ 1], s->pos,
-                                         c.num_seeds, c.width, c.height, p.k, p.vn, c.label,
-                                         c.metric, v, c0.seg_rows, s->stream), "launch"))
-                    s->cur ^= 1;
+                const hipError_t le =
+                    dyn && fold && first
+                        ? vd::launch_flood_relabel(s->map[s->cur], s->map[s->cur ^ 1], s->idx,
+                                                   c.width, c.height, p.k, p.vn, c.metric, v,
+                                                   c0.seg_rows, s->stream)
+                        : vd::launch_flood(s->map[s->cur], s->map[s->cur ^ 1], s->pos,
+                                           c.num_seeds, c.width, c.height, p.k, p.vn, c.label,
+                                           c.metric, v, c0.seg_rows, s->stream);
+                first = false;
+                if (hip(le, "launch")) s->cur ^= 1;
             }
             hip(hipEventRecord(e1, s->stream), "hipEventRecord");
             float ms = 0.f;
@@ -690,8 +739,10 @@ int vd_autotune(vd_sim *s, int32_t reps)
             if (save_pm)
                 hip(hipMemcpyAsync(s->pos_map, save_pm, tab_bytes, hipMemcpyDeviceToDevice,
                                    s->stream), "restore");
+            const int32_t th = policy ? kTailHeights[policy - 1] : 0;
+            const bool fold_t = dyn && fold_for(s, passes, th);
             if (r == VD_OK) {
-                int pr = dyn ? djfa_prologue(s) : jfa_prologue(s);
+                int pr = dyn ? djfa_prologue(s, fold_t) : jfa_prologue(s);
                 if (pr) r = pr;
             }
             hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -701,7 +752,7 @@ int vd_autotune(vd_sim *s, int32_t reps)
             ev.push_back(e1);
             hip(hipEventRecord(e0, s->stream), "hipEventRecord");
             if (r == VD_OK) {
-                int lr = launch_passes(s, passes, policy ? kTailHeights[policy - 1] : 0);
+                int lr = launch_passes(s, passes, th, fold_t ? s->idx : nullptr);
                 if (lr) r = lr;
             }
             hip(hipEventRecord(e1, s->stream), "hipEventRecord");
@@ -890,6 +941,10 @@ int vd_init_sim(const vd_config *cfg, const int32_t *host_xy, void *dev_workspac
     base += align_up(npix * 4);
     s->map[1] = (uint32_t *)base;
     base += align_up(npix * 4);
+    if (cfg->label == VD_LABEL_XY16) {
+        s->idx = (uint32_t *)base;
+        base += align_up(npix * 4);
+    }
     s->pos = (uint32_t *)base;
     base += align_up((size_t)S * 4 + 4);
     if (cfg->label == VD_LABEL_XY16) {
