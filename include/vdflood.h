@@ -338,8 +338,9 @@ int vd_tuning_import(const char *text);
 int vd_tuning_clear(void);
 
 /* Releases the handle (never the caller's workspace).  Waits for the
- * simulation's pending work.  NULL is ignored, and so is a simulation that
- * still belongs to a batch (destroy the batch first). */
+ * simulation's pending work.  NULL is ignored.  A simulation that still
+ * belongs to a batch is only marked: vd_batch_destroy releases it, and its
+ * workspace must stay untouched until then. */
 void vd_destroy(vd_sim *sim);
 
 /* ---------------------------------------------------------------------- */
@@ -355,11 +356,13 @@ enum { VD_STEP_JFA = 0, VD_STEP_DJFA = 1 };
 size_t vd_batch_footprint_bytes(int32_t n);
 
 /* Groups n existing simulations so that vd_batch_step advances them all.
- * Members must use ID labels, one metric and the batch's hip_stream (the
- * stream they were created on); their own workspaces stay in use.  While a
- * simulation belongs to the batch, vd_move_seeds / vd_jfa_step /
- * vd_djfa_step on it return VD_ESTATE and vd_destroy ignores it; reads and
- * vd_get_info keep working.  dev_workspace (any alignment, at least
+ * Members (ID or XY labels, mixed as needed) must use one metric and the
+ * batch's hip_stream (the stream they were created on); their own
+ * workspaces stay in use.  While a simulation belongs to the batch,
+ * vd_move_seeds / vd_jfa_step / vd_djfa_step on it return VD_ESTATE, and
+ * vd_destroy only marks it: vd_batch_destroy then releases the handle (its
+ * workspace must stay untouched until then); reads and vd_get_info keep
+ * working.  dev_workspace (any alignment, at least
  * vd_batch_footprint_bytes(n) bytes) is owned by the caller and must stay
  * untouched until vd_batch_destroy.  The pointer array is copied. */
 int vd_batch_create(vd_sim *const *sims, int32_t n, void *dev_workspace, size_t ws_bytes,
@@ -438,16 +441,16 @@ typedef struct vd_server_stats {
  * max_sims simulations; simulations need vd_footprint_bytes each on top. */
 size_t vd_server_footprint_bytes(int32_t max_sims);
 
-/* Starts a server (and its scheduler thread) for up to max_sims ID-label
- * simulations of one metric.  dev_pool (pool_bytes, any alignment) is
+/* Starts a server (and its scheduler thread) for up to max_sims
+ * simulations (ID or XY labels) of one metric.  dev_pool (pool_bytes, any alignment) is
  * caller-owned device memory holding the server tables and every
  * simulation's workspace; it must outlive vd_server_destroy.  All device
  * work runs on hip_stream. */
 int vd_server_create(int32_t max_sims, int32_t metric, void *dev_pool, size_t pool_bytes,
                      void *hip_stream, vd_server **out);
 
-/* Registers a simulation (cfg as for vd_init_sim; label must be ID and the
- * metric the server's) and returns its id.  It becomes resident (workspace
+/* Registers a simulation (cfg as for vd_init_sim; the metric must be the
+ * server's) and returns its id.  It becomes resident (workspace
  * placed in the pool, VD_0 computed) as soon as its footprint fits;
  * simulations wait for memory in registration order.  host_xy is copied. */
 int vd_server_add_sim(vd_server *sv, const vd_config *cfg, const int32_t *host_xy,

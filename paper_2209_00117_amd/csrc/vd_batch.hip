@@ -3,9 +3,14 @@
 // One batch step advances every member simulation by one time step (move,
 // then a JFA or a dJFA step, Sec. III / Sec. V) with a fixed number of
 // launches, whatever the number of simulations:
-//   begin (clear work counters), move, fill (JFA only), splat x 2, then one
+//   begin (clear work counters), move, then the step's start as a lone
+//   simulation makes it -- JFA: fill (ID labels: all ones) and splat; dJFA:
+//   the compare-and-swap splat into the previous diagram, or for XY labels
+//   the old-position index, the relabel and the splat -- then one
 //   persistent flood launch per pass level, then end (advance t, flip the
-//   current-map index where the pass count is odd).
+//   current-map index where the pass count is odd; XY labels: the diagram
+//   now refers to the current positions).  The per-seed arithmetic is the
+//   single-simulation kernels' (vd_device.h), the relabel theirs too.
 // Level i runs pass i of every simulation that has one; the tiles of all of
 // them form one work list.  A fixed grid of workgroups (as many as fit on
 // the GPU at once) takes tiles from it until it is empty: each XCD first
@@ -26,7 +31,7 @@
 #include <new>
 #include <vector>
 
-#include "vd_device.h"
+#include "vd_multi.h"
 #include "vd_sim.h"
 
 namespace vd {
@@ -36,10 +41,12 @@ namespace {
 struct BatchSim {        // device copy of one member simulation
     uint32_t *map[2];
     uint32_t *table;
+    uint32_t *pos_map;   // XY labels: the positions the diagram refers to
+    uint32_t *idx;       // XY labels: the old-position index
     int32_t W, H, S;
     int32_t lo;          // move range [lo, lo + span)
     uint32_t span;
-    int32_t pad;
+    int32_t label;
     uint64_t move_seed;
 };
 
@@ -55,6 +62,8 @@ struct LevelSim {        // one simulation's pass at one level
     FloodGrid g;
     uint32_t first;      // index of its first item in the level's work list
     uint32_t per;        // tiles per item
+    int32_t quad;        // four-column tiles (item_grid)
+    int32_t pad;
 };
 
 struct LevelInfo {
@@ -84,49 +93,103 @@ __global__ void __launch_bounds__(kBlock) k_batch_begin(uint32_t *__restrict__ c
     for (int32_t i = threadIdx.x; i < n; i += blockDim.x) ctr[i] = 0u;
 }
 
+// Per-member kernels: blockIdx.y is the member, blockIdx.x strides over
+// its seeds (or its relabel blocks).
 __global__ void __launch_bounds__(kBlock) k_batch_move(const BatchSim *__restrict__ sims,
                                                        const DevState *__restrict__ st)
 {
     const BatchSim sm = sims[blockIdx.y];
     const uint64_t t = st[blockIdx.y].t + 1;
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < sm.S;
-         i += gridDim.x * blockDim.x) {
-        uint64_t n = ((t - 1) * (uint64_t)sm.S + (uint64_t)i) * 2u;
-        uint32_t p = sm.table[i + 1];
-        int32_t x = (int32_t)(p & 0xFFFFu) - (int32_t)kOff + draw(sm.move_seed, n + 0, sm.lo, sm.span);
-        int32_t y = (int32_t)(p >> 16) - (int32_t)kOff + draw(sm.move_seed, n + 1, sm.lo, sm.span);
-        x = min(max(x, 0), sm.W - 1);
-        y = min(max(y, 0), sm.H - 1);
-        sm.table[i + 1] = ((uint32_t)(y + (int32_t)kOff) << 16) | (uint32_t)(x + (int32_t)kOff);
-    }
+         i += gridDim.x * blockDim.x)
+        move_one(sm.table, i, sm.S, sm.W, sm.H, sm.move_seed, t, sm.lo, sm.span);
 }
 
+// A JFA step's map: unclaimed everywhere (ID labels: all ones, which the
+// atomic minimum of the splat needs no reset for).
 __global__ void __launch_bounds__(kBlock) k_batch_fill(const BatchSim *__restrict__ sims,
                                                        const DevState *__restrict__ st)
 {
     const BatchSim sm = sims[blockIdx.y];
     uint32_t *map = sm.map[st[blockIdx.y].cur];
+    const uint32_t v = sm.label == kLabelId ? 0xFFFFFFFFu : kEmpty;
     const int64_t n = (int64_t)sm.W * sm.H;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
-        map[i] = kEmpty;
+        map[i] = v;
 }
 
-// Seed pixels, lowest index where seeds coincide (as launch_splat_id).
-template <bool RESET>
-__global__ void __launch_bounds__(kBlock) k_batch_splat(const BatchSim *__restrict__ sims,
-                                                        const DevState *__restrict__ st)
+// Seed pixels of a JFA step (on the filled map).
+__global__ void __launch_bounds__(kBlock) k_batch_splat_jfa(const BatchSim *__restrict__ sims,
+                                                            const DevState *__restrict__ st)
 {
     const BatchSim sm = sims[blockIdx.y];
     uint32_t *map = sm.map[st[blockIdx.y].cur];
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < sm.S;
          i += gridDim.x * blockDim.x) {
-        uint32_t *px = &map[pixel_of(sm.table[i + 1], sm.W)];
-        if (RESET)
-            *px = 0xFFFFFFFFu;
+        if (sm.label == kLabelId)
+            splat_min_seed(map, sm.table, i, sm.W);
         else
-            atomicMin(px, (uint32_t)(i + 1));
+            splat_xy_seed(map, sm.table, i, sm.W, 0u);
     }
+}
+
+// A dJFA step's splat: ID labels into the previous diagram; XY labels the
+// first half of the old-position index (every seed claims its old pixel).
+__global__ void __launch_bounds__(kBlock) k_batch_splat_djfa(const BatchSim *__restrict__ sims,
+                                                             const DevState *__restrict__ st)
+{
+    const BatchSim sm = sims[blockIdx.y];
+    uint32_t *map = sm.map[st[blockIdx.y].cur];
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < sm.S;
+         i += gridDim.x * blockDim.x) {
+        if (sm.label == kLabelId)
+            splat_swap_seed(map, sm.table, sm.S, sm.W, i, nullptr, 0u);
+        else
+            splat_swap_seed(sm.idx, sm.pos_map, sm.S, sm.W, i, nullptr, 0u);
+    }
+}
+
+// XY labels, dJFA: the index resolved to the moved positions ...
+__global__ void __launch_bounds__(kBlock) k_batch_index(const BatchSim *__restrict__ sims)
+{
+    const BatchSim sm = sims[blockIdx.y];
+    if (sm.label != kLabelXy) return;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < sm.S;
+         i += gridDim.x * blockDim.x)
+        index_resolve_seed(sm.idx, sm.pos_map, sm.table, i, sm.W);
+}
+
+// ... every label relabelled through it (widths divisible by 4 with the
+// pipelined blocks, others one pixel per lane) ...
+__global__ void __launch_bounds__(kBlock) k_batch_relabel(const BatchSim *__restrict__ sims,
+                                                          const DevState *__restrict__ st)
+{
+    const BatchSim sm = sims[blockIdx.y];
+    if (sm.label != kLabelXy) return;
+    uint32_t *map = sm.map[st[blockIdx.y].cur];
+    if (sm.W % kQuad == 0) {
+        const int64_t nb = relabel_blocks(sm.W, sm.H);
+        for (int64_t b = blockIdx.x; b < nb; b += gridDim.x)
+            relabel_block(map, sm.idx, sm.W, sm.H, kRelabelBlockRows, (uint32_t)b);
+    } else {
+        const int64_t n = (int64_t)sm.W * sm.H;
+        for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+             p += (int64_t)gridDim.x * blockDim.x)
+            map[p] = relabel_one(map[p], sm.idx, sm.W, sm.H);
+    }
+}
+
+// ... and the seed pixels claimed.
+__global__ void __launch_bounds__(kBlock) k_batch_splat_xy(const BatchSim *__restrict__ sims,
+                                                           const DevState *__restrict__ st)
+{
+    const BatchSim sm = sims[blockIdx.y];
+    if (sm.label != kLabelXy) return;
+    uint32_t *map = sm.map[st[blockIdx.y].cur];
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < sm.S;
+         i += gridDim.x * blockDim.x)
+        splat_xy_seed(map, sm.table, i, sm.W, 0u);
 }
 
 __global__ void __launch_bounds__(kBlock) k_batch_end(DevState *__restrict__ st,
@@ -139,41 +202,33 @@ __global__ void __launch_bounds__(kBlock) k_batch_end(DevState *__restrict__ st,
     }
 }
 
-// Persistent flood pass of one level over every member simulation (ID
-// labels).  Each iteration takes one work item: one or more adjacent tiles
-// (256 columns of one chain segment) of one simulation, run by the same tile
-// functions as the single-simulation kernels (LDS-shared rows for k <= 128,
-// else the chain walk with rows requested two ahead).
-template <int METRIC>
-__global__ void __launch_bounds__(kTW) k_batch_flood(const BatchSim *__restrict__ sims,
-                                                     const DevState *__restrict__ st,
-                                                     const LevelSim *__restrict__ ls,
-                                                     const LevelInfo *__restrict__ info,
-                                                     int32_t n, int32_t level,
-                                                     uint32_t *__restrict__ ctr)
+// XY labels: the diagram now refers to the current positions.
+__global__ void __launch_bounds__(kBlock) k_batch_posmap(const BatchSim *__restrict__ sims)
 {
-    __shared__ uint2 lds[2][kLdsRow];
+    const BatchSim sm = sims[blockIdx.y];
+    if (sm.label != kLabelXy) return;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= sm.S;
+         i += gridDim.x * blockDim.x)
+        sm.pos_map[i] = sm.table[i];
+}
+
+// Persistent flood pass of one level over every member simulation.  Each
+// iteration takes one work item -- one or more adjacent tiles of one chain
+// segment of one simulation -- and runs it with the tile functions a lone
+// simulation's kernels use (member_tiles).
+template <int METRIC>
+__global__ void __launch_bounds__(kBlock) k_batch_flood(const BatchSim *__restrict__ sims,
+                                                        const DevState *__restrict__ st,
+                                                        const LevelSim *__restrict__ ls,
+                                                        const LevelInfo *__restrict__ info,
+                                                        int32_t n, int32_t level,
+                                                        uint32_t *__restrict__ ctr)
+{
+    __shared__ __align__(16) uint8_t lds[kMultiLds];
     __shared__ uint32_t s_item;
-    const uint32_t home = blockIdx.x & 7u;
-    uint32_t probe = 0;       // chunks already found empty
+    uint32_t probe = 0;   // chunks already found empty
     for (;;) {
-        __syncthreads();      // the previous tile's LDS reads are finished
-        if (threadIdx.x == 0) {
-            uint32_t item = 0xFFFFFFFFu;
-            while (probe < 8u) {
-                const uint32_t c = (home + probe) & 7u;
-                const uint32_t lo = info->chunk[c], hi = info->chunk[c + 1];
-                const uint32_t i = lo < hi ? atomicAdd(&ctr[c], 1u) : 0xFFFFFFFFu;
-                if (i < hi - lo) {
-                    item = lo + i;
-                    break;
-                }
-                ++probe;
-            }
-            s_item = item;
-        }
-        __syncthreads();
-        const uint32_t item = __builtin_amdgcn_readfirstlane(s_item);
+        const uint32_t item = claim_item(info->chunk, ctr, probe, &s_item);
         if (item == 0xFFFFFFFFu) return;
         // the last simulation whose first tile is <= item owns it (a
         // simulation without tiles shares its first with the next one).
@@ -187,35 +242,27 @@ __global__ void __launch_bounds__(kTW) k_batch_flood(const BatchSim *__restrict_
         }
         const LevelSim &lv = ls[a];
         const BatchSim &sm = sims[a];
-        const int32_t k = uni(lv.k), vn = uni(lv.vn);
-        FloodGrid g;
-        g.ncol = uni(lv.g.ncol);
-        g.nseg = uni(lv.g.nseg);
-        g.L = uni(lv.g.L);
-        g.nblocks = uni(lv.g.nblocks);
-        const int32_t W = uni(sm.W), H = uni(sm.H), S = uni(sm.S);
+        MemberPass mp;
+        mp.k = uni(lv.k);
+        mp.vn = uni(lv.vn);
+        mp.quad = uni(lv.quad);
+        mp.g.ncol = uni(lv.g.ncol);
+        mp.g.nseg = uni(lv.g.nseg);
+        mp.g.L = uni(lv.g.L);
+        mp.g.nblocks = uni(lv.g.nblocks);
+        mp.W = uni(sm.W);
+        mp.H = uni(sm.H);
+        mp.S = uni(sm.S);
+        mp.label = uni(sm.label);
         const int32_t c = uni(st[a].cur) ^ (level & 1);
         uint32_t *m0 = uni_ptr(sm.map[0]), *m1 = uni_ptr(sm.map[1]);
-        const uint32_t *src = c ? m1 : m0;
-        uint32_t *dst = c ? m0 : m1;
-        const i32x4 tab = table_rsrc(uni_ptr(sm.table), (uint32_t)S);
+        mp.src = c ? m1 : m0;
+        mp.dst = c ? m0 : m1;
+        mp.table = uni_ptr(sm.table);
         const uint32_t per = uni(lv.per);
         const uint32_t t0 = (item - uni(lv.first)) * per;
-        const uint32_t t1 = min(t0 + per, g.nblocks);
-        for (uint32_t tile = t0; tile < t1; ++tile) {
-            if (tile != t0) __syncthreads();   // LDS of the previous tile is free
-            if (k <= kMaxLdsStep) {
-                if (vn)
-                    flood_lds_tile<kLabelId, METRIC, 1, 2>(src, dst, tab, W, H, k, g, tile, lds);
-                else
-                    flood_lds_tile<kLabelId, METRIC, 0, 2>(src, dst, tab, W, H, k, g, tile, lds);
-            } else {
-                if (vn)
-                    flood_chain_tile<kLabelId, METRIC, 1, 2>(src, dst, tab, W, H, k, g, tile);
-                else
-                    flood_chain_tile<kLabelId, METRIC, 0, 2>(src, dst, tab, W, H, k, g, tile);
-            }
-        }
+        const uint32_t t1 = min(t0 + per, mp.g.nblocks);
+        member_tiles<METRIC>(mp, t0, t1, lds);
     }
 }
 
@@ -258,6 +305,7 @@ struct vd_batch {
     uint8_t *base = nullptr;      // aligned start of the device workspace
     vd::Layout lay{};
     int32_t metric = 0;
+    bool any_xy = false;          // a member has XY labels (their relabel and table copy run)
     int32_t levels[2] = {0, 0};   // pass levels of a JFA / dJFA step
     std::vector<int64_t> level_pixels[2];    // pixel-updates per level (timing)
     int32_t grid[2] = {0, 0};     // persistent flood workgroups per mode
@@ -361,11 +409,11 @@ hipError_t launch_level(vd_batch *b, int mode, int32_t lvl, int32_t parity_level
     const vd::LevelInfo *info = at<vd::LevelInfo>(b, b->lay.info[mode]) + lvl;
     uint32_t *ctr = at<uint32_t>(b, b->lay.ctr) + 8 * lvl;
     if (b->metric == VD_EUCLID)
-        hipLaunchKernelGGL(vd::k_batch_flood<vd::kEuclid>, dim3((unsigned)grid), dim3(vd::kTW),
-                           0, stream, sims, st, ls, info, n, parity_level, ctr);
+        hipLaunchKernelGGL(vd::k_batch_flood<vd::kEuclid>, dim3((unsigned)grid),
+                           dim3(vd::kBlock), 0, stream, sims, st, ls, info, n, parity_level, ctr);
     else
         hipLaunchKernelGGL(vd::k_batch_flood<vd::kManhattan>, dim3((unsigned)grid),
-                           dim3(vd::kTW), 0, stream, sims, st, ls, info, n, parity_level, ctr);
+                           dim3(vd::kBlock), 0, stream, sims, st, ls, info, n, parity_level, ctr);
     return hipGetLastError();
 }
 
@@ -444,13 +492,24 @@ int enqueue_step(vd_batch *b, int mode, int moved, hipStream_t stream)
         hipLaunchKernelGGL(vd::k_batch_fill, dim3(256, (unsigned)n), blk, 0, stream, sims,
                            (const vd::DevState *)st);
         VD_HIP(hipGetLastError());
+        hipLaunchKernelGGL(vd::k_batch_splat_jfa, gseeds, blk, 0, stream, sims,
+                           (const vd::DevState *)st);
+        VD_HIP(hipGetLastError());
+    } else {
+        hipLaunchKernelGGL(vd::k_batch_splat_djfa, gseeds, blk, 0, stream, sims,
+                           (const vd::DevState *)st);
+        VD_HIP(hipGetLastError());
+        if (b->any_xy) {
+            hipLaunchKernelGGL(vd::k_batch_index, gseeds, blk, 0, stream, sims);
+            VD_HIP(hipGetLastError());
+            hipLaunchKernelGGL(vd::k_batch_relabel, dim3(256, (unsigned)n), blk, 0, stream, sims,
+                               (const vd::DevState *)st);
+            VD_HIP(hipGetLastError());
+            hipLaunchKernelGGL(vd::k_batch_splat_xy, gseeds, blk, 0, stream, sims,
+                               (const vd::DevState *)st);
+            VD_HIP(hipGetLastError());
+        }
     }
-    hipLaunchKernelGGL(vd::k_batch_splat<true>, gseeds, blk, 0, stream, sims,
-                       (const vd::DevState *)st);
-    VD_HIP(hipGetLastError());
-    hipLaunchKernelGGL(vd::k_batch_splat<false>, gseeds, blk, 0, stream, sims,
-                       (const vd::DevState *)st);
-    VD_HIP(hipGetLastError());
     if (b->solo_passes[mode] > 0) {
         size_t slot = 0;
         int r = batch_record(b, 2 + 2 * vd::kMaxLevels + mode, true, &slot);
@@ -471,6 +530,10 @@ int enqueue_step(vd_batch *b, int mode, int moved, hipStream_t stream)
     hipLaunchKernelGGL(vd::k_batch_end, dim3(1), blk, 0, stream, st,
                        (const int32_t *)at<int32_t>(b, b->lay.npasses[mode]), n, moved);
     VD_HIP(hipGetLastError());
+    if (b->any_xy) {
+        hipLaunchKernelGGL(vd::k_batch_posmap, gseeds, blk, 0, stream, sims);
+        VD_HIP(hipGetLastError());
+    }
     return VD_OK;
 }
 
@@ -481,10 +544,10 @@ int query_fit(vd_batch *b)
     VD_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
     if (b->metric == VD_EUCLID)
         VD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &fit, vd::k_batch_flood<vd::kEuclid>, vd::kTW, 0));
+            &fit, vd::k_batch_flood<vd::kEuclid>, vd::kBlock, 0));
     else
         VD_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-            &fit, vd::k_batch_flood<vd::kManhattan>, vd::kTW, 0));
+            &fit, vd::k_batch_flood<vd::kManhattan>, vd::kBlock, 0));
     b->cus = std::max(cus, 1);
     b->fit = std::max(fit, 1);
     return VD_OK;
@@ -532,6 +595,9 @@ int build_tables(vd_batch *b)
         d.map[0] = s->map[0];
         d.map[1] = s->map[1];
         d.table = s->pos;
+        d.pos_map = s->pos_map;
+        d.idx = s->idx;
+        d.label = s->cfg.label;
         d.W = s->cfg.width;
         d.H = s->cfg.height;
         d.S = s->cfg.num_seeds;
@@ -575,6 +641,7 @@ int build_tables(vd_batch *b)
                     const vd::ItemGrid ig = vd::item_grid(s->cfg.width, s->cfg.height, e.k);
                     e.g = ig.g;
                     e.per = ig.per;
+                    e.quad = ig.quad;
                     if (ig.items == 0 || (uint64_t)first + ig.items > 0xFFFFFFF0ull)
                         return fail(VD_EINVAL, "level %d of the batch is too large", lvl);
                     first += ig.items;
@@ -641,8 +708,6 @@ int vd_batch_create(vd_sim *const *sims, int32_t n, void *dev_workspace, size_t 
         if (!s) return fail(VD_EINVAL, "simulation %d is NULL", i);
         if (s->batch) return fail(VD_ESTATE, "simulation %d already belongs to a batch", i);
         if (s->broken) return fail(VD_ESTATE, "simulation %d is unusable", i);
-        if (s->cfg.label != VD_LABEL_ID32)
-            return fail(VD_EINVAL, "batches take ID-label simulations (simulation %d)", i);
         if (s->cfg.metric != sims[0]->cfg.metric)
             return fail(VD_EINVAL, "all simulations of a batch share one metric");
         if (s->measured)
@@ -661,6 +726,7 @@ int vd_batch_create(vd_sim *const *sims, int32_t n, void *dev_workspace, size_t 
     b->stream = stream;
     b->lay = lay;
     b->metric = sims[0]->cfg.metric;
+    for (int32_t i = 0; i < n; ++i) b->any_xy = b->any_xy || sims[i]->cfg.label == VD_LABEL_XY16;
     b->base = (uint8_t *)(((uintptr_t)dev_workspace + 255) / 256 * 256);
 
     int r = build_tables(b);
@@ -908,7 +974,10 @@ void vd_batch_destroy(vd_batch *b)
         if (p.a) (void)hipEventDestroy(p.a);
         if (p.b) (void)hipEventDestroy(p.b);
     }
-    for (vd_sim *s : b->sims) s->batch = nullptr;
+    for (vd_sim *s : b->sims) {
+        s->batch = nullptr;
+        if (s->release) vd_destroy(s);   // destroyed by its owner while in the batch
+    }
     if (b->capture) (void)hipStreamDestroy(b->capture);
     delete b;
 }

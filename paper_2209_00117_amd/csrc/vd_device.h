@@ -78,6 +78,114 @@ __device__ __forceinline__ int32_t draw(uint64_t seed, uint64_t n, int32_t lo, u
 }
 
 // ---------------------------------------------------------------------------
+// Per-seed steps shared by the single-simulation kernels and the batched and
+// served ones (which run them over many simulations in one launch).  Seed i
+// lives in table[i + 1]; table[0] is the sentinel.
+// ---------------------------------------------------------------------------
+
+// `state` (optional, one byte per seed): a seed takes part only if its
+// byte has a bit of `need` (kPresent: in the seed set now; kKept: in it
+// since the diagram was made).  Null: every seed takes part.
+__device__ __forceinline__ bool takes_part(const uint8_t *state, int32_t i, uint32_t need)
+{
+    return !state || (state[i] & need) != 0u;
+}
+
+// Moves seed i at time step t >= 1 (Alg. 1, SimulateParticles; Sec. V-A):
+// per axis a uniform integer in [lo, lo + span) from draw n = ((t - 1) S +
+// i) 2 + axis of the move stream, then clamped to the grid.  Returns the
+// position before the move; the table holds the new one.
+__device__ __forceinline__ uint32_t move_one(uint32_t *table, int32_t i, int32_t S, int32_t W,
+                                             int32_t H, uint64_t move_seed, uint64_t t,
+                                             int32_t lo, uint32_t span)
+{
+    const uint64_t n = ((t - 1) * (uint64_t)S + (uint64_t)i) * 2u;
+    const uint32_t p = table[i + 1];
+    int32_t x = (int32_t)(p & 0xFFFFu) - (int32_t)kOff + draw(move_seed, n + 0, lo, span);
+    int32_t y = (int32_t)(p >> 16) - (int32_t)kOff + draw(move_seed, n + 1, lo, span);
+    x = min(max(x, 0), W - 1);
+    y = min(max(y, 0), H - 1);
+    table[i + 1] = ((uint32_t)(y + (int32_t)kOff) << 16) | (uint32_t)(x + (int32_t)kOff);
+    return p;
+}
+
+// Seed pixel of seed i on a map whose other pixels hold all ones (a JFA
+// step's start): the atomic minimum leaves the lowest coincident label.
+__device__ __forceinline__ void splat_min_seed(uint32_t *map, const uint32_t *table, int32_t i,
+                                               int32_t W)
+{
+    atomicMin(&map[pixel_of(table[i + 1], W)], (uint32_t)(i + 1));
+}
+
+// XY labels: the seed pixel takes its own packed position, or-ed with
+// `mark` (0, or the top bit for a pass that reads through an index).
+__device__ __forceinline__ void splat_xy_seed(uint32_t *map, const uint32_t *table, int32_t i,
+                                              int32_t W, uint32_t mark)
+{
+    const uint32_t p = table[i + 1];
+    map[pixel_of(p, W)] = p | mark;
+}
+
+// Seed pixel of seed i over whatever the pixel held before (a dJFA step's
+// splat into the previous diagram, or the old-position index).  The seed
+// claims its pixel with label i + 1 if label_state has a bit of label_need,
+// else with all ones (no label).  A pixel's value is settled if it is all
+// ones or the label of a label-claiming seed that sits on that pixel (per
+// `table`); any other value is stale.  A seed leaves a settled value no
+// larger than its own claim and otherwise puts its claim in by
+// compare-and-swap.  At one pixel the value only goes from stale to all
+// ones or a label, from all ones to a label, and from a label to a smaller
+// one, so every loop ends, and the final value is the smallest label of the
+// label-claiming seeds on the pixel, or all ones if every seed there claims
+// without one -- whatever the pixel held before.
+__device__ __forceinline__ void splat_swap_seed(uint32_t *map, const uint32_t *table, int32_t S,
+                                                int32_t W, int32_t i,
+                                                const uint8_t *label_state, uint32_t label_need)
+{
+    const uint32_t p = table[i + 1];
+    const uint32_t me = takes_part(label_state, i, label_need) ? (uint32_t)(i + 1) : 0xFFFFFFFFu;
+    uint32_t *const at = &map[pixel_of(p, W)];
+    uint32_t cur = __hip_atomic_load(at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    for (;;) {
+        const bool settled =
+            cur == 0xFFFFFFFFu ||
+            (cur - 1u < (uint32_t)S && takes_part(label_state, (int32_t)(cur - 1u), label_need) &&
+             table[cur] == p);
+        if (settled && cur <= me) return;
+        const uint32_t seen = atomicCAS(at, cur, me);
+        if (seen == cur) return;
+        cur = seen;
+    }
+}
+
+// After splat_swap_seed of every seed on the old positions (old_table)
+// into idx, idx[old position] holds the lowest kept seed label (index + 1)
+// sitting there, or all ones.  That seed writes its new position (table)
+// over it; positions are >= (kOff << 16 | kOff), above every label, so no
+// other seed of the same old position can mistake the overwritten entry for
+// its own label.
+__device__ __forceinline__ void index_resolve_seed(uint32_t *idx, const uint32_t *old_table,
+                                                   const uint32_t *table, int32_t i, int32_t W)
+{
+    uint32_t *e = &idx[pixel_of(old_table[i + 1], W)];
+    if (*e == (uint32_t)(i + 1)) *e = table[i + 1];
+}
+
+// An XY label (an old position) relabelled through the resolved index: the
+// moved position of the lowest kept seed that sat there, else unclaimed (the
+// entry then holds a leftover label or all ones, both below every
+// position); label 0 stays unclaimed.
+__device__ __forceinline__ uint32_t relabel_one(uint32_t l, const uint32_t *idx, int32_t W,
+                                                int32_t H)
+{
+    if (l == kEmpty) return kEmpty;
+    const int32_t lx = (int32_t)(l & 0xFFFFu) - (int32_t)kOff;
+    const int32_t ly = (int32_t)(l >> 16) - (int32_t)kOff;
+    const uint32_t np = (lx >= 0 && lx < W && ly >= 0 && ly < H) ? idx[(int64_t)ly * W + lx] : 0u;
+    return (int32_t)np >= (int32_t)((kOff << 16) | kOff) ? np : kEmpty;
+}
+
+// ---------------------------------------------------------------------------
 // Flood pass.
 //
 // Residue-chain schedule.  At step k, output row y reads input rows y - k,

@@ -131,13 +131,16 @@ constexpr int kMaxTunedSegRows = 128;
 FloodGrid flood_grid(int32_t W, int32_t H, int32_t k, int32_t seg_rows);
 
 // Work items of a persistent (batched or served) pass: tiles of 32-row
-// segments (the batch gives parallelism, so segments need not be short),
-// grouped so that one item covers about 8192 output pixels even where
-// chains are short (large k).  Item i covers tiles [i*per, (i+1)*per).
+// segments (the batch gives parallelism, so segments need not be short) --
+// four-column tiles of 1024 columns where quad_ok(W, k), else one-column
+// tiles of 256 -- grouped so that one item covers about 8192 output pixels
+// even where chains are short (large k).  Item i covers tiles
+// [i*per, (i+1)*per).
 struct ItemGrid {
     FloodGrid g;
     uint32_t per;      // tiles per item
     uint32_t items;
+    int32_t quad;      // tiles of the four-column kernels (flood_grid_quad)
 };
 ItemGrid item_grid(int32_t W, int32_t H, int32_t k);
 

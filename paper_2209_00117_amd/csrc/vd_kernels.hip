@@ -19,26 +19,9 @@ __global__ void __launch_bounds__(kBlock) k_fill(uint32_t *__restrict__ map, int
         map[i] = value;
 }
 
-// `state` (optional, one byte per seed): a seed takes part only if its
-// byte has a bit of `need` (kPresent: in the seed set now; kKept: in it
-// since the diagram was made).  Null: every seed takes part.
-__device__ __forceinline__ bool takes_part(const uint8_t *state, int32_t i, uint32_t need)
-{
-    return !state || (state[i] & need) != 0u;
-}
-
-// Seed pixels over whatever they held before, in one launch.  Seed i takes
-// part if part_state has a bit of part_need (all seeds for a null
-// part_state); it claims its pixel with label i + 1 if label_state has a
-// bit of label_need, else with all ones (no label).  A pixel's value is
-// settled if it is all ones or the label of a label-claiming seed that sits
-// on that pixel (per `table`); any other value is stale.  A seed leaves a
-// settled value no larger than its own claim and otherwise puts its claim
-// in by compare-and-swap.  At one pixel the value only goes from stale to
-// all ones or a label, from all ones to a label, and from a label to a
-// smaller one, so every loop ends, and the final value is the smallest
-// label of the label-claiming seeds on the pixel, or all ones if every
-// seed there claims without one -- whatever the pixel held before.
+// Seed pixels over whatever they held before, in one launch (see
+// splat_swap_seed).  Seed i takes part if part_state has a bit of
+// part_need (all seeds for a null part_state).
 __global__ void __launch_bounds__(kBlock) k_splat_swap(uint32_t *__restrict__ map,
                                                        const uint32_t *__restrict__ table,
                                                        int32_t S, int32_t W,
@@ -48,21 +31,8 @@ __global__ void __launch_bounds__(kBlock) k_splat_swap(uint32_t *__restrict__ ma
                                                        uint32_t label_need)
 {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= S || !takes_part(part_state, i, part_need)) return;
-    const uint32_t p = table[i + 1];
-    const uint32_t me = takes_part(label_state, i, label_need) ? (uint32_t)(i + 1) : 0xFFFFFFFFu;
-    uint32_t *const at = &map[pixel_of(p, W)];
-    uint32_t cur = __hip_atomic_load(at, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    for (;;) {
-        const bool settled =
-            cur == 0xFFFFFFFFu ||
-            (cur - 1u < (uint32_t)S && takes_part(label_state, (int32_t)(cur - 1u), label_need) &&
-             table[cur] == p);
-        if (settled && cur <= me) return;
-        const uint32_t seen = atomicCAS(at, cur, me);
-        if (seen == cur) return;
-        cur = seen;
-    }
+    if (i < S && takes_part(part_state, i, part_need))
+        splat_swap_seed(map, table, S, W, i, label_state, label_need);
 }
 
 __global__ void __launch_bounds__(kBlock) k_splat_min(uint32_t *__restrict__ map,
@@ -72,8 +42,7 @@ __global__ void __launch_bounds__(kBlock) k_splat_min(uint32_t *__restrict__ map
                                                       uint32_t need)
 {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < S && takes_part(state, i, need))
-        atomicMin(&map[pixel_of(table[i + 1], W)], (uint32_t)(i + 1));
+    if (i < S && takes_part(state, i, need)) splat_min_seed(map, table, i, W);
 }
 
 // `mark` is or-ed into the written position (0, or the top bit).
@@ -84,10 +53,7 @@ __global__ void __launch_bounds__(kBlock) k_splat_xy(uint32_t *__restrict__ map,
                                                      uint32_t mark)
 {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < S && takes_part(state, i, kPresent)) {
-        uint32_t p = table[i + 1];
-        map[pixel_of(p, W)] = p | mark;
-    }
+    if (i < S && takes_part(state, i, kPresent)) splat_xy_seed(map, table, i, W, mark);
 }
 
 // Largest per-axis displacement between two packed positions.
@@ -119,15 +85,8 @@ __global__ void __launch_bounds__(kBlock) k_move(uint32_t *__restrict__ table, i
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     uint32_t moved = 0;
     if (i < S && takes_part(state, i, kPresent)) {
-        uint64_t n = ((t - 1) * (uint64_t)S + (uint64_t)i) * 2u;
-        uint32_t p = table[i + 1];
-        int32_t x = (int32_t)(p & 0xFFFFu) - (int32_t)kOff + draw(move_seed, n + 0, lo, span);
-        int32_t y = (int32_t)(p >> 16) - (int32_t)kOff + draw(move_seed, n + 1, lo, span);
-        x = min(max(x, 0), W - 1);
-        y = min(max(y, 0), H - 1);
-        const uint32_t q = ((uint32_t)(y + (int32_t)kOff) << 16) | (uint32_t)(x + (int32_t)kOff);
-        table[i + 1] = q;
-        moved = cheb(p, q);
+        const uint32_t p = move_one(table, i, S, W, H, move_seed, t, lo, span);
+        moved = cheb(p, table[i + 1]);
     }
     if (disp) wave_max_into(&disp[1], moved);
 }
@@ -340,12 +299,7 @@ __global__ void k_disp_acc(uint32_t *__restrict__ disp)
     }
 }
 
-// After k_splat_swap on the old positions, idx[old position]
-// holds the lowest kept seed label (index + 1) sitting there, or all ones
-// if no kept seed sat there.  That seed writes its new position over it;
-// positions are >= (kOff << 16 | kOff), above every label, so no other seed
-// of the same old position can mistake the overwritten entry for its own
-// label.
+// The old-position index after k_splat_swap (see index_resolve_seed).
 __global__ void __launch_bounds__(kBlock) k_index_resolve(uint32_t *__restrict__ idx,
                                                           const uint32_t *__restrict__ old_table,
                                                           const uint32_t *__restrict__ table,
@@ -353,9 +307,7 @@ __global__ void __launch_bounds__(kBlock) k_index_resolve(uint32_t *__restrict__
                                                           const uint8_t *__restrict__ state)
 {
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= S || !takes_part(state, i, kKept)) return;
-    uint32_t *e = &idx[pixel_of(old_table[i + 1], W)];
-    if (*e == (uint32_t)(i + 1)) *e = table[i + 1];
+    if (i < S && takes_part(state, i, kKept)) index_resolve_seed(idx, old_table, table, i, W);
 }
 
 __global__ void __launch_bounds__(kBlock) k_relabel(uint32_t *__restrict__ map,
@@ -364,74 +316,17 @@ __global__ void __launch_bounds__(kBlock) k_relabel(uint32_t *__restrict__ map,
 {
     int64_t n = (int64_t)W * H;
     int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
-        uint32_t l = map[p];
-        if (l == kEmpty) continue;
-        int32_t lx = (int32_t)(l & 0xFFFFu) - (int32_t)kOff;
-        int32_t ly = (int32_t)(l >> 16) - (int32_t)kOff;
-        uint32_t np = (lx >= 0 && lx < W && ly >= 0 && ly < H) ? idx[(int64_t)ly * W + lx] : 0u;
-        // a position, not a leftover label nor the all-ones of "no kept seed"
-        map[p] = (int32_t)np >= (int32_t)((kOff << 16) | kOff) ? np : kEmpty;
-    }
+    for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride)
+        map[p] = relabel_one(map[p], idx, W, H);
 }
 
-// k_relabel for widths divisible by 4, pipelined: each lane relabels four
-// adjacent pixels in each of kRelabelRows rows at once -- all their label
-// loads are requested, then all their gathers, then the results stored --
-// so the gathers of eight rows are in flight together instead of one row's.
-// A pixel whose label equals its left neighbour's in the group reuses that
-// result (its gather goes to an offset past the map, which the hardware
-// answers without a memory access); rows are independent of each other.
-// A workgroup covers 1024 columns of `rows` rows (a multiple of
-// kRelabelRows), where old positions -- near the pixels that carry them --
-// fall in a few lines of the index that neighbouring rows share in L2.
-constexpr int kRelabelRows = 8;
-
+// k_relabel for widths divisible by 4 (see relabel_block): workgroup b
+// relabels block b of the map.
 __global__ void __launch_bounds__(kBlock) k_relabel_deep(uint32_t *__restrict__ map,
                                                          const uint32_t *__restrict__ idx,
                                                          int32_t W, int32_t H, int32_t rows)
 {
-    const int32_t strips = (W + kTWQ - 1) / kTWQ;
-    const int32_t strip = (int32_t)blockIdx.x % strips;
-    const int32_t y0 = ((int32_t)blockIdx.x / strips) * rows;
-    const int32_t y1 = min(y0 + rows, H);
-    const int32_t off = 4 * (strip * kTWQ + kQuad * (int32_t)threadIdx.x);
-    const __amdgpu_buffer_rsrc_t ir = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)idx, 0, (int32_t)min((int64_t)W * H * 4, (int64_t)0x7FFFFFFF), kRsrcWord3);
-    const int32_t base = (int32_t)((kOff << 16) | kOff);
-    for (int32_t y = y0; y < y1; y += kRelabelRows) {
-        u32x4 l[kRelabelRows], v[kRelabelRows];
-#pragma unroll
-        for (int r = 0; r < kRelabelRows; ++r)   // rows past y1 read as unclaimed (size 0)
-            l[r] = load4(row_rsrc(map, y + r < y1 ? y + r : H, W, H), off);
-#pragma unroll
-        for (int r = 0; r < kRelabelRows; ++r) {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const uint32_t le = l[r][e];
-                const int32_t lx = (int32_t)(le & 0xFFFFu) - (int32_t)kOff;
-                const int32_t ly = (int32_t)(le >> 16) - (int32_t)kOff;
-                const bool valid = le != kEmpty && lx >= 0 && lx < W && ly >= 0 && ly < H;
-                const bool reuse = e > 0 && le == l[r][e > 0 ? e - 1 : 0];
-                const int32_t at = (valid && !reuse) ? 4 * (ly * W + lx) : -1;
-                v[r][e] = __builtin_amdgcn_raw_buffer_load_b32(ir, at, 0, 0);
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < kRelabelRows; ++r) {
-            u32x4 n;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const uint32_t le = l[r][e];
-                const bool reuse = e > 0 && le == l[r][e > 0 ? e - 1 : 0];
-                // a position, not a leftover label nor the all-ones of "no kept seed"
-                // (label 0 and labels off the grid gathered nothing: 0)
-                const uint32_t np = (int32_t)v[r][e] >= base ? v[r][e] : kEmpty;
-                n[e] = reuse ? n[e > 0 ? e - 1 : 0] : np;
-            }
-            store4<0>(n, row_rsrc(map, y + r < y1 ? y + r : H, W, H), off);
-        }
-    }
+    relabel_block(map, idx, W, H, rows, blockIdx.x);
 }
 
 __global__ void __launch_bounds__(kBlock) k_export(const uint32_t *__restrict__ map,
@@ -663,10 +558,8 @@ hipError_t launch_relabel(uint32_t *map, const uint32_t *idx, int32_t W, int32_t
                           hipStream_t s)
 {
     if (W % kQuad == 0) {
-        const int32_t rows = 4 * kRelabelRows;
-        const int64_t blocks = (int64_t)((W + kTWQ - 1) / kTWQ) * ((H + rows - 1) / rows);
-        hipLaunchKernelGGL(k_relabel_deep, dim3((unsigned)blocks), dim3(kBlock), 0, s, map, idx,
-                           W, H, rows);
+        hipLaunchKernelGGL(k_relabel_deep, dim3((unsigned)relabel_blocks(W, H)), dim3(kBlock), 0,
+                           s, map, idx, W, H, kRelabelBlockRows);
     } else {
         hipLaunchKernelGGL(k_relabel, grid1d((int64_t)W * H, 8192), dim3(kBlock), 0, s, map,
                            idx, W, H);
@@ -722,11 +615,12 @@ bool quad_ok(int32_t W, int32_t k)
 ItemGrid item_grid(int32_t W, int32_t H, int32_t k)
 {
     ItemGrid it{};
-    it.g = flood_grid(W, H, k, kMaxSegRows);
+    it.quad = quad_ok(W, k) ? 1 : 0;
+    it.g = it.quad ? flood_grid_quad(W, H, k, kMaxSegRows) : flood_grid(W, H, k, kMaxSegRows);
     if (it.g.nblocks == 0) return it;
     const int64_t chain = (H + k - 1) / k;
     const int64_t rows = chain < it.g.L ? chain : it.g.L;
-    const int64_t tile_px = (int64_t)kTW * rows;
+    const int64_t tile_px = (int64_t)(it.quad ? kTWQ : kTW) * rows;
     it.per = (uint32_t)((8192 + tile_px - 1) / tile_px);
     it.items = (it.g.nblocks + it.per - 1) / it.per;
     return it;

@@ -456,6 +456,71 @@ __device__ __forceinline__ void flood_quad_id_tile(const uint32_t *src, uint32_t
     quad_walk<METRIC, VN, KC, NS, ST>(dst, W, H, k, tl, oc, request, fetch);
 }
 
+// XY labels after a move (widths divisible by 4), one block of the map:
+// each lane relabels four adjacent pixels in each of kRelabelRows rows at
+// once -- all their label loads are requested, then all their gathers from
+// the old-position index, then the results stored -- so the gathers of
+// eight rows are in flight together.  A pixel whose label equals its left
+// neighbour's in the group reuses that result (its gather goes to an offset
+// past the map, which the hardware answers without a memory access); rows
+// are independent of each other.  Block b covers 1024 columns of `rows`
+// rows (a multiple of kRelabelRows); old positions lie near the pixels that
+// carry them, so neighbouring rows share their index lines in L2.
+constexpr int kRelabelRows = 8;
+
+__device__ __forceinline__ void relabel_block(uint32_t *map, const uint32_t *idx, int32_t W,
+                                              int32_t H, int32_t rows, uint32_t b)
+{
+    const int32_t strips = (W + kTWQ - 1) / kTWQ;
+    const int32_t strip = (int32_t)(b % (uint32_t)strips);
+    const int32_t y0 = (int32_t)(b / (uint32_t)strips) * rows;
+    const int32_t y1 = min(y0 + rows, H);
+    const int32_t off = 4 * (strip * kTWQ + kQuad * (int32_t)threadIdx.x);
+    const __amdgpu_buffer_rsrc_t ir = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)idx, 0, (int32_t)min((int64_t)W * H * 4, (int64_t)0x7FFFFFFF), kRsrcWord3);
+    const int32_t base = (int32_t)((kOff << 16) | kOff);
+    for (int32_t y = y0; y < y1; y += kRelabelRows) {
+        u32x4 l[kRelabelRows], v[kRelabelRows];
+#pragma unroll
+        for (int r = 0; r < kRelabelRows; ++r)   // rows past y1 read as unclaimed (size 0)
+            l[r] = load4(row_rsrc(map, y + r < y1 ? y + r : H, W, H), off);
+#pragma unroll
+        for (int r = 0; r < kRelabelRows; ++r) {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t le = l[r][e];
+                const int32_t lx = (int32_t)(le & 0xFFFFu) - (int32_t)kOff;
+                const int32_t ly = (int32_t)(le >> 16) - (int32_t)kOff;
+                const bool valid = le != kEmpty && lx >= 0 && lx < W && ly >= 0 && ly < H;
+                const bool reuse = e > 0 && le == l[r][e > 0 ? e - 1 : 0];
+                const int32_t at = (valid && !reuse) ? 4 * (ly * W + lx) : -1;
+                v[r][e] = __builtin_amdgcn_raw_buffer_load_b32(ir, at, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int r = 0; r < kRelabelRows; ++r) {
+            u32x4 n;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t le = l[r][e];
+                const bool reuse = e > 0 && le == l[r][e > 0 ? e - 1 : 0];
+                // a position, not a leftover label nor the all-ones of "no kept
+                // seed" (label 0 and labels off the grid gathered nothing: 0)
+                const uint32_t np = (int32_t)v[r][e] >= base ? v[r][e] : kEmpty;
+                n[e] = reuse ? n[e > 0 ? e - 1 : 0] : np;
+            }
+            store4<0>(n, row_rsrc(map, y + r < y1 ? y + r : H, W, H), off);
+        }
+    }
+}
+
+// Blocks of relabel_block for a W x H map.
+__host__ __device__ __forceinline__ int64_t relabel_blocks(int32_t W, int32_t H)
+{
+    return (int64_t)((W + kTWQ - 1) / kTWQ) * ((H + 4 * kRelabelRows - 1) / (4 * kRelabelRows));
+}
+constexpr int kRelabelBlockRows = 4 * kRelabelRows;
+
 }  // namespace
 
 }  // namespace vd

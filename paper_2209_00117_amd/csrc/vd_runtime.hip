@@ -1262,7 +1262,11 @@ int vd_get_timing(vd_sim *s, vd_timing *out)
 
 void vd_destroy(vd_sim *s)
 {
-    if (!s || s->batch) return;   // a batch member is released after vd_batch_destroy
+    if (!s) return;
+    if (s->batch) {   // a batch member is released by vd_batch_destroy
+        s->release = true;
+        return;
+    }
     (void)hipStreamSynchronize(s->stream);
     for (EventPair &p : s->pool) {
         if (p.a) (void)hipEventDestroy(p.a);

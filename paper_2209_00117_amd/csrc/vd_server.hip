@@ -42,7 +42,7 @@
 #include <thread>
 #include <vector>
 
-#include "vd_device.h"
+#include "vd_multi.h"
 #include "vd_sim.h"
 
 namespace vd {
@@ -57,19 +57,23 @@ struct TickSim {            // one active simulation's pass in a tick
     const uint32_t *src;
     uint32_t *dst;
     const uint32_t *table;
-    int32_t W, H, S, k, vn;
+    int32_t W, H, S, k, vn, label;
     FloodGrid g;
     uint32_t first;         // its first item in the tick's work list
     uint32_t per;           // tiles per item
-    int32_t pad;
+    int32_t quad;           // four-column tiles (item_grid)
 };
 
-struct TickPrep {           // one simulation starting a request in a tick
+struct TickPrep {           // one simulation starting (or ending) a request in a tick
     uint32_t *map;          // its current diagram
     uint32_t *table;
+    uint32_t *pos_map;      // XY labels: the positions the diagram refers to
+    uint32_t *idx;          // XY labels: the old-position index
     int32_t W, H, S, lo;
     uint32_t span;
-    int32_t fill;           // JFA: clear the map first
+    int32_t fill;           // JFA: the step starts from an unclaimed map
+    int32_t label;
+    int32_t pad;
     uint64_t move_seed;
     uint64_t t;             // the time step being entered (>= 1)
 };
@@ -102,70 +106,109 @@ __device__ __forceinline__ T *uni_ptr(T *p)
     return (T *)(lo | (hi << 32));
 }
 
+// Kernels over the simulations starting a request in a tick: blockIdx.y is
+// the simulation, blockIdx.x strides over its seeds or pixels.  Each does
+// what a lone simulation's move and step start do (vd_device.h): the move;
+// for a JFA step the fill (ID labels: all ones) and splat; for a dJFA step
+// the compare-and-swap splat into the previous diagram, or for XY labels
+// the old-position index, the relabel and the splat.
 __global__ void __launch_bounds__(kBlock) k_tick_fill(const TickPrep *__restrict__ prep)
 {
     const TickPrep p = prep[blockIdx.y];
     if (!p.fill) return;
+    const uint32_t v = p.label == kLabelId ? 0xFFFFFFFFu : kEmpty;
     const int64_t n = (int64_t)p.W * p.H;
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
-        p.map[i] = kEmpty;
+        p.map[i] = v;
 }
 
-// Moves seed i (as k_move) and marks its new pixel for the splat.
-__global__ void __launch_bounds__(kBlock) k_tick_move_reset(const TickPrep *__restrict__ prep)
-{
-    const TickPrep p = prep[blockIdx.y];
-    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < p.S;
-         i += gridDim.x * blockDim.x) {
-        uint64_t n = ((p.t - 1) * (uint64_t)p.S + (uint64_t)i) * 2u;
-        uint32_t q = p.table[i + 1];
-        int32_t x = (int32_t)(q & 0xFFFFu) - (int32_t)kOff + draw(p.move_seed, n + 0, p.lo, p.span);
-        int32_t y = (int32_t)(q >> 16) - (int32_t)kOff + draw(p.move_seed, n + 1, p.lo, p.span);
-        x = min(max(x, 0), p.W - 1);
-        y = min(max(y, 0), p.H - 1);
-        q = ((uint32_t)(y + (int32_t)kOff) << 16) | (uint32_t)(x + (int32_t)kOff);
-        p.table[i + 1] = q;
-        p.map[pixel_of(q, p.W)] = 0xFFFFFFFFu;
-    }
-}
-
-__global__ void __launch_bounds__(kBlock) k_tick_splat_min(const TickPrep *__restrict__ prep)
+__global__ void __launch_bounds__(kBlock) k_tick_move(const TickPrep *__restrict__ prep)
 {
     const TickPrep p = prep[blockIdx.y];
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < p.S;
          i += gridDim.x * blockDim.x)
-        atomicMin(&p.map[pixel_of(p.table[i + 1], p.W)], (uint32_t)(i + 1));
+        move_one(p.table, i, p.S, p.W, p.H, p.move_seed, p.t, p.lo, p.span);
 }
 
-template <int METRIC>
-__global__ void __launch_bounds__(kTW) k_tick_flood(const TickHeader *__restrict__ hd,
-                                                    const TickSim *__restrict__ sims,
-                                                    uint32_t *__restrict__ ctr)
+__global__ void __launch_bounds__(kBlock) k_tick_splat(const TickPrep *__restrict__ prep)
 {
-    __shared__ uint2 lds[2][kLdsRow];
+    const TickPrep p = prep[blockIdx.y];
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < p.S;
+         i += gridDim.x * blockDim.x) {
+        if (p.fill) {
+            if (p.label == kLabelId)
+                splat_min_seed(p.map, p.table, i, p.W);
+            else
+                splat_xy_seed(p.map, p.table, i, p.W, 0u);
+        } else if (p.label == kLabelId) {
+            splat_swap_seed(p.map, p.table, p.S, p.W, i, nullptr, 0u);
+        } else {   // the first half of the old-position index
+            splat_swap_seed(p.idx, p.pos_map, p.S, p.W, i, nullptr, 0u);
+        }
+    }
+}
+
+// XY labels, dJFA: the index resolved, every label relabelled through it,
+// the seed pixels claimed.
+__global__ void __launch_bounds__(kBlock) k_tick_index(const TickPrep *__restrict__ prep)
+{
+    const TickPrep p = prep[blockIdx.y];
+    if (p.fill || p.label != kLabelXy) return;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < p.S;
+         i += gridDim.x * blockDim.x)
+        index_resolve_seed(p.idx, p.pos_map, p.table, i, p.W);
+}
+
+__global__ void __launch_bounds__(kBlock) k_tick_relabel(const TickPrep *__restrict__ prep)
+{
+    const TickPrep p = prep[blockIdx.y];
+    if (p.fill || p.label != kLabelXy) return;
+    if (p.W % kQuad == 0) {
+        const int64_t nb = relabel_blocks(p.W, p.H);
+        for (int64_t b = blockIdx.x; b < nb; b += gridDim.x)
+            relabel_block(p.map, p.idx, p.W, p.H, kRelabelBlockRows, (uint32_t)b);
+    } else {
+        const int64_t n = (int64_t)p.W * p.H;
+        for (int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; q < n;
+             q += (int64_t)gridDim.x * blockDim.x)
+            p.map[q] = relabel_one(p.map[q], p.idx, p.W, p.H);
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_tick_splat_xy(const TickPrep *__restrict__ prep)
+{
+    const TickPrep p = prep[blockIdx.y];
+    if (p.fill || p.label != kLabelXy) return;
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < p.S;
+         i += gridDim.x * blockDim.x)
+        splat_xy_seed(p.map, p.table, i, p.W, 0u);
+}
+
+// Simulations whose request ends in a tick (XY labels): the diagram now
+// refers to the current positions.
+__global__ void __launch_bounds__(kBlock) k_tick_posmap(const TickPrep *__restrict__ leave)
+{
+    const TickPrep p = leave[blockIdx.y];
+    for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= p.S;
+         i += gridDim.x * blockDim.x)
+        p.pos_map[i] = p.table[i];
+}
+
+// The flood pass of every active simulation, each at its own pass: work
+// items claimed as in a batch level, run by the tiles a lone simulation's
+// kernels use (member_tiles).
+template <int METRIC>
+__global__ void __launch_bounds__(kBlock) k_tick_flood(const TickHeader *__restrict__ hd,
+                                                       const TickSim *__restrict__ sims,
+                                                       uint32_t *__restrict__ ctr)
+{
+    __shared__ __align__(16) uint8_t lds[kMultiLds];
     __shared__ uint32_t s_item;
-    const uint32_t home = blockIdx.x & 7u;
     const int32_t n = uni(hd->nactive);
     uint32_t probe = 0;
     for (;;) {
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            uint32_t item = 0xFFFFFFFFu;
-            while (probe < 8u) {
-                const uint32_t c = (home + probe) & 7u;
-                const uint32_t lo = hd->chunk[c], hi = hd->chunk[c + 1];
-                const uint32_t i = lo < hi ? atomicAdd(&ctr[c], 1u) : 0xFFFFFFFFu;
-                if (i < hi - lo) {
-                    item = lo + i;
-                    break;
-                }
-                ++probe;
-            }
-            s_item = item;
-        }
-        __syncthreads();
-        const uint32_t item = uni(s_item);
+        const uint32_t item = claim_item(hd->chunk, ctr, probe, &s_item);
         if (item == 0xFFFFFFFFu) return;
         int32_t a = 0, b = n;
         while (b - a > 1) {
@@ -173,33 +216,25 @@ __global__ void __launch_bounds__(kTW) k_tick_flood(const TickHeader *__restrict
             if (uni(sims[m].first) <= item) a = m; else b = m;
         }
         const TickSim &ts = sims[a];
-        const int32_t k = uni(ts.k), vn = uni(ts.vn);
-        FloodGrid g;
-        g.ncol = uni(ts.g.ncol);
-        g.nseg = uni(ts.g.nseg);
-        g.L = uni(ts.g.L);
-        g.nblocks = uni(ts.g.nblocks);
-        const int32_t W = uni(ts.W), H = uni(ts.H), S = uni(ts.S);
-        const uint32_t *src = uni_ptr(ts.src);
-        uint32_t *dst = uni_ptr(ts.dst);
-        const i32x4 tab = table_rsrc(uni_ptr(ts.table), (uint32_t)S);
+        MemberPass mp;
+        mp.k = uni(ts.k);
+        mp.vn = uni(ts.vn);
+        mp.label = uni(ts.label);
+        mp.quad = uni(ts.quad);
+        mp.g.ncol = uni(ts.g.ncol);
+        mp.g.nseg = uni(ts.g.nseg);
+        mp.g.L = uni(ts.g.L);
+        mp.g.nblocks = uni(ts.g.nblocks);
+        mp.W = uni(ts.W);
+        mp.H = uni(ts.H);
+        mp.S = uni(ts.S);
+        mp.src = uni_ptr(ts.src);
+        mp.dst = uni_ptr(ts.dst);
+        mp.table = uni_ptr(ts.table);
         const uint32_t per = uni(ts.per);
         const uint32_t t0 = (item - uni(ts.first)) * per;
-        const uint32_t t1 = min(t0 + per, g.nblocks);
-        for (uint32_t tile = t0; tile < t1; ++tile) {
-            if (tile != t0) __syncthreads();   // LDS of the previous tile is free
-            if (k <= kMaxLdsStep) {
-                if (vn)
-                    flood_lds_tile<kLabelId, METRIC, 1, 2>(src, dst, tab, W, H, k, g, tile, lds);
-                else
-                    flood_lds_tile<kLabelId, METRIC, 0, 2>(src, dst, tab, W, H, k, g, tile, lds);
-            } else {
-                if (vn)
-                    flood_chain_tile<kLabelId, METRIC, 1, 2>(src, dst, tab, W, H, k, g, tile);
-                else
-                    flood_chain_tile<kLabelId, METRIC, 0, 2>(src, dst, tab, W, H, k, g, tile);
-            }
-        }
+        const uint32_t t1 = min(t0 + per, mp.g.nblocks);
+        member_tiles<METRIC>(mp, t0, t1, lds);
     }
 }
 
@@ -322,9 +357,10 @@ size_t off_prep(int32_t max_sims)
 {
     return off_sims() + vd::align_up(sizeof(vd::TickSim) * (size_t)max_sims);
 }
+// (joiners and leavers each take at most max_sims TickPrep entries)
 size_t slot_size(int32_t max_sims)
 {
-    return off_prep(max_sims) + vd::align_up(sizeof(vd::TickPrep) * (size_t)max_sims);
+    return off_prep(max_sims) + 2 * vd::align_up(sizeof(vd::TickPrep) * (size_t)max_sims);
 }
 
 // Called with mu held.  Admits waiting simulations in arrival order while
@@ -465,11 +501,15 @@ bool tick(vd_server *sv)
     const int slot = (int)(sv->ticks % vd::kRing);
     uint8_t *h = sv->host_ring + (size_t)slot * sv->slot_bytes;
     uint8_t *d = sv->base + (size_t)slot * sv->slot_bytes;
-    // slot layout this tick: header | counters | TickSim x active | TickPrep x joiners
+    // slot layout this tick: header | counters | TickSim x active | TickPrep x joiners |
+    // TickPrep x leavers (XY labels: their table copy)
     vd::TickHeader *hh = (vd::TickHeader *)h;
     vd::TickSim *hs = (vd::TickSim *)(h + off_sims());
     const size_t prep_at = off_sims() + vd::align_up(sizeof(vd::TickSim) * active.size());
     vd::TickPrep *hp = (vd::TickPrep *)(h + prep_at);
+    const size_t leave_at = prep_at + vd::align_up(sizeof(vd::TickPrep) * joiners.size());
+    vd::TickPrep *hl = (vd::TickPrep *)(h + leave_at);
+    int32_t nleave = 0;
     memset(hh, 0, sizeof *hh);
     memset(h + off_counters(), 0, sizeof(vd::TickCounters));
     Tick t;
@@ -489,6 +529,9 @@ bool tick(vd_server *sv)
         memset(&p, 0, sizeof p);
         p.map = m->map[m->cur];
         p.table = m->pos;
+        p.pos_map = m->pos_map;
+        p.idx = m->idx;
+        p.label = m->cfg.label;
         p.W = m->cfg.width;
         p.H = m->cfg.height;
         p.S = m->cfg.num_seeds;
@@ -517,9 +560,11 @@ bool tick(vd_server *sv)
             e.S = m->cfg.num_seeds;
             e.k = ps.k;
             e.vn = ps.vn;
+            e.label = m->cfg.label;
             const vd::ItemGrid ig = vd::item_grid(e.W, e.H, e.k);
             e.g = ig.g;
             e.per = ig.per;
+            e.quad = ig.quad;
             e.first = first;
             first += ig.items;
             t.pixel_updates += (int64_t)e.W * e.H;
@@ -529,24 +574,41 @@ bool tick(vd_server *sv)
         if (s.pass >= s.npasses) {   // leaves after this tick
             s.active = false;
             t.completes.emplace_back(id, s.req);
+            if (m->cfg.label == VD_LABEL_XY16) {
+                vd::TickPrep &p = hl[nleave++];
+                memset(&p, 0, sizeof p);
+                p.table = m->pos;
+                p.pos_map = m->pos_map;
+                p.S = m->cfg.num_seeds;
+                maxS = std::max(maxS, p.S);
+            }
         }
     }
     hh->total = first;
     for (int c = 0; c <= 8; ++c) hh->chunk[c] = (uint32_t)((uint64_t)first * c / 8);
     hh->nactive = na;
     hh->nprep = (int32_t)joiners.size();
-    const size_t used = prep_at + sizeof(vd::TickPrep) * joiners.size();
+    const size_t used = leave_at + sizeof(vd::TickPrep) * (size_t)nleave;
     hipError_t e = hipMemcpyAsync(d, h, used, hipMemcpyHostToDevice, sv->stream);
     const vd::TickPrep *dp = (const vd::TickPrep *)(d + prep_at);
-    bool any_fill = false;
-    for (size_t j = 0; j < joiners.size(); ++j) any_fill |= hp[j].fill != 0;
+    const vd::TickPrep *dl = (const vd::TickPrep *)(d + leave_at);
+    bool any_fill = false, any_relabel = false;
+    for (size_t j = 0; j < joiners.size(); ++j) {
+        any_fill |= hp[j].fill != 0;
+        any_relabel |= hp[j].fill == 0 && hp[j].label == VD_LABEL_XY16;
+    }
     const dim3 blk(vd::kBlock);
+    const unsigned gs = (unsigned)std::min<int64_t>((maxS + vd::kBlock - 1) / vd::kBlock, 1024);
     if (e == hipSuccess && !joiners.empty()) {
         const unsigned nj = (unsigned)joiners.size();
-        const unsigned gs = (unsigned)std::min<int64_t>((maxS + vd::kBlock - 1) / vd::kBlock, 1024);
+        hipLaunchKernelGGL(vd::k_tick_move, dim3(gs, nj), blk, 0, sv->stream, dp);
         if (any_fill) hipLaunchKernelGGL(vd::k_tick_fill, dim3(256, nj), blk, 0, sv->stream, dp);
-        hipLaunchKernelGGL(vd::k_tick_move_reset, dim3(gs, nj), blk, 0, sv->stream, dp);
-        hipLaunchKernelGGL(vd::k_tick_splat_min, dim3(gs, nj), blk, 0, sv->stream, dp);
+        hipLaunchKernelGGL(vd::k_tick_splat, dim3(gs, nj), blk, 0, sv->stream, dp);
+        if (any_relabel) {
+            hipLaunchKernelGGL(vd::k_tick_index, dim3(gs, nj), blk, 0, sv->stream, dp);
+            hipLaunchKernelGGL(vd::k_tick_relabel, dim3(256, nj), blk, 0, sv->stream, dp);
+            hipLaunchKernelGGL(vd::k_tick_splat_xy, dim3(gs, nj), blk, 0, sv->stream, dp);
+        }
         e = hipGetLastError();
     }
     if (e == hipSuccess && na > 0) {
@@ -555,10 +617,14 @@ bool tick(vd_server *sv)
         uint32_t *dc = (uint32_t *)(d + off_counters());
         if (sv->metric == VD_EUCLID)
             hipLaunchKernelGGL(vd::k_tick_flood<vd::kEuclid>, dim3((unsigned)sv->grid),
-                               dim3(vd::kTW), 0, sv->stream, dh, ds, dc);
+                               dim3(vd::kBlock), 0, sv->stream, dh, ds, dc);
         else
             hipLaunchKernelGGL(vd::k_tick_flood<vd::kManhattan>, dim3((unsigned)sv->grid),
-                               dim3(vd::kTW), 0, sv->stream, dh, ds, dc);
+                               dim3(vd::kBlock), 0, sv->stream, dh, ds, dc);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess && nleave > 0) {
+        hipLaunchKernelGGL(vd::k_tick_posmap, dim3(gs, (unsigned)nleave), blk, 0, sv->stream, dl);
         e = hipGetLastError();
     }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&t.done, hipEventDisableTiming);
@@ -645,9 +711,9 @@ int vd_server_create(int32_t max_sims, int32_t metric, void *dev_pool, size_t po
     if (e == hipSuccess)
         e = metric == VD_EUCLID
                 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&fit, vd::k_tick_flood<vd::kEuclid>,
-                                                               vd::kTW, 0)
+                                                               vd::kBlock, 0)
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                      &fit, vd::k_tick_flood<vd::kManhattan>, vd::kTW, 0);
+                      &fit, vd::k_tick_flood<vd::kManhattan>, vd::kBlock, 0);
     if (e == hipSuccess) e = hipHostMalloc((void **)&sv->host_ring, ring, hipHostMallocDefault);
     if (e != hipSuccess) {
         delete sv;
@@ -669,8 +735,6 @@ int vd_server_add_sim(vd_server *sv, const vd_config *cfg, const int32_t *host_x
                       int32_t *sim_id)
 {
     if (!sv || !cfg || !host_xy || !sim_id) return fail(VD_EINVAL, "NULL argument");
-    if (cfg->label != VD_LABEL_ID32)
-        return fail(VD_EINVAL, "the server takes ID-label simulations");
     if (cfg->metric != sv->metric)
         return fail(VD_EINVAL, "simulation metric %d differs from the server's %d", cfg->metric,
                     sv->metric);

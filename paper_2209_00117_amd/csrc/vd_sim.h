@@ -98,6 +98,8 @@ struct vd_sim {
     vd_timing acc{};
     bool broken = false;
     vd_batch *batch = nullptr;   // set while a batch drives this simulation
+    bool release = false;        // vd_destroy was called while in a batch: the batch's
+                                 // destruction releases the handle
 };
 
 namespace vd {

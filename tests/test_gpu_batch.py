@@ -28,16 +28,19 @@ SHAPES = [(300, 200, 120, -2, 2), (64, 64, 4096, -1, 1), (1, 1, 1, -1, 1), (1000
           (257, 257, 1, -5, 5), (2048, 256, 2000, -1, 3)]
 
 
-def _make(V, specs, metric=0):
+def _make(V, specs, metric=0, labels=None):
     out = []
     for j, (W, H, S, lo, hi) in enumerate(specs):
         xy = inputs.place_seeds(W, H, S, 50 + j)
-        out.append((xy, dict(disp_lo=lo, disp_hi=hi, sim_seed=900 + j, metric=metric)))
+        label = labels[j % len(labels)] if labels else 0
+        out.append((xy, dict(disp_lo=lo, disp_hi=hi, sim_seed=900 + j, metric=metric,
+                             label=label)))
     return out
 
 
-def _run(V, specs, plan, metric=0, graph=False, tune=False, solo=None, variant=None, fuse=None):
-    made = _make(V, specs, metric)
+def _run(V, specs, plan, metric=0, graph=False, tune=False, solo=None, variant=None, fuse=None,
+         labels=None):
+    made = _make(V, specs, metric, labels)
     members = [V.Sim(s[0], s[1], xy, **kw) for s, (xy, kw) in zip(specs, made)]
     alone = [V.Sim(s[0], s[1], xy, **kw) for s, (xy, kw) in zip(specs, made)]
     if variant is not None:
@@ -104,11 +107,26 @@ def test_batch_manhattan(V):
     _run(V, SHAPES[:5], [(1, True), (0, True), (1, True)], metric=1)
 
 
-def test_batch_members_equal_oracle(V):
+@pytest.mark.parametrize("graph", [False, True])
+@pytest.mark.parametrize("solo", [-1, 60000])
+def test_batch_xy_members(V, graph, solo):
+    """XY and ID members mixed in one batch (their relabel, index and table
+    copy run batched), fused or solo, every step equal to the lone runs."""
+    plan = [(1, True), (0, True), (1, False), (1, True), (0, False), (1, True)]
+    _run(V, SHAPES, plan, graph=graph, solo=solo, labels=[1, 0, 1])
+
+
+def test_batch_xy_all_variants(V):
+    _run(V, SHAPES, [(1, True), (1, True), (0, True)], variant=4, labels=[1])
+    _run(V, SHAPES, [(1, True), (0, True), (1, True)], metric=1, labels=[1, 1, 0])
+
+
+@pytest.mark.parametrize("label", [0, 1])
+def test_batch_members_equal_oracle(V, label):
     specs = SHAPES[:5]
-    members, _, made = _run(V, specs, [(1, True), (1, True), (0, True)])
+    members, _, made = _run(V, specs, [(1, True), (1, True), (0, True)], labels=[label])
     for (W, H, S, lo, hi), m, (xy, kw) in zip(specs, members, made):
-        o = O.Sim(W, H, xy, kw["sim_seed"], lo, hi)
+        o = O.Sim(W, H, xy, kw["sim_seed"], lo, hi, label_mode=label)
         for mode in (1, 1, 0):
             o.move()
             o.djfa_step() if mode == 1 else o.jfa_step()
@@ -127,9 +145,15 @@ def test_batch_rejects_misuse(V):
         V.set_tail_fusion(a.handle, 0)     # fixed while batched
     b.close()
     a.djfa_step()                          # free again
-    x = V.Sim(100, 100, xy, label=V.LABEL_XY16)
-    with pytest.raises(V.VdError):
-        V.Batch([x])                       # XY labels are not batched
+    # a member destroyed while batched is only marked; the batch keeps
+    # stepping it and releases it when it is destroyed
+    c = V.Sim(100, 100, xy)
+    d = V.Sim(100, 100, xy, label=V.LABEL_XY16)
+    bc = V.Batch([c, d])
+    c.close()
+    bc.step(V.STEP_DJFA, True)
+    assert d.info().t == 1
+    bc.close()
 
 
 def test_batched_workload_subset(V):

@@ -115,6 +115,9 @@ def draw_batch(case: int) -> dict:
                             fuse=int(r.choice([-1, 0, 1, 24])),
                             seed=int(r.integers(1, 1 << 30))))
     plan = [(int(r.integers(0, 2)), bool(r.integers(0, 4))) for _ in range(6)]
+    rl = np.random.default_rng(7000 + case)    # label encodings, drawn apart from the rest
+    for m in members:
+        m["label"] = int(rl.integers(0, 2))
     return dict(members=members, metric=int(r.integers(0, 2)), graph=bool(r.integers(0, 2)),
                 shape=int(r.choice([0, 1, 2, 4, 8])),
                 solo=int(r.choice([-1, 0, 1, 20000, 60000])), plan=plan)
@@ -122,9 +125,9 @@ def draw_batch(case: int) -> dict:
 
 @pytest.mark.parametrize("case", range(N_BATCH_CASES))
 def test_random_batch(V, case):
-    """A batch of 1..10 uneven members (ID labels, one metric) with random
-    per-member options, persistent grid shape, graphs on or off and solo
-    members or not, over six random steps (JFA or dJFA, with or without
+    """A batch of 1..10 uneven members (ID or XY labels, one metric) with
+    random per-member options, persistent grid shape, graphs on or off and
+    solo members or not, over six random steps (JFA or dJFA, with or without
     moves); every member equals its oracle after every step."""
     c = draw_batch(case)
     print(f"[random-batch] case {case}: {c}", flush=True)
@@ -133,13 +136,13 @@ def test_random_batch(V, case):
         xy = inputs.place_seeds(m["W"], m["H"], m["S"], m["seed"])
         g = V.Sim(m["W"], m["H"], xy, disp_lo=m["lo"], disp_hi=m["hi"], metric=c["metric"],
                   vn_passes=m["vn"], extra_passes=m["extra"], dmax_override=m["dmax"],
-                  sim_seed=m["seed"])
+                  sim_seed=m["seed"], label=m["label"])
         V.set_flood_variant(g.handle, m["variant"])
         V.set_tail_fusion(g.handle, m["fuse"])
         sims.append(g)
         orcs.append(O.Sim(m["W"], m["H"], xy, m["seed"], m["lo"], m["hi"], metric=c["metric"],
                           vn_passes=m["vn"], extra_passes=m["extra"],
-                          dmax=m["dmax"] if m["dmax"] > 0 else None))
+                          dmax=m["dmax"] if m["dmax"] > 0 else None, label_mode=m["label"]))
     b = V.Batch(sims)
     b.set_shape(c["shape"])
     if c["solo"] >= 0:
@@ -166,12 +169,13 @@ N_SERVER_CASES = 12
 
 @pytest.mark.parametrize("case", range(N_SERVER_CASES))
 def test_random_server(V, case):
-    """A server with 2..8 uneven simulations (random pass options, one
-    metric) takes 40 random requests in bursts, switching policy at random
+    """A server with 2..8 uneven simulations (random labels and pass
+    options, one metric) takes 40 random requests in bursts, switching policy at random
     and draining at random points (every resident simulation is then read
     and compared); at the end every simulation equals its oracle run of the
     same request sequence."""
     r = np.random.default_rng(9000 + case)
+    rl = np.random.default_rng(9500 + case)    # label encodings, drawn apart from the rest
     metric = int(r.integers(0, 2))
     sv = V.Server(8, 1 << 31, metric=metric)
     sv.set_policy(int(r.integers(0, 2)))
@@ -184,12 +188,13 @@ def test_random_server(V, case):
         hi = int(r.integers(lo, 4))
         vn, extra = int(r.integers(0, 3)), int(r.integers(0, 3))
         seed = int(r.integers(1, 1 << 30))
+        label = int(rl.integers(0, 2))
         xy = inputs.place_seeds(W, H, S, seed)
         i = sv.add_sim(W, H, xy, disp_lo=lo, disp_hi=hi, metric=metric, vn_passes=vn,
-                       extra_passes=extra, sim_seed=seed)
+                       extra_passes=extra, sim_seed=seed, label=label)
         ids.append(i)
         orcs[i] = O.Sim(W, H, xy, seed, lo, hi, metric=metric, vn_passes=vn,
-                        extra_passes=extra)
+                        extra_passes=extra, label_mode=label)
     print(f"[random-server] case {case}: {len(ids)} sims, metric {metric}", flush=True)
     for n in range(40):
         if r.random() < 0.1:

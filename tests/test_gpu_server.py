@@ -29,11 +29,12 @@ SHAPES = [(300, 200, 120, -2, 2), (64, 64, 4096, -1, 1), (1, 1, 1, -1, 1), (1000
           (257, 257, 1, -5, 5)]
 
 
-def _sims(specs, base_seed=70):
+def _sims(specs, base_seed=70, labels=(0,)):
     out = []
     for j, (W, H, S, lo, hi) in enumerate(specs):
         out.append((W, H, inputs.place_seeds(W, H, S, base_seed + j),
-                    dict(disp_lo=lo, disp_hi=hi, sim_seed=base_seed + 100 + j)))
+                    dict(disp_lo=lo, disp_hi=hi, sim_seed=base_seed + 100 + j,
+                         label=labels[j % len(labels)])))
     return out
 
 
@@ -45,9 +46,10 @@ def _alone(V, W, H, xy, kw, modes):
     return a.read_map()
 
 
+@pytest.mark.parametrize("labels", [(0,), (1, 0)])
 @pytest.mark.parametrize("policy", ["steps", "passes", "switch"])
-def test_server_mix_equals_alone(V, policy):
-    made = _sims(SHAPES)
+def test_server_mix_equals_alone(V, policy, labels):
+    made = _sims(SHAPES, labels=labels)
     sv = V.Server(len(made), 1 << 30)
     sv.set_policy(V.SERVE_PASSES if policy == "passes" else V.SERVE_STEPS)
     ids = [sv.add_sim(W, H, xy, **kw) for W, H, xy, kw in made]
@@ -74,7 +76,7 @@ def test_server_mix_equals_alone(V, policy):
         assert np.array_equal(got, _alone(V, W, H, xy, kw, plan[i])), (i, plan[i])
     # and the lone runs equal the oracle (two sims)
     for (W, H, xy, kw), i in list(zip(made, ids))[:2]:
-        o = O.Sim(W, H, xy, kw["sim_seed"], kw["disp_lo"], kw["disp_hi"])
+        o = O.Sim(W, H, xy, kw["sim_seed"], kw["disp_lo"], kw["disp_hi"], label_mode=kw["label"])
         for m in plan[i]:
             o.move()
             o.djfa_step() if m == V.STEP_DJFA else o.jfa_step()
@@ -110,7 +112,7 @@ def test_server_rejects_misuse(V):
     sv = V.Server(2, 1 << 26)
     xy = inputs.place_seeds(100, 100, 10, 1)
     with pytest.raises(V.VdError):
-        sv.add_sim(100, 100, xy, label=V.LABEL_XY16)
+        sv.add_sim(100, 100, xy, metric=V.MANHATTAN)   # not the server's metric
     i = sv.add_sim(100, 100, xy)
     with pytest.raises(V.VdError):
         sv.submit(i, 7)
