@@ -375,7 +375,9 @@ using QuadRowWide = QuadRowT<kQuadLdsRowWide>;   // steps up to kMaxQuadLdsStep:
 // alternate, and the barrier of each exchange also orders the reuse of the
 // row written two exchanges earlier.  Callers must not let a previous use
 // of `lds` overlap the first exchange (a barrier between tiles suffices).
-template <int METRIC, int VN, int KC, int NS, int ST, class Q, class LK>
+// DL (0: NS - 2) is the number of rows between a row's label request and
+// its lookups; the lookups then have NS - 1 - DL rows to arrive.
+template <int METRIC, int VN, int KC, int NS, int ST, class Q, class LK, int DL = 0>
 __device__ __forceinline__ void flood_quad_id_tile(const uint32_t *src, uint32_t *dst,
                                                    const LK &lk, int32_t W, int32_t H,
                                                    int32_t k, const FloodGrid &g,
@@ -390,7 +392,8 @@ __device__ __forceinline__ void flood_quad_id_tile(const uint32_t *src, uint32_t
     const int32_t o2 = t < h / 2 ? 4 * (tl.x0 - h + kTWQ + kQuad * t) : INT32_MIN;
     const bool wave2 = __builtin_amdgcn_readfirstlane(t & ~63) < h / 2;   // any lane of the wave
     const uint32_t step_bytes = 4u * (uint32_t)k * (uint32_t)W;
-    constexpr int D = NS - 2;   // rows between a row's label request and its lookups
+    constexpr int D = DL > 0 ? DL : NS - 2;   // rows between a row's label request and its lookups
+    static_assert(D >= 1 && D <= NS - 2, "lookups need one row after the labels, one before use");
     struct Slot_ {
         G4 g1, g2;   // groups t and 256 + t
     };

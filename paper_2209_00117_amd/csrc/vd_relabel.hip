@@ -12,7 +12,7 @@ namespace vd {
 
 namespace {
 
-template <int METRIC, int VN, int NS, int ST, bool WIDE>
+template <int METRIC, int VN, int NS, int ST, bool WIDE, int DL>
 __global__ void __launch_bounds__(kBlock) k_flood_quad_relabel(const uint32_t *__restrict__ src,
                                                                uint32_t *__restrict__ dst,
                                                                const uint32_t *__restrict__ idx,
@@ -23,8 +23,17 @@ __global__ void __launch_bounds__(kBlock) k_flood_quad_relabel(const uint32_t *_
     __shared__ Q lds[2];
     const RelabelLookup lk{
         __builtin_amdgcn_make_buffer_rsrc((void *)idx, 0, 4 * W * H, kRsrcWord3), W};
-    flood_quad_id_tile<METRIC, VN, 0, NS, ST>(src, dst, lk, W, H, k, g,
-                                              xcd_logical(blockIdx.x, g.nblocks), lds);
+    // Tiles are taken segment-major: consecutive tiles (and so each XCD's
+    // run of them) are the segments of all residue chains that cover one
+    // band of rows, so the index lines of the old positions in that band --
+    // each cell's rows lie on different chains -- are fetched into one L2
+    // and reused there.  The tile function numbers tiles chain-major.
+    const uint32_t nres = g.nblocks / (g.ncol * g.nseg);
+    const uint32_t t = xcd_logical(blockIdx.x, g.nblocks);
+    const uint32_t col = t % g.ncol, rs = t / g.ncol;
+    const uint32_t seg = rs / nres, res = rs % nres;
+    flood_quad_id_tile<METRIC, VN, 0, NS, ST, Q, RelabelLookup, DL>(
+        src, dst, lk, W, H, k, g, (res * g.nseg + seg) * g.ncol + col, lds);
 }
 
 }  // namespace
@@ -43,26 +52,31 @@ hipError_t launch_flood_relabel(const uint32_t *src, uint32_t *dst, const uint32
     const FloodGrid g = flood_grid_quad(W, H, k, seg_rows);
     if (g.nblocks == 0) return hipErrorInvalidValue;
     const dim3 grid(g.nblocks), block(kBlock);
+    // rows in flight: 3 (labels one row ahead of their gathers, gathers one
+    // row ahead of use), 4 with the gathers one row ahead (base variants 2)
+    // or two rows ahead (5, for their latency)
     const int base = variant % (kFloodVariants / 2);
-    const bool ns4 = base == 2 || base == 5;          // rows requested three ahead
+    const int rows = base == 2 ? 1 : (base == 5 ? 2 : 0);
     const bool nt = variant >= kFloodVariants / 2;    // non-temporal stores
     const bool wide = k > kMaxLdsStep;
-#define VD_RL(MT, V, NS, ST)                                                                 \
+#define VD_RL(MT, V, NS, ST, DL)                                                             \
     do {                                                                                     \
         if (wide)                                                                            \
-            hipLaunchKernelGGL((k_flood_quad_relabel<MT, V, NS, ST, true>), grid, block, 0, s, \
-                               src, dst, idx, W, H, k, g);                                   \
-        else                                                                                 \
-            hipLaunchKernelGGL((k_flood_quad_relabel<MT, V, NS, ST, false>), grid, block, 0, \
+            hipLaunchKernelGGL((k_flood_quad_relabel<MT, V, NS, ST, true, DL>), grid, block, 0, \
                                s, src, dst, idx, W, H, k, g);                                \
+        else                                                                                 \
+            hipLaunchKernelGGL((k_flood_quad_relabel<MT, V, NS, ST, false, DL>), grid, block, \
+                               0, s, src, dst, idx, W, H, k, g);                             \
     } while (0)
-#define VD_RL_ST(MT, V, NS)                                                                  \
+#define VD_RL_ST(MT, V, NS, DL)                                                              \
     do {                                                                                     \
-        if (nt) VD_RL(MT, V, NS, kStoreNT); else VD_RL(MT, V, NS, 0);                        \
+        if (nt) VD_RL(MT, V, NS, kStoreNT, DL); else VD_RL(MT, V, NS, 0, DL);                \
     } while (0)
 #define VD_RL_NS(MT, V)                                                                      \
     do {                                                                                     \
-        if (ns4) VD_RL_ST(MT, V, 4); else VD_RL_ST(MT, V, 3);                                \
+        if (rows == 1) VD_RL_ST(MT, V, 4, 2);                                                \
+        else if (rows == 2) VD_RL_ST(MT, V, 4, 1);                                           \
+        else VD_RL_ST(MT, V, 3, 1);                                                          \
     } while (0)
     if (metric == kEuclid) {
         if (vn) VD_RL_NS(kEuclid, 1); else VD_RL_NS(kEuclid, 0);
