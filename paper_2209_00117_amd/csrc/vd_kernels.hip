@@ -385,7 +385,8 @@ __global__ void __launch_bounds__(kBlock) k_flood_quad_id(const uint32_t *__rest
     __shared__ Q lds[2];
     const TableLookup lk{table_rsrc(table, S)};
     flood_quad_id_tile<METRIC, VN, KC, NS, ST>(src, dst, lk, W, H, k, g,
-                                               xcd_logical(blockIdx.x, g.nblocks), lds);
+                                               seg_major(xcd_logical(blockIdx.x, g.nblocks), g),
+                                               lds);
 }
 
 template <int METRIC, int VN, int NS, int ST>

@@ -137,6 +137,18 @@ __device__ __forceinline__ TileQ decode_tile_q(uint32_t logical, const FloodGrid
     return t;
 }
 
+// Tile t of a segment-major order, as the chain-major number the tile
+// functions decode: consecutive tiles (and so each XCD's run of them) are
+// the segments of all residue chains that cover one band of rows, so what
+// the labels of that band look up -- seed-table entries, index lines --
+// stays in one L2.
+__device__ __forceinline__ uint32_t seg_major(uint32_t t, const FloodGrid &g)
+{
+    const uint32_t nres = g.nblocks / (g.ncol * g.nseg);
+    const uint32_t col = t % g.ncol, rs = t / g.ncol;
+    return ((rs % nres) * g.nseg + rs / nres) * g.ncol + col;
+}
+
 template <int N>
 using IC = std::integral_constant<int, N>;
 

@@ -23,17 +23,11 @@ __global__ void __launch_bounds__(kBlock) k_flood_quad_relabel(const uint32_t *_
     __shared__ Q lds[2];
     const RelabelLookup lk{
         __builtin_amdgcn_make_buffer_rsrc((void *)idx, 0, 4 * W * H, kRsrcWord3), W};
-    // Tiles are taken segment-major: consecutive tiles (and so each XCD's
-    // run of them) are the segments of all residue chains that cover one
-    // band of rows, so the index lines of the old positions in that band --
-    // each cell's rows lie on different chains -- are fetched into one L2
-    // and reused there.  The tile function numbers tiles chain-major.
-    const uint32_t nres = g.nblocks / (g.ncol * g.nseg);
-    const uint32_t t = xcd_logical(blockIdx.x, g.nblocks);
-    const uint32_t col = t % g.ncol, rs = t / g.ncol;
-    const uint32_t seg = rs / nres, res = rs % nres;
+    // Tiles are taken segment-major: the index lines of the old positions in
+    // one band of rows -- each cell's rows lie on different chains -- are
+    // fetched into one L2 and reused there.
     flood_quad_id_tile<METRIC, VN, 0, NS, ST, Q, RelabelLookup, DL>(
-        src, dst, lk, W, H, k, g, (res * g.nseg + seg) * g.ncol + col, lds);
+        src, dst, lk, W, H, k, g, seg_major(xcd_logical(blockIdx.x, g.nblocks), g), lds);
 }
 
 }  // namespace
