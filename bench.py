@@ -50,7 +50,7 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, published peak
 BYTES_PER_PIXEL_UPDATE = 8     # one 4-byte label read + one 4-byte label write per pass
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2209_00117_amd", "csrc", f)
                   for f in ("vd_device.h", "vd_quad.h", "vd_tail.h", "vd_kernels.hip",
-                            "vd_kernels.h")]
+                            "vd_kernels.h", "vd_relabel.hip")]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "flood_traffic.json")
 
 
