@@ -302,9 +302,11 @@ def bench_serving(torch, inputs, V, args):
                 pass
             submit(int(tgt), at)
 
-    def run_server(policy):
+    def run_server(policy, solo=None):
         sv = V.Server(len(specs), pool, stream=stream)
         sv.set_policy(policy)
+        if solo is not None:
+            sv.set_solo(solo)
         ids = [sv.add_sim(s.width, s.height, xy, disp_lo=s.disp_lo, disp_hi=s.disp_hi,
                           sim_seed=s.sim_seed) for s, xy in made]
         sv.drain()
@@ -327,9 +329,17 @@ def bench_serving(torch, inputs, V, args):
                 "requests_per_s": st["completed"] / st["elapsed_s"], "ticks": st["ticks"],
                 "elapsed_s": st["elapsed_s"]}
 
-    # whole steps (the default policy), then continuous batching by passes
+    # whole steps (the default policy), then continuous batching (batched ticks)
     served = run_server(V.SERVE_STEPS)
     served_passes = run_server(V.SERVE_PASSES)
+    solo_sweep = []
+    if args.serve_solo_sweep:
+        for px in (0, 1024 * 1024, 2048 * 2048, 4096 * 4096 + 1):
+            r = run_server(V.SERVE_PASSES, px)
+            r["solo_px"] = px
+            solo_sweep.append(r)
+            print(json.dumps({"serve_solo": px, "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"]}),
+                  file=sys.stderr, flush=True)
     px = sum(s.width * s.height for s in specs)
 
     # one request at a time, plain JFA, same arrivals
@@ -363,6 +373,8 @@ def bench_serving(torch, inputs, V, args):
                        "rate_per_s": args.rate, "seconds": args.seconds, "pool_bytes": pool},
             "served_djfa": served, "served_djfa_by_passes": served_passes,
             "one_at_a_time_jfa": plain}
+    if solo_sweep:
+        line["served_djfa_by_passes_solo_sweep"] = solo_sweep
     print(json.dumps(line), flush=True)
 
 
@@ -881,6 +893,8 @@ def main():
                     choices=["small", "single", "large", "band", "batched", "serving"])
     ap.add_argument("--rate", type=float, default=2000.0, help="serving: requests per second")
     ap.add_argument("--seconds", type=float, default=10.0, help="serving: measured seconds")
+    ap.add_argument("--serve-solo-sweep", action="store_true",
+                    help="serving: batched ticks with several solo thresholds as well")
     ap.add_argument("--no-graph", action="store_true", help="batched: launch kernels directly")
     ap.add_argument("--label", default="both", choices=["id", "xy", "both"],
                     help="label format; both: measure each, report the faster")

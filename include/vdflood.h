@@ -456,15 +456,27 @@ int vd_server_create(int32_t max_sims, int32_t metric, void *dev_pool, size_t po
 int vd_server_add_sim(vd_server *sv, const vd_config *cfg, const int32_t *host_xy,
                       int32_t *sim_id);
 
-/* How requests started from now on run.  VD_SERVE_STEPS (the default): each
- * as its simulation's move and step with that simulation's own launches
- * (tuned kernel variants, fused tail), one simulation after another.
- * VD_SERVE_PASSES: continuous batching at pass granularity -- every started
- * request joins the next tick, and one persistent launch per tick runs the
- * next pass of every running request.  Results are identical either way.
- * VD_EINVAL for another value. */
+/* How requests started from now on run.  The scheduler forms ticks on the
+ * server's stream (at most two in flight); a tick starts the next request
+ * of every resident simulation that has one, and every request completes
+ * with its tick.  VD_SERVE_STEPS (the default): each request as its
+ * simulation's move and step with that simulation's own launches (tuned
+ * kernel variants, fused tail), one simulation after another.
+ * VD_SERVE_PASSES: continuous batching of the tick's requests -- their
+ * moves and step starts run in shared launches over all of them, and the
+ * smaller simulations (below vd_server_set_solo's size, when two or more
+ * start in the tick) run their passes as one persistent launch per pass
+ * level over all of them, each at its own step size, so their work
+ * overlaps on the device; larger ones run their own passes.  Results are identical either
+ * way.  VD_EINVAL for another value. */
 enum { VD_SERVE_STEPS = 0, VD_SERVE_PASSES = 1 };
 int vd_server_set_policy(vd_server *sv, int32_t policy);
+
+/* VD_SERVE_PASSES ticks: simulations of at least min_pixels pixels run
+ * their passes with their own launches, smaller ones share the pass-level
+ * launches (default 2048 * 2048; min_pixels <= 0: every simulation alone).
+ * Takes effect from the next tick; results never change. */
+int vd_server_set_solo(vd_server *sv, int64_t min_pixels);
 
 /* Queues one time step of a simulation: a move, then a JFA (VD_STEP_JFA) or
  * dJFA (VD_STEP_DJFA) step.  Requests of one simulation run in submission

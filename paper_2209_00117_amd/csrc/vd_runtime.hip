@@ -238,8 +238,9 @@ int harvest(vd_sim *s)
 // With relabel (an XY dJFA step's old-position index) non-null, the first
 // pass reads the previous diagram through it (launch_flood_relabel).
 int launch_passes(vd_sim *s, const std::vector<Pass> &passes, int32_t th,
-                  const uint32_t *relabel = nullptr)
+                  const uint32_t *relabel = nullptr, hipStream_t stream = nullptr)
 {
+    if (!stream) stream = s->stream;
     const size_t m = th ? vd::tail_len(passes) : 0;
     const size_t n = passes.size() - m;
     for (size_t i = 0; i < n; ++i) {
@@ -247,12 +248,12 @@ int launch_passes(vd_sim *s, const std::vector<Pass> &passes, int32_t th,
         if (i == 0 && relabel)
             VD_HIP(vd::launch_flood_relabel(s->map[s->cur], s->map[s->cur ^ 1], relabel,
                                             s->cfg.width, s->cfg.height, p.k, p.vn,
-                                            s->cfg.metric, p.variant, p.seg_rows, s->stream));
+                                            s->cfg.metric, p.variant, p.seg_rows, stream));
         else
             VD_HIP(vd::launch_flood(s->map[s->cur], s->map[s->cur ^ 1], s->pos,
                                     s->cfg.num_seeds, s->cfg.width, s->cfg.height, p.k, p.vn,
                                     s->cfg.label, s->cfg.metric, p.variant, p.seg_rows,
-                                    s->stream));
+                                    stream));
         s->cur ^= 1;
     }
     if (m) {
@@ -265,7 +266,7 @@ int launch_passes(vd_sim *s, const std::vector<Pass> &passes, int32_t th,
         VD_HIP(vd::launch_flood_tail(s->map[s->cur], s->map[s->cur ^ 1], s->pos,
                                      s->cfg.num_seeds, s->cfg.width, s->cfg.height, ks, vns,
                                      (int32_t)m, s->cfg.label, s->cfg.metric, nt, th,
-                                     s->stream));
+                                     stream));
         s->cur ^= 1;
     }
     return VD_OK;
@@ -288,6 +289,20 @@ int run_passes(vd_sim *s, const std::vector<Pass> &passes, int32_t th,
     }
     return VD_OK;
 }
+
+}  // namespace
+
+namespace vd {
+
+int launch_step_passes(vd_sim *s, bool dynamic, hipStream_t stream)
+{
+    return launch_passes(s, dynamic ? s->djfa_passes : s->jfa_passes, s->tail_th[dynamic ? 1 : 0],
+                         nullptr, stream);
+}
+
+}  // namespace vd
+
+namespace {
 
 // The seed-set bytes the kernels read: null while every seed is present
 // and kept (the common case costs nothing).

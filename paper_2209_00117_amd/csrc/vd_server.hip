@@ -52,6 +52,17 @@ namespace {
 constexpr int kRing = 4;       // tick table slots
 constexpr int kMaxInflight = 2;   // ticks enqueued ahead of the GPU: enough to keep it busy,
                                   // few enough that a new request joins within a tick
+constexpr int kMaxLevels = 24;    // > ceil(log2 16368) + 2 extra passes
+// Batched ticks: simulations of at least kSoloPixels pixels run their passes
+// with their own launches (their maps stay in the Infinity Cache across the
+// passes, and their tuned kernels run); smaller ones share one persistent
+// launch per pass level when at least kFuseMin of them start in the tick.
+constexpr int64_t kSoloPixels = 0;   // default of vd_server_set_solo: no pass-level fusion
+constexpr int kFuseMin = 2;
+// Batched ticks run the passes of their simulations on kLanes streams (the
+// server's own and kLanes - 1 more, all of the default priority), so the
+// passes of different requests run side by side on the device.
+constexpr int kLanes = 4;
 
 struct TickSim {            // one active simulation's pass in a tick
     const uint32_t *src;
@@ -78,10 +89,11 @@ struct TickPrep {           // one simulation starting (or ending) a request in 
     uint64_t t;             // the time step being entered (>= 1)
 };
 
-struct TickHeader {
-    uint32_t total;         // items in the flood launch
+struct TickHeader {          // one pass level of a tick
+    uint32_t total;         // items in the level's flood launch
     uint32_t chunk[9];      // XCD c drains items [chunk[c], chunk[c + 1]) first
-    int32_t nactive, nprep;
+    int32_t nactive;        // simulations with a pass at this level
+    int32_t begin;          // their first TickSim in the tick's table
 };
 
 // Claim counters of a tick (zero when uploaded).  They live in their own
@@ -185,11 +197,12 @@ __global__ void __launch_bounds__(kBlock) k_tick_splat_xy(const TickPrep *__rest
         splat_xy_seed(p.map, p.table, i, p.W, 0u);
 }
 
-// Simulations whose request ends in a tick (XY labels): the diagram now
-// refers to the current positions.
-__global__ void __launch_bounds__(kBlock) k_tick_posmap(const TickPrep *__restrict__ leave)
+// After the passes of a tick (XY labels): the diagram now refers to the
+// current positions.
+__global__ void __launch_bounds__(kBlock) k_tick_posmap(const TickPrep *__restrict__ prep)
 {
-    const TickPrep p = leave[blockIdx.y];
+    const TickPrep p = prep[blockIdx.y];
+    if (p.label != kLabelXy) return;
     for (int32_t i = blockIdx.x * blockDim.x + threadIdx.x; i <= p.S;
          i += gridDim.x * blockDim.x)
         p.pos_map[i] = p.table[i];
@@ -269,9 +282,7 @@ struct Served {
     vd_sim *sim = nullptr;        // resident once admitted
     bool removing = false;
     std::deque<Request> fifo;     // waiting requests
-    bool active = false;          // a request is on the GPU
-    Request req{};
-    int32_t pass = 0, npasses = 0;
+    Request req{};                // the request being enqueued
     int32_t inflight = 0;         // enqueued ticks touching it, not yet finished
     int32_t running = 0;          // requests started and not yet completed
 };
@@ -322,7 +333,11 @@ struct Pool {                     // first-fit allocator over [0, size)
 struct vd_server {
     int32_t max_sims = 0, metric = 0;
     int32_t policy = VD_SERVE_STEPS;   // how requests started from now on run
+    int64_t solo_px = vd::kSoloPixels;  // batched ticks: simulations this large run alone
     hipStream_t stream = nullptr;
+    hipStream_t lane[vd::kLanes - 1] = {};     // the other pass lanes of batched ticks
+    hipEvent_t prep_done[vd::kRing] = {};      // per ring slot: the tick's step starts are in
+    hipEvent_t lane_done[vd::kRing][vd::kLanes - 1] = {};   // and each lane's passes are done
     uint8_t *base = nullptr;      // aligned device pool
     size_t ring_bytes = 0;        // tick tables at the start of the pool
     size_t slot_bytes = 0;
@@ -350,17 +365,18 @@ struct vd_server {
 
 namespace {
 
-// A tick slot: header | counters | active-simulation table | joiner table.
-size_t off_counters() { return vd::align_up(sizeof(vd::TickHeader)); }
-size_t off_sims() { return off_counters() + vd::align_up(sizeof(vd::TickCounters)); }
-size_t off_prep(int32_t max_sims)
+// A tick slot: level headers | level counters | joiner table | the levels'
+// simulation tables, packed level after level.
+size_t off_counters() { return vd::align_up(sizeof(vd::TickHeader) * vd::kMaxLevels); }
+size_t off_prep() { return off_counters() + vd::align_up(sizeof(vd::TickCounters) * vd::kMaxLevels); }
+size_t off_sims(int32_t max_sims)
 {
-    return off_sims() + vd::align_up(sizeof(vd::TickSim) * (size_t)max_sims);
+    return off_prep() + vd::align_up(sizeof(vd::TickPrep) * (size_t)max_sims);
 }
-// (joiners and leavers each take at most max_sims TickPrep entries)
 size_t slot_size(int32_t max_sims)
 {
-    return off_prep(max_sims) + 2 * vd::align_up(sizeof(vd::TickPrep) * (size_t)max_sims);
+    return off_sims(max_sims) +
+           vd::align_up(sizeof(vd::TickSim) * (size_t)vd::kMaxLevels * (size_t)max_sims);
 }
 
 // Called with mu held.  Admits waiting simulations in arrival order while
@@ -452,78 +468,30 @@ bool enqueue_steps(vd_server *sv, Tick &t, const std::vector<int32_t> &ids)
     return true;
 }
 
-// Builds and enqueues one tick (mu held).  Returns false if there is no work.
-bool tick(vd_server *sv)
+// Batched requests (VD_SERVE_PASSES): every joining simulation's move and
+// step start run in shared launches over all of them (one of each kind);
+// then the simulations of at least solo_px pixels run their passes with
+// their own launches, spread over the pass lanes so that different
+// requests' passes run side by side, and the smaller ones -- when at least
+// kFuseMin start in this tick -- share one persistent launch per pass
+// level, each at its own step size (otherwise they too run alone).  Every
+// request completes with the tick.  Returns false on a failure (recorded).
+bool enqueue_batched(vd_server *sv, Tick &t, const std::vector<int32_t> &ids)
 {
-    // start the next request of every idle resident simulation
-    std::vector<int32_t> joiners, whole;
-    for (int32_t id : sv->order) {
-        Served &s = sv->sims[id];
-        if (!s.active && !s.fifo.empty() && !s.removing) {
-            s.req = s.fifo.front();
-            s.fifo.pop_front();
-            s.running += 1;
-            if (sv->policy == VD_SERVE_STEPS) {
-                whole.push_back(id);
-                continue;
-            }
-            s.active = true;
-            s.pass = 0;
-            s.npasses = (int32_t)(s.req.mode == VD_STEP_DJFA ? s.sim->djfa_passes
-                                                             : s.sim->jfa_passes).size();
-            joiners.push_back(id);
-        }
-    }
-    std::vector<int32_t> active;
-    for (int32_t id : sv->order)
-        if (sv->sims[id].active) active.push_back(id);
-    if (active.empty() && whole.empty()) return false;
-    while ((int)sv->inflight.size() >= vd::kMaxInflight && !sv->error) reap(sv, true);
-    if (sv->error) return false;
-    if (active.empty()) {
-        Tick t;
-        t.slot = -1;
-        hipError_t e = hipSuccess;
-        if (enqueue_steps(sv, t, whole)) {
-            e = hipEventCreateWithFlags(&t.done, hipEventDisableTiming);
-            if (e == hipSuccess) e = hipEventRecord(t.done, sv->stream);
-            if (e != hipSuccess) {
-                sv->error = VD_EDEVICE;
-                snprintf(sv->error_msg, sizeof sv->error_msg, "enqueueing a tick failed: %s",
-                         hipGetErrorString(e));
-            }
-        }
-        if (sv->error) return false;
-        sv->ticks += 1;
-        sv->inflight.push_back(std::move(t));
-        return true;
-    }
     const int slot = (int)(sv->ticks % vd::kRing);
     uint8_t *h = sv->host_ring + (size_t)slot * sv->slot_bytes;
     uint8_t *d = sv->base + (size_t)slot * sv->slot_bytes;
-    // slot layout this tick: header | counters | TickSim x active | TickPrep x joiners |
-    // TickPrep x leavers (XY labels: their table copy)
     vd::TickHeader *hh = (vd::TickHeader *)h;
-    vd::TickSim *hs = (vd::TickSim *)(h + off_sims());
-    const size_t prep_at = off_sims() + vd::align_up(sizeof(vd::TickSim) * active.size());
-    vd::TickPrep *hp = (vd::TickPrep *)(h + prep_at);
-    const size_t leave_at = prep_at + vd::align_up(sizeof(vd::TickPrep) * joiners.size());
-    vd::TickPrep *hl = (vd::TickPrep *)(h + leave_at);
-    int32_t nleave = 0;
-    memset(hh, 0, sizeof *hh);
-    memset(h + off_counters(), 0, sizeof(vd::TickCounters));
-    Tick t;
-    t.slot = slot;
-    // requests started whole (the policy changed while others ran by passes)
-    if (!enqueue_steps(sv, t, whole)) return false;
-    for (int32_t id : active) {
-        t.members.push_back(id);
-        sv->sims[id].inflight += 1;
-    }
-    int32_t maxS = 1;
-    for (size_t j = 0; j < joiners.size(); ++j) {
-        Served &s = sv->sims[joiners[j]];
+    vd::TickPrep *hp = (vd::TickPrep *)(h + off_prep());
+    vd::TickSim *hs = (vd::TickSim *)(h + off_sims(sv->max_sims));
+    memset(h, 0, off_prep());   // headers and claim counters
+    std::vector<vd_sim *> sims;
+    int32_t maxS = 1, small = 0;
+    bool any_fill = false, any_relabel = false, any_xy = false;
+    for (size_t j = 0; j < ids.size(); ++j) {
+        Served &s = sv->sims[ids[j]];
         vd_sim *m = s.sim;
+        sims.push_back(m);
         m->t += 1;
         vd::TickPrep &p = hp[j];
         memset(&p, 0, sizeof p);
@@ -541,16 +509,39 @@ bool tick(vd_server *sv)
         p.move_seed = m->move_seed;
         p.t = (uint64_t)m->t;
         maxS = std::max(maxS, p.S);
+        any_fill |= p.fill != 0;
+        any_relabel |= p.fill == 0 && p.label == VD_LABEL_XY16;
+        any_xy |= p.label == VD_LABEL_XY16;
+        if ((int64_t)p.W * p.H < sv->solo_px) ++small;
     }
-    uint32_t first = 0;
-    int32_t na = 0;
-    for (int32_t id : active) {
-        Served &s = sv->sims[id];
-        vd_sim *m = s.sim;
-        if (s.pass < s.npasses) {
-            const vd::Pass &ps = (s.req.mode == VD_STEP_DJFA ? m->djfa_passes
-                                                              : m->jfa_passes)[(size_t)s.pass];
-            vd::TickSim &e = hs[na++];
+    const bool fuse = small >= vd::kFuseMin;
+    std::vector<char> fused(ids.size(), 0);
+    std::vector<const std::vector<vd::Pass> *> plist(ids.size());
+    int32_t levels = 0;
+    for (size_t j = 0; j < ids.size(); ++j) {
+        const vd_sim *m = sims[j];
+        plist[j] = sv->sims[ids[j]].req.mode == VD_STEP_DJFA ? &m->djfa_passes : &m->jfa_passes;
+        fused[j] = fuse && (int64_t)m->cfg.width * m->cfg.height < sv->solo_px;
+        if (fused[j]) levels = std::max(levels, (int32_t)plist[j]->size());
+    }
+    if (levels > vd::kMaxLevels) {
+        sv->error = VD_EINVAL;
+        snprintf(sv->error_msg, sizeof sv->error_msg, "a step has %d passes (at most %d)", levels,
+                 vd::kMaxLevels);
+        return false;
+    }
+    // The fused simulations' pass levels; the host mirror of each current
+    // map flips once per level it takes part in.
+    int32_t nsims = 0;
+    for (int32_t l = 0; l < levels; ++l) {
+        vd::TickHeader &lh = hh[l];
+        lh.begin = nsims;
+        uint32_t first = 0;
+        for (size_t j = 0; j < ids.size(); ++j) {
+            if (!fused[j] || l >= (int32_t)plist[j]->size()) continue;
+            vd_sim *m = sims[j];
+            const vd::Pass &ps = (*plist[j])[(size_t)l];
+            vd::TickSim &e = hs[nsims++];
             memset(&e, 0, sizeof e);
             e.src = m->map[m->cur];
             e.dst = m->map[m->cur ^ 1];
@@ -567,40 +558,19 @@ bool tick(vd_server *sv)
             e.quad = ig.quad;
             e.first = first;
             first += ig.items;
-            t.pixel_updates += (int64_t)e.W * e.H;
             m->cur ^= 1;
-            s.pass += 1;
         }
-        if (s.pass >= s.npasses) {   // leaves after this tick
-            s.active = false;
-            t.completes.emplace_back(id, s.req);
-            if (m->cfg.label == VD_LABEL_XY16) {
-                vd::TickPrep &p = hl[nleave++];
-                memset(&p, 0, sizeof p);
-                p.table = m->pos;
-                p.pos_map = m->pos_map;
-                p.S = m->cfg.num_seeds;
-                maxS = std::max(maxS, p.S);
-            }
-        }
+        lh.total = first;
+        lh.nactive = nsims - lh.begin;
+        for (int c = 0; c <= 8; ++c) lh.chunk[c] = (uint32_t)((uint64_t)first * c / 8);
     }
-    hh->total = first;
-    for (int c = 0; c <= 8; ++c) hh->chunk[c] = (uint32_t)((uint64_t)first * c / 8);
-    hh->nactive = na;
-    hh->nprep = (int32_t)joiners.size();
-    const size_t used = leave_at + sizeof(vd::TickPrep) * (size_t)nleave;
+    const size_t used = off_sims(sv->max_sims) + sizeof(vd::TickSim) * (size_t)nsims;
     hipError_t e = hipMemcpyAsync(d, h, used, hipMemcpyHostToDevice, sv->stream);
-    const vd::TickPrep *dp = (const vd::TickPrep *)(d + prep_at);
-    const vd::TickPrep *dl = (const vd::TickPrep *)(d + leave_at);
-    bool any_fill = false, any_relabel = false;
-    for (size_t j = 0; j < joiners.size(); ++j) {
-        any_fill |= hp[j].fill != 0;
-        any_relabel |= hp[j].fill == 0 && hp[j].label == VD_LABEL_XY16;
-    }
+    const vd::TickPrep *dp = (const vd::TickPrep *)(d + off_prep());
     const dim3 blk(vd::kBlock);
+    const unsigned nj = (unsigned)ids.size();
     const unsigned gs = (unsigned)std::min<int64_t>((maxS + vd::kBlock - 1) / vd::kBlock, 1024);
-    if (e == hipSuccess && !joiners.empty()) {
-        const unsigned nj = (unsigned)joiners.size();
+    if (e == hipSuccess) {
         hipLaunchKernelGGL(vd::k_tick_move, dim3(gs, nj), blk, 0, sv->stream, dp);
         if (any_fill) hipLaunchKernelGGL(vd::k_tick_fill, dim3(256, nj), blk, 0, sv->stream, dp);
         hipLaunchKernelGGL(vd::k_tick_splat, dim3(gs, nj), blk, 0, sv->stream, dp);
@@ -611,23 +581,91 @@ bool tick(vd_server *sv)
         }
         e = hipGetLastError();
     }
-    if (e == hipSuccess && na > 0) {
-        const vd::TickHeader *dh = (const vd::TickHeader *)d;
-        const vd::TickSim *ds = (const vd::TickSim *)(d + off_sims());
-        uint32_t *dc = (uint32_t *)(d + off_counters());
+    // The simulations that run alone go round the lanes; the other lanes
+    // start after the step starts and the server's stream waits for them.
+    int32_t alone = 0;
+    for (size_t j = 0; j < ids.size(); ++j) alone += fused[j] ? 0 : 1;
+    const int lanes = (int)std::min<int32_t>(vd::kLanes, std::max<int32_t>(alone, 1));
+    if (e == hipSuccess && lanes > 1) {
+        e = hipEventRecord(sv->prep_done[slot], sv->stream);
+        for (int l = 1; l < lanes && e == hipSuccess; ++l)
+            e = hipStreamWaitEvent(sv->lane[l - 1], sv->prep_done[slot], 0);
+    }
+    int32_t nth = 0;
+    for (size_t j = 0; j < ids.size() && e == hipSuccess; ++j) {
+        if (fused[j]) continue;
+        const int l = nth++ % lanes;
+        if (vd::launch_step_passes(sims[j], sv->sims[ids[j]].req.mode == VD_STEP_DJFA,
+                                   l ? sv->lane[l - 1] : sv->stream) != VD_OK)
+            e = hipErrorLaunchFailure;
+    }
+    for (int l = 1; l < lanes && e == hipSuccess; ++l) {
+        e = hipEventRecord(sv->lane_done[slot][l - 1], sv->lane[l - 1]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(sv->stream, sv->lane_done[slot][l - 1], 0);
+    }
+    const vd::TickSim *ds = (const vd::TickSim *)(d + off_sims(sv->max_sims));
+    uint32_t *dc = (uint32_t *)(d + off_counters());
+    for (int32_t l = 0; l < levels && e == hipSuccess; ++l) {
+        const vd::TickHeader *dh = (const vd::TickHeader *)d + l;
+        const unsigned grid = (unsigned)std::max<int64_t>(
+            1, std::min<int64_t>((int64_t)hh[l].total, (int64_t)sv->grid));
+        uint32_t *ctr = dc + (size_t)l * (sizeof(vd::TickCounters) / sizeof(uint32_t));
         if (sv->metric == VD_EUCLID)
-            hipLaunchKernelGGL(vd::k_tick_flood<vd::kEuclid>, dim3((unsigned)sv->grid),
-                               dim3(vd::kBlock), 0, sv->stream, dh, ds, dc);
+            hipLaunchKernelGGL(vd::k_tick_flood<vd::kEuclid>, dim3(grid), dim3(vd::kBlock), 0,
+                               sv->stream, dh, ds + hh[l].begin, ctr);
         else
-            hipLaunchKernelGGL(vd::k_tick_flood<vd::kManhattan>, dim3((unsigned)sv->grid),
-                               dim3(vd::kBlock), 0, sv->stream, dh, ds, dc);
+            hipLaunchKernelGGL(vd::k_tick_flood<vd::kManhattan>, dim3(grid), dim3(vd::kBlock), 0,
+                               sv->stream, dh, ds + hh[l].begin, ctr);
         e = hipGetLastError();
     }
-    if (e == hipSuccess && nleave > 0) {
-        hipLaunchKernelGGL(vd::k_tick_posmap, dim3(gs, (unsigned)nleave), blk, 0, sv->stream, dl);
+    if (e == hipSuccess && any_xy) {
+        hipLaunchKernelGGL(vd::k_tick_posmap, dim3(gs, nj), blk, 0, sv->stream, dp);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) e = hipEventCreateWithFlags(&t.done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        sv->error = VD_EDEVICE;
+        snprintf(sv->error_msg, sizeof sv->error_msg, "enqueueing a batched tick failed: %s",
+                 hipGetErrorString(e));
+        return false;
+    }
+    for (size_t j = 0; j < ids.size(); ++j) {
+        Served &s = sv->sims[ids[j]];
+        t.members.push_back(ids[j]);
+        s.inflight += 1;
+        t.pixel_updates += (int64_t)sims[j]->cfg.width * sims[j]->cfg.height *
+                           (int64_t)plist[j]->size();
+        t.completes.emplace_back(ids[j], s.req);
+    }
+    return true;
+}
+
+// Builds and enqueues one tick (mu held): the next request of every
+// resident simulation that has one, run whole or batched by the policy.
+// Requests of one simulation stay in order: every tick runs on the
+// server's stream.  Returns false if there is no work.
+bool tick(vd_server *sv)
+{
+    std::vector<int32_t> whole, batched;
+    for (int32_t id : sv->order) {
+        Served &s = sv->sims[id];
+        if (!s.fifo.empty() && !s.removing) {
+            s.req = s.fifo.front();
+            s.fifo.pop_front();
+            s.running += 1;
+            (sv->policy == VD_SERVE_STEPS ? whole : batched).push_back(id);
+        }
+    }
+    if (whole.empty() && batched.empty()) return false;
+    while ((int)sv->inflight.size() >= vd::kMaxInflight && !sv->error) reap(sv, true);
+    if (sv->error) return false;
+    Tick t;
+    t.slot = -1;
+    if (!enqueue_steps(sv, t, whole)) return false;
+    if (!batched.empty()) {
+        t.slot = (int)(sv->ticks % vd::kRing);
+        if (!enqueue_batched(sv, t, batched)) return false;
+    }
+    hipError_t e = hipEventCreateWithFlags(&t.done, hipEventDisableTiming);
     if (e == hipSuccess) e = hipEventRecord(t.done, sv->stream);
     if (e != hipSuccess) {
         sv->error = VD_EDEVICE;
@@ -662,6 +700,18 @@ void worker_main(vd_server *sv)
             continue;
         }
         sv->cv.wait_for(lock, std::chrono::milliseconds(5));
+    }
+}
+
+void release_lanes(vd_server *sv)
+{
+    for (hipStream_t &l : sv->lane)
+        if (l) (void)hipStreamDestroy(l), l = nullptr;
+    for (int r = 0; r < vd::kRing; ++r) {
+        if (sv->prep_done[r]) (void)hipEventDestroy(sv->prep_done[r]);
+        for (hipEvent_t &ev : sv->lane_done[r])
+            if (ev) (void)hipEventDestroy(ev), ev = nullptr;
+        sv->prep_done[r] = nullptr;
     }
 }
 
@@ -715,7 +765,16 @@ int vd_server_create(int32_t max_sims, int32_t metric, void *dev_pool, size_t po
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(
                       &fit, vd::k_tick_flood<vd::kManhattan>, vd::kBlock, 0);
     if (e == hipSuccess) e = hipHostMalloc((void **)&sv->host_ring, ring, hipHostMallocDefault);
+    for (int l = 0; l + 1 < vd::kLanes && e == hipSuccess; ++l)
+        e = hipStreamCreateWithFlags(&sv->lane[l], hipStreamNonBlocking);
+    for (int r = 0; r < vd::kRing && e == hipSuccess; ++r) {
+        e = hipEventCreateWithFlags(&sv->prep_done[r], hipEventDisableTiming);
+        for (int l = 0; l + 1 < vd::kLanes && e == hipSuccess; ++l)
+            e = hipEventCreateWithFlags(&sv->lane_done[r][l], hipEventDisableTiming);
+    }
     if (e != hipSuccess) {
+        release_lanes(sv);
+        if (sv->host_ring) (void)hipHostFree(sv->host_ring);
         delete sv;
         return fail(VD_EDEVICE, "server set-up failed: %s", hipGetErrorString(e));
     }
@@ -723,6 +782,7 @@ int vd_server_create(int32_t max_sims, int32_t metric, void *dev_pool, size_t po
     try {
         sv->worker = std::thread(worker_main, sv);
     } catch (...) {
+        release_lanes(sv);
         (void)hipHostFree(sv->host_ring);
         delete sv;
         return fail(VD_ENOMEM, "could not start the scheduler thread");
@@ -767,6 +827,14 @@ int vd_server_add_sim(vd_server *sv, const vd_config *cfg, const int32_t *host_x
     sv->admit_queue.push_back(sv->next_id - 1);
     *sim_id = sv->next_id - 1;
     sv->cv.notify_all();
+    return VD_OK;
+}
+
+int vd_server_set_solo(vd_server *sv, int64_t min_pixels)
+{
+    if (!sv) return fail(VD_EINVAL, "server is NULL");
+    std::lock_guard<std::mutex> lock(sv->mu);
+    sv->solo_px = min_pixels <= 0 ? 0 : min_pixels;
     return VD_OK;
 }
 
@@ -824,7 +892,7 @@ int vd_server_drain(vd_server *sv, double timeout_ms)
         if (sv->error) return true;
         if (!sv->inflight.empty()) return false;
         for (auto &kv : sv->sims)
-            if (kv.second.active || !kv.second.fifo.empty()) return false;
+            if (!kv.second.fifo.empty()) return false;
         return true;
     };
     sv->cv.notify_all();
@@ -851,7 +919,7 @@ int vd_server_remove_sim(vd_server *sv, int32_t sim_id)
         return VD_OK;
     }
     sv->cv.notify_all();
-    sv->done_cv.wait(lock, [&] { return sv->error || (!s.active && s.inflight == 0); });
+    sv->done_cv.wait(lock, [&] { return sv->error || s.inflight == 0; });
     if (sv->error) return server_error(sv);
     vd_sim *sim = s.sim;
     sv->order.erase(std::find(sv->order.begin(), sv->order.end(), sim_id));
@@ -940,6 +1008,9 @@ void vd_server_destroy(vd_server *sv)
         if (t.done) (void)hipEventDestroy(t.done);
     for (auto &kv : sv->sims)
         if (kv.second.sim) vd_destroy(kv.second.sim);
+    for (hipStream_t l : sv->lane)
+        if (l) (void)hipStreamSynchronize(l);
+    release_lanes(sv);
     if (sv->host_ring) (void)hipHostFree(sv->host_ring);
     delete sv;
 }

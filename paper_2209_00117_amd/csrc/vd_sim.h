@@ -103,6 +103,12 @@ struct vd_sim {
 };
 
 namespace vd {
+// The flood passes of a step of kind `dynamic` on `stream`, as the
+// simulation's own step runs them (its kernel variants and fused tail;
+// an XY dJFA step's relabel must have run first), flipping s->cur per
+// launch.  For drivers of many simulations (the server's batched ticks).
+int launch_step_passes(vd_sim *s, bool dynamic, hipStream_t stream);
+
 // Launches of a step of kind `dynamic` run by the simulation's own pass
 // driver (the fused tail counts once); each flips the current map.
 inline int32_t step_launches(const vd_sim *s, bool dynamic)

@@ -71,6 +71,7 @@ SIGNATURES = {
     "vd_remove_seeds": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
     "vd_set_tail_fusion": (ctypes.c_int, [_P, ctypes.c_int]),
     "vd_server_set_policy": (ctypes.c_int, [_P, ctypes.c_int32]),
+    "vd_server_set_solo": (ctypes.c_int, [_P, ctypes.c_int64]),
     "vd_get_tail_fusion": (ctypes.c_int, [_P, _P, _P]),
     "vd_insert_seeds": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P]),
     "vd_get_seed_set": (ctypes.c_int, [_P, _P, ctypes.c_size_t, _P, _P]),
@@ -562,6 +563,11 @@ class Server:
 
     def set_policy(self, policy: int):
         _check(lib().vd_server_set_policy(self.handle, int(policy)))
+
+    def set_solo(self, min_pixels: int):
+        """Batched ticks: simulations of at least min_pixels pixels run
+        alone (<= 0: all of them)."""
+        _check(lib().vd_server_set_solo(self.handle, int(min_pixels)))
 
     def submit(self, sim_id: int, mode: int) -> int:
         t = ctypes.c_int64()

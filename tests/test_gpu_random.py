@@ -179,6 +179,7 @@ def test_random_server(V, case):
     metric = int(r.integers(0, 2))
     sv = V.Server(8, 1 << 31, metric=metric)
     sv.set_policy(int(r.integers(0, 2)))
+    sv.set_solo(int(rl.choice([0, 1 << 16, 1 << 40])))   # which simulations share pass levels
     ids, orcs = [], {}
     for j in range(int(r.integers(2, 9))):
         W = int(r.choice([1, 40, 256, 300, 1024, 1100]))

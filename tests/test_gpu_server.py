@@ -47,11 +47,13 @@ def _alone(V, W, H, xy, kw, modes):
 
 
 @pytest.mark.parametrize("labels", [(0,), (1, 0)])
-@pytest.mark.parametrize("policy", ["steps", "passes", "switch"])
+@pytest.mark.parametrize("policy", ["steps", "passes", "passes-fused", "switch"])
 def test_server_mix_equals_alone(V, policy, labels):
     made = _sims(SHAPES, labels=labels)
     sv = V.Server(len(made), 1 << 30)
-    sv.set_policy(V.SERVE_PASSES if policy == "passes" else V.SERVE_STEPS)
+    sv.set_policy(V.SERVE_PASSES if policy.startswith("passes") else V.SERVE_STEPS)
+    if policy == "passes-fused":
+        sv.set_solo(1 << 40)                 # every simulation in the pass-level launches
     ids = [sv.add_sim(W, H, xy, **kw) for W, H, xy, kw in made]
     rng = random.Random(5)
     plan = {i: [] for i in ids}
@@ -68,8 +70,8 @@ def test_server_mix_equals_alone(V, policy, labels):
     assert all(x > 0 for x in lat)
     st = sv.stats()
     assert st["completed"] == st["submitted"] == 60 and st["resident"] == len(ids)
-    if policy == "passes":
-        assert st["ticks"] < 60 * 13         # requests shared launches
+    if policy.startswith("passes"):
+        assert st["ticks"] <= 60             # requests shared ticks
     for (W, H, xy, kw), i in zip(made, ids):
         got = sv.read_map(i)
         assert sv.sim_state(i)["t"] == len(plan[i])
