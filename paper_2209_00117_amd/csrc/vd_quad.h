@@ -243,12 +243,16 @@ __device__ __forceinline__ void flood_quad_xy_tile(const uint32_t *src, uint32_t
     // input row s of the segment is grid row y0 + (s - 1) k; rows above the
     // grid only occur among the first two
     Cursor in = cursor_at(src, tl.y0 + k, W);   // input row 2
+    // input rows past the segment's last output row + 1 are requested with
+    // an empty descriptor (no memory access): short segments need not fetch
+    // the rows their ring would hold next
+    const int32_t last_in = tl.jend - tl.j0 + 1;
     auto request = [&](int32_t s, auto Slot, auto Phase) {
         __amdgpu_buffer_rsrc_t r;
         if (decltype(Phase)::value < 2) {
             r = row_rsrc(src, tl.y0 + (s - 1) * k, W, H);
         } else {
-            r = cursor_rsrc(in, W, H);
+            r = cursor_rsrc(in, W, s <= last_in ? H : 0);
             advance(in, step_bytes, k);
         }
         u32x4 *q = ring[decltype(Slot)::value];
