@@ -153,11 +153,30 @@ size_t vd_footprint_bytes(const vd_config *cfg);
 int vd_jfa_noalloc(const vd_config *cfg, const int32_t *dev_xy, int32_t *dev_map,
                    void *hip_stream);
 
+/* Initial seed positions as the paper's experiments draw them (Sec. VI-A:
+ * seeds uniformly at random on the grid), host only (no device work):
+ * num_seeds distinct pixels taken in order from the splitmix64 stream of
+ * `seed` (Steele, Lea and Flood, 2014: output n is mix64(seed + (n + 1) *
+ * 0x9E3779B97F4A7C15) with Stafford's variant-13 mixer); pair j is
+ * (x, y) = (bounded(output 2j, width), bounded(output 2j + 1, height)),
+ * bounded(r, m) = ((r >> 32) * m) >> 32, and a pair whose pixel is already
+ * taken is skipped.
+ *  host_xy: receives 2*num_seeds int32 values, (x, y) of seed i at [2i],
+ *           [2i+1].
+ * Returns VD_EINVAL for sizes outside those vd_init_sim accepts
+ * (1 <= num_seeds <= width*height) or a NULL host_xy, VD_ENOMEM if the
+ * width*height-byte mask of taken pixels cannot be allocated.  With
+ * num_seeds close to width*height the number of draws grows like
+ * width*height*ln(width*height). */
+int vd_place_seeds(int32_t width, int32_t height, int32_t num_seeds, uint64_t seed,
+                   int32_t *host_xy);
+
 /* Creates a simulation (Sec. IV: the diagram VD and the seed set S are the
  * state carried across time steps) and computes VD_0 by a full JFA on the
  * initial positions; t = 0.
  *  host_xy:  2*S int32 values, (x, y) of seed i at [2i], [2i+1]; positions in
  *            the grid; need not be distinct.  Copied; the caller keeps it.
+ *            NULL: the positions vd_place_seeds draws from cfg->sim_seed.
  *  dev_workspace, ws_bytes: device buffer of at least vd_footprint_bytes(cfg)
  *            bytes, any alignment.  Owned by the caller, who keeps it alive
  *            and untouched until vd_destroy.
@@ -452,7 +471,8 @@ int vd_server_create(int32_t max_sims, int32_t metric, void *dev_pool, size_t po
 /* Registers a simulation (cfg as for vd_init_sim; the metric must be the
  * server's) and returns its id.  It becomes resident (workspace
  * placed in the pool, VD_0 computed) as soon as its footprint fits;
- * simulations wait for memory in registration order.  host_xy is copied. */
+ * simulations wait for memory in registration order.  host_xy is copied;
+ * NULL: the positions vd_place_seeds draws from cfg->sim_seed. */
 int vd_server_add_sim(vd_server *sv, const vd_config *cfg, const int32_t *host_xy,
                       int32_t *sim_id);
 

@@ -914,6 +914,43 @@ size_t vd_footprint_bytes(const vd_config *cfg)
     return footprint(cfg);
 }
 
+int vd_place_seeds(int32_t width, int32_t height, int32_t num_seeds, uint64_t seed,
+                   int32_t *host_xy)
+{
+    if (!host_xy) return fail(VD_EINVAL, "host_xy is NULL");
+    if (width < 1 || width > VD_MAX_SIDE || height < 1 || height > VD_MAX_SIDE)
+        return fail(VD_EINVAL, "width and height must be in [1, %d], got %d x %d", VD_MAX_SIDE,
+                    width, height);
+    if (num_seeds < 1 || (int64_t)num_seeds > (int64_t)width * height)
+        return fail(VD_EINVAL, "num_seeds must be in [1, width*height], got %d", num_seeds);
+    std::vector<uint8_t> taken;
+    try {
+        taken.assign((size_t)width * (size_t)height, 0);
+    } catch (...) {
+        return fail(VD_ENOMEM, "host allocation of the %d x %d placement mask failed", width,
+                    height);
+    }
+    // splitmix64: output n of the stream of `seed` is mix64(seed + (n + 1) * gamma);
+    // pair j = (output 2j, output 2j + 1), each mapped onto [0, m) by
+    // ((r >> 32) * m) >> 32; a pair whose pixel is taken is skipped.
+    constexpr uint64_t kGamma = 0x9E3779B97F4A7C15ull;
+    uint64_t n = 0;
+    for (int32_t got = 0; got < num_seeds;) {
+        const uint64_t rx = mix64(seed + (n + 1) * kGamma);
+        const uint64_t ry = mix64(seed + (n + 2) * kGamma);
+        n += 2;
+        const int32_t x = (int32_t)(((rx >> 32) * (uint64_t)width) >> 32);
+        const int32_t y = (int32_t)(((ry >> 32) * (uint64_t)height) >> 32);
+        uint8_t &seen = taken[(size_t)y * (size_t)width + (size_t)x];
+        if (seen) continue;
+        seen = 1;
+        host_xy[2 * (size_t)got] = x;
+        host_xy[2 * (size_t)got + 1] = y;
+        ++got;
+    }
+    return VD_OK;
+}
+
 int vd_init_sim(const vd_config *cfg, const int32_t *host_xy, void *dev_workspace,
                 size_t ws_bytes, void *hip_stream, vd_sim **out)
 {
@@ -921,13 +958,23 @@ int vd_init_sim(const vd_config *cfg, const int32_t *host_xy, void *dev_workspac
     if (r) return r;
     if (!out) return fail(VD_EINVAL, "out is NULL");
     *out = nullptr;
-    if (!host_xy) return fail(VD_EINVAL, "host_xy is NULL");
     if (!dev_workspace) return fail(VD_EINVAL, "dev_workspace is NULL");
     size_t need = footprint(cfg);
     if (ws_bytes < need)
         return fail(VD_ENOMEM, "workspace holds %zu bytes, the simulation needs %zu", ws_bytes,
                     need);
     const int32_t S = cfg->num_seeds;
+    std::vector<int32_t> placed;   // positions drawn from sim_seed when the caller gives none
+    if (!host_xy) {
+        try {
+            placed.resize(2 * (size_t)S);
+        } catch (...) {
+            return fail(VD_ENOMEM, "host allocation of %d seeds failed", S);
+        }
+        r = vd_place_seeds(cfg->width, cfg->height, S, cfg->sim_seed, placed.data());
+        if (r) return r;
+        host_xy = placed.data();
+    }
     std::vector<uint32_t> packed;
     try {
         packed.resize((size_t)S + 1);

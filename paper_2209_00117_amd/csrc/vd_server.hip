@@ -794,7 +794,7 @@ int vd_server_create(int32_t max_sims, int32_t metric, void *dev_pool, size_t po
 int vd_server_add_sim(vd_server *sv, const vd_config *cfg, const int32_t *host_xy,
                       int32_t *sim_id)
 {
-    if (!sv || !cfg || !host_xy || !sim_id) return fail(VD_EINVAL, "NULL argument");
+    if (!sv || !cfg || !sim_id) return fail(VD_EINVAL, "NULL argument");
     if (cfg->metric != sv->metric)
         return fail(VD_EINVAL, "simulation metric %d differs from the server's %d", cfg->metric,
                     sv->metric);
@@ -803,6 +803,18 @@ int vd_server_add_sim(vd_server *sv, const vd_config *cfg, const int32_t *host_x
                                "request is planned ahead)");
     size_t bytes = vd_footprint_bytes(cfg);
     if (bytes == 0) return VD_EINVAL;   // message set by the validation
+    std::vector<int32_t> placed;        // positions drawn from sim_seed when none are given
+    if (!host_xy) {
+        try {
+            placed.resize(2 * (size_t)cfg->num_seeds);
+        } catch (...) {
+            return fail(VD_ENOMEM, "host allocation failed");
+        }
+        const int r = vd_place_seeds(cfg->width, cfg->height, cfg->num_seeds, cfg->sim_seed,
+                                     placed.data());
+        if (r) return r;
+        host_xy = placed.data();
+    }
     for (int64_t i = 0; i < 2 * (int64_t)cfg->num_seeds; i += 2)
         if (host_xy[i] < 0 || host_xy[i] >= cfg->width || host_xy[i + 1] < 0 ||
             host_xy[i + 1] >= cfg->height)

@@ -81,6 +81,8 @@ SIGNATURES = {
     "vd_read_seeds": (ctypes.c_int, [_P, _P, ctypes.c_size_t]),
     "vd_map_device": (ctypes.c_int, [_P, ctypes.POINTER(_P)]),
     "vd_get_info": (ctypes.c_int, [_P, ctypes.POINTER(SimInfo)]),
+    "vd_place_seeds": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                      ctypes.c_uint64, _P]),
     "vd_set_timing": (ctypes.c_int, [_P, ctypes.c_int]),
     "vd_get_timing": (ctypes.c_int, [_P, ctypes.POINTER(Timing)]),
     "vd_set_flood_variant": (ctypes.c_int, [_P, ctypes.c_int]),
@@ -198,13 +200,25 @@ def jfa_noalloc(cfg: Config, dev_xy: int, dev_map: int, stream=None):
                                 ctypes.c_void_p(dev_map), _stream_ptr(stream)))
 
 
-def init_sim(cfg: Config, xy: np.ndarray, workspace, stream=None) -> ctypes.c_void_p:
-    """Raw vd_init_sim; `workspace` is a uint8 CUDA tensor the caller keeps."""
-    xy = np.ascontiguousarray(xy, dtype=np.int32)
-    if xy.shape != (cfg.num_seeds, 2):
-        raise ValueError(f"positions must be ({cfg.num_seeds}, 2) int32, got {xy.shape}")
+def place_seeds(width: int, height: int, num_seeds: int, seed: int) -> np.ndarray:
+    """vd_place_seeds: the (num_seeds, 2) int32 positions vd_init_sim draws
+    from `seed` when it is given none (host only)."""
+    out = np.empty((num_seeds, 2), dtype=np.int32)
+    _check(lib().vd_place_seeds(width, height, num_seeds, seed, out.ctypes.data_as(_P)))
+    return out
+
+
+def init_sim(cfg: Config, xy, workspace, stream=None) -> ctypes.c_void_p:
+    """Raw vd_init_sim; `workspace` is a uint8 CUDA tensor the caller keeps.
+    xy None: the library draws the positions from cfg.sim_seed."""
+    ptr = None
+    if xy is not None:
+        xy = np.ascontiguousarray(xy, dtype=np.int32)
+        if xy.shape != (cfg.num_seeds, 2):
+            raise ValueError(f"positions must be ({cfg.num_seeds}, 2) int32, got {xy.shape}")
+        ptr = xy.ctypes.data_as(_P)
     h = ctypes.c_void_p()
-    _check(lib().vd_init_sim(ctypes.byref(cfg), xy.ctypes.data_as(_P),
+    _check(lib().vd_init_sim(ctypes.byref(cfg), ptr,
                              ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
                              _stream_ptr(stream), ctypes.byref(h)))
     return h
@@ -389,9 +403,13 @@ def last_error() -> str:
 class Sim:
     """A simulation and the workspace tensor it lives in."""
 
-    def __init__(self, width, height, xy, device="cuda", stream=None, **kw):
+    def __init__(self, width, height, xy, device="cuda", stream=None, num_seeds=None, **kw):
+        """xy None: num_seeds positions drawn by the library from sim_seed."""
         import torch
-        self.cfg = config(width, height, int(np.asarray(xy).shape[0]), **kw)
+        n = num_seeds if xy is None else int(np.asarray(xy).shape[0])
+        if n is None:
+            raise ValueError("give positions or num_seeds")
+        self.cfg = config(width, height, n, **kw)
         nbytes = footprint_bytes(self.cfg)
         if nbytes == 0:
             raise VdError(-1, last_error())
@@ -552,12 +570,18 @@ class Server:
     def footprint_bytes(max_sims: int) -> int:
         return int(lib().vd_server_footprint_bytes(max_sims))
 
-    def add_sim(self, width, height, xy, **kw) -> int:
-        cfg = config(width, height, int(np.asarray(xy).shape[0]), **kw)
-        xy = np.ascontiguousarray(xy, dtype=np.int32)
+    def add_sim(self, width, height, xy, num_seeds=None, **kw) -> int:
+        """xy None: num_seeds positions drawn by the library from sim_seed."""
+        n = num_seeds if xy is None else int(np.asarray(xy).shape[0])
+        if n is None:
+            raise ValueError("give positions or num_seeds")
+        cfg = config(width, height, n, **kw)
+        ptr = None
+        if xy is not None:
+            xy = np.ascontiguousarray(xy, dtype=np.int32)
+            ptr = xy.ctypes.data_as(_P)
         sid = ctypes.c_int32()
-        _check(lib().vd_server_add_sim(self.handle, ctypes.byref(cfg), xy.ctypes.data_as(_P),
-                                       ctypes.byref(sid)))
+        _check(lib().vd_server_add_sim(self.handle, ctypes.byref(cfg), ptr, ctypes.byref(sid)))
         self.shapes[sid.value] = (height, width)
         return sid.value
 

@@ -78,8 +78,13 @@ def test_null_and_small_workspace():
     xy = (ctypes.c_int32 * 4)(0, 0, 1, 1)
     out = ctypes.c_void_p()
     L = V.lib()
-    assert L.vd_init_sim(ctypes.byref(c), None, ctypes.c_void_p(0x1000), 1 << 20, None,
+    # positions drawn by the library (host_xy NULL) still need a valid
+    # config and a large enough workspace before any device work
+    bad_cfg = V.config(8, 8, 65)
+    assert L.vd_init_sim(ctypes.byref(bad_cfg), None, ctypes.c_void_p(0x1000), 1 << 20, None,
                          ctypes.byref(out)) == -1
+    assert L.vd_init_sim(ctypes.byref(c), None, ctypes.c_void_p(0x1000), 100, None,
+                         ctypes.byref(out)) == -2
     assert L.vd_init_sim(ctypes.byref(c), ctypes.cast(xy, ctypes.c_void_p), None, 1 << 20, None,
                          ctypes.byref(out)) == -1
     assert L.vd_init_sim(ctypes.byref(c), ctypes.cast(xy, ctypes.c_void_p),
@@ -108,3 +113,26 @@ def test_tuning_table_round_trip():
     assert t["gfx950 64x64 S10 xy euclid k1 vn"] == [1, 0]
     for bad in ("no separators\n", "k|99|0\n", "k|-1|0\n", "k|1|999\n"):
         assert V.lib().vd_tuning_import(bad.encode()) == -1
+
+
+# vd_place_seeds is host code: the library draws the same initial positions
+# as the input generator the tests and the oracle use (shapes: one pixel, a
+# saturated grid, a single row and column, the 4096^2 and 8192^2 workloads).
+@pytest.mark.parametrize("W,H,S,seed", [(1, 1, 1, 5), (64, 64, 4096, 3), (1000, 1, 700, 9),
+                                        (1, 900, 899, 2), (1000, 700, 5000, 17),
+                                        (4096, 4096, 65536, 1), (8192, 8192, 1 << 20, 1)])
+def test_place_seeds_matches_input_generator(W, H, S, seed):
+    from paper_2209_00117_amd import inputs
+    got = V.place_seeds(W, H, S, seed)
+    want = inputs.place_seeds(W, H, S, seed)
+    assert got.shape == want.shape and (got == want).all()
+    assert len({(int(x), int(y)) for x, y in got}) == S
+
+
+def test_place_seeds_rejects_bad_arguments():
+    out = (ctypes.c_int32 * 16)()
+    L = V.lib()
+    for w, h, s in ((0, 4, 1), (4, 16369, 1), (2, 2, 0), (2, 2, 5)):
+        assert L.vd_place_seeds(w, h, s, 1, ctypes.cast(out, ctypes.c_void_p)) == -1
+        assert V.last_error()
+    assert L.vd_place_seeds(2, 2, 1, 1, None) == -1

@@ -403,6 +403,25 @@ def test_measured_dmax_and_set_seeds(V, label):
         assert g.info().t == o.t
 
 
+@pytest.mark.parametrize("label", [0, 1])
+def test_library_placement(V, label):
+    """vd_init_sim with no positions draws them from sim_seed exactly as the
+    input generator does; the simulation then matches the oracle's."""
+    W, H, S, seed = 700, 450, 900, 13
+    print(f"[parity] library placement W={W} H={H} S={S} seed={seed} label={label}", flush=True)
+    g = V.Sim(W, H, None, num_seeds=S, sim_seed=seed, disp_lo=-2, disp_hi=2, label=label)
+    xy = inputs.place_seeds(W, H, S, seed)
+    assert np.array_equal(g.read_seeds(), xy)
+    o = O.Sim(W, H, xy, seed, -2, 2, label_mode=label)
+    assert np.array_equal(g.read_map(), o.map)
+    for _ in range(2):
+        g.move_seeds(), o.move()
+        g.djfa_step(), o.djfa_step()
+        assert np.array_equal(g.read_seeds(), o.xy)
+        assert np.array_equal(g.read_map(), o.map)
+    g.close()
+
+
 def test_set_seeds_rejects_bad_input(V):
     g = V.Sim(64, 64, inputs.place_seeds(64, 64, 10, 1))
     with pytest.raises(V.VdError):

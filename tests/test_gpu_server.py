@@ -127,3 +127,16 @@ def test_server_rejects_misuse(V):
     with pytest.raises(V.VdError):
         sv.wait(t, 10)                       # a ticket is collected once
     sv.close()
+
+
+def test_server_draws_positions(V):
+    """A simulation registered without positions gets those vd_place_seeds
+    draws from its sim_seed (as vd_init_sim does)."""
+    sv = V.Server(2, 1 << 26)
+    kw = dict(disp_lo=-2, disp_hi=2, sim_seed=41)
+    i = sv.add_sim(300, 200, None, num_seeds=150, **kw)
+    t = sv.submit(i, V.STEP_DJFA)
+    sv.wait(t, 60000)
+    xy = inputs.place_seeds(300, 200, 150, 41)
+    assert np.array_equal(sv.read_map(i), _alone(V, 300, 200, xy, kw, [V.STEP_DJFA]))
+    sv.close()
