@@ -282,8 +282,8 @@ def bench_serving(torch, inputs, V, args):
     requests (move + dJFA) at args.rate per second, uniformly over the
     simulations, for 1 s of warm-up and args.seconds measured.  Latency runs
     from submission to the request's completion on the GPU.  Served twice:
-    whole steps (the server's default policy) and continuous batching by
-    passes.  The same arrival stream is then served one request at a time
+    whole steps and continuous batching (batched ticks, the server's default
+    policy).  The same arrival stream is then served one request at a time
     with plain JFA (move + JFA per request, each waited for before the next
     starts)."""
     wl = inputs.serving()
@@ -329,7 +329,7 @@ def bench_serving(torch, inputs, V, args):
                 "requests_per_s": st["completed"] / st["elapsed_s"], "ticks": st["ticks"],
                 "elapsed_s": st["elapsed_s"]}
 
-    # whole steps (the default policy), then continuous batching (batched ticks)
+    # whole steps, then continuous batching (batched ticks, the default policy)
     served = run_server(V.SERVE_STEPS)
     served_passes = run_server(V.SERVE_PASSES)
     solo_sweep = []

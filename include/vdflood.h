@@ -479,22 +479,24 @@ int vd_server_add_sim(vd_server *sv, const vd_config *cfg, const int32_t *host_x
 /* How requests started from now on run.  The scheduler forms ticks on the
  * server's stream (at most two in flight); a tick starts the next request
  * of every resident simulation that has one, and every request completes
- * with its tick.  VD_SERVE_STEPS (the default): each request as its
- * simulation's move and step with that simulation's own launches (tuned
- * kernel variants, fused tail), one simulation after another.
- * VD_SERVE_PASSES: continuous batching of the tick's requests -- their
- * moves and step starts run in shared launches over all of them, and the
- * smaller simulations (below vd_server_set_solo's size, when two or more
- * start in the tick) run their passes as one persistent launch per pass
- * level over all of them, each at its own step size, so their work
- * overlaps on the device; larger ones run their own passes.  Results are identical either
- * way.  VD_EINVAL for another value. */
+ * with its tick.  VD_SERVE_STEPS: each request as its simulation's move
+ * and step with that simulation's own launches (tuned kernel variants,
+ * fused tail), one simulation after another.  VD_SERVE_PASSES (the
+ * default; continuous batching of the tick's requests): their moves and
+ * step starts run in shared launches over all of them; then each runs its
+ * passes with its own launches on one of four streams -- simulations of
+ * 4096 x 4096 pixels and up one after another on the first, so each keeps
+ * its maps in the Infinity Cache, the others round the other three beside
+ * them -- or, below vd_server_set_solo's size when two or more start in the
+ * tick, in one persistent launch per pass level over all of them.  A tick
+ * in which a single request starts runs it as a whole step.  Results are
+ * identical either way.  VD_EINVAL for another value. */
 enum { VD_SERVE_STEPS = 0, VD_SERVE_PASSES = 1 };
 int vd_server_set_policy(vd_server *sv, int32_t policy);
 
 /* VD_SERVE_PASSES ticks: simulations of at least min_pixels pixels run
  * their passes with their own launches, smaller ones share the pass-level
- * launches (default 2048 * 2048; min_pixels <= 0: every simulation alone).
+ * launches (min_pixels <= 0, the default: every simulation alone).
  * Takes effect from the next tick; results never change. */
 int vd_server_set_solo(vd_server *sv, int64_t min_pixels);
 

@@ -5,23 +5,26 @@
 // scheduler thread forms "ticks", enqueued on the server's stream with at
 // most two in flight.  Two policies decide how a started request runs.
 //
-// Whole steps (VD_SERVE_STEPS, the default): the next request of every idle
-// simulation runs as its move and step with the simulation's own launches
-// (its tuned kernel variants and fused tail), simulation after simulation,
-// and the tick's event completes them.  Each step keeps its two maps in the
-// Infinity Cache across its passes and uses the fastest kernels, so at the
-// loads measured it gave several times lower latency than batching.
+// Whole steps (VD_SERVE_STEPS): the next request of every idle simulation
+// runs as its move and step with the simulation's own launches (its tuned
+// kernel variants and fused tail), simulation after simulation, and the
+// tick's event completes them.  Each step keeps its two maps in the
+// Infinity Cache across its passes and uses the simulation's fastest
+// kernels.
 //
-// Pass-level batching (VD_SERVE_PASSES): in a tick, every simulation that starts a
-// request joins (its move and seed splat run in two or three small batched
-// launches), and one persistent flood launch then runs the next pass of
-// every active simulation, each at its own pass index and step size, with
-// the same tile functions as the single-simulation kernels.  A simulation
-// that has run its last pass leaves; its request completes when the tick's
-// event fires.  New requests thus join at the next pass boundary instead of
-// waiting for running steps to finish, and the next tick is enqueued while
-// the current one runs (two in flight), so the work of many requests
-// overlaps on the GPU without long queues in front of newcomers.
+// Batched ticks (VD_SERVE_PASSES, the default; continuous batching): the
+// requests that start in a tick run their moves and step starts (fill and
+// splat, or for XY dJFA the old-position index, the relabel and the splat)
+// as one launch of each kind over all of them; then each simulation's
+// passes run with its own launches, spread over four streams joined by
+// events, so different requests' passes run side by side.  Simulations of
+// kLaneBigPixels and up share the first stream, so that only one at a time
+// streams its maps through the Infinity Cache; those below
+// vd_server_set_solo's size can instead share one persistent launch per
+// pass level.  A tick in which only one request starts has nothing to
+// share or overlap: that request runs as a whole step.  The next tick is
+// enqueued while the current one runs (two in flight), so newcomers wait at
+// most for the tick in progress.
 //
 // Memory: the caller hands the server one device pool.  The server keeps
 // its tick tables in it and places each simulation's workspace (two maps
@@ -63,6 +66,7 @@ constexpr int kFuseMin = 2;
 // server's own and kLanes - 1 more, all of the default priority), so the
 // passes of different requests run side by side on the device.
 constexpr int kLanes = 4;
+constexpr int64_t kLaneBigPixels = 4096 * 4096;   // two maps: 128 MiB
 
 struct TickSim {            // one active simulation's pass in a tick
     const uint32_t *src;
@@ -332,7 +336,7 @@ struct Pool {                     // first-fit allocator over [0, size)
 
 struct vd_server {
     int32_t max_sims = 0, metric = 0;
-    int32_t policy = VD_SERVE_STEPS;   // how requests started from now on run
+    int32_t policy = VD_SERVE_PASSES;  // how requests started from now on run
     int64_t solo_px = vd::kSoloPixels;  // batched ticks: simulations this large run alone
     hipStream_t stream = nullptr;
     hipStream_t lane[vd::kLanes - 1] = {};     // the other pass lanes of batched ticks
@@ -581,11 +585,19 @@ bool enqueue_batched(vd_server *sv, Tick &t, const std::vector<int32_t> &ids)
         }
         e = hipGetLastError();
     }
-    // The simulations that run alone go round the lanes; the other lanes
-    // start after the step starts and the server's stream waits for them.
-    int32_t alone = 0;
-    for (size_t j = 0; j < ids.size(); ++j) alone += fused[j] ? 0 : 1;
-    const int lanes = (int)std::min<int32_t>(vd::kLanes, std::max<int32_t>(alone, 1));
+    // The simulations that run alone go over the lanes: those whose two maps
+    // fill a large share of the Infinity Cache (kLaneBigPixels and up) one
+    // after another on the first lane, so that each keeps its maps cached
+    // across its passes, the others round the remaining lanes beside them.
+    // The other lanes start after the step starts and the server's stream
+    // waits for them.
+    int32_t alone = 0, big = 0;
+    for (size_t j = 0; j < ids.size(); ++j) {
+        if (fused[j]) continue;
+        ++alone;
+        big += (int64_t)sims[j]->cfg.width * sims[j]->cfg.height >= vd::kLaneBigPixels ? 1 : 0;
+    }
+    const int lanes = (int)std::min<int32_t>(vd::kLanes, std::max<int32_t>(alone - std::max(big - 1, 0), 1));
     if (e == hipSuccess && lanes > 1) {
         e = hipEventRecord(sv->prep_done[slot], sv->stream);
         for (int l = 1; l < lanes && e == hipSuccess; ++l)
@@ -594,7 +606,8 @@ bool enqueue_batched(vd_server *sv, Tick &t, const std::vector<int32_t> &ids)
     int32_t nth = 0;
     for (size_t j = 0; j < ids.size() && e == hipSuccess; ++j) {
         if (fused[j]) continue;
-        const int l = nth++ % lanes;
+        const bool large = (int64_t)sims[j]->cfg.width * sims[j]->cfg.height >= vd::kLaneBigPixels;
+        const int l = large || lanes == 1 ? 0 : (big ? 1 + nth++ % (lanes - 1) : nth++ % lanes);
         if (vd::launch_step_passes(sims[j], sv->sims[ids[j]].req.mode == VD_STEP_DJFA,
                                    l ? sv->lane[l - 1] : sv->stream) != VD_OK)
             e = hipErrorLaunchFailure;
@@ -656,6 +669,10 @@ bool tick(vd_server *sv)
         }
     }
     if (whole.empty() && batched.empty()) return false;
+    if (batched.size() == 1) {   // nothing to share or overlap: the same result as a whole step
+        whole.push_back(batched.front());
+        batched.clear();
+    }
     while ((int)sv->inflight.size() >= vd::kMaxInflight && !sv->error) reap(sv, true);
     if (sv->error) return false;
     Tick t;

@@ -553,8 +553,8 @@ class Batch:
 class Server:
     """A serving loop over resident simulations (vd_server_*): time-step
     requests are queued per simulation and run on the GPU by the library's
-    scheduler thread, as whole steps (SERVE_STEPS, the default) or batched
-    at pass granularity (SERVE_PASSES)."""
+    scheduler thread, as batched ticks (SERVE_PASSES, the default:
+    continuous batching) or whole steps (SERVE_STEPS)."""
 
     def __init__(self, max_sims: int, pool_bytes: int, metric=EUCLID, device="cuda",
                  stream=None):
