@@ -415,11 +415,15 @@ int vd_batch_autotune(vd_batch *b, int32_t reps);
 /* Members of at least min_pixels pixels (<= 0: none) run the passes of
  * `mode` steps solo: with their own launches, kernel variants and tail
  * fusion (as chosen by vd_autotune / vd_set_flood_variant /
- * vd_set_tail_fusion before the batch was built), one member after another,
- * so each member's maps stay in the Infinity Cache across its passes; the
- * others share one persistent launch per pass level.  Move, fill, splat and
- * the step's bookkeeping stay batched.  Results do not change.  Drops
- * captured graphs; waits for the stream. */
+ * vd_set_tail_fusion before the batch was built), on four streams forked
+ * from the batch's stream and joined before the step ends: members of
+ * 4096 x 4096 pixels and up one after another on the first, those of
+ * 2048 x 2048 and up on the second, so each keeps its maps in the Infinity
+ * Cache across its passes, the smaller ones alternating on the other two
+ * (one stream while per-launch timing is on); the others share one
+ * persistent launch per pass level.  Move, fill, splat and the step's
+ * bookkeeping stay batched.  Results do not change.  Drops captured graphs;
+ * waits for the stream. */
 int vd_batch_set_solo(vd_batch *b, int32_t mode, int64_t min_pixels);
 
 /* Per-level flood and per-step timing with HIP events, as for a single

@@ -72,6 +72,9 @@ struct LevelInfo {
 };
 
 constexpr int kMaxLevels = 24;   // > ceil(log2 16368) + 2 extra passes
+// Solo members' passes run on kSoloLanes streams, by size (lane_of).
+constexpr int kSoloLanes = 4;
+constexpr int64_t kLaneBigPixels = 4096 * 4096;
 
 // A wave-uniform 32-bit value or pointer, stated as such to the compiler.
 __device__ __forceinline__ int32_t uni(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
@@ -328,6 +331,11 @@ struct vd_batch {
     std::map<std::vector<char>, hipGraphExec_t> graphs;
     hipStream_t capture = nullptr;   // private stream to capture on (the caller's may be
                                      // the null stream, which cannot be captured)
+    // Solo passes are spread over the step's stream and kSoloLanes - 1 more
+    // (forked and joined by events; see enqueue_solo).
+    hipStream_t lane[vd::kSoloLanes - 1] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[vd::kSoloLanes - 1] = {};
     bool timing = false;
     std::vector<vd::EventPair> pool;
     size_t used = 0;
@@ -434,11 +442,64 @@ int32_t flips(const vd_batch *b, int mode, int32_t i)
     return (int32_t)(dyn ? s->djfa_passes : s->jfa_passes).size();
 }
 
-int enqueue_solo(vd_batch *b, int mode, bool tuning, hipStream_t stream)
+// The stream of a solo member by its size: members of kLaneBigPixels and
+// up on lane 0, those of a quarter of that and up on lane 1, one of each at
+// a time, so that their maps stay in the Infinity Cache beside each other
+// (128 + 32 MiB at 4096^2 and 2048^2); smaller ones alternate between
+// lanes 2 and 3.
+int lane_of(const vd_sim *s, int32_t *nth)
 {
+    const int64_t px = (int64_t)s->cfg.width * s->cfg.height;
+    if (px >= vd::kLaneBigPixels) return 0;
+    if (px >= vd::kLaneBigPixels / 4) return 1;
+    return 2 + (*nth)++ % 2;
+}
+
+// Streams for the solo passes of a `mode` step: `stream` and the batch's
+// other lanes (created on first use), which wait for what `stream` has
+// queued so far; *used receives the number of streams (1 when a single
+// member runs solo).
+int fork_lanes(vd_batch *b, int mode, hipStream_t stream, int *used)
+{
+    int32_t alone = 0;
+    for (size_t i = 0; i < b->sims.size(); ++i) alone += b->solo[mode][i] ? 1 : 0;
+    const int n = alone > 1 ? vd::kSoloLanes : 1;
+    *used = n;
+    if (n == 1) return VD_OK;
+    if (!b->fork) {
+        VD_HIP(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
+        for (int l = 0; l < vd::kSoloLanes - 1; ++l) {
+            VD_HIP(hipStreamCreateWithFlags(&b->lane[l], hipStreamNonBlocking));
+            VD_HIP(hipEventCreateWithFlags(&b->join[l], hipEventDisableTiming));
+        }
+    }
+    VD_HIP(hipEventRecord(b->fork, stream));
+    for (int l = 1; l < n; ++l) VD_HIP(hipStreamWaitEvent(b->lane[l - 1], b->fork, 0));
+    return VD_OK;
+}
+
+int join_lanes(vd_batch *b, hipStream_t stream, int used)
+{
+    for (int l = 1; l < used; ++l) {
+        VD_HIP(hipEventRecord(b->join[l - 1], b->lane[l - 1]));
+        VD_HIP(hipStreamWaitEvent(stream, b->join[l - 1], 0));
+    }
+    return VD_OK;
+}
+
+// The passes of the solo members, each as its own step would run them, on
+// lane_of's stream when `lanes` streams are in use (fork_lanes).
+int enqueue_solo(vd_batch *b, int mode, bool tuning, hipStream_t stream, int lanes = 1)
+{
+    int32_t nth = 0;
     for (size_t i = 0; i < b->sims.size(); ++i) {
         if (!b->solo[mode][i]) continue;
         const vd_sim *s = b->sims[i];
+        hipStream_t on = stream;
+        if (lanes > 1) {
+            const int l = lane_of(s, &nth);
+            if (l) on = b->lane[l - 1];
+        }
         const vd_config &c = s->cfg;
         const std::vector<vd::Pass> &ps = mode == VD_STEP_DJFA ? s->djfa_passes : s->jfa_passes;
         const int32_t th = s->tail_th[mode == VD_STEP_DJFA ? 1 : 0];
@@ -448,7 +509,7 @@ int enqueue_solo(vd_batch *b, int mode, bool tuning, hipStream_t stream)
             const vd::Pass &p = ps[j];
             VD_HIP(vd::launch_flood(s->map[cur], s->map[cur ^ 1], s->pos, c.num_seeds, c.width,
                                     c.height, p.k, p.vn, c.label, c.metric, p.variant,
-                                    p.seg_rows, stream));
+                                    p.seg_rows, on));
             if (!tuning) cur ^= 1;
         }
         if (m) {
@@ -460,7 +521,7 @@ int enqueue_solo(vd_batch *b, int mode, bool tuning, hipStream_t stream)
             const bool nt = ps.back().variant >= vd::kFloodVariants / 2;
             VD_HIP(vd::launch_flood_tail(s->map[cur], s->map[cur ^ 1], s->pos, c.num_seeds,
                                          c.width, c.height, ks, vns, (int32_t)m, c.label,
-                                         c.metric, nt, th, stream));
+                                         c.metric, nt, th, on));
             if (!tuning) cur ^= 1;
         }
     }
@@ -511,10 +572,16 @@ int enqueue_step(vd_batch *b, int mode, int moved, hipStream_t stream)
         }
     }
     if (b->solo_passes[mode] > 0) {
+        // per-launch timing keeps one stream, so each timed range covers
+        // one kind of work
         size_t slot = 0;
         int r = batch_record(b, 2 + 2 * vd::kMaxLevels + mode, true, &slot);
         if (r) return r;
-        r = enqueue_solo(b, mode, false, stream);
+        int lanes = 1;
+        if (!b->timing) r = fork_lanes(b, mode, stream, &lanes);
+        if (r) return r;
+        r = enqueue_solo(b, mode, false, stream, lanes);
+        if (r == VD_OK) r = join_lanes(b, stream, lanes);
         if (r) return r;
         r = batch_record(b, 0, false, &slot);
         if (r) return r;
@@ -842,9 +909,13 @@ int vd_batch_autotune(vd_batch *b, int32_t reps)
             e = hipGetLastError();
             if (e == hipSuccess) e = launch_level(b, mode, lvl, 0, grid, b->stream);
         }
-        if (e == hipSuccess && b->solo_passes[mode] > 0 &&
-            enqueue_solo(b, mode, true, b->stream) != VD_OK)
-            e = hipErrorUnknown;
+        if (e == hipSuccess && b->solo_passes[mode] > 0) {
+            int lanes = 1;
+            if (fork_lanes(b, mode, b->stream, &lanes) != VD_OK ||
+                enqueue_solo(b, mode, true, b->stream, lanes) != VD_OK ||
+                join_lanes(b, b->stream, lanes) != VD_OK)
+                e = hipErrorUnknown;
+        }
         return e;
     };
     // Times `cands.size()` configurations of one mode; set(c) installs
@@ -979,6 +1050,11 @@ void vd_batch_destroy(vd_batch *b)
         if (s->release) vd_destroy(s);   // destroyed by its owner while in the batch
     }
     if (b->capture) (void)hipStreamDestroy(b->capture);
+    for (int l = 0; l < vd::kSoloLanes - 1; ++l) {
+        if (b->lane[l]) (void)hipStreamDestroy(b->lane[l]);
+        if (b->join[l]) (void)hipEventDestroy(b->join[l]);
+    }
+    if (b->fork) (void)hipEventDestroy(b->fork);
     delete b;
 }
 
