@@ -164,7 +164,10 @@ bool quad_ok(int32_t W, int32_t k);
 // otherwise variant 1; 4, 5: four columns per lane where quad_ok holds (ID
 // labels: rows shared through LDS for k <= 512, direct loads above),
 // requesting rows 2 (4) or 3 (5) rows ahead, otherwise variant 3 (ID) or 1
-// (XY).  Variants 6-11 are 0-5 with non-temporal stores of the output map.
+// (XY); at a step of at least a quarter of both sides (block_ok: a step's
+// first two passes when it starts at k1) both run one lane per 2 x 2 or
+// 4 x 4 block of groups, which reads and writes every pixel once.  Variants 6-11 are 0-5 with
+// non-temporal stores of the output map.
 constexpr int kFloodVariants = 12;
 hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *table, int32_t S,
                         int32_t W, int32_t H, int32_t k, int32_t vn, int32_t label,

@@ -400,6 +400,26 @@ __global__ void __launch_bounds__(kBlock) k_flood_quad_idd(const uint32_t *__res
                                               xcd_logical(blockIdx.x, g.nblocks));
 }
 
+// One lane per NB x NB block of four-column groups {x0 + n k} x {y0 + m k}
+// (x0 = 4 * the lane's group, y0 = blockIdx.y), for steps with
+// block_span(W, H, k) == NB.
+template <int NB, int LABEL, int METRIC, int VN, int ST>
+__global__ void __launch_bounds__(kBlock) k_flood_block(const uint32_t *__restrict__ src,
+                                                        uint32_t *__restrict__ dst,
+                                                        const uint32_t *__restrict__ table,
+                                                        uint32_t S, int32_t W, int32_t H,
+                                                        int32_t k)
+{
+    const int32_t gx = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (kQuad * gx >= min(k, W)) return;
+    if (LABEL == kLabelId)
+        flood_block_tile<NB, METRIC, VN, ST>(src, dst, TableLookup{table_rsrc(table, S)}, W, H,
+                                             k, gx, (int32_t)blockIdx.y);
+    else
+        flood_block_tile<NB, METRIC, VN, ST>(src, dst, PosLabels{}, W, H, k, gx,
+                                             (int32_t)blockIdx.y);
+}
+
 template <int LABEL, int METRIC, int ST, int TH>
 __global__ void __launch_bounds__(kBlock) k_flood_tail(const uint32_t *__restrict__ src,
                                                        uint32_t *__restrict__ dst,
@@ -636,6 +656,33 @@ hipError_t launch_flood_st(const uint32_t *src, uint32_t *dst, const uint32_t *t
                            int32_t metric, int32_t variant, int32_t seg_rows, hipStream_t s)
 {
     uint32_t uS = (uint32_t)S;
+    if (variant >= 4 && block_ok(W, H, k)) {
+        // every pixel's candidates in one block of 2 x 2 or 4 x 4 groups per lane
+        const int32_t gx = std::min(k, W) / kQuad;
+        const dim3 grid((unsigned)((gx + kBlock - 1) / kBlock), (unsigned)std::min(k, H));
+        const bool two = block_span(W, H, k) == 2;
+#define VD_BLOCK(LB, MT, V)                                                                    \
+    do {                                                                                       \
+        if (two)                                                                               \
+            hipLaunchKernelGGL((k_flood_block<2, LB, MT, V, ST>), grid, dim3(kBlock), 0, s, src,  \
+                               dst, table, uS, W, H, k);                                       \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_flood_block<4, LB, MT, V, ST>), grid, dim3(kBlock), 0, s, src,  \
+                               dst, table, uS, W, H, k);                                       \
+    } while (0)
+#define VD_BLOCK_M(LB)                                                                         \
+    do {                                                                                       \
+        if (metric == kEuclid) {                                                               \
+            if (vn) VD_BLOCK(LB, kEuclid, 1); else VD_BLOCK(LB, kEuclid, 0);                   \
+        } else {                                                                               \
+            if (vn) VD_BLOCK(LB, kManhattan, 1); else VD_BLOCK(LB, kManhattan, 0);             \
+        }                                                                                      \
+    } while (0)
+        if (label == kLabelId) VD_BLOCK_M(kLabelId); else VD_BLOCK_M(kLabelXy);
+#undef VD_BLOCK_M
+#undef VD_BLOCK
+        return hipGetLastError();
+    }
     if (variant >= 4) {
         if (!quad_ok(W, k)) {
             variant = label == kLabelId ? 3 : 1;   // same labels, single-column kernels

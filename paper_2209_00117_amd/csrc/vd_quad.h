@@ -475,6 +475,82 @@ __device__ __forceinline__ void flood_quad_id_tile(const uint32_t *src, uint32_t
     quad_walk<METRIC, VN, KC, NS, ST>(dst, W, H, k, tl, oc, request, fetch);
 }
 
+// Passes at a step k of at least a quarter of both sides (a JFA step's first
+// two passes, k = k1 and k1 / 2, and a dJFA step's first ones when delta_1
+// is that large).  Then the columns congruent to x0 mod k (x0 < k) number
+// at most NB = 2 or 4 on the grid, x0 + m k for m < NB, and likewise the
+// rows, so the NB x NB pixels {x0 + m k} x {y0 + n k} hold each other's
+// candidates and nothing else: a lane owns one such block of four-column
+// groups, loads its NB x NB groups once, folds every pixel's candidates
+// from the block (the same column of each group, since k is a multiple of
+// 4) and stores the groups.  The map streams through once, with no row or
+// group read twice.  Groups off the grid read as unclaimed and are not
+// stored (buffer range checks), exactly as in the walks above.
+__host__ __device__ __forceinline__ int32_t block_span(int32_t W, int32_t H, int32_t k)
+{
+    if (W % kQuad != 0 || k % kQuad != 0) return 0;
+    if (W <= 2 * k && H <= 2 * k) return 2;
+    if (W <= 4 * k && H <= 4 * k) return 4;
+    return 0;
+}
+__host__ __device__ __forceinline__ bool block_ok(int32_t W, int32_t H, int32_t k)
+{
+    return block_span(W, H, k) != 0;
+}
+
+// XY labels: the label is the position.
+struct PosLabels {
+    __device__ __forceinline__ u32x4 pos4(u32x4 l, const G4 &) const { return l; }
+};
+
+template <int NB, int METRIC, int VN, int ST, class LK>
+__device__ __forceinline__ void flood_block_tile(const uint32_t *src, uint32_t *dst,
+                                                 const LK &lk, int32_t W, int32_t H, int32_t k,
+                                                 int32_t gx, int32_t y0)
+{
+    const int32_t x0 = kQuad * gx;
+    const G4 none = {u32x4{0u, 0u, 0u, 0u}, u32x4{0u, 0u, 0u, 0u}};
+    G4 q[NB][NB];   // [row m][column n]: the group at (x0 + n k, y0 + m k)
+#pragma unroll
+    for (int m = 0; m < NB; ++m) {
+        const __amdgpu_buffer_rsrc_t r = row_rsrc(src, y0 + m * k, W, H);
+#pragma unroll
+        for (int n = 0; n < NB; ++n) q[m][n].l = load4(r, 4 * (x0 + n * k));
+    }
+#pragma unroll
+    for (int m = 0; m < NB; ++m)
+#pragma unroll
+        for (int n = 0; n < NB; ++n) q[m][n].s = lk.pos4(q[m][n].l, none);
+    const uint32_t p0 = ((uint32_t)(y0 + (int32_t)kOff) << 16) | (uint32_t)(x0 + (int32_t)kOff);
+#pragma unroll
+    for (int m = 0; m < NB; ++m) {
+        const __amdgpu_buffer_rsrc_t out = row_rsrc(dst, y0 + m * k, W, H);
+#pragma unroll
+        for (int n = 0; n < NB; ++n) {
+            const uint32_t pb = p0 + (uint32_t)(n * k) + ((uint32_t)(m * k) << 16);
+            double best[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t p = pb + (uint32_t)e;
+                double v = cand_key<METRIC>(p, Ent{q[m][n].l[e], q[m][n].s[e]});
+#pragma unroll
+                for (int dm = -1; dm <= 1; ++dm)
+#pragma unroll
+                    for (int dn = -1; dn <= 1; ++dn) {
+                        const int mm = m + dm, nn = n + dn;
+                        if ((dm == 0 && dn == 0) || mm < 0 || mm >= NB || nn < 0 || nn >= NB)
+                            continue;
+                        if (VN && dm != 0 && dn != 0) continue;
+                        v = __builtin_fmin(v, cand_key<METRIC>(p, Ent{q[mm][nn].l[e],
+                                                                      q[mm][nn].s[e]}));
+                    }
+                best[e] = v;
+            }
+            store4<ST>(labels_of(best), out, 4 * (x0 + n * k));
+        }
+    }
+}
+
 // XY labels after a move (widths divisible by 4), one block of the map:
 // each lane relabels four adjacent pixels in each of kRelabelRows rows at
 // once -- all their label loads are requested, then all their gathers from

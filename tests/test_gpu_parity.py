@@ -168,6 +168,22 @@ def test_flood_variants(V, variant, W, H, S):
                  tag="variant")
 
 
+# Variants 4 and 5 (and 10, 11) at a step of at least half of both sides --
+# a step's first pass when it starts at k1 -- run one lane per 2 x 2 block
+# of four-column groups.  d_max is overridden so that dJFA steps start at k1
+# too, with Von Neumann first passes; the shapes give blocks cut by both
+# edges, one row, one group, and a width that is not a power of two.
+@pytest.mark.parametrize("variant", [4, 11])
+@pytest.mark.parametrize("W,H,S", [(700, 450, 900), (1028, 64, 300), (8, 1, 3), (4, 37, 5),
+                                   (2060, 2000, 4000)])
+@pytest.mark.parametrize("metric,vn", [(0, 2), (1, 1)])
+@pytest.mark.parametrize("label", [0, 1])
+def test_block_first_pass(V, variant, W, H, S, metric, vn, label):
+    xy = inputs.place_seeds(W, H, S, W + 11 * H)
+    run_twin(V, W, H, xy, 2, -3, 3, sim_seed=17, label=label, metric=metric, vn=vn,
+             dmax=max(W, H), variant=variant, tag="block")
+
+
 # Tail fusion (the last passes of a step in one LDS-tiled launch): tiles of
 # 48 x 32 outputs with up to 8 pixels of halo, so the shapes span one tile,
 # ragged last tiles, grids smaller than the halo, and fused runs whose
