@@ -166,7 +166,11 @@ bool quad_ok(int32_t W, int32_t k);
 // requesting rows 2 (4) or 3 (5) rows ahead, otherwise variant 3 (ID) or 1
 // (XY); at a step of at least a quarter of both sides (block_ok: a step's
 // first two passes when it starts at k1) both run one lane per 2 x 2 or
-// 4 x 4 block of groups, which reads and writes every pixel once.  Variants 6-11 are 0-5 with
+// 4 x 4 block of groups, which reads and writes every pixel once; at other
+// steps of 128 and up whose column classes (columns congruent mod k) fit 16
+// lanes of 2 or 4 groups (class_groups), variant 4 gives lanes whole classes
+// and swaps their end groups over DPP, so no row is shared through LDS and
+// no label is looked up twice.  Variants 6-11 are 0-5 with
 // non-temporal stores of the output map.
 constexpr int kFloodVariants = 12;
 hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *table, int32_t S,

@@ -420,6 +420,23 @@ __global__ void __launch_bounds__(kBlock) k_flood_block(const uint32_t *__restri
                                              (int32_t)blockIdx.y);
 }
 
+// Column-class tiles (see flood_class_tile): G groups per lane, C lanes per
+// class.
+template <int G, int LABEL, int METRIC, int VN, int ST>
+__global__ void __launch_bounds__(kBlock) k_flood_class(const uint32_t *__restrict__ src,
+                                                        uint32_t *__restrict__ dst,
+                                                        const uint32_t *__restrict__ table,
+                                                        uint32_t S, int32_t W, int32_t H,
+                                                        int32_t k, int32_t C, FloodGrid g)
+{
+    const uint32_t logical = xcd_logical(blockIdx.x, g.nblocks);
+    if (LABEL == kLabelId)
+        flood_class_tile<G, METRIC, VN, 3, ST>(src, dst, TableLookup{table_rsrc(table, S)}, W, H,
+                                               k, C, g, seg_major(logical, g));
+    else
+        flood_class_tile<G, METRIC, VN, 3, ST>(src, dst, PosLabels{}, W, H, k, C, g, logical);
+}
+
 template <int LABEL, int METRIC, int ST, int TH>
 __global__ void __launch_bounds__(kBlock) k_flood_tail(const uint32_t *__restrict__ src,
                                                        uint32_t *__restrict__ dst,
@@ -681,6 +698,37 @@ hipError_t launch_flood_st(const uint32_t *src, uint32_t *dst, const uint32_t *t
         if (label == kLabelId) VD_BLOCK_M(kLabelId); else VD_BLOCK_M(kLabelXy);
 #undef VD_BLOCK_M
 #undef VD_BLOCK
+        return hipGetLastError();
+    }
+    if (variant == 4 && k >= kClassMinStep && class_groups(W, k) > 0) {
+        // whole column classes per group of lanes, neighbours over DPP
+        const int32_t G = class_groups(W, k), C = class_lanes(W, k, G);
+        FloodGrid g = flood_grid_quad(W, H, k, seg_rows);
+        const uint64_t nb = (uint64_t)class_blocks(k, C) * (uint64_t)std::min(k, H) * g.nseg;
+        if (nb == 0 || nb > 0x7FFFFFFFull) return hipErrorInvalidValue;
+        g.ncol = (uint32_t)class_blocks(k, C);
+        g.nblocks = (uint32_t)nb;
+        const dim3 grid(g.nblocks), block(kBlock);
+#define VD_CLASS(LB, MT, V)                                                                    \
+    do {                                                                                       \
+        if (G == 2)                                                                            \
+            hipLaunchKernelGGL((k_flood_class<2, LB, MT, V, ST>), grid, block, 0, s, src, dst,    \
+                               table, uS, W, H, k, C, g);                                      \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_flood_class<4, LB, MT, V, ST>), grid, block, 0, s, src, dst,    \
+                               table, uS, W, H, k, C, g);                                      \
+    } while (0)
+#define VD_CLASS_M(LB)                                                                         \
+    do {                                                                                       \
+        if (metric == kEuclid) {                                                               \
+            if (vn) VD_CLASS(LB, kEuclid, 1); else VD_CLASS(LB, kEuclid, 0);                   \
+        } else {                                                                               \
+            if (vn) VD_CLASS(LB, kManhattan, 1); else VD_CLASS(LB, kManhattan, 0);             \
+        }                                                                                      \
+    } while (0)
+        if (label == kLabelId) VD_CLASS_M(kLabelId); else VD_CLASS_M(kLabelXy);
+#undef VD_CLASS_M
+#undef VD_CLASS
         return hipGetLastError();
     }
     if (variant >= 4) {

@@ -500,6 +500,7 @@ __host__ __device__ __forceinline__ bool block_ok(int32_t W, int32_t H, int32_t 
 
 // XY labels: the label is the position.
 struct PosLabels {
+    static constexpr bool kLabelIsPos = true;
     __device__ __forceinline__ u32x4 pos4(u32x4 l, const G4 &) const { return l; }
 };
 
@@ -548,6 +549,210 @@ __device__ __forceinline__ void flood_block_tile(const uint32_t *src, uint32_t *
             }
             store4<ST>(labels_of(best), out, 4 * (x0 + n * k));
         }
+    }
+}
+
+// Column-class tile (steps of k >= 4 where a class fits one DPP row, see
+// class_lanes).  The columns congruent to x0 mod k, x0 + m k, are the only
+// ones a pixel of column x0 + m k takes candidates from, so lanes are given
+// whole classes instead of adjacent columns: lane j of a class (C lanes per
+// class, C a power of two up to 16, classes aligned to C lanes) owns the
+// G groups m = G j .. G j + G - 1 (G = 2 or 4).  A group's
+// neighbours at x -+ k are then the lane's own next groups, or for its
+// first and last group the last group of lane j - 1 and the first of lane
+// j + 1, which come over one DPP row shift each -- no shared rows, no halo,
+// and each label is loaded and (ID labels) looked up once per row.  Rows
+// are walked down the residue chain with quad_walk's rolling accumulators,
+// one set per group.  Lanes whose class lies past k address offsets past
+// the row (no memory access), so they neither read nor write.
+constexpr int kClassMaxC = 16;      // lanes per class: one DPP row
+constexpr int kClassMinStep = 128;  // below, the shared-row tiles' halo is small
+
+// Lanes per class with G groups per lane, 0 if a class does not fit.
+__host__ __device__ __forceinline__ int32_t class_lanes(int32_t W, int32_t k, int32_t G)
+{
+    if (W % kQuad != 0 || k % kQuad != 0 || k < kQuad) return 0;
+    const int32_t members = (W + k - 1) / k;   // columns of class 0 on the grid
+    const int32_t need = (members + G - 1) / G;
+    int32_t c = 1;
+    while (c < need) c <<= 1;
+    return c <= kClassMaxC ? c : 0;
+}
+
+// Groups per lane of the column-class tile for a pass: 2 where a class fits
+// 16 lanes of two, else 4 where it fits 16 of four, else 0 (not available).
+__host__ __device__ __forceinline__ int32_t class_groups(int32_t W, int32_t k)
+{
+    return class_lanes(W, k, 2) ? 2 : (class_lanes(W, k, 4) ? 4 : 0);
+}
+
+// Grid of the column-class tile: ncol blocks of kBlock / C classes x
+// min(k, H) chains x segments of at most L rows (chain-major, class-block
+// minor, as flood_grid_quad numbers its tiles).
+__host__ __device__ __forceinline__ int32_t class_blocks(int32_t k, int32_t C)
+{
+    const int32_t per = kBlock / C;   // classes per workgroup
+    return (k / kQuad + per - 1) / per;
+}
+
+// Value of lane - 1 (east == false) or lane + 1 (east == true) within the
+// lane's DPP row of 16 (row_shr:1 / row_shl:1); 0 for the lanes the shift
+// leaves without one.  (Whole-wave shifts, which would let a class span 64
+// lanes, measured slower.)
+__device__ __forceinline__ uint32_t dpp_shift(uint32_t v, bool east)
+{
+    return east ? (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x101, 0xF, 0xF, true)
+                : (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);
+}
+__device__ __forceinline__ u32x4 dpp_shift4(u32x4 v, bool east)
+{
+    return u32x4{dpp_shift(v[0], east), dpp_shift(v[1], east), dpp_shift(v[2], east),
+                 dpp_shift(v[3], east)};
+}
+
+template <int G, int METRIC, int VN, int NS, int ST, class LK>
+__device__ __forceinline__ void flood_class_tile(const uint32_t *src, uint32_t *dst,
+                                                 const LK &lk, int32_t W, int32_t H, int32_t k,
+                                                 int32_t C, const FloodGrid &g, uint32_t logical)
+{
+    static_assert(NS == 3 || NS == 4, "ring of 3 or 4 rows");
+    constexpr int A = NS - 1;                 // rows requested ahead of use
+    constexpr int U = NS == 3 ? 3 : 12;       // lcm(3, NS)
+    constexpr int D = NS - 2;                 // rows between a row's labels and its lookups
+    // tile: class block, residue chain, segment
+    const uint32_t cb = __builtin_amdgcn_readfirstlane(logical % g.ncol);
+    const uint32_t rs = logical / g.ncol;
+    const int32_t seg = __builtin_amdgcn_readfirstlane((int32_t)(rs % g.nseg));
+    const int32_t r = __builtin_amdgcn_readfirstlane((int32_t)(rs / g.nseg));
+    const int32_t nj = (H - 1 - r) / k + 1;
+    const int32_t j0 = seg * g.L, jend = min(j0 + g.L, nj);
+    if (j0 >= jend) return;
+    const int32_t y0 = r + j0 * k;
+    const int32_t nout = jend - j0;
+    const int32_t t = (int32_t)threadIdx.x;
+    const int32_t lane = t % C;   // lane of the class
+    const int32_t x0 = kQuad * ((int32_t)cb * (kBlock / C) + t / C);
+    const bool live = x0 < k;
+    const bool first = lane == 0, last = lane == C - 1;
+    int32_t oc[G];                // byte offsets of the lane's groups in a row
+    uint32_t p0[G];               // packed position of each group's first pixel in row y0
+#pragma unroll
+    for (int i = 0; i < G; ++i) {
+        const int32_t x = x0 + (G * lane + i) * k;
+        oc[i] = live ? 4 * x : INT32_MIN;
+        p0[i] = ((uint32_t)(y0 + (int32_t)kOff) << 16) | (uint32_t)(x + (int32_t)kOff);
+    }
+    const uint32_t step_bytes = 4u * (uint32_t)k * (uint32_t)W;
+    const uint32_t pk = (uint32_t)k << 16;
+    struct Slot_ {
+        G4 q[G];
+    };
+    Slot_ ring[NS];
+    const G4 none = {u32x4{0u, 0u, 0u, 0u}, u32x4{0u, 0u, 0u, 0u}};
+    Cursor in = cursor_at(src, y0 + k, W);   // input row 2
+    Cursor out = cursor_at(dst, y0, W);
+
+    // Labels of input row s, and (ID labels) positions of input row s - D.
+    auto request = [&](int32_t s, auto Slot, auto Phase) {
+        constexpr int slot = decltype(Slot)::value, phase = decltype(Phase)::value;
+        __amdgpu_buffer_rsrc_t rr;
+        if (phase < 2) {
+            rr = row_rsrc(src, y0 + (s - 1) * k, W, H);
+        } else {
+            rr = cursor_rsrc(in, W, H);
+            advance(in, step_bytes, k);
+        }
+#pragma unroll
+        for (int i = 0; i < G; ++i) ring[slot].q[i].l = load4(rr, oc[i]);
+        if (!LK::kLabelIsPos && phase >= D) {
+            Slot_ &n = ring[(slot + NS - D) % NS];
+#pragma unroll
+            for (int i = 0; i < G; ++i) {
+                const G4 &up = phase >= D + 1 ? ring[(slot + NS - D - 1) % NS].q[i] : none;
+                n.q[i].s = lk.pos4(n.q[i].l, up);
+            }
+        }
+    };
+    // The row in a slot as one Three per group: the neighbours at x -+ k.
+    auto fetch = [&](auto Slot, Three (&th)[G]) {
+        const Slot_ &q = ring[decltype(Slot)::value];
+        G4 grp[G];
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            grp[i].l = q.q[i].l;
+            grp[i].s = LK::kLabelIsPos ? q.q[i].l : q.q[i].s;
+        }
+        const u32x4 zero = {0u, 0u, 0u, 0u};
+        G4 west, east;   // last group of lane - 1, first group of lane + 1
+        west.l = dpp_shift4(grp[G - 1].l, false);
+        east.l = dpp_shift4(grp[0].l, true);
+        if (LK::kLabelIsPos) {
+            west.s = west.l;
+            east.s = east.l;
+        } else {
+            west.s = dpp_shift4(grp[G - 1].s, false);
+            east.s = dpp_shift4(grp[0].s, true);
+        }
+        if (first) west = G4{zero, zero};
+        if (last) east = G4{zero, zero};
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            th[i].a = i == 0 ? west : grp[i > 0 ? i - 1 : 0];
+            th[i].b = grp[i];
+            th[i].c = i == G - 1 ? east : grp[i < G - 1 ? i + 1 : 0];
+        }
+    };
+
+    u32x4 prow[3][G];
+    double acc[3][G][4];
+    auto pre = [&](auto M) { request(decltype(M)::value, IC<decltype(M)::value % NS>{}, M); };
+    pre(IC<0>{});
+    pre(IC<1>{});
+    pre(IC<2>{});
+    if constexpr (A >= 3) pre(IC<3>{});
+    {
+        Three th[G];
+        fetch(IC<0>{}, th);
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            prow[0][i] = u32x4{p0[i], p0[i] + 1, p0[i] + 2, p0[i] + 3};
+            fold<METRIC, 0, VN != 0, true>(acc[0][i], prow[0][i], th[i]);
+        }
+    }
+    pre(IC<A + 1>{});
+    {
+        Three th[G];
+        fetch(IC<1>{}, th);
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            prow[1][i] = prow[0][i] + pk;
+            fold<METRIC, 0, false, false>(acc[0][i], prow[0][i], th[i]);
+            fold<METRIC, 0, VN != 0, true>(acc[1][i], prow[1][i], th[i]);
+        }
+    }
+    int32_t s = 2;
+    auto step = [&](auto I) -> bool {
+        constexpr int u = (decltype(I)::value + 2) % U;   // s mod U
+        constexpr int c0 = (u + 1) % 3, c1 = (u + 2) % 3, c2 = u % 3;
+        if (s - 2 >= nout) return false;
+        request(s + A, IC<(u + A) % NS>{}, IC<kSteady>{});
+        Three th[G];
+        fetch(IC<u % NS>{}, th);
+        const __amdgpu_buffer_rsrc_t o = cursor_rsrc(out, W, H);
+#pragma unroll
+        for (int i = 0; i < G; ++i) {
+            prow[c2][i] = prow[c1][i] + pk;
+            fold<METRIC, 0, VN != 0, false>(acc[c0][i], prow[c0][i], th[i]);
+            store4<ST>(labels_of(acc[c0][i]), o, oc[i]);
+            fold<METRIC, 0, false, false>(acc[c1][i], prow[c1][i], th[i]);
+            fold<METRIC, 0, VN != 0, true>(acc[c2][i], prow[c2][i], th[i]);
+        }
+        advance(out, step_bytes, k);
+        ++s;
+        return true;
+    };
+    auto round = [&](auto... I) -> bool { return (step(I) && ...); };
+    while (expand<U>(round)) {
     }
 }
 

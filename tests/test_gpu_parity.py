@@ -184,6 +184,23 @@ def test_block_first_pass(V, variant, W, H, S, metric, vn, label):
              dmax=max(W, H), variant=variant, tag="block")
 
 
+# Variant 4 (and 10) at steps of 128 and up where one column class (the
+# columns congruent mod k) fits 16 lanes of two or four groups: lanes hold
+# whole classes and swap their end groups over DPP.  The widths give 1 to 16
+# lanes per class, both group counts, a last lane past the grid and classes
+# cut by the width; d_max is overridden so that dJFA steps start at k1 with
+# five Von Neumann passes, which reach these steps.
+@pytest.mark.parametrize("variant", [4, 10])
+@pytest.mark.parametrize("W,H,S", [(2060, 2000, 4000), (4100, 700, 3000), (1100, 300, 2000),
+                                   (8188, 600, 6000)])
+@pytest.mark.parametrize("metric,vn", [(0, 0), (1, 5)])
+@pytest.mark.parametrize("label", [0, 1])
+def test_class_tile(V, variant, W, H, S, metric, vn, label):
+    xy = inputs.place_seeds(W, H, S, W + 13 * H)
+    run_twin(V, W, H, xy, 2, -3, 3, sim_seed=19, label=label, metric=metric, vn=vn,
+             dmax=max(W, H), variant=variant, tag="class")
+
+
 # Tail fusion (the last passes of a step in one LDS-tiled launch): tiles of
 # 48 x 32 outputs with up to 8 pixels of halo, so the shapes span one tile,
 # ragged last tiles, grids smaller than the halo, and fused runs whose
