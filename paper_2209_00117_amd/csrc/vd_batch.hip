@@ -1047,6 +1047,9 @@ void vd_batch_destroy(vd_batch *b)
     }
     for (vd_sim *s : b->sims) {
         s->batch = nullptr;
+        // the batch built 4-byte indices in idx: its own steps' single-launch
+        // index starts from a fill
+        s->idx_builds = vd::kIndexEpochs;
         if (s->release) vd_destroy(s);   // destroyed by its owner while in the batch
     }
     if (b->capture) (void)hipStreamDestroy(b->capture);

@@ -158,8 +158,28 @@ __device__ __forceinline__ void splat_swap_seed(uint32_t *map, const uint32_t *t
     }
 }
 
-// After splat_swap_seed of every seed on the old positions (old_table)
-// into idx, idx[old position] holds the lowest kept seed label (index + 1)
+// The single-launch old-position index of an XY dJFA step: one 8-byte entry
+// per pixel, (epoch byte << 56) | (label << 32) | new position, built by
+// atomic minima.  Epoch bytes count down from 255 over the builds since the
+// index was last filled with all ones, so this build's entries are below
+// every earlier one and below all ones.  At one old position the lowest
+// kept label wins and brings its new position along; a seed that is not
+// kept offers kIndexNoLabel with position 0 (unclaimed once read), which
+// any kept seed's entry beats.  Labels must be below kIndexNoLabel.
+
+// (old_pos, new_pos: seed i's positions before and after the move.)
+__device__ __forceinline__ void index_mark_seed(uint64_t *idx, uint32_t old_pos,
+                                                uint32_t new_pos, int32_t i, int32_t W, bool kept,
+                                                uint32_t epoch)
+{
+    const uint32_t hi = (epoch << 24) | (kept ? (uint32_t)(i + 1) : kIndexNoLabel);
+    const uint64_t e = ((uint64_t)hi << 32) | (kept ? new_pos : 0u);
+    __hip_atomic_fetch_min(&idx[pixel_of(old_pos, W)], e, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// After splat_swap_seed of every seed on the old positions (old_table) into
+// idx, idx[old position] holds the lowest kept seed label (index + 1)
 // sitting there, or all ones.  That seed writes its new position (table)
 // over it; positions are >= (kOff << 16 | kOff), above every label, so no
 // other seed of the same old position can mistake the overwritten entry for

@@ -50,10 +50,6 @@ hipError_t launch_splat_id(uint32_t *map, const uint32_t *table, int32_t S, int3
                            const uint8_t *state, hipStream_t s);
 hipError_t launch_splat_xy(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
                            const uint8_t *state, hipStream_t s);
-// The same with the top bit set (a seed pixel of this step, which a first
-// pass reading through the old-position index takes as it is).
-hipError_t launch_splat_xy_marked(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
-                                  const uint8_t *state, hipStream_t s);
 // The ID splat on a map filled with all ones (a JFA step's start): the
 // atomic minimum alone.  All ones is no label: it indexes past the seed
 // table, whose answer is the sentinel position, so the flood passes treat
@@ -111,6 +107,20 @@ hipError_t launch_index_old(uint32_t *idx, const uint32_t *old_table, const uint
                             int32_t S, int32_t W, const uint8_t *state, hipStream_t s);
 hipError_t launch_relabel(uint32_t *map, const uint32_t *idx, int32_t W, int32_t H,
                           hipStream_t s);
+constexpr uint32_t kIndexNoLabel = 0xFFFFFFu;   // 24-bit label field, none
+constexpr int kIndexEpochs = 256;                // 8-bit epoch field
+
+// The single-launch form of launch_index_old for a dJFA step whose first
+// pass reads through the index (launch_flood_relabel): idx holds 8 bytes
+// per pixel, filled with all ones when it was carved out and again every
+// kIndexEpochs builds; `epoch` is 255 minus the builds since that fill.
+// Each seed marks its old position with one 64-bit atomic minimum of
+// (epoch, label, new position), and present seeds mark their pixels of this
+// step in `map` with the top bit set (a seed pixel of this step, which the
+// first pass takes as it is).  Needs S < kIndexNoLabel.
+hipError_t launch_index_marked(uint64_t *idx, uint32_t *map, const uint32_t *old_table,
+                               const uint32_t *table, int32_t S, int32_t W, const uint8_t *state,
+                               uint32_t epoch, hipStream_t s);
 
 // Internal labels to the external encoding of include/vdflood.h.
 hipError_t launch_export(const uint32_t *map, uint32_t *out, int64_t n, int32_t label,
@@ -180,8 +190,8 @@ hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *tabl
 // The first pass of an XY-label dJFA step, reading the previous diagram
 // through the old-position index instead of after a relabel pass: src holds
 // old positions (and this step's seed pixels, marked with the top bit by
-// launch_splat_xy_marked), idx is the index launch_index_old built (a
-// width*height map of its own).  dst equals the pass run on the relabelled
+// launch_index_marked), idx is the 8-byte-per-pixel index that launch
+// built.  dst equals the pass run on the relabelled
 // and splatted map.  Available where relabel_fold_ok(W, k) holds (width a
 // multiple of 4, k a multiple of 4 up to kMaxQuadLdsStep); `variant` picks
 // the rows in flight and the store policy as for launch_flood.

@@ -310,6 +310,22 @@ __global__ void __launch_bounds__(kBlock) k_index_resolve(uint32_t *__restrict__
     if (i < S && takes_part(state, i, kKept)) index_resolve_seed(idx, old_table, table, i, W);
 }
 
+// The 8-byte old-position index (see index_mark_seed) and, in the same
+// launch, the present seeds' pixels of this step marked in `map`
+// (splat_xy_seed with the top bit).
+__global__ void __launch_bounds__(kBlock) k_index_mark_splat(
+    uint64_t *__restrict__ idx, uint32_t *__restrict__ map,
+    const uint32_t *__restrict__ old_table, const uint32_t *__restrict__ table, int32_t S,
+    int32_t W, const uint8_t *__restrict__ state, uint32_t epoch)
+{
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= S) return;
+    const uint32_t now = table[i + 1];
+    const uint8_t st = state ? state[i] : (uint8_t)(kPresent | kKept);
+    index_mark_seed(idx, old_table[i + 1], now, i, W, (st & kKept) != 0u, epoch);
+    if (st & kPresent) map[pixel_of(now, W)] = now | kMarked;   // as splat_xy_seed
+}
+
 __global__ void __launch_bounds__(kBlock) k_relabel(uint32_t *__restrict__ map,
                                                     const uint32_t *__restrict__ idx,
                                                     int32_t W, int32_t H)
@@ -489,14 +505,6 @@ hipError_t launch_splat_xy(uint32_t *map, const uint32_t *table, int32_t S, int3
     return hipGetLastError();
 }
 
-hipError_t launch_splat_xy_marked(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
-                                  const uint8_t *state, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_splat_xy, grid1d(S), dim3(kBlock), 0, s, map, table, S, W, state,
-                       kMarked);
-    return hipGetLastError();
-}
-
 hipError_t launch_move(uint32_t *table, int32_t S, int32_t W, int32_t H, uint64_t move_seed,
                        int64_t t, int32_t lo, int32_t hi, const uint8_t *state, uint32_t *disp,
                        hipStream_t s)
@@ -589,6 +597,16 @@ hipError_t launch_index_old(uint32_t *idx, const uint32_t *old_table, const uint
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_index_resolve, grid1d(S), dim3(kBlock), 0, s, idx, old_table, table, S,
                        W, state);
+    return hipGetLastError();
+}
+
+hipError_t launch_index_marked(uint64_t *idx, uint32_t *map, const uint32_t *old_table,
+                               const uint32_t *table, int32_t S, int32_t W, const uint8_t *state,
+                               uint32_t epoch, hipStream_t s)
+{
+    if (S >= (int32_t)kIndexNoLabel || epoch > 255u) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_index_mark_splat, grid1d(S), dim3(kBlock), 0, s, idx, map, old_table,
+                       table, S, W, state, epoch);
     return hipGetLastError();
 }
 

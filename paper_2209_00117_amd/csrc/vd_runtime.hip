@@ -179,7 +179,7 @@ size_t footprint(const vd_config *c)
     size_t npix = (size_t)c->width * (size_t)c->height;
     size_t seeds = (size_t)c->num_seeds * 4;
     size_t b = 2 * align_up(npix * 4) + align_up(seeds + 4);   // + the sentinel entry
-    if (c->label == VD_LABEL_XY16) b += align_up(seeds + 4) + align_up(npix * 4);
+    if (c->label == VD_LABEL_XY16) b += align_up(seeds + 4) + align_up(npix * 8);
     b += align_up(12);                     // step counters
     b += align_up((size_t)c->num_seeds);   // seed-set state bytes
     if (c->label == VD_LABEL_ID32) b += align_up(seeds);   // parked positions
@@ -342,7 +342,9 @@ int jfa_prologue(vd_sim *s)
 // runs that pass and it is not part of a fused tail.
 bool fold_for(const vd_sim *s, const std::vector<Pass> &passes, int32_t th)
 {
-    if (s->cfg.label != VD_LABEL_XY16 || !s->idx || passes.empty()) return false;
+    if (s->cfg.label != VD_LABEL_XY16 || !s->idx || passes.empty() ||
+        (uint32_t)s->cfg.num_seeds >= vd::kIndexNoLabel)
+        return false;
     const size_t m = th ? vd::tail_len(passes) : 0;
     if (m >= passes.size()) return false;
     return vd::relabel_fold_ok(s->cfg.width, passes[0].k);
@@ -358,10 +360,14 @@ int djfa_prologue(vd_sim *s, bool fold)
         // The index of old positions goes to its own map; the first pass
         // reads the diagram through it.  This step's seed pixels are marked
         // so that the first pass takes them as they are.
-        VD_HIP(vd::launch_index_old(s->idx, s->pos_map, s->pos, c.num_seeds, c.width,
-                                    seed_state(s), s->stream));
-        VD_HIP(vd::launch_splat_xy_marked(cur, s->pos, c.num_seeds, c.width, seed_state(s),
-                                          s->stream));
+        if (s->idx_builds >= vd::kIndexEpochs) {
+            VD_HIP(vd::launch_fill(s->idx, 2 * (int64_t)c.width * c.height, 0xFFFFFFFFu,
+                                   s->stream));
+            s->idx_builds = 0;
+        }
+        const uint32_t epoch = (uint32_t)(vd::kIndexEpochs - 1 - s->idx_builds++);
+        VD_HIP(vd::launch_index_marked((uint64_t *)s->idx, cur, s->pos_map, s->pos, c.num_seeds,
+                                       c.width, seed_state(s), epoch, s->stream));
     } else if (c.label == VD_LABEL_XY16) {
         // The idle ping-pong buffer serves as the old-position index; the
         // first flood pass overwrites it.
@@ -1005,7 +1011,7 @@ int vd_init_sim(const vd_config *cfg, const int32_t *host_xy, void *dev_workspac
     base += align_up(npix * 4);
     if (cfg->label == VD_LABEL_XY16) {
         s->idx = (uint32_t *)base;
-        base += align_up(npix * 4);
+        base += align_up(npix * 8);
     }
     s->pos = (uint32_t *)base;
     base += align_up((size_t)S * 4 + 4);
@@ -1043,6 +1049,9 @@ int vd_init_sim(const vd_config *cfg, const int32_t *host_xy, void *dev_workspac
                            s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);   // packed is a local buffer
     if (e == hipSuccess) e = vd::launch_fill(s->disp, 3, 0u, s->stream);
+    // the old-position index starts empty (see launch_index_marked)
+    if (e == hipSuccess && s->idx)
+        e = vd::launch_fill(s->idx, 2 * (int64_t)npix, 0xFFFFFFFFu, s->stream);
     if (e != hipSuccess) {
         delete s;
         return fail(VD_EDEVICE, "copying seed positions failed: %s", hipGetErrorString(e));

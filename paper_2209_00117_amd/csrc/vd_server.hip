@@ -503,6 +503,9 @@ bool enqueue_batched(vd_server *sv, Tick &t, const std::vector<int32_t> &ids)
         p.table = m->pos;
         p.pos_map = m->pos_map;
         p.idx = m->idx;
+        // the tick builds a 4-byte index in idx: the simulation's own next
+        // single-launch index build starts from a fill
+        m->idx_builds = vd::kIndexEpochs;
         p.label = m->cfg.label;
         p.W = m->cfg.width;
         p.H = m->cfg.height;

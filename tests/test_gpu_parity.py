@@ -487,6 +487,61 @@ def test_read_map_into_caller_memory(V):
         g.close()
 
 
+@pytest.mark.parametrize("fill", [0x00, 0x01, 0xFF])
+def test_xy_index_in_dirty_workspace(V, fill):
+    """XY dJFA steps in a workspace whose bytes all start as `fill` (0 and
+    small values lie below every seed label, so an old-position index built
+    by atomic minima must not trust what the workspace held), with
+    coincident seeds and a removed seed: every map equals the oracle's."""
+    import torch
+    W, H, S = 256, 192, 300
+    xy = inputs.place_seeds(W, H, S, 21)
+    xy[7] = xy[3]                    # coincident seeds from the start
+    xy[150] = xy[3]
+    kw = dict(disp_lo=-2, disp_hi=2, label=1)
+    g = V.Sim.__new__(V.Sim)
+    g.cfg = V.config(W, H, S, **kw)
+    g.workspace = torch.full((V.footprint_bytes(g.cfg),), fill, dtype=torch.uint8,
+                             device="cuda")
+    g.stream = None
+    g.handle = V.init_sim(g.cfg, xy, g.workspace, None)
+    o = O.Sim(W, H, xy, 1, -2, 2, label_mode=1)
+    assert np.array_equal(g.read_map(), o.map)
+    for t in range(1, 6):
+        if t == 3:
+            g.remove_seeds([3, 40]), o.remove([3, 40])
+        g.move_seeds(), o.move()
+        g.djfa_step(), o.djfa_step()
+        nd = int((g.read_map() != o.map).sum())
+        assert nd == 0, f"fill={fill:#x}: dJFA map differs at t={t} on {nd} pixels"
+    g.close()
+
+
+def test_xy_index_epochs_and_batch(V):
+    """An XY simulation through more dJFA steps than the index has epoch
+    values (so the index is refilled and its epochs restart), with three
+    batched steps in between (the batch keeps its own form of the index in
+    the same memory): every map equals the oracle's."""
+    W, H, S = 64, 48, 40
+    xy = inputs.place_seeds(W, H, S, 9)
+    xy[5] = xy[1]
+    g = V.Sim(W, H, xy, disp_lo=-1, disp_hi=1, label=1)
+    o = O.Sim(W, H, xy, 1, -1, 1, label_mode=1)
+    for t in range(1, 271):
+        if t == 120:
+            b = V.Batch([g])
+            for _ in range(3):
+                b.step(V.STEP_DJFA)
+                o.move(), o.djfa_step()
+            b.close()
+            assert np.array_equal(g.read_map(), o.map), "after the batched steps"
+        g.move_seeds(), o.move()
+        g.djfa_step(), o.djfa_step()
+        nd = int((g.read_map() != o.map).sum())
+        assert nd == 0, f"dJFA map differs at step {t} on {nd} pixels"
+    g.close()
+
+
 @pytest.mark.parametrize("label", [0, 1])
 def test_djfa_splat_over_stale_labels(V, label):
     """Seeds moved (vd_set_seeds) onto pixels that hold smaller labels of
