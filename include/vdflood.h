@@ -112,8 +112,8 @@ typedef struct vd_timing {
 void vd_config_default(vd_config *cfg);
 
 /* Device bytes vd_init_sim needs for cfg: two ping-pong label maps
- * (4 B per pixel each; in XY mode also the old-position index of dJFA
- * steps, 8 B per pixel), the seed table (4 B per seed plus one sentinel entry; in XY mode
+ * (4 B per pixel each; in XY mode a third, the old-position index of dJFA
+ * steps), the seed table (4 B per seed plus one sentinel entry; in XY mode
  * also the positions the diagram refers to), 256 B of
  * step counters, the seed-set state (1 B per seed; in ID mode also 4 B per
  * seed for the positions of removed seeds) and 256 B of alignment slack,

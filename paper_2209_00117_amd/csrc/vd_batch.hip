@@ -869,6 +869,7 @@ int vd_batch_step(vd_batch *b, int32_t mode, int32_t move)
         vd_sim *s = b->sims[i];
         s->cur ^= (int)(flips(b, mode, (int32_t)i) & 1);
         s->t += moved;
+        s->reach = 0;   // the diagram refers to the current positions
     }
     if (b->timing && b->used >= 4096) return batch_harvest(b);
     return VD_OK;

@@ -158,22 +158,24 @@ __device__ __forceinline__ void splat_swap_seed(uint32_t *map, const uint32_t *t
     }
 }
 
-// The single-launch old-position index of an XY dJFA step: one 8-byte entry
-// per pixel, (epoch byte << 56) | (label << 32) | new position, built by
-// atomic minima.  Epoch bytes count down from 255 over the builds since the
-// index was last filled with all ones, so this build's entries are below
-// every earlier one and below all ones.  At one old position the lowest
-// kept label wins and brings its new position along; a seed that is not
-// kept offers kIndexNoLabel with position 0 (unclaimed once read), which
-// any kept seed's entry beats.  Labels must be below kIndexNoLabel.
-
-// (old_pos, new_pos: seed i's positions before and after the move.)
-__device__ __forceinline__ void index_mark_seed(uint64_t *idx, uint32_t old_pos,
+// The single-launch old-position index of an XY dJFA step: one 32-bit entry
+// per pixel, (epoch << 29) | (label << 8) | move code, built by atomic
+// minima.  Epochs count down from kIndexEpochs - 1 over the builds since
+// the index was last filled with all ones, so this build's entries are
+// below every earlier one and below all ones.  At one old position the
+// lowest kept label wins and brings its move along: code = (dy + 8) << 4 |
+// (dx + 8), the new position minus the old, at most kIndexMaxReach per
+// axis.  A seed that is not kept offers the label kIndexNoLabel, which any
+// kept seed's entry beats and which reads as unclaimed.  (old_pos,
+// new_pos: seed i's position in the diagram and now.)
+__device__ __forceinline__ void index_mark_seed(uint32_t *idx, uint32_t old_pos,
                                                 uint32_t new_pos, int32_t i, int32_t W, bool kept,
                                                 uint32_t epoch)
 {
-    const uint32_t hi = (epoch << 24) | (kept ? (uint32_t)(i + 1) : kIndexNoLabel);
-    const uint64_t e = ((uint64_t)hi << 32) | (kept ? new_pos : 0u);
+    const uint32_t dx = (new_pos & 0xFFFFu) + 8u - (old_pos & 0xFFFFu);
+    const uint32_t dy = (new_pos >> 16) + 8u - (old_pos >> 16);
+    const uint32_t e = (epoch << 29) |
+                       (kept ? ((uint32_t)(i + 1) << 8) | (dy << 4) | dx : kIndexNoLabel << 8);
     __hip_atomic_fetch_min(&idx[pixel_of(old_pos, W)], e, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
 }

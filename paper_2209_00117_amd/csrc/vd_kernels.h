@@ -107,18 +107,22 @@ hipError_t launch_index_old(uint32_t *idx, const uint32_t *old_table, const uint
                             int32_t S, int32_t W, const uint8_t *state, hipStream_t s);
 hipError_t launch_relabel(uint32_t *map, const uint32_t *idx, int32_t W, int32_t H,
                           hipStream_t s);
-constexpr uint32_t kIndexNoLabel = 0xFFFFFFu;   // 24-bit label field, none
-constexpr int kIndexEpochs = 256;                // 8-bit epoch field
+// The single-launch old-position index (index_mark_seed): 32-bit entries of
+// a 3-bit epoch, a 21-bit label and an 8-bit move code.
+constexpr uint32_t kIndexNoLabel = 0x1FFFFFu;   // label field: no kept seed
+constexpr int kIndexEpochs = 8;                 // epoch values before a refill
+constexpr int kIndexMaxReach = 7;               // largest move per axis it encodes
 
 // The single-launch form of launch_index_old for a dJFA step whose first
-// pass reads through the index (launch_flood_relabel): idx holds 8 bytes
-// per pixel, filled with all ones when it was carved out and again every
-// kIndexEpochs builds; `epoch` is 255 minus the builds since that fill.
-// Each seed marks its old position with one 64-bit atomic minimum of
-// (epoch, label, new position), and present seeds mark their pixels of this
-// step in `map` with the top bit set (a seed pixel of this step, which the
-// first pass takes as it is).  Needs S < kIndexNoLabel.
-hipError_t launch_index_marked(uint64_t *idx, uint32_t *map, const uint32_t *old_table,
+// pass reads through the index (launch_flood_relabel): idx (a width*height
+// map of its own) is filled with all ones when it is carved out and again
+// every kIndexEpochs builds; `epoch` is kIndexEpochs - 1 minus the builds
+// since that fill.  Each seed marks its old position with one atomic
+// minimum, and present seeds mark their pixels of this step in `map` with
+// the top bit set (a seed pixel of this step, which the first pass takes as
+// it is).  Needs S + 1 < kIndexNoLabel, and no kept seed more than
+// kIndexMaxReach pixels per axis from the position the diagram refers to.
+hipError_t launch_index_marked(uint32_t *idx, uint32_t *map, const uint32_t *old_table,
                                const uint32_t *table, int32_t S, int32_t W, const uint8_t *state,
                                uint32_t epoch, hipStream_t s);
 
@@ -190,8 +194,8 @@ hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *tabl
 // The first pass of an XY-label dJFA step, reading the previous diagram
 // through the old-position index instead of after a relabel pass: src holds
 // old positions (and this step's seed pixels, marked with the top bit by
-// launch_index_marked), idx is the 8-byte-per-pixel index that launch
-// built.  dst equals the pass run on the relabelled
+// launch_index_marked), idx is the index that launch built.  dst equals the
+// pass run on the relabelled
 // and splatted map.  Available where relabel_fold_ok(W, k) holds (width a
 // multiple of 4, k a multiple of 4 up to kMaxQuadLdsStep); `variant` picks
 // the rows in flight and the store policy as for launch_flood.

@@ -310,11 +310,11 @@ __global__ void __launch_bounds__(kBlock) k_index_resolve(uint32_t *__restrict__
     if (i < S && takes_part(state, i, kKept)) index_resolve_seed(idx, old_table, table, i, W);
 }
 
-// The 8-byte old-position index (see index_mark_seed) and, in the same
+// The single-launch old-position index (see index_mark_seed) and, in the same
 // launch, the present seeds' pixels of this step marked in `map`
 // (splat_xy_seed with the top bit).
 __global__ void __launch_bounds__(kBlock) k_index_mark_splat(
-    uint64_t *__restrict__ idx, uint32_t *__restrict__ map,
+    uint32_t *__restrict__ idx, uint32_t *__restrict__ map,
     const uint32_t *__restrict__ old_table, const uint32_t *__restrict__ table, int32_t S,
     int32_t W, const uint8_t *__restrict__ state, uint32_t epoch)
 {
@@ -600,11 +600,12 @@ hipError_t launch_index_old(uint32_t *idx, const uint32_t *old_table, const uint
     return hipGetLastError();
 }
 
-hipError_t launch_index_marked(uint64_t *idx, uint32_t *map, const uint32_t *old_table,
+hipError_t launch_index_marked(uint32_t *idx, uint32_t *map, const uint32_t *old_table,
                                const uint32_t *table, int32_t S, int32_t W, const uint8_t *state,
                                uint32_t epoch, hipStream_t s)
 {
-    if (S >= (int32_t)kIndexNoLabel || epoch > 255u) return hipErrorInvalidValue;
+    if (S + 1 >= (int32_t)kIndexNoLabel || epoch >= (uint32_t)kIndexEpochs)
+        return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_index_mark_splat, grid1d(S), dim3(kBlock), 0, s, idx, map, old_table,
                        table, S, W, state, epoch);
     return hipGetLastError();

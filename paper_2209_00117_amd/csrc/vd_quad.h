@@ -332,10 +332,9 @@ struct TableLookup {
 
 // RelabelLookup: the XY labels of the previous diagram, read by a dJFA
 // step's first pass.  A label is an old position, which stands for the
-// moved position of the lowest kept seed that sat there (the low word of
-// the 8-byte index entry at the old position, see index_mark_seed: a
-// position, else 0 or all ones for "no such seed", both below every
-// position as signed values), or a seed pixel
+// moved position of the lowest kept seed that sat there (the old position
+// plus the move code of the index entry there, see index_mark_seed; the
+// label field kIndexNoLabel: no such seed, unclaimed), or a seed pixel
 // claimed by this step's splat, marked with the top bit, which stands for
 // itself; 0 stays unclaimed.  The translated value is both the label and
 // the position.  Where the label repeats that of the left neighbour in the
@@ -353,9 +352,11 @@ struct RelabelLookup {
         const bool marked = (l & kMarked) != 0u;
         const int32_t x = (int32_t)(l & 0xFFFFu) - (int32_t)kOff;
         const int32_t y = (int32_t)(l >> 16) - (int32_t)kOff;
-        const int32_t at = (fresh && !marked && l != kEmpty) ? 8 * (y * W + x) : -1;
+        const int32_t at = (fresh && !marked && l != kEmpty) ? 4 * (y * W + x) : -1;
         const uint32_t v = __builtin_amdgcn_raw_buffer_load_b32(idx, at, 0, 0);
-        const uint32_t moved = (int32_t)v >= (int32_t)((kOff << 16) | kOff) ? v : kEmpty;
+        const bool kept = l != kEmpty && ((v >> 8) & kIndexNoLabel) != kIndexNoLabel;
+        const uint32_t moved =
+            kept ? l + ((((v >> 4) & 15u) << 16) | (v & 15u)) - 0x00080008u : kEmpty;
         return marked ? (l & ~kMarked) : moved;
     }
     __device__ __forceinline__ u32x4 pos4(u32x4 l, const G4 &up) const

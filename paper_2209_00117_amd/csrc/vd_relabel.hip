@@ -22,9 +22,7 @@ __global__ void __launch_bounds__(kBlock) k_flood_quad_relabel(const uint32_t *_
     using Q = typename std::conditional<WIDE, QuadRowWide, QuadRow>::type;
     __shared__ Q lds[2];
     const RelabelLookup lk{
-        __builtin_amdgcn_make_buffer_rsrc((void *)idx, 0, (int)(8u * (uint32_t)W * (uint32_t)H),
-                                          kRsrcWord3),
-        W};
+        __builtin_amdgcn_make_buffer_rsrc((void *)idx, 0, 4 * W * H, kRsrcWord3), W};
     // Tiles are taken segment-major: the index lines of the old positions in
     // one band of rows -- each cell's rows lie on different chains -- are
     // fetched into one L2 and reused there.

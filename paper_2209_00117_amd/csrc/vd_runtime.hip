@@ -179,7 +179,7 @@ size_t footprint(const vd_config *c)
     size_t npix = (size_t)c->width * (size_t)c->height;
     size_t seeds = (size_t)c->num_seeds * 4;
     size_t b = 2 * align_up(npix * 4) + align_up(seeds + 4);   // + the sentinel entry
-    if (c->label == VD_LABEL_XY16) b += align_up(seeds + 4) + align_up(npix * 8);
+    if (c->label == VD_LABEL_XY16) b += align_up(seeds + 4) + align_up(npix * 4);
     b += align_up(12);                     // step counters
     b += align_up((size_t)c->num_seeds);   // seed-set state bytes
     if (c->label == VD_LABEL_ID32) b += align_up(seeds);   // parked positions
@@ -339,11 +339,12 @@ int jfa_prologue(vd_sim *s)
 // Whether an XY dJFA step translates the previous diagram's labels inside
 // its first flood pass (which then reads the map through the index) rather
 // than in a relabel pass of its own: where the four-column shared-row tile
-// runs that pass and it is not part of a fused tail.
+// runs that pass and it is not part of a fused tail, and the index's move
+// codes hold every seed's move since the diagram was made.
 bool fold_for(const vd_sim *s, const std::vector<Pass> &passes, int32_t th)
 {
     if (s->cfg.label != VD_LABEL_XY16 || !s->idx || passes.empty() ||
-        (uint32_t)s->cfg.num_seeds >= vd::kIndexNoLabel)
+        (uint32_t)s->cfg.num_seeds + 1u >= vd::kIndexNoLabel || s->reach > vd::kIndexMaxReach)
         return false;
     const size_t m = th ? vd::tail_len(passes) : 0;
     if (m >= passes.size()) return false;
@@ -361,13 +362,13 @@ int djfa_prologue(vd_sim *s, bool fold)
         // reads the diagram through it.  This step's seed pixels are marked
         // so that the first pass takes them as they are.
         if (s->idx_builds >= vd::kIndexEpochs) {
-            VD_HIP(vd::launch_fill(s->idx, 2 * (int64_t)c.width * c.height, 0xFFFFFFFFu,
+            VD_HIP(vd::launch_fill(s->idx, (int64_t)c.width * c.height, 0xFFFFFFFFu,
                                    s->stream));
             s->idx_builds = 0;
         }
         const uint32_t epoch = (uint32_t)(vd::kIndexEpochs - 1 - s->idx_builds++);
-        VD_HIP(vd::launch_index_marked((uint64_t *)s->idx, cur, s->pos_map, s->pos, c.num_seeds,
-                                       c.width, seed_state(s), epoch, s->stream));
+        VD_HIP(vd::launch_index_marked(s->idx, cur, s->pos_map, s->pos, c.num_seeds, c.width,
+                                       seed_state(s), epoch, s->stream));
     } else if (c.label == VD_LABEL_XY16) {
         // The idle ping-pong buffer serves as the old-position index; the
         // first flood pass overwrites it.
@@ -488,6 +489,7 @@ int step(vd_sim *s, bool dynamic)
     if (r) return r;
     const bool removed = s->removed;
     r = dynamic ? do_djfa(s) : do_jfa(s);
+    if (r == VD_OK) s->reach = 0;   // the diagram refers to the current positions
     if (r == VD_OK && dynamic && removed) r = refill_check(s);
     if (r == VD_OK) r = settle(s);
     // the diagram now refers to the current positions
@@ -1011,7 +1013,7 @@ int vd_init_sim(const vd_config *cfg, const int32_t *host_xy, void *dev_workspac
     base += align_up(npix * 4);
     if (cfg->label == VD_LABEL_XY16) {
         s->idx = (uint32_t *)base;
-        base += align_up(npix * 8);
+        base += align_up(npix * 4);
     }
     s->pos = (uint32_t *)base;
     base += align_up((size_t)S * 4 + 4);
@@ -1051,7 +1053,7 @@ int vd_init_sim(const vd_config *cfg, const int32_t *host_xy, void *dev_workspac
     if (e == hipSuccess) e = vd::launch_fill(s->disp, 3, 0u, s->stream);
     // the old-position index starts empty (see launch_index_marked)
     if (e == hipSuccess && s->idx)
-        e = vd::launch_fill(s->idx, 2 * (int64_t)npix, 0xFFFFFFFFu, s->stream);
+        e = vd::launch_fill(s->idx, (int64_t)npix, 0xFFFFFFFFu, s->stream);
     if (e != hipSuccess) {
         delete s;
         return fail(VD_EDEVICE, "copying seed positions failed: %s", hipGetErrorString(e));
@@ -1071,6 +1073,7 @@ int vd_move_seeds(vd_sim *s)
     if (s->broken) return fail(VD_ESTATE, "simulation unusable after an earlier device error");
     if (s->batch) return fail(VD_ESTATE, "simulation is driven by a batch (vd_batch_step)");
     s->t += 1;
+    s->reach = std::min(s->reach + std::max(abs(s->cfg.disp_lo), abs(s->cfg.disp_hi)), 1 << 20);
     hipError_t e = vd::launch_move(s->pos, s->cfg.num_seeds, s->cfg.width, s->cfg.height,
                                    s->move_seed, s->t, s->cfg.disp_lo, s->cfg.disp_hi,
                                    seed_state(s), s->measured ? s->disp : nullptr, s->stream);
@@ -1115,6 +1118,7 @@ int vd_set_seeds(vd_sim *s, const int32_t *host_xy, size_t count)
         return fail(VD_EDEVICE, "setting seed positions failed: %s", hipGetErrorString(e));
     }
     s->t += 1;
+    s->reach = 1 << 20;   // any distance
     return VD_OK;
 }
 

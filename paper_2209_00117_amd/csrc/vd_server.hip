@@ -497,6 +497,7 @@ bool enqueue_batched(vd_server *sv, Tick &t, const std::vector<int32_t> &ids)
         vd_sim *m = s.sim;
         sims.push_back(m);
         m->t += 1;
+        m->reach = 0;   // after the tick the diagram refers to the moved positions
         vd::TickPrep &p = hp[j];
         memset(&p, 0, sizeof p);
         p.map = m->map[m->cur];

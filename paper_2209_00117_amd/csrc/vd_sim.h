@@ -66,10 +66,11 @@ struct vd_sim {
     int cur = 0;                 // map[cur] holds the current diagram
     uint32_t *pos = nullptr;     // seed table: sentinel, then current positions
     uint32_t *pos_map = nullptr; // XY mode: the table the diagram's labels refer to
-    uint32_t *idx = nullptr;     // XY mode: the old-position index of dJFA steps, 8 B per
-                                 // pixel (batches and servers use its first half)
+    uint32_t *idx = nullptr;     // XY mode: the old-position index of dJFA steps (a map)
     int32_t idx_builds = 0;      // single-launch index builds since idx was filled with
                                  // all ones (kIndexEpochs: fill before the next)
+    int32_t reach = 0;           // bound on how far (per axis) any seed has moved since the
+                                 // diagram was made
     int64_t t = 0;
     int32_t dmax = 0;
     uint32_t *disp = nullptr;    // [0]: displacement bound since the last step, [1]: scratch

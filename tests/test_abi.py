@@ -42,9 +42,9 @@ def test_footprint():
     # mode: parked positions (4 B per seed), slack (256 B)
     assert V.footprint_bytes(c) == 2 * npix + 1280 + 256 + 256 + 1024 + 256
     cx = V.config(512, 512, 256, label=V.LABEL_XY16)
-    # XY mode: the old-position index of dJFA steps (8 B per pixel) and the
+    # XY mode: a third map (the old-position index of dJFA steps) and the
     # positions the diagram refers to instead of the parked positions
-    assert V.footprint_bytes(cx) == 4 * npix + 1280 + 1280 + 256 + 256 + 256
+    assert V.footprint_bytes(cx) == 3 * npix + 1280 + 1280 + 256 + 256 + 256
     big = V.config(8192, 8192, 1 << 20)
     assert V.footprint_bytes(big) == (2 * 8192 * 8192 * 4 + 4 * (1 << 20) + 256 + 256
                                       + (1 << 20) + 4 * (1 << 20) + 256)

@@ -542,6 +542,25 @@ def test_xy_index_epochs_and_batch(V):
     g.close()
 
 
+@pytest.mark.parametrize("d,moves", [(7, 1), (8, 1), (3, 2), (4, 2), (1, 9)])
+def test_xy_index_move_reach(V, d, moves):
+    """XY dJFA steps after `moves` moves of up to d pixels per axis: up to 7
+    pixels in all the index codes each seed's move, beyond that the step
+    relabels in a pass of its own; both give the oracle's maps."""
+    W, H, S = 192, 160, 200
+    xy = inputs.place_seeds(W, H, S, 33)
+    xy[9] = xy[2]
+    g = V.Sim(W, H, xy, disp_lo=-d, disp_hi=d, label=1, sim_seed=4)
+    o = O.Sim(W, H, xy, 4, -d, d, label_mode=1)
+    for t in range(1, 5):
+        for _ in range(moves):
+            g.move_seeds(), o.move()
+        g.djfa_step(), o.djfa_step()
+        nd = int((g.read_map() != o.map).sum())
+        assert nd == 0, f"d={d} moves={moves}: dJFA map differs at step {t} on {nd} pixels"
+    g.close()
+
+
 @pytest.mark.parametrize("label", [0, 1])
 def test_djfa_splat_over_stale_labels(V, label):
     """Seeds moved (vd_set_seeds) onto pixels that hold smaller labels of
