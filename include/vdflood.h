@@ -296,8 +296,12 @@ int vd_get_timing(vd_sim *sim, vd_timing *out);
  * two maps exceed the 256 MB Infinity Cache); -1 restores the defaults:
  * per pass, 4 in JFA and 3 in dJFA steps for ID labels, 4 for JFA steps of
  * k >= 512 and 1 otherwise for XY labels, plus 6 where the two maps exceed
- * 192 MiB.  Variants differ in speed only: every variant writes the same
- * labels. */
+ * 192 MiB.  An XY JFA step that starts from the previous diagram instead of
+ * a filled map (where its first pass has k of at least a quarter of both
+ * sides, and width and k are multiples of 4) runs that pass with one lane
+ * per block of four-column groups whatever the variant, which then picks
+ * only the store policy.  Variants differ in speed only: every variant
+ * writes the same labels. */
 int vd_set_flood_variant(vd_sim *sim, int variant);
 
 /* Tail fusion: a step's last passes (the longest run of steps 1, 2 or 4

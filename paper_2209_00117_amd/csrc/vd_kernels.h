@@ -50,6 +50,10 @@ hipError_t launch_splat_id(uint32_t *map, const uint32_t *table, int32_t S, int3
                            const uint8_t *state, hipStream_t s);
 hipError_t launch_splat_xy(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
                            const uint8_t *state, hipStream_t s);
+// The same with the top bit set (a seed pixel of this step, over the
+// previous diagram: see launch_flood_seeds).
+hipError_t launch_splat_xy_marked(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
+                                  const uint8_t *state, hipStream_t s);
 // The ID splat on a map filled with all ones (a JFA step's start): the
 // atomic minimum alone.  All ones is no label: it indexes past the seed
 // table, whose answer is the sentinel position, so the flood passes treat
@@ -190,6 +194,17 @@ constexpr int kFloodVariants = 12;
 hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *table, int32_t S,
                         int32_t W, int32_t H, int32_t k, int32_t vn, int32_t label,
                         int32_t metric, int32_t variant, int32_t seg_rows, hipStream_t s);
+
+// The first pass of an XY-label JFA step on the previous diagram instead of
+// a filled map: src holds the previous diagram with this step's seed pixels
+// splatted with the top bit set (launch_splat_xy_marked); only those count
+// as claimed, so dst equals the pass on the filled and splatted map.  The
+// block tile runs it (flood_seeds_ok(W, H, k): widths and k multiples of 4,
+// k at least a quarter of both sides, as at a step's first pass); `variant`
+// picks only the store policy.
+bool flood_seeds_ok(int32_t W, int32_t H, int32_t k);
+hipError_t launch_flood_seeds(const uint32_t *src, uint32_t *dst, int32_t W, int32_t H, int32_t k,
+                              int32_t vn, int32_t metric, int32_t variant, hipStream_t s);
 
 // The first pass of an XY-label dJFA step, reading the previous diagram
 // through the old-position index instead of after a relabel pass: src holds

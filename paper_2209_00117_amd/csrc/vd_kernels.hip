@@ -416,6 +416,10 @@ __global__ void __launch_bounds__(kBlock) k_flood_quad_idd(const uint32_t *__res
                                               xcd_logical(blockIdx.x, g.nblocks));
 }
 
+// LABEL of k_flood_block for the first pass of an XY JFA step that reads the
+// previous diagram with this step's seed pixels marked (SeedMarks).
+constexpr int kLabelXySeeds = 2;
+
 // One lane per NB x NB block of four-column groups {x0 + n k} x {y0 + m k}
 // (x0 = 4 * the lane's group, y0 = blockIdx.y), for steps with
 // block_span(W, H, k) == NB.
@@ -431,8 +435,11 @@ __global__ void __launch_bounds__(kBlock) k_flood_block(const uint32_t *__restri
     if (LABEL == kLabelId)
         flood_block_tile<NB, METRIC, VN, ST>(src, dst, TableLookup{table_rsrc(table, S)}, W, H,
                                              k, gx, (int32_t)blockIdx.y);
-    else
+    else if (LABEL == kLabelXy)
         flood_block_tile<NB, METRIC, VN, ST>(src, dst, PosLabels{}, W, H, k, gx,
+                                             (int32_t)blockIdx.y);
+    else   // kLabelXySeeds
+        flood_block_tile<NB, METRIC, VN, ST>(src, dst, SeedMarks{}, W, H, k, gx,
                                              (int32_t)blockIdx.y);
 }
 
@@ -502,6 +509,14 @@ hipError_t launch_splat_xy(uint32_t *map, const uint32_t *table, int32_t S, int3
                            const uint8_t *state, hipStream_t s)
 {
     hipLaunchKernelGGL(k_splat_xy, grid1d(S), dim3(kBlock), 0, s, map, table, S, W, state, 0u);
+    return hipGetLastError();
+}
+
+hipError_t launch_splat_xy_marked(uint32_t *map, const uint32_t *table, int32_t S, int32_t W,
+                                  const uint8_t *state, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_splat_xy, grid1d(S), dim3(kBlock), 0, s, map, table, S, W, state,
+                       kMarked);
     return hipGetLastError();
 }
 
@@ -692,7 +707,8 @@ hipError_t launch_flood_st(const uint32_t *src, uint32_t *dst, const uint32_t *t
                            int32_t metric, int32_t variant, int32_t seg_rows, hipStream_t s)
 {
     uint32_t uS = (uint32_t)S;
-    if (variant >= 4 && block_ok(W, H, k)) {
+    if (label == kLabelXySeeds && !block_ok(W, H, k)) return hipErrorInvalidValue;
+    if ((variant >= 4 || label == kLabelXySeeds) && block_ok(W, H, k)) {
         // every pixel's candidates in one block of 2 x 2 or 4 x 4 groups per lane
         const int32_t gx = std::min(k, W) / kQuad;
         const dim3 grid((unsigned)((gx + kBlock - 1) / kBlock), (unsigned)std::min(k, H));
@@ -714,7 +730,12 @@ hipError_t launch_flood_st(const uint32_t *src, uint32_t *dst, const uint32_t *t
             if (vn) VD_BLOCK(LB, kManhattan, 1); else VD_BLOCK(LB, kManhattan, 0);             \
         }                                                                                      \
     } while (0)
-        if (label == kLabelId) VD_BLOCK_M(kLabelId); else VD_BLOCK_M(kLabelXy);
+        if (label == kLabelId)
+            VD_BLOCK_M(kLabelId);
+        else if (label == kLabelXy)
+            VD_BLOCK_M(kLabelXy);
+        else
+            VD_BLOCK_M(kLabelXySeeds);
 #undef VD_BLOCK_M
 #undef VD_BLOCK
         return hipGetLastError();
@@ -886,6 +907,14 @@ hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *tabl
                                          variant - kFloodVariants / 2, seg_rows, s);
     return launch_flood_st<0>(src, dst, table, S, W, H, k, vn, label, metric, variant, seg_rows,
                               s);
+}
+
+bool flood_seeds_ok(int32_t W, int32_t H, int32_t k) { return block_ok(W, H, k); }
+
+hipError_t launch_flood_seeds(const uint32_t *src, uint32_t *dst, int32_t W, int32_t H, int32_t k,
+                              int32_t vn, int32_t metric, int32_t variant, hipStream_t s)
+{
+    return launch_flood(src, dst, nullptr, 0, W, H, k, vn, kLabelXySeeds, metric, variant, 0, s);
 }
 
 }  // namespace vd

@@ -374,6 +374,22 @@ struct RelabelLookup {
     __device__ __forceinline__ uint32_t pos1(uint32_t l) const { return one(l, true); }
 };
 
+// XY labels of a JFA step's first pass read straight from the previous
+// diagram: only this step's seed pixels, marked with the top bit by the
+// splat, are claimed (by themselves); every other label is left from the
+// previous diagram and counts as unclaimed, as on a filled map.  A pass
+// writes no marked label, so a diagram holds none.
+struct SeedMarks {
+    static constexpr bool kLabelIsPos = true;
+    __device__ __forceinline__ u32x4 pos4(u32x4 l, const G4 &) const
+    {
+        u32x4 r;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) r[e] = (l[e] & kMarked) ? (l[e] & ~kMarked) : kEmpty;
+        return r;
+    }
+};
+
 // Shared rows of the ID tile, in groups of four entries: entry e is column
 // x0 - h + e.  Labels and positions are kept apart so that a lane moves 16
 // contiguous bytes of each array per group.
@@ -523,7 +539,10 @@ __device__ __forceinline__ void flood_block_tile(const uint32_t *src, uint32_t *
 #pragma unroll
     for (int m = 0; m < NB; ++m)
 #pragma unroll
-        for (int n = 0; n < NB; ++n) q[m][n].s = lk.pos4(q[m][n].l, none);
+        for (int n = 0; n < NB; ++n) {
+            q[m][n].s = lk.pos4(q[m][n].l, none);
+            if (LK::kLabelIsPos) q[m][n].l = q[m][n].s;   // the translated label
+        }
     const uint32_t p0 = ((uint32_t)(y0 + (int32_t)kOff) << 16) | (uint32_t)(x0 + (int32_t)kOff);
 #pragma unroll
     for (int m = 0; m < NB; ++m) {

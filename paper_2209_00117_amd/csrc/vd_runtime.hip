@@ -236,9 +236,12 @@ int harvest(vd_sim *s)
 // With th (a tile height) non-zero, the step's last passes (tail_len) run
 // as one launch with the store policy of the last pass.
 // With relabel (an XY dJFA step's old-position index) non-null, the first
-// pass reads the previous diagram through it (launch_flood_relabel).
+// pass reads the previous diagram through it (launch_flood_relabel); with
+// seeds, an XY JFA step's first pass reads the previous diagram with the
+// seed pixels marked (launch_flood_seeds).
 int launch_passes(vd_sim *s, const std::vector<Pass> &passes, int32_t th,
-                  const uint32_t *relabel = nullptr, hipStream_t stream = nullptr)
+                  const uint32_t *relabel = nullptr, hipStream_t stream = nullptr,
+                  bool seeds = false)
 {
     if (!stream) stream = s->stream;
     const size_t m = th ? vd::tail_len(passes) : 0;
@@ -249,6 +252,10 @@ int launch_passes(vd_sim *s, const std::vector<Pass> &passes, int32_t th,
             VD_HIP(vd::launch_flood_relabel(s->map[s->cur], s->map[s->cur ^ 1], relabel,
                                             s->cfg.width, s->cfg.height, p.k, p.vn,
                                             s->cfg.metric, p.variant, p.seg_rows, stream));
+        else if (i == 0 && seeds)
+            VD_HIP(vd::launch_flood_seeds(s->map[s->cur], s->map[s->cur ^ 1], s->cfg.width,
+                                          s->cfg.height, p.k, p.vn, s->cfg.metric, p.variant,
+                                          stream));
         else
             VD_HIP(vd::launch_flood(s->map[s->cur], s->map[s->cur ^ 1], s->pos,
                                     s->cfg.num_seeds, s->cfg.width, s->cfg.height, p.k, p.vn,
@@ -273,13 +280,13 @@ int launch_passes(vd_sim *s, const std::vector<Pass> &passes, int32_t th,
 }
 
 int run_passes(vd_sim *s, const std::vector<Pass> &passes, int32_t th,
-               const uint32_t *relabel = nullptr)
+               const uint32_t *relabel = nullptr, bool seeds = false)
 {
     if (passes.empty()) return VD_OK;
     size_t slot = 0;
     int r = record(s, 0, true, &slot, (int)passes.size());
     if (r) return r;
-    r = launch_passes(s, passes, th, relabel);
+    r = launch_passes(s, passes, th, relabel, nullptr, seeds);
     if (r) return r;
     r = record(s, 0, false, &slot);
     if (r) return r;
@@ -312,11 +319,26 @@ const uint8_t *seed_state(const vd_sim *s) { return s->masked ? s->state : nullp
 // maps are filled with all ones rather than label 0 (both read as the
 // sentinel position in the passes, and every pixel is claimed by the end
 // of the step), so the atomic minimum of the seed labels needs no reset.
-int jfa_prologue(vd_sim *s)
+// Whether an XY JFA step skips the fill: its first pass then reads the
+// previous diagram, where only the seed pixels (splatted with the top bit)
+// count as claimed.  Needs a diagram in map[cur] and the block tile for the
+// first pass, run with its own launch.
+bool seeds_for(const vd_sim *s, const std::vector<Pass> &passes, int32_t th)
+{
+    if (s->cfg.label != VD_LABEL_XY16 || !s->diagram || passes.empty()) return false;
+    const size_t m = th ? vd::tail_len(passes) : 0;
+    if (m >= passes.size()) return false;
+    return vd::flood_seeds_ok(s->cfg.width, s->cfg.height, passes[0].k);
+}
+
+int jfa_prologue(vd_sim *s, bool seeds)
 {
     const vd_config &c = s->cfg;
     int64_t npix = (int64_t)c.width * c.height;
-    if (c.label == VD_LABEL_XY16) {
+    if (c.label == VD_LABEL_XY16 && seeds) {
+        VD_HIP(vd::launch_splat_xy_marked(s->map[s->cur], s->pos, c.num_seeds, c.width,
+                                          seed_state(s), s->stream));
+    } else if (c.label == VD_LABEL_XY16) {
         VD_HIP(vd::launch_fill(s->map[s->cur], npix, vd::kEmpty, s->stream));
         VD_HIP(vd::launch_splat_xy(s->map[s->cur], s->pos, c.num_seeds, c.width, seed_state(s),
                                    s->stream));
@@ -398,8 +420,9 @@ int step_epilogue(vd_sim *s)
 
 int do_jfa(vd_sim *s)
 {
-    int r = jfa_prologue(s);
-    if (r == VD_OK) r = run_passes(s, s->jfa_passes, s->tail_th[0]);
+    const bool seeds = seeds_for(s, s->jfa_passes, s->tail_th[0]);
+    int r = jfa_prologue(s, seeds);
+    if (r == VD_OK) r = run_passes(s, s->jfa_passes, s->tail_th[0], nullptr, seeds);
     if (r == VD_OK) r = step_epilogue(s);
     return r;
 }
@@ -489,7 +512,10 @@ int step(vd_sim *s, bool dynamic)
     if (r) return r;
     const bool removed = s->removed;
     r = dynamic ? do_djfa(s) : do_jfa(s);
-    if (r == VD_OK) s->reach = 0;   // the diagram refers to the current positions
+    if (r == VD_OK) {
+        s->reach = 0;   // the diagram refers to the current positions
+        s->diagram = true;
+    }
     if (r == VD_OK && dynamic && removed) r = refill_check(s);
     if (r == VD_OK) r = settle(s);
     // the diagram now refers to the current positions
@@ -628,6 +654,7 @@ int vd_autotune(vd_sim *s, int32_t reps)
     // The replays run every pass with its own launch; an XY dJFA step's first
     // pass then reads through the old-position index where it can.
     const bool fold = fold_for(s, s->djfa_passes, 0);
+    const bool seeds = seeds_for(s, s->jfa_passes, 0);
     for (int dyn = 0; dyn < 2 && r == VD_OK; ++dyn) {
         if (dyn) {
             hip(hipMemcpyAsync(s->map[s->cur], save, npix * 4, hipMemcpyDeviceToDevice,
@@ -637,7 +664,7 @@ int vd_autotune(vd_sim *s, int32_t reps)
                                    s->stream), "restore");
         }
         if (r == VD_OK) {
-            int pr = dyn ? djfa_prologue(s, fold) : jfa_prologue(s);
+            int pr = dyn ? djfa_prologue(s, fold) : jfa_prologue(s, seeds);
             if (pr) r = pr;
         }
         size_t pass_i = 0;
@@ -645,12 +672,18 @@ int vd_autotune(vd_sim *s, int32_t reps)
             if (r != VD_OK) break;
             std::string key = tune_key(arch, c, p, dyn != 0);
             bool fresh = std::find(keys.begin(), keys.end(), key) == keys.end();
-            const bool relabel = dyn && fold && pass_i++ == 0;
+            const bool first_pass = pass_i++ == 0;
+            const bool relabel = dyn && fold && first_pass;
+            const bool from_seeds = !dyn && seeds && first_pass;
             auto launch = [&](int32_t variant, int32_t seg_rows) {
                 if (relabel)
                     return vd::launch_flood_relabel(s->map[s->cur], s->map[s->cur ^ 1], s->idx,
                                                     c.width, c.height, p.k, p.vn, c.metric,
                                                     variant, seg_rows, s->stream);
+                if (from_seeds)
+                    return vd::launch_flood_seeds(s->map[s->cur], s->map[s->cur ^ 1], c.width,
+                                                  c.height, p.k, p.vn, c.metric, variant,
+                                                  s->stream);
                 return vd::launch_flood(s->map[s->cur], s->map[s->cur ^ 1], s->pos, c.num_seeds,
                                         c.width, c.height, p.k, p.vn, c.label, c.metric,
                                         variant, seg_rows, s->stream);
@@ -707,7 +740,7 @@ int vd_autotune(vd_sim *s, int32_t reps)
                 hip(hipMemcpyAsync(s->pos_map, save_pm, tab_bytes, hipMemcpyDeviceToDevice,
                                    s->stream), "restore");
             if (r == VD_OK) {
-                int pr = dyn ? djfa_prologue(s, fold) : jfa_prologue(s);
+                int pr = dyn ? djfa_prologue(s, fold) : jfa_prologue(s, seeds);
                 if (pr) r = pr;
             }
             hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -726,6 +759,9 @@ int vd_autotune(vd_sim *s, int32_t reps)
                         ? vd::launch_flood_relabel(s->map[s->cur], s->map[s->cur ^ 1], s->idx,
                                                    c.width, c.height, p.k, p.vn, c.metric, v,
                                                    c0.seg_rows, s->stream)
+                    : !dyn && seeds && first
+                        ? vd::launch_flood_seeds(s->map[s->cur], s->map[s->cur ^ 1], c.width,
+                                                 c.height, p.k, p.vn, c.metric, v, s->stream)
                         : vd::launch_flood(s->map[s->cur], s->map[s->cur ^ 1], s->pos,
                                            c.num_seeds, c.width, c.height, p.k, p.vn, c.label,
                                            c.metric, v, c0.seg_rows, s->stream);
@@ -764,8 +800,9 @@ int vd_autotune(vd_sim *s, int32_t reps)
                                    s->stream), "restore");
             const int32_t th = policy ? kTailHeights[policy - 1] : 0;
             const bool fold_t = dyn && fold_for(s, passes, th);
+            const bool seeds_t = !dyn && seeds_for(s, passes, th);
             if (r == VD_OK) {
-                int pr = dyn ? djfa_prologue(s, fold_t) : jfa_prologue(s);
+                int pr = dyn ? djfa_prologue(s, fold_t) : jfa_prologue(s, seeds_t);
                 if (pr) r = pr;
             }
             hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -775,7 +812,7 @@ int vd_autotune(vd_sim *s, int32_t reps)
             ev.push_back(e1);
             hip(hipEventRecord(e0, s->stream), "hipEventRecord");
             if (r == VD_OK) {
-                int lr = launch_passes(s, passes, th, fold_t ? s->idx : nullptr);
+                int lr = launch_passes(s, passes, th, fold_t ? s->idx : nullptr, nullptr, seeds_t);
                 if (lr) r = lr;
             }
             hip(hipEventRecord(e1, s->stream), "hipEventRecord");

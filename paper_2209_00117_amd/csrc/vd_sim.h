@@ -71,6 +71,8 @@ struct vd_sim {
                                  // all ones (kIndexEpochs: fill before the next)
     int32_t reach = 0;           // bound on how far (per axis) any seed has moved since the
                                  // diagram was made
+    bool diagram = false;        // map[cur] holds a diagram (no marked labels): an XY JFA
+                                 // step may start from it instead of a filled map
     int64_t t = 0;
     int32_t dmax = 0;
     uint32_t *disp = nullptr;    // [0]: displacement bound since the last step, [1]: scratch
