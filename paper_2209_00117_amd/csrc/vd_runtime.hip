@@ -315,10 +315,6 @@ namespace {
 // and kept (the common case costs nothing).
 const uint8_t *seed_state(const vd_sim *s) { return s->masked ? s->state : nullptr; }
 
-// The map a JFA step floods: unclaimed everywhere but the seed pixels.  ID
-// maps are filled with all ones rather than label 0 (both read as the
-// sentinel position in the passes, and every pixel is claimed by the end
-// of the step), so the atomic minimum of the seed labels needs no reset.
 // Whether an XY JFA step skips the fill: its first pass then reads the
 // previous diagram, where only the seed pixels (splatted with the top bit)
 // count as claimed.  Needs a diagram in map[cur] and the block tile for the
@@ -331,6 +327,12 @@ bool seeds_for(const vd_sim *s, const std::vector<Pass> &passes, int32_t th)
     return vd::flood_seeds_ok(s->cfg.width, s->cfg.height, passes[0].k);
 }
 
+// The map a JFA step floods: unclaimed everywhere but the seed pixels.  ID
+// maps are filled with all ones rather than label 0 (both read as the
+// sentinel position in the passes, and every pixel is claimed by the end
+// of the step), so the atomic minimum of the seed labels needs no reset.
+// With seeds (seeds_for), an XY step leaves the previous diagram in place
+// and marks the seed pixels instead.
 int jfa_prologue(vd_sim *s, bool seeds)
 {
     const vd_config &c = s->cfg;
