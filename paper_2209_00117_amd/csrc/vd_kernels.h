@@ -206,6 +206,18 @@ bool flood_seeds_ok(int32_t W, int32_t H, int32_t k);
 hipError_t launch_flood_seeds(const uint32_t *src, uint32_t *dst, int32_t W, int32_t H, int32_t k,
                               int32_t vn, int32_t metric, int32_t variant, hipStream_t s);
 
+// The first two passes of a step (k, then k / 2, both Moore) in one
+// launch: where both sides are at most 2 k, the width is a
+// multiple of 4 and k of 8 (flood_pair_ok), every candidate of both passes
+// for a pixel lies in one 4 x 4 block of four-column groups at spacing
+// k / 2, which a lane loads once.  With seeds (XY labels), the first pass
+// reads as launch_flood_seeds does.  dst equals the two passes run one after
+// the other (through a map in between).
+bool flood_pair_ok(int32_t W, int32_t H, int32_t k);
+hipError_t launch_flood_pair(const uint32_t *src, uint32_t *dst, const uint32_t *table,
+                             int32_t S, int32_t W, int32_t H, int32_t k, int32_t label,
+                             bool seeds, int32_t metric, bool nt, hipStream_t s);
+
 // The first pass of an XY-label dJFA step, reading the previous diagram
 // through the old-position index instead of after a relabel pass: src holds
 // old positions (and this step's seed pixels, marked with the top bit by

@@ -443,6 +443,28 @@ __global__ void __launch_bounds__(kBlock) k_flood_block(const uint32_t *__restri
                                              (int32_t)blockIdx.y);
 }
 
+// The first two passes of a step, k and kh = k / 2, both Moore, in one
+// launch (flood_block_pair_tile; pair_ok(W, H, k)): one lane per 4 x 4
+// block of groups at spacing kh.
+template <int LABEL, int METRIC, int ST>
+__global__ void __launch_bounds__(kBlock) k_flood_pair(const uint32_t *__restrict__ src,
+                                                       uint32_t *__restrict__ dst,
+                                                       const uint32_t *__restrict__ table,
+                                                       uint32_t S, int32_t W, int32_t H,
+                                                       int32_t kh)
+{
+    const int32_t gx = (int32_t)(blockIdx.x * kBlock + threadIdx.x);
+    if (kQuad * gx >= min(kh, W)) return;
+    const int32_t y0 = (int32_t)blockIdx.y;
+    if (LABEL == kLabelId)
+        flood_block_pair_tile<METRIC, ST>(src, dst, TableLookup{table_rsrc(table, S)}, W, H, kh,
+                                          gx, y0);
+    else if (LABEL == kLabelXy)
+        flood_block_pair_tile<METRIC, ST>(src, dst, PosLabels{}, W, H, kh, gx, y0);
+    else   // kLabelXySeeds
+        flood_block_pair_tile<METRIC, ST>(src, dst, SeedMarks{}, W, H, kh, gx, y0);
+}
+
 // Column-class tiles (see flood_class_tile): G groups per lane, C lanes per
 // class.
 template <int G, int LABEL, int METRIC, int VN, int ST>
@@ -910,6 +932,42 @@ hipError_t launch_flood(const uint32_t *src, uint32_t *dst, const uint32_t *tabl
 }
 
 bool flood_seeds_ok(int32_t W, int32_t H, int32_t k) { return block_ok(W, H, k); }
+
+bool flood_pair_ok(int32_t W, int32_t H, int32_t k) { return pair_ok(W, H, k); }
+
+hipError_t launch_flood_pair(const uint32_t *src, uint32_t *dst, const uint32_t *table,
+                             int32_t S, int32_t W, int32_t H, int32_t k, int32_t label,
+                             bool seeds, int32_t metric, bool nt, hipStream_t s)
+{
+    if (!pair_ok(W, H, k) || (seeds && label != kLabelXy)) return hipErrorInvalidValue;
+    const int32_t kh = k / 2;
+    const int32_t gx = std::min(kh, W) / kQuad;
+    const dim3 grid((unsigned)((gx + kBlock - 1) / kBlock), (unsigned)std::min(kh, H));
+    const uint32_t uS = (uint32_t)S;
+    const int lb = seeds ? kLabelXySeeds : label;
+#define VD_PAIR(LB, MT)                                                                        \
+    do {                                                                                       \
+        if (nt)                                                                                \
+            hipLaunchKernelGGL((k_flood_pair<LB, MT, kStoreNT>), grid, dim3(kBlock), 0, s, src, \
+                               dst, table, uS, W, H, kh);                                      \
+        else                                                                                   \
+            hipLaunchKernelGGL((k_flood_pair<LB, MT, 0>), grid, dim3(kBlock), 0, s, src, dst,   \
+                               table, uS, W, H, kh);                                           \
+    } while (0)
+#define VD_PAIR_M(LB)                                                                          \
+    do {                                                                                       \
+        if (metric == kEuclid) VD_PAIR(LB, kEuclid); else VD_PAIR(LB, kManhattan);             \
+    } while (0)
+    if (lb == kLabelId)
+        VD_PAIR_M(kLabelId);
+    else if (lb == kLabelXy)
+        VD_PAIR_M(kLabelXy);
+    else
+        VD_PAIR_M(kLabelXySeeds);
+#undef VD_PAIR_M
+#undef VD_PAIR
+    return hipGetLastError();
+}
 
 hipError_t launch_flood_seeds(const uint32_t *src, uint32_t *dst, int32_t W, int32_t H, int32_t k,
                               int32_t vn, int32_t metric, int32_t variant, hipStream_t s)

@@ -573,6 +573,120 @@ __device__ __forceinline__ void flood_block_tile(const uint32_t *src, uint32_t *
     }
 }
 
+// The first two passes of a step, k and kh = k / 2, where both sides are at
+// most 2 k (pair_ok): the 4 x 4 block of groups {x0 + n kh} x {y0 + m kh}
+// (x0, y0 < kh) holds every candidate of both passes for its pixels (the
+// first pass's partners lie two groups away, the second's one), so a lane
+// loads its 16 groups once, runs the first pass into registers (pixels off
+// the grid stay unclaimed, as the map would hold them between the passes),
+// takes the positions of the labels it produced (ID: from the seed table)
+// and runs the second pass.  Both passes take the Moore neighbourhood (the
+// first two passes of a JFA step).
+__host__ __device__ __forceinline__ bool pair_ok(int32_t W, int32_t H, int32_t k)
+{
+    return W % kQuad == 0 && k % (2 * kQuad) == 0 && W <= 2 * k && H <= 2 * k;
+}
+
+template <int METRIC, int ST, class LK>
+__device__ __forceinline__ void flood_block_pair_tile(const uint32_t *src, uint32_t *dst,
+                                                      const LK &lk, int32_t W, int32_t H,
+                                                      int32_t kh, int32_t gx, int32_t y0)
+{
+    constexpr bool POS = LK::kLabelIsPos;   // positions are the labels: one array per level
+    const int32_t x0 = kQuad * gx;
+    const G4 none = {u32x4{0u, 0u, 0u, 0u}, u32x4{0u, 0u, 0u, 0u}};
+    const uint32_t p0 = ((uint32_t)(y0 + (int32_t)kOff) << 16) | (uint32_t)(x0 + (int32_t)kOff);
+    auto ent = [](const G4 &g, int e) { return Ent{g.l[e], POS ? g.l[e] : g.s[e]}; };
+    G4 q[4][4];   // [row m][column n]: the group at (x0 + n kh, y0 + m kh)
+    G4 h[4][4];   // the first pass's labels (and positions) there
+    // The first pass pairs rows 0 with 2 and 1 with 3, so it runs on rows 0
+    // and 2, then on rows 1 and 3: each pair of input rows is dead once its
+    // outputs exist, which bounds the registers in use.
+#pragma unroll
+    for (int half = 0; half < 2; ++half) {
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi) {
+            const int m = half + 2 * mi;
+            const __amdgpu_buffer_rsrc_t r = row_rsrc(src, y0 + m * kh, W, H);
+#pragma unroll
+            for (int n = 0; n < 4; ++n) q[m][n].l = load4(r, 4 * (x0 + n * kh));
+        }
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                const int m = half + 2 * mi;
+                if (POS)
+                    q[m][n].l = lk.pos4(q[m][n].l, none);   // the translated label
+                else
+                    q[m][n].s = lk.pos4(q[m][n].l, none);
+            }
+        // first pass (step 2 kh): partners two groups away
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                const int m = half + 2 * mi;
+                const uint32_t pb = p0 + (uint32_t)(n * kh) + ((uint32_t)(m * kh) << 16);
+                double best[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint32_t p = pb + (uint32_t)e;
+                    double v = cand_key<METRIC>(p, ent(q[m][n], e));
+#pragma unroll
+                    for (int dm = -2; dm <= 2; dm += 2)
+#pragma unroll
+                        for (int dn = -2; dn <= 2; dn += 2) {
+                            const int mm = m + dm, nn = n + dn;
+                            if ((dm == 0 && dn == 0) || mm < 0 || mm >= 4 || nn < 0 || nn >= 4)
+                                continue;
+                            v = __builtin_fmin(v, cand_key<METRIC>(p, ent(q[mm][nn], e)));
+                        }
+                    best[e] = v;
+                }
+                u32x4 l = labels_of(best);
+                const bool row_in = y0 + m * kh < H;
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (!row_in || x0 + n * kh + e >= W) l[e] = kEmpty;
+                h[m][n].l = l;
+            }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (!POS) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) h[m][n].s = lk.pos4(h[m][n].l, none);
+    }
+    // second pass (step kh): partners one group away
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+        const __amdgpu_buffer_rsrc_t out = row_rsrc(dst, y0 + m * kh, W, H);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            const uint32_t pb = p0 + (uint32_t)(n * kh) + ((uint32_t)(m * kh) << 16);
+            double best[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t p = pb + (uint32_t)e;
+                double v = cand_key<METRIC>(p, ent(h[m][n], e));
+#pragma unroll
+                for (int dm = -1; dm <= 1; ++dm)
+#pragma unroll
+                    for (int dn = -1; dn <= 1; ++dn) {
+                        const int mm = m + dm, nn = n + dn;
+                        if ((dm == 0 && dn == 0) || mm < 0 || mm >= 4 || nn < 0 || nn >= 4)
+                            continue;
+                        v = __builtin_fmin(v, cand_key<METRIC>(p, ent(h[mm][nn], e)));
+                    }
+                best[e] = v;
+            }
+            store4<ST>(labels_of(best), out, 4 * (x0 + n * kh));
+        }
+    }
+}
+
 // Column-class tile (steps of k >= 4 where a class fits one DPP row, see
 // class_lanes).  The columns congruent to x0 mod k, x0 + m k, are the only
 // ones a pixel of column x0 + m k takes candidates from, so lanes are given

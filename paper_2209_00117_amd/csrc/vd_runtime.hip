@@ -238,7 +238,9 @@ int harvest(vd_sim *s)
 // With relabel (an XY dJFA step's old-position index) non-null, the first
 // pass reads the previous diagram through it (launch_flood_relabel); with
 // seeds, an XY JFA step's first pass reads the previous diagram with the
-// seed pixels marked (launch_flood_seeds).
+// seed pixels marked (launch_flood_seeds).  Where the first two passes are
+// k and k / 2 on a map of sides at most 2 k (a JFA step's start), they run
+// as one launch (launch_flood_pair).
 int launch_passes(vd_sim *s, const std::vector<Pass> &passes, int32_t th,
                   const uint32_t *relabel = nullptr, hipStream_t stream = nullptr,
                   bool seeds = false)
@@ -248,6 +250,17 @@ int launch_passes(vd_sim *s, const std::vector<Pass> &passes, int32_t th,
     const size_t n = passes.size() - m;
     for (size_t i = 0; i < n; ++i) {
         const Pass &p = passes[i];
+        if (i == 0 && !relabel && n >= 2 && p.vn == 0 && passes[1].vn == 0 &&
+            passes[1].k * 2 == p.k && vd::flood_pair_ok(s->cfg.width, s->cfg.height, p.k)) {
+            // the first two passes in one launch (the store policy of the second)
+            VD_HIP(vd::launch_flood_pair(s->map[s->cur], s->map[s->cur ^ 1], s->pos,
+                                         s->cfg.num_seeds, s->cfg.width, s->cfg.height, p.k,
+                                         s->cfg.label, seeds, s->cfg.metric,
+                                         passes[1].variant >= vd::kFloodVariants / 2, stream));
+            s->cur ^= 1;
+            ++i;
+            continue;
+        }
         if (i == 0 && relabel)
             VD_HIP(vd::launch_flood_relabel(s->map[s->cur], s->map[s->cur ^ 1], relabel,
                                             s->cfg.width, s->cfg.height, p.k, p.vn,
