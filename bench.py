@@ -64,8 +64,9 @@ def kernel_sha() -> str:
 
 
 def measured_traffic(workload: str):
-    """HBM bytes per flood launch from the committed rocprofv3 counter runs,
-    or None when they were taken on a different kernel source."""
+    """HBM bytes per flood pass from the committed rocprofv3 counter runs
+    (a launch that runs two passes counts as two), or None when they were
+    taken on a different kernel source."""
     try:
         with open(TRAFFIC_FILE) as f:
             rec = json.load(f)
@@ -74,7 +75,7 @@ def measured_traffic(workload: str):
     entry = rec.get(workload)
     if not entry or entry.get("kernel_sha") != kernel_sha():
         return None
-    return entry.get("bytes_per_launch")
+    return entry.get("bytes_per_pass")
 
 
 def pct(a, q):
@@ -800,18 +801,20 @@ def measure_label(torch, V, args, wl, spec, xy, name):
     value = px_updates / (total_ms / 1e3)
     roofline = None
     if tj is not None and tj.flood_launches + tdd.flood_launches > 0:
-        launches = tj.flood_launches + tdd.flood_launches
-        avg_ms = (tj.flood_ms + tdd.flood_ms) / launches
+        # per flood pass (the library's pass count; a JFA step's first two
+        # passes may share one launch)
+        npass = tj.flood_launches + tdd.flood_launches
+        avg_ms = (tj.flood_ms + tdd.flood_ms) / npass
         achieved = BYTES_PER_PIXEL_UPDATE * W * H / (avg_ms / 1e3) / 1e9
         traffic = measured_traffic(args.workload + ("" if name == "id" else "-xy"))
         roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                     "traffic": traffic, "kernel": "flood pass",
-                    "avg_launch_us": round(avg_ms * 1e3, 3), "launches": launches,
-                    "algorithmic_bytes_per_launch": BYTES_PER_PIXEL_UPDATE * W * H,
-                    "jfa_avg_launch_us": round(tj.flood_ms / max(tj.flood_launches, 1) * 1e3, 3),
-                    "djfa_avg_launch_us": round(tdd.flood_ms / max(tdd.flood_launches, 1) * 1e3,
-                                                3)}
+                    "avg_pass_us": round(avg_ms * 1e3, 3), "passes": npass,
+                    "algorithmic_bytes_per_pass": BYTES_PER_PIXEL_UPDATE * W * H,
+                    "jfa_avg_pass_us": round(tj.flood_ms / max(tj.flood_launches, 1) * 1e3, 3),
+                    "djfa_avg_pass_us": round(tdd.flood_ms / max(tdd.flood_launches, 1) * 1e3,
+                                              3)}
 
     out = {
         "metric": METRIC,
