@@ -505,7 +505,15 @@ int enqueue_solo(vd_batch *b, int mode, bool tuning, hipStream_t stream, int lan
         const int32_t th = s->tail_th[mode == VD_STEP_DJFA ? 1 : 0];
         const size_t m = th ? vd::tail_len(ps) : 0;
         int cur = s->cur;
-        for (size_t j = 0; j + m < ps.size(); ++j) {
+        size_t j0 = 0;
+        if (vd::pair_at_start(s, ps, ps.size() - m)) {   // as the simulation's own step
+            VD_HIP(vd::launch_flood_pair(s->map[cur], s->map[cur ^ 1], s->pos, c.num_seeds,
+                                         c.width, c.height, ps[0].k, c.label, false, c.metric,
+                                         ps[1].variant >= vd::kFloodVariants / 2, on));
+            if (!tuning) cur ^= 1;
+            j0 = 2;
+        }
+        for (size_t j = j0; j + m < ps.size(); ++j) {
             const vd::Pass &p = ps[j];
             VD_HIP(vd::launch_flood(s->map[cur], s->map[cur ^ 1], s->pos, c.num_seeds, c.width,
                                     c.height, p.k, p.vn, c.label, c.metric, p.variant,

@@ -250,8 +250,7 @@ int launch_passes(vd_sim *s, const std::vector<Pass> &passes, int32_t th,
     const size_t n = passes.size() - m;
     for (size_t i = 0; i < n; ++i) {
         const Pass &p = passes[i];
-        if (i == 0 && !relabel && n >= 2 && p.vn == 0 && passes[1].vn == 0 &&
-            passes[1].k * 2 == p.k && vd::flood_pair_ok(s->cfg.width, s->cfg.height, p.k)) {
+        if (i == 0 && !relabel && vd::pair_at_start(s, passes, n)) {
             // the first two passes in one launch (the store policy of the second)
             VD_HIP(vd::launch_flood_pair(s->map[s->cur], s->map[s->cur ^ 1], s->pos,
                                          s->cfg.num_seeds, s->cfg.width, s->cfg.height, p.k,

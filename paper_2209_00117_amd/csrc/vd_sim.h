@@ -115,12 +115,23 @@ namespace vd {
 // launch.  For drivers of many simulations (the server's batched ticks).
 int launch_step_passes(vd_sim *s, bool dynamic, hipStream_t stream);
 
+// Whether the first two of the n passes that run with launches of their
+// own (ps minus a fused tail) run as one launch (launch_flood_pair): k and
+// k / 2, both Moore, on a map of sides at most 2 k (a JFA step's start).
+inline bool pair_at_start(const vd_sim *s, const std::vector<Pass> &ps, size_t n)
+{
+    return n >= 2 && ps[0].vn == 0 && ps[1].vn == 0 && ps[1].k * 2 == ps[0].k &&
+           flood_pair_ok(s->cfg.width, s->cfg.height, ps[0].k);
+}
+
 // Launches of a step of kind `dynamic` run by the simulation's own pass
-// driver (the fused tail counts once); each flips the current map.
+// driver (the fused tail and the fused first two passes count once); each
+// flips the current map.
 inline int32_t step_launches(const vd_sim *s, bool dynamic)
 {
     const std::vector<Pass> &ps = dynamic ? s->djfa_passes : s->jfa_passes;
     const size_t m = s->tail_th[dynamic ? 1 : 0] ? tail_len(ps) : 0;
-    return (int32_t)(ps.size() - (m ? m - 1 : 0));
+    const bool pair = pair_at_start(s, ps, ps.size() - m);
+    return (int32_t)(ps.size() - (m ? m - 1 : 0) - (pair ? 1 : 0));
 }
 }  // namespace vd
