@@ -6,8 +6,8 @@ small workload; 2^20 sampled pixels of the single and large workloads).
 sim_jfa: share of pixels whose dJFA label equals the JFA label (the paper's
 metric).  The same two figures are reported for dJFAm, a Manhattan-metric
 dJFA twin on the same seed trajectory, against the Euclidean references.  The paper finds dJFAe agreeing with JFA on close to all pixels (Sec. VI-B);
-the assertions hold the GPU to 99%.  The numbers are printed and written
-to gpurun_out/similarity.json when that folder exists.
+the assertions hold the GPU to 99%.  The numbers are printed, and written
+as JSON into the folder VD_RESULTS_DIR names when it is set.
 """
 import json
 import os
@@ -70,8 +70,8 @@ def test_similarity_per_workload(V, name, steps):
         # well below dJFAe); this only catches a broken diagram
         assert bf_m >= 0.5 and sim_m >= 0.5
     RESULTS[name] = {"workload": wl.name, "sampled_pixels": int(len(px)), "steps": rows}
-    out = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    if os.path.isdir(out):
+    out = os.environ.get("VD_RESULTS_DIR")
+    if out and os.path.isdir(out):
         with open(os.path.join(out, "similarity.json"), "w") as f:
             json.dump(RESULTS, f, indent=1)
 
@@ -79,8 +79,8 @@ def test_similarity_per_workload(V, name, steps):
 def test_similarity_sweep_vn_extra(V):
     """Similarity to the exact diagram of JFA+e and of dJFA with v leading
     Von Neumann passes and e extra passes, v, e in {0, 1, 2} (small and
-    single workloads, 3 steps).  Reported, and written to
-    gpurun_out/sweep.json; each configuration is held to 99%."""
+    single workloads, 3 steps).  Reported, and written to sweep.json in the
+    folder VD_RESULTS_DIR names; each configuration is held to 99%."""
     out = {}
     for name, steps in (("small", 3), ("single", 3)):
         wl = inputs.WORKLOADS[name]()
@@ -111,7 +111,7 @@ def test_similarity_sweep_vn_extra(V):
                 assert r >= 0.99
                 sm.close()
         out[name] = rows
-    d = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "gpurun_out")
-    if os.path.isdir(d):
+    d = os.environ.get("VD_RESULTS_DIR")
+    if d and os.path.isdir(d):
         with open(os.path.join(d, "sweep.json"), "w") as f:
             json.dump(out, f, indent=1)
